@@ -1,0 +1,217 @@
+"""Least-squares oracle: y = Z^+ x with Z formed explicitly and Householder QR.
+
+Test infrastructure only (see the package docstring).
+
+Z is the modulated square root of the horizontally localized covariance:
+its column (k, m), at position k*M + m, is the element-wise product of the
+scaled member z_k with the localization mode w_m repeated over the n_w levels
+(eqs. SqrtOfC, SQRTofPCModulation and DiagZC of the paper).  Rows are in the
+paper's segment order i = l*n_h + j (Sec. 3.4): level/kind l, grid column j.
+
+Reading used for the operation itself: the paper's left inverse (eq.
+InverseSquareRootSwift) needs n_w = K; for the general tall Z the library
+computes the Moore-Penrose left inverse, i.e. the least-squares solution
+argmin_y ||Z y - x||_2, which coincides with the paper's left inverse on
+range(Z) (and everywhere when Z is square).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+import scipy.linalg.lapack as lapack
+
+U64 = 2.0 ** -53
+
+
+def form_z(E: np.ndarray, W: np.ndarray, n_w: int) -> np.ndarray:
+    """Explicit Z (n x K*M): Z[l*n_h + j, k*M + m] = E[l*n_h + j, k] * W[j, m].
+
+    Follows eq. SQRTofPCModulation: Z = [diag(z_1) C^{1/2}, ..., diag(z_K) C^{1/2}]
+    with C^{1/2} the n_w-fold vertical stack of C_b^{1/2} = W (eq. SqrtOfC).
+    """
+    n, K = E.shape
+    n_h, M = W.shape
+    assert n == n_h * n_w
+    C_half = np.tile(W, (n_w, 1))                      # eq. SqrtOfC
+    return np.concatenate([E[:, k:k + 1] * C_half for k in range(K)], axis=1)
+
+
+def localized_covariance(E: np.ndarray, W: np.ndarray, n_w: int) -> np.ndarray:
+    """P^c = C o P^s (eq. HLocalizedPc) with P^s = E E^T and C = 1 (x) (W W^T) blocks."""
+    Ps = E @ E.T                                       # eq. PsAndItsSquareRoot
+    Cb = W @ W.T
+    C = np.tile(Cb, (n_w, n_w))                        # eq. blockStructureCEqualBlocks
+    return C * Ps
+
+
+# ---------------------------------------------------------------- Householder QR
+def householder_qr(A: np.ndarray):
+    """Unblocked Householder QR of a tall matrix (for tiny inputs).
+
+    Standard reflectors H_j = I - tau_j v_j v_j^T with v_j[0] = 1 and
+    beta_j = -sign(alpha_j) ||x_j||, so that R[j, j] = beta_j.
+    Returns (V, tau, R): V holds the reflectors below the diagonal.
+    """
+    A = np.array(A, dtype=np.float64, copy=True)
+    m, n = A.shape
+    tau = np.zeros(n)
+    for j in range(n):
+        x = A[j:, j]
+        alpha = x[0]
+        xnorm = np.linalg.norm(x[1:])
+        if xnorm == 0.0:
+            tau[j] = 0.0
+            continue
+        beta = -np.copysign(np.hypot(alpha, xnorm), alpha)
+        tau[j] = (beta - alpha) / beta
+        v = x.copy()
+        v[0] = 1.0
+        v[1:] = x[1:] / (alpha - beta)
+        A[j:, j + 1:] -= tau[j] * np.outer(v, v @ A[j:, j + 1:])
+        A[j, j] = beta
+        A[j + 1:, j] = v[1:]
+    R = np.triu(A[:n, :n])
+    return A, tau, R
+
+
+def apply_qt(V: np.ndarray, tau: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Q^T X for the reflectors of `householder_qr`."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    n = V.shape[1]
+    for j in range(n):
+        v = np.concatenate([[1.0], V[j + 1:, j]])
+        X[j:] -= tau[j] * np.outer(v, v @ X[j:])
+    return X
+
+
+# ----------------------------------------------------------- least squares
+class RankDeficient(Exception):
+    """Z has no left inverse: the QR diagonal has an (almost) zero entry."""
+
+
+def lstsq_qr(Z: np.ndarray, X: np.ndarray, own: bool = False, check_rank: bool = True):
+    """Least-squares solve min ||Z y - x|| for every column of X by Householder QR.
+
+    Steps: Z = QR (LAPACK dgeqrf, or the unblocked `householder_qr` when own=True);
+    rank check on diag(R); c = Q^T x (dormqr); y = R^{-1} c[:ncols] (dtrtrs).
+    Returns (Y, info) with info = {"residual_norm": ||c[ncols:]|| per column,
+    "rdiag": diag(R)}.
+    """
+    Z = np.asarray(Z, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    vec = X.ndim == 1
+    if vec:
+        X = X[:, None]
+    m, n = Z.shape
+    if n > m:
+        raise ValueError("Z must be tall (K*M <= n)")
+    if own:
+        V, tau, R = householder_qr(Z)
+        C = apply_qt(V, tau, X)
+    else:
+        qr, tau, _, info = lapack.dgeqrf(np.array(Z, order="F", copy=True), overwrite_a=1)
+        if info != 0:
+            raise RuntimeError("dgeqrf failed")
+        R = np.triu(qr[:n, :n])
+        lwork = max(1, X.shape[1] * 64)
+        C, _, info = lapack.dormqr("L", "T", qr, tau, np.asfortranarray(X.copy()), lwork)
+        if info != 0:
+            raise RuntimeError("dormqr failed")
+    rd = np.abs(np.diag(R))
+    if check_rank and (rd.size == 0 or rd.min() <= m * U64 * rd.max()):
+        raise RankDeficient(f"min |R_ii| = {rd.min():.3e}, max = {rd.max():.3e}")
+    Y = scipy.linalg.solve_triangular(R, C[:n], lower=False)
+    info = {"residual_norm": np.linalg.norm(C[n:], axis=0), "rdiag": np.diag(R).copy()}
+    return (Y[:, 0] if vec else Y), info
+
+
+def left_inverse_apply(E: np.ndarray, W: np.ndarray, n_w: int, X: np.ndarray,
+                       own: bool = False):
+    """The operation the library performs: Y = Z^+ X (eq. svTransform with the
+    Moore-Penrose left inverse), by explicit Z and Householder QR."""
+    return lstsq_qr(form_z(E, W, n_w), X, own=own)[0]
+
+
+def project_range(E: np.ndarray, W: np.ndarray, n_w: int, X: np.ndarray) -> np.ndarray:
+    """Orthogonal projection Q Q^T X onto range(Z) (Q from the QR of Z)."""
+    Z = form_z(E, W, n_w)
+    Q, _ = np.linalg.qr(Z, mode="reduced")
+    return Q @ (Q.T @ X)
+
+
+def cond(E: np.ndarray, W: np.ndarray, n_w: int) -> float:
+    """2-norm condition number of Z from its singular values."""
+    s = np.linalg.svd(form_z(E, W, n_w), compute_uv=False)
+    return float(s[0] / s[-1])
+
+
+# ------------------------------------------------ reference sub-steps (explicit)
+def zt_apply(E, W, n_w, X):
+    """Z^T X with Z explicit."""
+    return form_z(E, W, n_w).T @ X
+
+
+def z_apply(E, W, n_w, Y):
+    """Z Y with Z explicit (the forward square root x = Z x~)."""
+    return form_z(E, W, n_w) @ Y
+
+
+def gram(E, W, n_w):
+    """Z^T Z with Z explicit."""
+    Z = form_z(E, W, n_w)
+    return Z.T @ Z
+
+
+def column_grams(E: np.ndarray, n_h: int, n_w: int) -> np.ndarray:
+    """Per-grid-column Grams S[j] = A_j^T A_j (K x K), A_j the n_w x K rows of
+    the members that belong to grid column j (the paper's A_m, Sec. 3.9)."""
+    n, K = E.shape
+    A = E.reshape(n_w, n_h, K)                          # A[l, j, k]
+    return np.einsum("ljk,ljq->jkq", A, A)
+
+
+def cholesky(G):
+    """Lower Cholesky factor (LAPACK dpotrf through numpy)."""
+    return np.linalg.cholesky(G)
+
+
+def tri_solves(L, B):
+    """Y = L^{-T} (L^{-1} B)."""
+    Z = scipy.linalg.solve_triangular(L, B, lower=True)
+    return scipy.linalg.solve_triangular(L.T, Z, lower=False)
+
+
+# --------------------------------------------------- low-precision copies of Z
+def round_fp32(x: np.ndarray) -> np.ndarray:
+    """Round float64 values to the nearest float32 (ties to even), returned as float64."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 (8 significant bits, ties to
+    even), returned as float64.  Written from the format's definition: keep the
+    sign, the 8 exponent bits and the top 7 fraction bits of the float32 layout,
+    i.e. round the binary64 significand to 8 bits.  Magnitudes below the
+    smallest normal bfloat16 (2**-126) are flushed to a signed zero; magnitudes
+    that would overflow raise (they never occur for these inputs)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = np.abs(x) >= 2.0 ** -126
+    out[~nz] = np.copysign(0.0, x[~nz])
+    m, e = np.frexp(x[nz])            # x = m * 2**e, 0.5 <= |m| < 1
+    if np.any(e > 128):
+        raise ValueError("value outside the bfloat16 range")
+    scaled = np.ldexp(m, 8)           # |scaled| in [128, 256): integer part has 8 bits
+    r = np.round(scaled)              # numpy rounds half to even
+    out[nz] = np.ldexp(r, e - 8)
+    return out
+
+
+def gram_lowprec(E, W, n_w, fmt: str):
+    """Exact (float64) Gram of the rounded square root Z~ = round(E*W) elementwise.
+
+    fmt: "bf16" or "fp32".  The product E[i,k]*W[j,m] is formed in float64
+    and rounded once to the format."""
+    Z = form_z(E, W, n_w)
+    Zt = round_bf16(Z) if fmt == "bf16" else round_fp32(Z)
+    return Zt.T @ Zt
