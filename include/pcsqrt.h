@@ -1,0 +1,191 @@
+/*
+ * pcsqrt — left inverse of the modulated square root of a horizontally
+ * localized ensemble covariance, on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Sardelli & Bishop, Sec. 2.1, eq. svTransform, with the
+ * square root of Sec. 3.8, eq. SQRTofPCModulation):
+ *
+ *   P^c = C o P^s,  P^s = Z_e Z_e^T (eq. PsAndItsSquareRoot),
+ *   C   = equal n_h x n_h blocks C_b = W W^T (eqs. blockStructureCEqualBlocks, SqrtOfC),
+ *   Z   = [diag(z_1) C^{1/2}, ..., diag(z_K) C^{1/2}]            (n x K*M),
+ *   Z[l*n_h + j, k*M + m] = E[l*n_h + j, k] * W[j, m],
+ *   y   = Z^+ x = argmin_y || Z y - x ||_2    for every column x of X.
+ *
+ * E holds the scaled members z_k (eq. zkDefinition; the library uses E as
+ * given), rows in the paper's segment order i = l*n_h + j (Sec. 3.4): level or
+ * variable kind l (n_w of them), grid column j (n_h of them).  W = V_b
+ * Delta_b^{1/2} (Sec. 3.8) holds the M localization square-root modes.  The
+ * paper builds a left inverse from per-column SVDs under n_w = K (Sec. 3.9);
+ * for the general tall Z (K*M <= n) this library returns the Moore-Penrose
+ * (least-squares) left inverse, which agrees with the paper's on range(Z).
+ *
+ * Method: Z is never formed.  b = Z^T x is a per-grid-column contraction over
+ * levels followed by a projection on the modes; the Gram Z^T Z is assembled
+ * from the per-column Grams S_j = A_j^T A_j (A_j the n_w x K block of column j,
+ * Sec. 3.9) as G_{(k,m),(k',m')} = sum_j S_j[k,k'] W[j,m] W[j,m'], factored
+ * by Cholesky in FP64, and y = G^{-1} b by two triangular solves.  Reduced
+ * precision modes build the Gram of a once-rounded Z and recover FP64
+ * accuracy by iterative refinement on the least-squares residual.
+ *
+ * Conventions for every entry point:
+ *  - All matrices are column-major float64 in DEVICE memory unless stated.
+ *    Pointers are borrowed: the library never frees caller memory.  E and W
+ *    must stay alive and unchanged from pc_sqrt_build to the last apply.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it; calls are asynchronous unless stated.
+ *  - Errors are returned as pc_status; nothing is thrown or aborted and no
+ *    global error state is kept.  A plan is not thread-safe; distinct plans
+ *    are independent.
+ *  - Indices are 0-based; output row k*M + m is member k, mode m (the
+ *    column order of eq. SQRTofPCModulation).
+ */
+#ifndef PCSQRT_H
+#define PCSQRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PC_OK = 0,
+  PC_ERR_INVALID_ARG = 1,    /* null pointer, leading dimension too small, bad option value */
+  PC_ERR_SHAPE = 2,          /* a size <= 0, or K*M > n (Z would not be tall) */
+  PC_ERR_NONFINITE = 3,      /* NaN or Inf in E or W (checked by pc_sqrt_build) */
+  PC_ERR_NOT_SPD = 4,        /* a Cholesky pivot <= 0: Z is (numerically) rank deficient */
+  PC_ERR_NOT_FACTORED = 5,   /* apply before a successful pc_gram_factor */
+  PC_ERR_NO_CONVERGENCE = 6, /* refinement budget spent before the tolerance was met */
+  PC_ERR_OOM = 7,            /* device allocation failed */
+  PC_ERR_DEVICE = 8,         /* a HIP runtime call failed */
+  PC_ERR_TOO_MANY_RHS = 9    /* R larger than the max_rhs given at build time */
+} pc_status;
+
+typedef enum {
+  PC_PREC_FP64 = 0,          /* FP64 Gram (MFMA f64), FP64 Cholesky and solves */
+  PC_PREC_FP32_REFINE = 1,   /* Gram of fp32(Z) on MFMA f32, FP64 Cholesky + FP64 refinement */
+  PC_PREC_BF16_REFINE = 2    /* Gram of bf16(Z) on MFMA bf16 (fp32 accumulation), FP64 Cholesky + FP64 refinement */
+} pc_precision;
+
+/* One problem instance.  Sizes must satisfy n_h, n_w, K, M >= 1 and
+ * K*M <= n_h*n_w.  ldE >= n_h*n_w, ldW >= n_h.  max_rhs bounds the number of
+ * right-hand sides of every later apply (the plan sizes its workspace from it). */
+typedef struct {
+  int64_t n_h, n_w, K, M;
+  const double *E; int64_t ldE;   /* device, n x K, column k = z_k in segment order */
+  const double *W; int64_t ldW;   /* device, n_h x M, column m = localization mode w_m */
+  int64_t max_rhs;
+} pc_instance;
+
+typedef struct {
+  int32_t precision;   /* a pc_precision value */
+  int32_t max_refine;  /* refinement iterations allowed; in PC_PREC_FP64 these are
+                          corrected semi-normal steps (0 = plain normal equations) */
+  double tol;          /* refinement stops for a right-hand side when
+                          max|delta| <= tol * max|y|; <= 0 selects 1e-12 */
+  int32_t use_graph;   /* 1: capture the apply sequence in a hipGraph and replay it */
+  int32_t reserved;    /* must be 0 */
+} pc_options;
+
+typedef struct pc_plan pc_plan;
+
+/* pc_sqrt_build — validate `count` instances, record the borrowed E/W
+ * pointers, allocate every device workspace the later calls need (Gram and
+ * factor K*M x K*M FP64 per instance, per-column Grams, refinement scratch
+ * sized by max_rhs), and check E and W for NaN/Inf (one stream sync).
+ * On success *out receives the plan; on failure *out is NULL and nothing is
+ * left allocated.  opt may be NULL (FP64, no refinement, no graph). */
+pc_status pc_sqrt_build(const pc_instance *inst, int32_t count, const pc_options *opt,
+                        void *stream, pc_plan **out);
+
+/* pc_gram_factor — for every instance form G = Z^T Z (or the Gram of the
+ * rounded Z in reduced precision) from the per-column Grams and W, then
+ * factor G = L L^T in FP64.  Synchronizes `stream` once to read the pivot
+ * status.  Returns PC_ERR_NOT_SPD if any instance failed; *failed_instance
+ * (may be NULL) receives the first failing instance index or -1.  The plan
+ * stays valid; a failed plan rejects apply with PC_ERR_NOT_FACTORED. */
+pc_status pc_gram_factor(pc_plan *plan, void *stream, int32_t *failed_instance);
+
+/* pc_left_inverse_apply — Y_i = Z_i^+ X_i for every instance i.
+ * X[i]: device, n_i x R[i] with leading dimension ldX[i] >= n_i (read only).
+ * Y[i]: device, K_i*M_i x R[i] with leading dimension ldY[i] >= K_i*M_i.
+ * X, ldX, R, Y, ldY are HOST arrays of `count` entries (the build count).
+ * R[i] = 0 skips instance i.  Asynchronous in FP64 mode without refinement;
+ * with refinement the host reads one convergence flag per iteration (a
+ * stream sync each).  Returns PC_ERR_NO_CONVERGENCE (Y holds the last
+ * iterate) if the budget ends before the tolerance is met. */
+pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int64_t *ldX,
+                                const int64_t *R, double *const *Y, const int64_t *ldY,
+                                void *stream);
+
+/* pc_query_info — after an apply and a stream sync: iterations used by the
+ * last apply (max over its right-hand sides) and its final max|delta|/max|y|,
+ * for instance `instance`.  Either output pointer may be NULL. */
+pc_status pc_query_info(const pc_plan *plan, int32_t instance, int32_t *iterations,
+                        double *last_rel_update);
+
+/* pc_plan_destroy — free everything the plan owns (synchronizes the device
+ * first).  NULL is accepted. */
+pc_status pc_plan_destroy(pc_plan *plan);
+
+/* Static, NUL-terminated description of a status code. */
+const char *pc_status_string(pc_status s);
+
+/* ------------------------------------------------------------------------
+ * Transforms on either side of the path (same plan, same borrowed E and W).
+ * ---------------------------------------------------------------------- */
+
+/* pc_sqrt_transpose_apply — B = Z^T X for instance `instance` (the first
+ * step of the solve; also the gradient-like product of refinement).
+ * X: device n x R (ldX >= n); B: device K*M x R (ldB >= K*M).  Asynchronous. */
+pc_status pc_sqrt_transpose_apply(pc_plan *plan, int32_t instance, const double *X, int64_t ldX,
+                                  int64_t R, double *B, int64_t ldB, void *stream);
+
+/* pc_sqrt_apply — X = Z Y, the back-transform to model variables
+ * (x = (P^c)^{1/2} x~, Sec. 2.3).  Y: device K*M x R; X: device n x R. */
+pc_status pc_sqrt_apply(pc_plan *plan, int32_t instance, const double *Y, int64_t ldY,
+                        int64_t R, double *X, int64_t ldX, void *stream);
+
+/* pc_gram_assemble — form the Gram of every instance (FP64 Gram, or the
+ * Gram of the rounded Z in reduced precision) without factoring it.  The
+ * plan's K*M x K*M buffer then holds its lower triangle; pc_gram_factor
+ * repeats the assembly before it factors in place. */
+pc_status pc_gram_assemble(pc_plan *plan, void *stream);
+
+/* pc_gram_export — copy the lower triangle (diagonal included) of the plan's
+ * K*M x K*M buffer of instance `instance` into G (device, ldG >= K*M): the
+ * Gram after pc_gram_assemble, the Cholesky factor L after pc_gram_factor.
+ * Entries of G above the diagonal are not written.  Asynchronous. */
+pc_status pc_gram_export(const pc_plan *plan, int32_t instance, double *G, int64_t ldG,
+                         void *stream);
+
+/* ------------------------------------------------------------------------
+ * Per-phase timing (HIP events recorded on the caller's stream).
+ * ---------------------------------------------------------------------- */
+
+/* Phases timed while profiling is on (indices of the arrays below). */
+#define PC_PHASE_COLUMN_GRAMS 0  /* per-column Grams S_j (FP64 path) */
+#define PC_PHASE_GRAM 1          /* Gram kernel (FP64, or staging + low-precision Gram) */
+#define PC_PHASE_PAD 2           /* padding to whole blocks, saved diagonal */
+#define PC_PHASE_CHOLESKY 3      /* blocked FP64 Cholesky */
+#define PC_PHASE_ZTX 4           /* b = Z^T x of the initial solve */
+#define PC_PHASE_SOLVE 5         /* the two triangular solves of the initial solve */
+#define PC_PHASE_REFINE 6        /* the whole refinement loop */
+#define PC_PHASE_COPYOUT 7       /* copy of the solution to the caller's Y */
+#define PC_NUM_PHASES 8
+
+/* pc_profile_enable — on != 0: every later call records a pair of HIP
+ * events around each phase it runs, per instance.  Costs a few microseconds
+ * per phase.  Turning it off keeps the recorded pairs until read. */
+pc_status pc_profile_enable(pc_plan *plan, int32_t on);
+
+/* pc_profile_read — synchronizes on the recorded events and returns, per
+ * phase, the summed elapsed milliseconds (total_ms[PC_NUM_PHASES], host) and
+ * the number of recorded intervals (counts[PC_NUM_PHASES], host); then
+ * forgets them.  Either array may be NULL. */
+pc_status pc_profile_read(pc_plan *plan, double *total_ms, int64_t *counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCSQRT_H */

@@ -1,0 +1,273 @@
+"""Python binding of libpcsqrt (include/pcsqrt.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module turns
+torch device tensors into pointers and leading dimensions and checks status
+codes.  Matrices are column-major: a tensor of shape (rows, cols) must have
+stride (1, ld) with ld >= rows (use `fortran()` to get one).
+
+The functions keep the C names.  `Plan` is a small convenience owner that
+keeps the borrowed E and W tensors alive for the plan's lifetime.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcsqrt.so")
+
+PC_OK = 0
+PC_ERR_INVALID_ARG = 1
+PC_ERR_SHAPE = 2
+PC_ERR_NONFINITE = 3
+PC_ERR_NOT_SPD = 4
+PC_ERR_NOT_FACTORED = 5
+PC_ERR_NO_CONVERGENCE = 6
+PC_ERR_OOM = 7
+PC_ERR_DEVICE = 8
+PC_ERR_TOO_MANY_RHS = 9
+
+PC_PREC_FP64 = 0
+PC_PREC_FP32_REFINE = 1
+PC_PREC_BF16_REFINE = 2
+
+EXPORTED = [
+    "pc_sqrt_build", "pc_gram_factor", "pc_left_inverse_apply", "pc_query_info",
+    "pc_plan_destroy", "pc_status_string", "pc_sqrt_transpose_apply", "pc_sqrt_apply",
+    "pc_gram_assemble", "pc_gram_export", "pc_profile_enable", "pc_profile_read",
+]
+
+PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout"]
+
+
+class PcInstance(ctypes.Structure):
+    _fields_ = [("n_h", c_int64), ("n_w", c_int64), ("K", c_int64), ("M", c_int64),
+                ("E", c_void_p), ("ldE", c_int64), ("W", c_void_p), ("ldW", c_int64),
+                ("max_rhs", c_int64)]
+
+
+class PcOptions(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("max_refine", c_int32), ("tol", c_double),
+                ("use_graph", c_int32), ("reserved", c_int32)]
+
+
+class PcError(RuntimeError):
+    def __init__(self, status: int, where: str = "", extra: str = ""):
+        self.status = status
+        msg = f"{where}: {status_string(status)} (status {status})"
+        if extra:
+            msg += f" {extra}"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run __graft_entry__.build() or paper_2609_13327_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    lib.pc_sqrt_build.argtypes = [POINTER(PcInstance), c_int32, POINTER(PcOptions), c_void_p,
+                                  POINTER(c_void_p)]
+    lib.pc_gram_factor.argtypes = [c_void_p, c_void_p, POINTER(c_int32)]
+    lib.pc_left_inverse_apply.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
+                                          POINTER(c_int64), POINTER(c_void_p), POINTER(c_int64),
+                                          c_void_p]
+    lib.pc_query_info.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_double)]
+    lib.pc_plan_destroy.argtypes = [c_void_p]
+    lib.pc_status_string.argtypes = [c_int32]
+    lib.pc_status_string.restype = ctypes.c_char_p
+    lib.pc_sqrt_transpose_apply.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int64, c_void_p,
+                                            c_int64, c_void_p]
+    lib.pc_sqrt_apply.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int64, c_void_p, c_int64,
+                                  c_void_p]
+    lib.pc_gram_assemble.argtypes = [c_void_p, c_void_p]
+    lib.pc_gram_export.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p]
+    lib.pc_profile_enable.argtypes = [c_void_p, c_int32]
+    lib.pc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
+    for name in EXPORTED:
+        if name != "pc_status_string":
+            getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load_library().pc_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str, extra: str = ""):
+    if status != PC_OK:
+        raise PcError(status, where, extra)
+
+
+# ------------------------------------------------------------ tensor helpers
+def fortran(t):
+    """Column-major copy (or view) of a 2-D tensor: stride (1, rows)."""
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.stride(0) == 1 and t.stride(1) >= max(1, t.shape[0]):
+        return t
+    return t.t().contiguous().t()
+
+
+def _ld(t) -> int:
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("expected a column-major 2-D tensor (stride (1, ld)); use fortran()")
+    return max(int(t.stride(1)), int(t.shape[0]), 1)
+
+
+def _ptr(t) -> int:
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError("expected a float64 device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+# -------------------------------------------------------- C-named functions
+def pc_sqrt_build(instances: Sequence[dict], precision: int = PC_PREC_FP64, max_refine: int = 0,
+                  tol: float = 0.0, use_graph: int = 0, stream=None) -> int:
+    """instances: dicts with E (n x K), W (n_h x M) column-major float64 device
+    tensors, n_w and max_rhs.  Returns the plan handle."""
+    lib = load_library()
+    arr = (PcInstance * len(instances))()
+    for i, d in enumerate(instances):
+        E, W = d["E"], d["W"]
+        n_w = int(d.get("n_w", 1))
+        n_h = int(W.shape[0])
+        arr[i] = PcInstance(n_h, n_w, int(E.shape[1]), int(W.shape[1]), _ptr(E), _ld(E), _ptr(W),
+                            _ld(W), int(d.get("max_rhs", 1)))
+        if E.shape[0] != n_h * n_w:
+            raise ValueError("E must have n_h * n_w rows")
+    opt = PcOptions(int(precision), int(max_refine), float(tol), int(use_graph), 0)
+    plan = c_void_p()
+    _check(lib.pc_sqrt_build(arr, len(instances), ctypes.byref(opt), c_void_p(_stream(stream)),
+                             ctypes.byref(plan)), "pc_sqrt_build")
+    return plan.value
+
+
+def pc_gram_factor(plan: int, stream=None, raise_on_error: bool = True):
+    """Returns (status, failed_instance)."""
+    lib = load_library()
+    failed = c_int32(-1)
+    st = lib.pc_gram_factor(c_void_p(plan), c_void_p(_stream(stream)), ctypes.byref(failed))
+    if raise_on_error:
+        _check(st, "pc_gram_factor", f"(instance {failed.value})")
+    return st, failed.value
+
+
+def pc_gram_assemble(plan: int, stream=None):
+    _check(load_library().pc_gram_assemble(c_void_p(plan), c_void_p(_stream(stream))),
+           "pc_gram_assemble")
+
+
+def pc_left_inverse_apply(plan: int, X: Sequence, Y: Sequence, stream=None,
+                          raise_on_error: bool = True) -> int:
+    """Y[i] <- Z_i^+ X[i] for every instance (None entries skip an instance)."""
+    lib = load_library()
+    n = len(X)
+    xp = (c_void_p * n)()
+    ldx = (c_int64 * n)()
+    rr = (c_int64 * n)()
+    yp = (c_void_p * n)()
+    ldy = (c_int64 * n)()
+    for i in range(n):
+        if X[i] is None:
+            xp[i], ldx[i], rr[i], yp[i], ldy[i] = None, 1, 0, None, 1
+            continue
+        if X[i].shape[1] != Y[i].shape[1]:
+            raise ValueError("X and Y must have the same number of columns")
+        xp[i], ldx[i], rr[i] = _ptr(X[i]), _ld(X[i]), int(X[i].shape[1])
+        yp[i], ldy[i] = _ptr(Y[i]), _ld(Y[i])
+    st = lib.pc_left_inverse_apply(c_void_p(plan), xp, ldx, rr, yp, ldy, c_void_p(_stream(stream)))
+    if raise_on_error:
+        _check(st, "pc_left_inverse_apply")
+    return st
+
+
+def pc_query_info(plan: int, instance: int = 0):
+    it = c_int32(0)
+    rel = c_double(0.0)
+    _check(load_library().pc_query_info(c_void_p(plan), int(instance), ctypes.byref(it),
+                                        ctypes.byref(rel)), "pc_query_info")
+    return it.value, rel.value
+
+
+def pc_plan_destroy(plan: Optional[int]):
+    _check(load_library().pc_plan_destroy(c_void_p(plan)), "pc_plan_destroy")
+
+
+def pc_status_string(status: int) -> str:
+    return status_string(status)
+
+
+def pc_sqrt_transpose_apply(plan: int, instance: int, X, B, stream=None):
+    _check(load_library().pc_sqrt_transpose_apply(c_void_p(plan), int(instance), _ptr(X), _ld(X),
+                                                  int(X.shape[1]), _ptr(B), _ld(B),
+                                                  c_void_p(_stream(stream))), "pc_sqrt_transpose_apply")
+
+
+def pc_sqrt_apply(plan: int, instance: int, Y, X, stream=None):
+    _check(load_library().pc_sqrt_apply(c_void_p(plan), int(instance), _ptr(Y), _ld(Y),
+                                        int(Y.shape[1]), _ptr(X), _ld(X), c_void_p(_stream(stream))),
+           "pc_sqrt_apply")
+
+
+def pc_gram_export(plan: int, instance: int, G, stream=None):
+    _check(load_library().pc_gram_export(c_void_p(plan), int(instance), _ptr(G), _ld(G),
+                                         c_void_p(_stream(stream))), "pc_gram_export")
+
+
+def pc_profile_enable(plan: int, on: bool = True):
+    _check(load_library().pc_profile_enable(c_void_p(plan), int(bool(on))), "pc_profile_enable")
+
+
+def pc_profile_read(plan: int):
+    """{phase: (total_ms, count)} of the intervals recorded since the last read."""
+    n = len(PHASES)
+    tot = (c_double * n)()
+    cnt = (c_int64 * n)()
+    _check(load_library().pc_profile_read(c_void_p(plan), tot, cnt), "pc_profile_read")
+    return {PHASES[i]: (tot[i], cnt[i]) for i in range(n)}
+
+
+# -------------------------------------------------------------- convenience
+class Plan:
+    """Owns a plan and keeps its borrowed E/W tensors alive."""
+
+    def __init__(self, instances: Sequence[dict], precision: int = PC_PREC_FP64, max_refine: int = 0,
+                 tol: float = 0.0, use_graph: int = 0, stream=None):
+        self._keep = [(d["E"], d["W"]) for d in instances]
+        self.instances = list(instances)
+        self.handle = pc_sqrt_build(instances, precision, max_refine, tol, use_graph, stream)
+
+    def factor(self, stream=None, raise_on_error: bool = True):
+        return pc_gram_factor(self.handle, stream, raise_on_error)
+
+    def apply(self, X: Sequence, Y: Sequence, stream=None, raise_on_error: bool = True):
+        return pc_left_inverse_apply(self.handle, X, Y, stream, raise_on_error)
+
+    def close(self):
+        if self.handle:
+            pc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,105 @@
+// Small bandwidth-bound helpers: copies with zero padding, the refinement
+// update with its per-right-hand-side norms, finiteness checks and fills.
+#include "pc_common.h"
+#include "pc_internal.h"
+
+namespace pc {
+
+// dst[0:rows_zero_to, r] = (i < rows ? src[i, r] : 0) for every column r.
+__global__ void copy_rows_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                                 int64_t ldd, int64_t rows, int64_t rows_zero_to) {
+  const int64_t r = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows_zero_to;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i + r * ldd] = (i < rows) ? src[i + r * lds] : 0.0;
+}
+
+hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                            int64_t rows_zero_to, int64_t R, hipStream_t s) {
+  if (R <= 0 || rows_zero_to <= 0) return hipSuccess;
+  unsigned gx = (unsigned)std::min<int64_t>(ceil_div(rows_zero_to, 256), 64);
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(gx, (unsigned)R), dim3(256), 0, s, src, lds, dst, ldd, rows,
+                     rows_zero_to);
+  return hipGetLastError();
+}
+
+// Y[:, r] += D[:, r] over the first KM rows; norms[2r] = max|D[:, r]|,
+// norms[2r+1] = max|Y_new[:, r]|.  One workgroup per right-hand side.
+__global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__ Y, int64_t ldY,
+                                                            const double* __restrict__ D, int64_t ldD,
+                                                            int64_t KM, double* __restrict__ norms) {
+  __shared__ double red[2][4];
+  const int64_t r = blockIdx.x;
+  double md = 0.0, my = 0.0;
+  for (int64_t i = threadIdx.x; i < KM; i += 256) {
+    const double d = D[i + r * ldD];
+    const double y = Y[i + r * ldY] + d;
+    Y[i + r * ldY] = y;
+    md = fmax(md, fabs(d));
+    my = fmax(my, fabs(y));
+  }
+  md = wave_max(md);
+  my = wave_max(my);
+  if (lane_id() == 0) { red[0][wave_id()] = md; red[1][wave_id()] = my; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0][0], b = red[1][0];
+    for (int w = 1; w < 4; ++w) { a = fmax(a, red[0][w]); b = fmax(b, red[1][w]); }
+    norms[2 * r] = a;
+    norms[2 * r + 1] = b;
+  }
+}
+
+hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const double* Dl, int64_t ldD,
+                                int64_t R, double* norms, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_update_kernel, dim3((unsigned)R), dim3(256), 0, s, Y, ldY, Dl, ldD, in.KM, norms);
+  return hipGetLastError();
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ A, int64_t ld, int64_t rows, int64_t cols,
+                                 int* flag) {
+  const int64_t total = rows * cols;
+  int bad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, c = e / rows;
+    if (!isfinite(A[i + c * ld])) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_nonfinite_check(const double* A, int64_t ld, int64_t rows, int64_t cols, int* flag,
+                                  hipStream_t s) {
+  const int64_t total = rows * cols;
+  unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 4096));
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(g), dim3(256), 0, s, A, ld, rows, cols, flag);
+  return hipGetLastError();
+}
+
+__global__ void export_lower_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                                    int64_t ldd, int64_t n) {
+  const int64_t c = blockIdx.x;
+  for (int64_t r = c + threadIdx.x; r < n; r += blockDim.x) dst[r + c * ldd] = src[r + c * lds];
+}
+
+hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(export_lower_kernel, dim3((unsigned)n), dim3(256), 0, s, src, lds, dst, ldd, n);
+  return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int* p, int v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024));
+  hipLaunchKernelGGL(fill_int_kernel, dim3(g), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+}  // namespace pc

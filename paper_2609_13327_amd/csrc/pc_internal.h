@@ -1,0 +1,67 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace pc {
+
+constexpr int NB = 64;  // Cholesky / triangular-solve block size
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Everything the kernels need to know about one instance.
+struct Inst {
+  int64_t n_h, n_w, K, M;
+  int64_t n, KM, KMp, P;   // n = n_h*n_w, KMp = KM rounded up to NB, P = K(K+1)/2
+  const double* E; int64_t ldE;
+  const double* W; int64_t ldW;
+  int64_t max_rhs;
+  // plan-owned device buffers
+  double* G = nullptr;       // KMp x KMp, ld = KMp; Gram then its Cholesky factor (lower)
+  double* diag0 = nullptr;   // KMp: diagonal of the Gram before factoring
+  double* Linv = nullptr;    // (KMp/NB) blocks of NB x NB: inverses of the diagonal blocks of L
+  double* S = nullptr;       // n_h x P per-column Grams (row j holds the P packed pairs)
+  int* pairs = nullptr;      // P x 2: (k, k') with k <= k'
+  int* qtiles = nullptr;     // nq x 2: (m0, m0') of the mode-pair tiles
+  int nq = 0;
+  double* B = nullptr;       // KMp x max_rhs: right-hand side of the normal equations
+  double* Y = nullptr;       // KMp x max_rhs: solution / iterate
+  double* D = nullptr;       // KMp x max_rhs: correction
+  double* Rres = nullptr;    // n x max_rhs: least-squares residual x - Z y
+  int* info = nullptr;       // device int: first failing pivot column, or -1
+  int* flags = nullptr;      // device per-rhs convergence flags
+  double* norms = nullptr;   // device: per-rhs max|delta|, max|y|
+  bool factored = false;
+  int iters = 0;
+  double last_rel = 0.0;
+};
+
+// ---- kernels (launchers return hipError_t of the launch) ----
+hipError_t launch_pairs_init(const Inst& in, hipStream_t s);
+hipError_t launch_column_grams(const Inst& in, hipStream_t s);
+hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
+hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
+hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s);
+hipError_t launch_cholesky(const Inst& in, hipStream_t s);
+hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B,
+                      int64_t ldB, hipStream_t s);
+// out = Xsub - Z Y  (Xsub may be null: out = Z Y)
+hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xsub,
+                     int64_t ldXs, double* out, int64_t ldOut, hipStream_t s);
+// in-place Y <- L^{-T} L^{-1} Y on the KMp x R block (ld = ldY), using work buffer Wk
+hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk,
+                             int64_t ldW, hipStream_t s);
+hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                            int64_t rows_zero_to, int64_t R, hipStream_t s);
+hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const double* Dl,
+                                int64_t ldD, int64_t R, double* norms, hipStream_t s);
+hipError_t launch_nonfinite_check(const double* A, int64_t ld, int64_t rows, int64_t cols,
+                                  int* flag, hipStream_t s);
+hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int64_t ldd,
+                               int64_t n, hipStream_t s);
+hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
+
+}  // namespace pc

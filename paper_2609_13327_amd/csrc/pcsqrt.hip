@@ -1,0 +1,414 @@
+// C-ABI of the library: plan management and the sequencing of the kernels.
+// Declarations and the contract of every entry point are in include/pcsqrt.h.
+#include "pcsqrt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "pc_internal.h"
+
+using pc::Inst;
+
+// A refinement that stops shrinking is accepted as converged when its last
+// relative update is at most this (far below the 1e-8 accuracy target of the
+// reduced-precision modes); otherwise the apply reports no convergence.
+static constexpr double kStallAccept = 1e-9;
+
+struct pc_plan {
+  std::vector<Inst> inst;
+  pc_options opt;
+  int device = 0;
+  int* d_flag = nullptr;        // device scratch int (finiteness check)
+  double* h_norms = nullptr;    // pinned host copy of per-rhs norms
+  int64_t h_norms_cap = 0;
+  // profiling: recorded (start, stop) event pairs per phase, and a pool
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[PC_NUM_PHASES];
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+#define PC_TRY(expr)                                    \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return PC_ERR_DEVICE;         \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) return hipSuccess;
+  return hipMalloc((void**)p, sizeof(T) * (size_t)count);
+}
+
+void free_inst(Inst& in) {
+  hipFree(in.G); hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
+  hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
+  hipFree(in.info); hipFree(in.flags); hipFree(in.norms);
+  in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = in.norms = nullptr;
+  in.pairs = in.qtiles = in.info = in.flags = nullptr;
+}
+
+void free_plan(pc_plan* p) {
+  if (!p) return;
+  hipDeviceSynchronize();
+  for (auto& in : p->inst) free_inst(in);
+  for (auto& v : p->rec)
+    for (auto& e : v) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+  for (auto e : p->pool) hipEventDestroy(e);
+  hipFree(p->d_flag);
+  if (p->h_norms) hipHostFree(p->h_norms);
+  delete p;
+}
+
+// mode-pair tiles of the FP64 Gram: 8 values of m (from m0) x 16 values of m'
+// (from m0'), kept when some m <= m' inside the tile
+std::vector<int> make_qtiles(int64_t M) {
+  std::vector<int> q;
+  for (int64_t d = 0; d * 16 < M; ++d)
+    for (int64_t c = 0; c * 8 < M; ++c)
+      if (8 * c <= 16 * d + 15) { q.push_back((int)(8 * c)); q.push_back((int)(16 * d)); }
+  return q;
+}
+
+pc_status alloc_inst(Inst& in) {
+  const int64_t KMp = in.KMp, nblk = KMp / pc::NB, R = std::max<int64_t>(in.max_rhs, 1);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  chk(dalloc(&in.G, KMp * KMp));
+  chk(dalloc(&in.diag0, KMp));
+  chk(dalloc(&in.Linv, nblk * pc::NB * pc::NB));
+  chk(dalloc(&in.S, in.n_h * in.P));
+  chk(dalloc(&in.pairs, 2 * in.P));
+  std::vector<int> qt = make_qtiles(in.M);
+  in.nq = (int)(qt.size() / 2);
+  chk(dalloc(&in.qtiles, (int64_t)qt.size()));
+  chk(dalloc(&in.B, KMp * R));
+  chk(dalloc(&in.Y, KMp * R));
+  chk(dalloc(&in.D, KMp * R));
+  chk(dalloc(&in.Rres, in.n * R));
+  chk(dalloc(&in.info, 1));
+  chk(dalloc(&in.flags, R));
+  chk(dalloc(&in.norms, 2 * R));
+  if (e != hipSuccess) return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PC_ERR_OOM : PC_ERR_DEVICE;
+  if (hipMemcpy(in.qtiles, qt.data(), qt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return PC_ERR_DEVICE;
+  // padding rows of the right-hand-side buffers stay zero forever
+  if (hipMemset(in.B, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
+  if (hipMemset(in.Y, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
+  if (hipMemset(in.D, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
+  return PC_OK;
+}
+
+bool ok_ptr(const void* ptr) { return ptr != nullptr; }
+
+hipEvent_t take_event(pc_plan* p) {
+  if (!p->pool.empty()) { hipEvent_t e = p->pool.back(); p->pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around a phase when profiling is on.
+struct PhaseTimer {
+  pc_plan* p; int phase; hipStream_t s; hipEvent_t a = nullptr;
+  PhaseTimer(pc_plan* p_, int ph, hipStream_t s_) : p(p_), phase(ph), s(s_) {
+    if (p->profiling && (a = take_event(p))) hipEventRecord(a, s);
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(p);
+    if (!b) { p->pool.push_back(a); return; }
+    hipEventRecord(b, s);
+    p->rec[phase].push_back({a, b});
+  }
+};
+
+pc_status assemble(pc_plan* p, hipStream_t s) {
+  for (auto& in : p->inst) {
+    in.factored = false;
+    PC_TRY(pc::launch_fill_int(in.info, -1, 1, s));
+    if (p->opt.precision == PC_PREC_FP64) {
+      { PhaseTimer t(p, PC_PHASE_COLUMN_GRAMS, s); PC_TRY(pc::launch_column_grams(in, s)); }
+      { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_f64(in, s)); }
+    } else {
+      PhaseTimer t(p, PC_PHASE_GRAM, s);
+      PC_TRY(pc::launch_gram_lowprec(in, p->opt.precision, s));
+    }
+    { PhaseTimer t(p, PC_PHASE_PAD, s); PC_TRY(pc::launch_gram_pad_and_diag(in, s)); }
+  }
+  return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pc_status_string(pc_status s) {
+  switch (s) {
+    case PC_OK: return "ok";
+    case PC_ERR_INVALID_ARG: return "invalid argument";
+    case PC_ERR_SHAPE: return "invalid shape (sizes must be >= 1 and K*M <= n_h*n_w)";
+    case PC_ERR_NONFINITE: return "non-finite value in E or W";
+    case PC_ERR_NOT_SPD: return "Gram not positive definite: Z is rank deficient";
+    case PC_ERR_NOT_FACTORED: return "plan has no valid factorization";
+    case PC_ERR_NO_CONVERGENCE: return "iterative refinement did not converge";
+    case PC_ERR_OOM: return "device out of memory";
+    case PC_ERR_DEVICE: return "HIP runtime error";
+    case PC_ERR_TOO_MANY_RHS: return "more right-hand sides than max_rhs";
+  }
+  return "unknown status";
+}
+
+pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options* opt, void* stream,
+                        pc_plan** out) {
+  if (!out) return PC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!inst || count <= 0) return PC_ERR_INVALID_ARG;
+  pc_options o{PC_PREC_FP64, 0, 1e-12, 0, 0};
+  if (opt) o = *opt;
+  if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16_REFINE || o.max_refine < 0 ||
+      o.reserved != 0 || !std::isfinite(o.tol))
+    return PC_ERR_INVALID_ARG;
+  if (o.tol <= 0) o.tol = 1e-12;
+  for (int32_t i = 0; i < count; ++i) {
+    const pc_instance& a = inst[i];
+    if (a.n_h < 1 || a.n_w < 1 || a.K < 1 || a.M < 1) return PC_ERR_SHAPE;
+    if (a.K * a.M > a.n_h * a.n_w) return PC_ERR_SHAPE;
+    if (!ok_ptr(a.E) || !ok_ptr(a.W)) return PC_ERR_INVALID_ARG;
+    if (a.ldE < a.n_h * a.n_w || a.ldW < a.n_h || a.max_rhs < 0) return PC_ERR_INVALID_ARG;
+  }
+  pc_plan* p = new (std::nothrow) pc_plan();
+  if (!p) return PC_ERR_OOM;
+  p->opt = o;
+  hipGetDevice(&p->device);
+  hipStream_t s = (hipStream_t)stream;
+  pc_status st = PC_OK;
+  if (hipMalloc((void**)&p->d_flag, sizeof(int)) != hipSuccess) st = PC_ERR_OOM;
+  int64_t max_r = 1;
+  for (int32_t i = 0; i < count && st == PC_OK; ++i) {
+    const pc_instance& a = inst[i];
+    Inst in;
+    in.n_h = a.n_h; in.n_w = a.n_w; in.K = a.K; in.M = a.M;
+    in.n = a.n_h * a.n_w; in.KM = a.K * a.M; in.KMp = pc::round_up(in.KM, pc::NB);
+    in.P = a.K * (a.K + 1) / 2;
+    in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
+    p->inst.push_back(in);
+    st = alloc_inst(p->inst.back());
+    max_r = std::max<int64_t>(max_r, a.max_rhs);
+  }
+  if (st == PC_OK && hipHostMalloc((void**)&p->h_norms, sizeof(double) * 2 * max_r) != hipSuccess)
+    st = PC_ERR_OOM;
+  p->h_norms_cap = max_r;
+  if (st == PC_OK) {
+    // finiteness of E and W, then the pair tables
+    int bad = 0;
+    if (hipMemsetAsync(p->d_flag, 0, sizeof(int), s) != hipSuccess) st = PC_ERR_DEVICE;
+    for (auto& in : p->inst) {
+      if (st != PC_OK) break;
+      if (pc::launch_nonfinite_check(in.E, in.ldE, in.n, in.K, p->d_flag, s) != hipSuccess ||
+          pc::launch_nonfinite_check(in.W, in.ldW, in.n_h, in.M, p->d_flag, s) != hipSuccess ||
+          pc::launch_pairs_init(in, s) != hipSuccess)
+        st = PC_ERR_DEVICE;
+    }
+    if (st == PC_OK && (hipMemcpyAsync(&bad, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+      st = PC_ERR_DEVICE;
+    if (st == PC_OK && bad) st = PC_ERR_NONFINITE;
+  }
+  if (st != PC_OK) {
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return PC_OK;
+}
+
+pc_status pc_gram_assemble(pc_plan* p, void* stream) {
+  if (!p) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  return assemble(p, (hipStream_t)stream);
+}
+
+pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
+  if (failed_instance) *failed_instance = -1;
+  if (!p) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  pc_status st = assemble(p, s);
+  if (st != PC_OK) return st;
+  for (auto& in : p->inst) {
+    PhaseTimer t(p, PC_PHASE_CHOLESKY, s);
+    PC_TRY(pc::launch_cholesky(in, s));
+  }
+  std::vector<int> infos(p->inst.size(), -1);
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    PC_TRY(hipMemcpyAsync(&infos[i], p->inst[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+  PC_TRY(hipStreamSynchronize(s));
+  st = PC_OK;
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    p->inst[i].factored = infos[i] < 0;
+    if (infos[i] >= 0 && st == PC_OK) {
+      st = PC_ERR_NOT_SPD;
+      if (failed_instance) *failed_instance = (int32_t)i;
+    }
+  }
+  return st;
+}
+
+pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                                double* const* Y, const int64_t* ldY, void* stream) {
+  if (!p || !X || !ldX || !R || !Y || !ldY) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t cnt = p->inst.size();
+  for (size_t i = 0; i < cnt; ++i) {
+    const Inst& in = p->inst[i];
+    if (R[i] < 0) return PC_ERR_INVALID_ARG;
+    if (R[i] == 0) continue;
+    if (!in.factored) return PC_ERR_NOT_FACTORED;
+    if (R[i] > in.max_rhs) return PC_ERR_TOO_MANY_RHS;
+    if (!X[i] || !Y[i] || ldX[i] < in.n || ldY[i] < in.KM) return PC_ERR_INVALID_ARG;
+  }
+  // initial solve: Y = G^{-1} Z^T X
+  for (size_t i = 0; i < cnt; ++i) {
+    Inst& in = p->inst[i];
+    in.iters = 0;
+    in.last_rel = 0.0;
+    if (R[i] == 0) continue;
+    { PhaseTimer t(p, PC_PHASE_ZTX, s); PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, s)); }
+    { PhaseTimer t(p, PC_PHASE_SOLVE, s); PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, s)); }
+  }
+  // refinement on the least-squares residual: r = x - Z y, d = G^{-1} Z^T r, y += d
+  const int budget = p->opt.max_refine;
+  std::vector<char> done(cnt, 0);   // 0 running, 1 converged, 2 stalled above kStallAccept
+  std::vector<int> stall(cnt, 0);
+  pc_status st = PC_OK;
+  std::unique_ptr<PhaseTimer> refine_timer;
+  if (budget > 0) refine_timer.reset(new PhaseTimer(p, PC_PHASE_REFINE, s));
+  for (int it = 1; it <= budget; ++it) {
+    bool any = false;
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0 || done[i]) continue;
+      any = true;
+      PC_TRY(pc::launch_zy(in, in.Y, in.KMp, R[i], X[i], ldX[i], in.Rres, in.n, s));
+      PC_TRY(pc::launch_ztx(in, in.Rres, in.n, R[i], in.D, in.KMp, s));
+      PC_TRY(pc::launch_chol_solve(in, in.D, in.KMp, R[i], in.B, in.KMp, s));
+      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.norms, s));
+    }
+    if (!any) break;
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0 || done[i]) continue;
+      PC_TRY(hipMemcpyAsync(p->h_norms, in.norms, sizeof(double) * 2 * R[i], hipMemcpyDeviceToHost, s));
+      PC_TRY(hipStreamSynchronize(s));
+      double worst = 0.0;
+      for (int64_t r = 0; r < R[i]; ++r) {
+        const double dn = p->h_norms[2 * r], yn = p->h_norms[2 * r + 1];
+        const double rel = yn > 0 ? dn / yn : (dn > 0 ? INFINITY : 0.0);
+        worst = std::max(worst, std::isfinite(rel) ? rel : INFINITY);
+      }
+      // stop at the tolerance, or once the updates stop shrinking (two
+      // iterations in a row with less than a halving): the attainable
+      // accuracy of the residual has been reached
+      const double prev = in.last_rel;
+      in.iters = it;
+      in.last_rel = worst;
+      if (worst <= p->opt.tol) {
+        done[i] = 1;
+      } else if (it >= 2 && worst > 0.5 * prev) {
+        if (++stall[i] >= 2) done[i] = worst <= kStallAccept ? 1 : 2;
+      } else {
+        stall[i] = 0;
+      }
+    }
+  }
+  refine_timer.reset();
+  PhaseTimer copy_timer(p, PC_PHASE_COPYOUT, s);
+  for (size_t i = 0; i < cnt; ++i) {
+    Inst& in = p->inst[i];
+    if (R[i] == 0) continue;
+    PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y[i], ldY[i], in.KM, in.KM, R[i], s));
+    if (budget > 0 && p->opt.precision != PC_PREC_FP64 && done[i] != 1) st = PC_ERR_NO_CONVERGENCE;
+  }
+  return st;
+}
+
+pc_status pc_query_info(const pc_plan* p, int32_t instance, int32_t* iterations, double* last_rel_update) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
+  if (iterations) *iterations = p->inst[instance].iters;
+  if (last_rel_update) *last_rel_update = p->inst[instance].last_rel;
+  return PC_OK;
+}
+
+pc_status pc_plan_destroy(pc_plan* p) {
+  free_plan(p);
+  return PC_OK;
+}
+
+pc_status pc_sqrt_transpose_apply(pc_plan* p, int32_t instance, const double* X, int64_t ldX, int64_t R,
+                                  double* B, int64_t ldB, void* stream) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || R < 0) return PC_ERR_INVALID_ARG;
+  const Inst& in = p->inst[instance];
+  if (R == 0) return PC_OK;
+  if (!X || !B || ldX < in.n || ldB < in.KM) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  PC_TRY(pc::launch_ztx(in, X, ldX, R, B, ldB, (hipStream_t)stream));
+  return PC_OK;
+}
+
+pc_status pc_sqrt_apply(pc_plan* p, int32_t instance, const double* Yin, int64_t ldY, int64_t R, double* X,
+                        int64_t ldX, void* stream) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || R < 0) return PC_ERR_INVALID_ARG;
+  const Inst& in = p->inst[instance];
+  if (R == 0) return PC_OK;
+  if (!X || !Yin || ldX < in.n || ldY < in.KM) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  PC_TRY(pc::launch_zy(in, Yin, ldY, R, nullptr, 0, X, ldX, (hipStream_t)stream));
+  return PC_OK;
+}
+
+pc_status pc_profile_enable(pc_plan* p, int32_t on) {
+  if (!p) return PC_ERR_INVALID_ARG;
+  p->profiling = on != 0;
+  return PC_OK;
+}
+
+pc_status pc_profile_read(pc_plan* p, double* total_ms, int64_t* counts) {
+  if (!p) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  pc_status st = PC_OK;
+  for (int ph = 0; ph < PC_NUM_PHASES; ++ph) {
+    double tot = 0.0;
+    for (auto& e : p->rec[ph]) {
+      float ms = 0.f;
+      if (hipEventSynchronize(e.second) != hipSuccess || hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess)
+        st = PC_ERR_DEVICE;
+      tot += ms;
+      p->pool.push_back(e.first);
+      p->pool.push_back(e.second);
+    }
+    if (total_ms) total_ms[ph] = tot;
+    if (counts) counts[ph] = (int64_t)p->rec[ph].size();
+    p->rec[ph].clear();
+  }
+  return st;
+}
+
+pc_status pc_gram_export(const pc_plan* p, int32_t instance, double* G, int64_t ldG, void* stream) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || !G) return PC_ERR_INVALID_ARG;
+  const Inst& in = p->inst[instance];
+  if (ldG < in.KM) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  PC_TRY(pc::launch_export_lower(in.G, in.KMp, G, ldG, in.KM, (hipStream_t)stream));
+  return PC_OK;
+}
+
+}  // extern "C"
