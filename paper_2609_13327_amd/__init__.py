@@ -37,6 +37,7 @@ EXPORTED = [
     "pc_sqrt_build", "pc_gram_factor", "pc_left_inverse_apply", "pc_query_info",
     "pc_plan_destroy", "pc_status_string", "pc_sqrt_transpose_apply", "pc_sqrt_apply",
     "pc_gram_assemble", "pc_gram_export", "pc_profile_enable", "pc_profile_read",
+    "pc_selftest_task_order",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout"]
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     lib.pc_gram_export.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p]
     lib.pc_profile_enable.argtypes = [c_void_p, c_int32]
     lib.pc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
+    lib.pc_selftest_task_order.argtypes = [c_int32]
     for name in EXPORTED:
         if name != "pc_status_string":
             getattr(lib, name).restype = c_int32
@@ -230,6 +232,11 @@ def pc_sqrt_apply(plan: int, instance: int, Y, X, stream=None):
 def pc_gram_export(plan: int, instance: int, G, stream=None):
     _check(load_library().pc_gram_export(c_void_p(plan), int(instance), _ptr(G), _ld(G),
                                          c_void_p(_stream(stream))), "pc_gram_export")
+
+
+def pc_selftest_task_order(T: int) -> int:
+    """0 when the Cholesky DAG task order for T tile rows is valid (host only)."""
+    return int(load_library().pc_selftest_task_order(int(T)))
 
 
 def pc_profile_enable(plan: int, on: bool = True):

@@ -1,0 +1,613 @@
+// Persistent tile-DAG kernels: FP64 Cholesky G = L L^T and the two
+// triangular solves, on 64 x 64 tiles.
+//
+// A fixed grid of workgroups (two per compute unit) takes tasks from a global
+// counter in a topological order and waits on per-tile counters before it
+// runs a task, so independent tiles proceed while the critical path (the
+// factorization of the diagonal tiles) is never held up by kernel launches.
+//
+// Cholesky tasks (T = KMp / 64 tile rows):
+//   POTRF(k)    factor the diagonal tile in registers, and form its inverse
+//   TRSM(i,k)   L_ik = G_ik L_kk^{-T}              (MFMA, with the inverse)
+//   GEMM(i,j,k) G_ij -= L_ik L_jk^T, k < j <= i     (MFMA)
+// Order (look-ahead of one step): POTRF(0), TRSM(*,0); then for every k the
+// updates of tile column k+1, POTRF(k+1) and TRSM(*,k+1), then the rest of
+// step k's trailing update.  Every task appears after the tasks it needs,
+// which makes the waits deadlock-free: a waiting workgroup only waits for a
+// task that another running workgroup has already taken.
+// state[i*T + j] counts the updates applied to tile (i,j); it becomes j + 1
+// once the tile is final (after its TRSM, or its POTRF on the diagonal).
+//
+// Pivot test: d_j <= 64 * KM * 2^-53 * G_jj or a non-finite pivot marks Z as
+// numerically rank deficient (d_j / G_jj is the squared sine between column
+// j of Z and the span of the previous columns; for a dependent column it is
+// rounding noise of order KM * u).  The failing column goes to *info and every
+// waiting workgroup abandons the DAG.
+//
+// Every wait is bounded: after kSpinLimit polls the workgroup records an
+// error in *err and leaves, so the kernel always terminates.
+#include "pc_common.h"
+#include "pc_internal.h"
+
+namespace pc {
+
+constexpr int T64 = 64;
+constexpr int LDP = T64 + 1;          // padded LDS stride
+constexpr long long kSpinLimit = 1LL << 22;   // about 0.2 s of polling
+
+__device__ __forceinline__ int ld_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_release(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile data that other workgroups read while the kernel runs is moved with
+// device-coherent accesses (relaxed atomics at agent scope: they go past the
+// per-XCD L2 caches), so that no cache-wide write-back or invalidate is needed.
+__device__ __forceinline__ double ld_c(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_c(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All threads: wait until this workgroup's coherent stores have completed,
+// then thread 0 publishes `v` in *flag.
+__device__ __forceinline__ void publish(int* flag, int v) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) st_release(flag, v);
+}
+
+// Thread 0 waits until *flag >= v (or the DAG is abandoned); the coherent
+// loads that follow see the producer's data.  Returns false if the task must
+// be skipped.
+__device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info, int* err, int* sh) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    long long spins = 0;
+    while (ld_acquire(flag) < v) {
+      if (ld_acquire(info) >= 0 || ld_acquire(err) != 0) { ok = 0; break; }
+      if (++spins > kSpinLimit) { atomicOr(err, 1); ok = 0; break; }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *sh = ok;
+  }
+  __syncthreads();
+  const bool ok = *sh != 0;
+  __syncthreads();
+  return ok;
+}
+
+__device__ __forceinline__ double rdlane(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+struct TaskDesc { int type, i, j, k; };   // type 0 POTRF, 1 TRSM, 2 GEMM
+
+// t -> task in the look-ahead order described above; offs[k] is the first
+// index of iteration k (k = 0..T-2) and offs[T-1] the task count.
+__host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) {
+  TaskDesc d{0, 0, 0, 0};
+  if (t < T) {
+    if (t == 0) { d.type = 0; d.i = d.j = d.k = 0; }
+    else { d.type = 1; d.i = (int)t; d.j = d.k = 0; }
+    return d;
+  }
+  int lo = 0, hi = T - 2;                  // largest k with offs[k] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (offs[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int k = lo;
+  const int64_t u = t - offs[k];
+  const int m1 = T - k - 1;
+  if (u < m1) { d.type = 2; d.i = k + 1 + (int)u; d.j = k + 1; d.k = k; return d; }
+  if (u < 2 * m1) {
+    const int v = (int)(u - m1);
+    if (v == 0) { d.type = 0; d.i = d.j = d.k = k + 1; }
+    else { d.type = 1; d.i = k + 1 + v; d.j = d.k = k + 1; }
+    return d;
+  }
+  const int64_t w = u - 2 * m1;            // lower triangle (a >= b) of size T-k-2
+  int64_t a = (int64_t)((sqrt(8.0 * (double)w + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= w) ++a;
+  while (a * (a + 1) / 2 > w) --a;
+  const int64_t b = w - a * (a + 1) / 2;
+  d.type = 2; d.i = k + 2 + (int)a; d.j = k + 2 + (int)b; d.k = k;
+  return d;
+}
+
+struct CholArgs {
+  double* G; int64_t ld; int T; int64_t KM;
+  const double* diag0; double* Linv;
+  int* state; int* head; int* info; int* err;
+  const int64_t* offs; int64_t ntasks;
+};
+
+// ---- 16 x 16 MFMA fragments on LDS matrices stored row-major (M[r * ld + c]).
+// A operand A[r][k] = M[r0 + r][c0 + k]; transposed-B operand B[k][n] = M[r0 + n][c0 + k]
+// uses the same addressing; plain B operand B[k][n] = M[r0 + k][c0 + n].
+__device__ __forceinline__ double fr_a(const double* M, int ld, int r0, int c0, int kk) {
+  const int l = lane_id();
+  return M[(r0 + (l & 15)) * ld + c0 + kk + (l >> 4)];
+}
+__device__ __forceinline__ double fr_b(const double* M, int ld, int r0, int c0, int kk) {
+  const int l = lane_id();
+  return M[(r0 + kk + (l >> 4)) * ld + c0 + (l & 15)];
+}
+__device__ __forceinline__ void fr_store(double* M, int ld, int r0, int c0, const d4& acc) {
+  const int l = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) M[(r0 + (l >> 4) + 4 * v) * ld + c0 + (l & 15)] = acc[v];
+}
+__device__ __forceinline__ d4 fr_load(const double* M, int ld, int r0, int c0) {
+  const int l = lane_id();
+  d4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = M[(r0 + (l >> 4) + 4 * v) * ld + c0 + (l & 15)];
+  return acc;
+}
+
+// Diagonal tile, blocked by 16: for each 16-column panel, one wave factors the
+// 16 x 16 diagonal block in registers (row per lane) and inverts it; the
+// panel below is solved with that inverse and the trailing lower part is
+// updated with MFMA.  The inverse of the whole tile is then assembled block
+// by block: Y_pp = X_pp and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq, wave q
+// owning block column q.  LDS: A (64 x 65), X (4 x 16 x 16), scratch (4 x 256).
+__device__ void potrf_task(const CholArgs& a, int k, double* A, double* X, double* Sc, int* sh) {
+  const int t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int64_t k0 = (int64_t)k * T64;
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
+      v[q] = (r >= c) ? ld_c(&a.G[(k0 + r) + (k0 + c) * a.ld]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
+      A[r * LDP + c] = v[q];
+    }
+  }
+  if (t == 0) sh[1] = -1;
+  __syncthreads();
+  const double thr_scale = 64.0 * (double)a.KM * 1.1102230246251565e-16;
+  // pivot thresholds of the 64 columns, read once
+  // Sc: 4 x 256 wave scratch, then 64 pivot thresholds, then 64 reciprocal pivots
+  if (t < T64) Sc[1024 + t] = a.diag0[k0 + t] * thr_scale;
+  __syncthreads();
+  const int er = t >> 4, eq = t & 15;     // this thread's element of a 16 x 16 block
+  for (int p = 0; p < 4; ++p) {
+    const int c = 16 * p;
+    double* B16 = A + c * LDP + c;        // the diagonal 16 x 16 block, stride LDP
+    // right-looking factorization, one element per thread, two barriers per pivot
+    for (int j = 0; j < 16; ++j) {
+      __syncthreads();                    // the previous update is complete
+      const double piv = B16[j * LDP + j];
+      if (!(piv > Sc[1024 + c + j]) || !isfinite(piv)) {   // uniform decision
+        if (t == 0) sh[1] = (int)(k0 + c + j);
+        break;
+      }
+      const double inv = rsqrt(piv);      // 1 / L_jj
+      if (eq == j && er > j) B16[er * LDP + j] *= inv;
+      __syncthreads();                    // the scaled column is visible
+      if (er == j && eq == j) { B16[j * LDP + j] = piv * inv; Sc[1088 + c + j] = inv; }
+      if (eq > j && er >= eq) B16[er * LDP + eq] -= B16[er * LDP + j] * B16[eq * LDP + j];
+    }
+    __syncthreads();
+    if (sh[1] >= 0) {
+      if (t == 0) st_release(a.info, sh[1]);
+      return;
+    }
+    // inverse X_pp by rows: row j of X is final once rows 0..j-1 are
+    double* Xp = X + p * 256;
+    if (er > eq) Xp[er * 16 + eq] = 0.0;  // placeholders; the upper part stays zero
+    if (er < eq) Xp[er * 16 + eq] = 0.0;
+    for (int j = 0; j < 16; ++j) {
+      __syncthreads();
+      if (er == j && eq <= j) {
+        double acc = (eq == j) ? 1.0 : 0.0;
+        for (int m = eq; m < j; ++m) acc -= B16[j * LDP + m] * Xp[m * 16 + eq];
+        Xp[j * 16 + eq] = acc * Sc[1088 + c + j];
+      }
+    }
+    if (er < eq) B16[er * LDP + eq] = 0.0;   // keep the upper part of the tile clean
+    __syncthreads();
+    const int nf = 3 - p;                 // 16-row fragments below the diagonal block
+    if (w < nf) {                         // panel: P = A[rows, c:c+16] * X_pp^T
+      const int r0 = c + 16 + 16 * w;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4)
+        acc = mfma_f64(fr_a(A, LDP, r0, c, kk), fr_a(X + p * 256, 16, 0, 0, kk), acc);
+      fr_store(A, LDP, r0, c, acc);
+    }
+    __syncthreads();
+    // trailing lower fragments (fi >= fj) of A[c+16:, c+16:] -= P P^T
+    for (int f = w; f < nf * (nf + 1) / 2; f += 4) {
+      int fi = 0;
+      while ((fi + 1) * (fi + 2) / 2 <= f) ++fi;
+      const int fj = f - fi * (fi + 1) / 2;
+      const int ri = c + 16 + 16 * fi, rj = c + 16 + 16 * fj;
+      d4 acc = fr_load(A, LDP, ri, rj);
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4)
+        acc = mfma_f64(-fr_a(A, LDP, ri, c, kk), fr_a(A, LDP, rj, c, kk), acc);
+      fr_store(A, LDP, ri, rj, acc);
+    }
+    __syncthreads();
+  }
+  // block inverse: wave q fills block column q.  The diagonal blocks are X;
+  // an off-diagonal block Y_pq (p > q) is kept transposed in the unused upper
+  // triangle of A (rows 16q.., columns 16p..), which L never touches.
+  {
+    const int q = w;
+    double* Sw = Sc + q * 256;            // wave-private 16 x 16 scratch
+    for (int pp = q + 1; pp < 4; ++pp) {
+      d4 s4 = {0.0, 0.0, 0.0, 0.0};
+      // S = L_pq X_qq + sum_{q<m<p} L_pm Y_mq   (B[k][n] = Y_mq[k][n] = A[16q + n][16m + k])
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4)
+        s4 = mfma_f64(fr_a(A, LDP, 16 * pp, 16 * q, kk), fr_b(X + q * 256, 16, 0, 0, kk), s4);
+      for (int m = q + 1; m < pp; ++m)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+          s4 = mfma_f64(fr_a(A, LDP, 16 * pp, 16 * m, kk), fr_a(A, LDP, 16 * q, 16 * m, kk), s4);
+      fr_store(Sw, 16, 0, 0, s4);
+      d4 y4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4)
+        y4 = mfma_f64(-fr_a(X + pp * 256, 16, 0, 0, kk), fr_b(Sw, 16, 0, 0, kk), y4);
+      // store Y_pq transposed: A[16q + n][16pp + r] = Y_pq[r][n]
+      {
+        const int l = lane_id();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(16 * q + (l & 15)) * LDP + 16 * pp + (l >> 4) + 4 * v] = y4[v];
+      }
+    }
+  }
+  __syncthreads();
+  double* Lb = a.Linv + (int64_t)k * T64 * T64;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = t + 256 * u, r = idx % T64, c = idx / T64;
+    const int pr = r >> 4, pc = c >> 4;
+    double yv;
+    if (pr == pc) yv = X[pr * 256 + (r & 15) * 16 + (c & 15)];
+    else if (pr > pc) yv = A[c * LDP + r];          // transposed storage of Y_{pr,pc}
+    else yv = 0.0;
+    if (r >= c) st_c(&a.G[(k0 + r) + (k0 + c) * a.ld], A[r * LDP + c]);
+    st_c(&Lb[r + c * T64], yv);
+  }
+}
+
+// 64 x 64 tile of column-major `M` (rows r0.., cols c0..) into LDS as
+// S[c * 64 + r] (the [k][row] operand layout when the tile's columns are the
+// contraction index), scaled by `scale`.  Each thread issues its 16
+// coherent loads before it writes any of them, so they are in flight together.
+__device__ __forceinline__ void tile_to_lds(const double* M, int64_t ld, int64_t r0, int64_t c0, double* S,
+                                            double scale = 1.0) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {            // two rounds of 8 loads in flight
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * (8 * h + q), r = idx % T64, c = idx / T64;
+      v[q] = ld_c(&M[(r0 + r) + (c0 + c) * ld]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) S[threadIdx.x + 256 * (8 * h + q)] = scale * v[q];
+  }
+}
+
+// Accumulator of a 64x64 tile (2x2 waves of 32x32) <-> column-major memory.
+__device__ __forceinline__ void tile_to_acc(const double* M, int64_t ld, int64_t r0, int64_t c0,
+                                            TileF64<T64, T64, 2, 2>& acc, int64_t ncols_valid) {
+  const int lane = lane_id(), w = wave_id(), wm = w / 2, wn = w % 2;
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm * 32 + fi * 16 + (lane >> 4) + 4 * v;
+        const int c = wn * 32 + fj * 16 + (lane & 15);
+        acc.acc[fi][fj][v] = (c < ncols_valid) ? ld_c(&M[(r0 + r) + (c0 + c) * ld]) : 0.0;
+      }
+}
+
+// Loads of one 64 x 64 column-major tile into registers, 16 per thread, in
+// the order tile_store_lds writes them (S[c * 64 + r] layout).
+struct TileRegs { double v[16]; };
+__device__ __forceinline__ void tile_load(const double* M, int64_t ld, int64_t r0, int64_t c0, TileRegs& t) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+    t.v[q] = ld_c(&M[(r0 + r) + (c0 + c) * ld]);
+  }
+}
+__device__ __forceinline__ void tile_store_lds(const TileRegs& t, double* S, double scale) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) S[threadIdx.x + 256 * q] = scale * t.v[q];
+}
+
+__device__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, double* Bs) {
+  const int64_t i0 = (int64_t)i * T64, j0 = (int64_t)j * T64, k0 = (int64_t)k * T64;
+  TileF64<T64, T64, 2, 2> acc;
+  TileRegs ta, tb;
+  tile_to_acc(a.G, a.ld, i0, j0, acc, T64);          // C = G_ij       (all loads in flight)
+  tile_load(a.G, a.ld, i0, k0, ta);                   // L_ik
+  tile_load(a.G, a.ld, j0, k0, tb);                   // L_jk
+  tile_store_lds(ta, As, -1.0);
+  tile_store_lds(tb, Bs, 1.0);
+  __syncthreads();
+  acc.template mma<T64, T64, T64>(As, Bs);            // C - L_ik L_jk^T
+  const bool diag = i == j;
+  acc.for_each([&](int r, int c, double v) {
+    if (!diag || r >= c) st_c(&a.G[(i0 + r) + (j0 + c) * a.ld], v);
+  });
+}
+
+__device__ void trsm_task(const CholArgs& a, int i, int k, double* As, double* Bs) {
+  const int64_t i0 = (int64_t)i * T64, k0 = (int64_t)k * T64;
+  const double* Lb = a.Linv + (int64_t)k * T64 * T64;
+  TileRegs ta, tb;
+  tile_load(a.G, a.ld, i0, k0, ta);                   // As[c][r] = G[i0+r][k0+c]
+  tile_load(Lb, T64, 0, 0, tb);                       // Bs[c][r] = Linv[r][c]
+  tile_store_lds(ta, As, 1.0);
+  tile_store_lds(tb, Bs, 1.0);
+  __syncthreads();
+  TileF64<T64, T64, 2, 2> acc;
+  acc.zero();
+  acc.template mma<T64, T64, T64>(As, Bs);
+  acc.for_each([&](int r, int c, double v) { st_c(&a.G[(i0 + r) + (k0 + c) * a.ld], v); });
+}
+
+__global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholArgs a) {
+  // POTRF: tile (64 x 65) + X and scratch (2 x 4 x 256) = 6208 doubles;
+  // TRSM/GEMM: two 64 x 64 operands = 8192 doubles
+  __shared__ double buf[2 * T64 * T64];
+  __shared__ int sh[4];
+  double* As = buf;
+  double* Bs = buf + T64 * T64;
+  const int T = a.T;
+  for (;;) {
+    if (threadIdx.x == 0) sh[0] = atomicAdd(a.head, 1);
+    __syncthreads();
+    const int64_t t = sh[0];
+    __syncthreads();
+    if (t >= a.ntasks) break;
+    const TaskDesc d = decode_task(t, T, a.offs);
+    int* st = a.state;
+    if (d.type == 0) {
+      if (!wait_ge(&st[d.k * T + d.k], d.k, a.info, a.err, &sh[2])) continue;
+      potrf_task(a, d.k, buf, buf + T64 * LDP, buf + T64 * LDP + 1024, sh);
+      __syncthreads();
+      if (sh[1] >= 0) continue;
+      publish(&st[d.k * T + d.k], d.k + 1);
+    } else if (d.type == 1) {
+      if (!wait_ge(&st[d.k * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
+      if (!wait_ge(&st[d.i * T + d.k], d.k, a.info, a.err, &sh[2])) continue;
+      trsm_task(a, d.i, d.k, As, Bs);
+      publish(&st[d.i * T + d.k], d.k + 1);
+    } else {
+      if (!wait_ge(&st[d.i * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
+      if (d.j != d.i && !wait_ge(&st[d.j * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
+      if (!wait_ge(&st[d.i * T + d.j], d.k, a.info, a.err, &sh[2])) continue;
+      gemm_task(a, d.i, d.j, d.k, As, Bs);
+      publish(&st[d.i * T + d.j], d.k + 1);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ solves
+// Forward: task (i, rt) in order i ascending: acc = B_i - sum_{j<i} L_ij Z_j,
+// Z_i = Linv_i acc.  Backward: i descending: acc = Z_i - sum_{j>i} L_ji^T Y_j,
+// Y_i = Linv_i^T acc.  flag[i * nrt + rt] = 1 once the block row is written.
+struct SolveArgs {
+  const double* G; int64_t ld; int T;
+  const double* Linv;
+  const double* In; int64_t ldIn;
+  double* Out; int64_t ldOut;
+  int64_t R; int nrt;
+  int* flags; int* head; const int* info; int* err;
+  int backward;
+};
+
+__global__ __launch_bounds__(256, 2) void solve_dag_kernel(SolveArgs a) {
+  __shared__ double As[T64 * T64];
+  __shared__ double Bs[T64 * T64];
+  __shared__ int sh[4];
+  const int64_t ntasks = (int64_t)a.T * a.nrt;
+  for (;;) {
+    if (threadIdx.x == 0) sh[0] = atomicAdd(a.head, 1);
+    __syncthreads();
+    const int64_t t = sh[0];
+    __syncthreads();
+    if (t >= ntasks) break;
+    const int step = (int)(t / a.nrt), rt = (int)(t % a.nrt);
+    const int i = a.backward ? a.T - 1 - step : step;
+    const int64_t i0 = (int64_t)i * T64, r0 = (int64_t)rt * T64;
+    TileF64<T64, T64, 2, 2> acc;
+    tile_to_acc(a.In, a.ldIn, i0, r0, acc, a.R - r0);    // acc = In[i block, rt]
+    bool ok = true;
+    const int nprev = a.backward ? (a.T - 1 - i) : i;
+    for (int s = 0; s < nprev && ok; ++s) {
+      const int j = a.backward ? a.T - 1 - s : s;       // producers in their own order
+      const int64_t j0 = (int64_t)j * T64;
+      // operand L block: forward L_ij (As[c][r] = L[i0+r][j0+c]); backward L_ji^T (As[c][r] = L[j0+c][i0+r])
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
+        if (!a.backward) As[q * T64 + p] = a.G[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
+        else As[p * T64 + q] = a.G[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
+      }
+      if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, a.err, &sh[2])) { ok = false; break; }
+      {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;  // p: row in block j, q: rhs
+            v[u] = (r0 + q < a.R) ? ld_c(&a.Out[(j0 + p) + (r0 + q) * a.ldOut]) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
+            Bs[p * T64 + q] = v[u];
+          }
+        }
+      }
+      __syncthreads();
+      // acc -= Lop * Out_j
+      {
+        const int lane = lane_id(), w = wave_id();
+        const int wm = w / 2, wn = w % 2, rr = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+        for (int kk = 0; kk < T64; kk += 4) {
+          double av[2], bv[2];
+#pragma unroll
+          for (int f = 0; f < 2; ++f) av[f] = -As[(kk + kq) * T64 + wm * 32 + f * 16 + rr];
+#pragma unroll
+          for (int f = 0; f < 2; ++f) bv[f] = Bs[(kk + kq) * T64 + wn * 32 + f * 16 + rr];
+#pragma unroll
+          for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+            for (int fj = 0; fj < 2; ++fj) acc.acc[fi][fj] = mfma_f64(av[fi], bv[fj], acc.acc[fi][fj]);
+        }
+      }
+      __syncthreads();
+    }
+    if (!ok) continue;
+    // Out_i = Linv_i (or its transpose) * acc
+    const double* Lb = a.Linv + (int64_t)i * T64 * T64;
+    acc.for_each([&](int r, int c, double v) { Bs[r * T64 + c] = v; });
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
+      // forward: As[k][row] = Linv[row][k]; backward: As[k][row] = Linv[k][row]
+      As[q * T64 + p] = a.backward ? Lb[q + p * T64] : Lb[p + q * T64];
+    }
+    __syncthreads();
+    TileF64<T64, T64, 2, 2> res;
+    res.zero();
+    res.template mma<T64, T64, T64>(As, Bs);
+    res.for_each([&](int r, int c, double v) {
+      if (r0 + c < a.R) st_c(&a.Out[(i0 + r) + (r0 + c) * a.ldOut], v);
+    });
+    publish(&a.flags[i * a.nrt + rt], 1);
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- resets
+__global__ void dag_reset_kernel(int* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// Host check of the task order for T tile rows: every task exactly once, and
+// each task after all the tasks it waits for.  Returns 0 when valid.
+int check_chol_task_order(int T) {
+  std::vector<int64_t> offs;
+  const int64_t n = chol_task_offsets(T, offs);
+  std::vector<int> state((size_t)T * T, 0);      // updates applied / final marker, as on the device
+  std::vector<char> seen_potrf(T, 0);
+  int64_t expect = T;                             // POTRF(0) and TRSM(*, 0)
+  for (int k = 0; k + 1 < T; ++k) expect += 2 * (int64_t)(T - k - 1) + (int64_t)(T - k - 2) * (T - k - 1) / 2;
+  if (n != expect) return 1;
+  for (int64_t t = 0; t < n; ++t) {
+    const TaskDesc d = decode_task(t, T, offs.data());
+    if (d.i < 0 || d.i >= T || d.j < 0 || d.j >= T || d.k < 0 || d.k >= T) return 2;
+    int& sij = state[(size_t)d.i * T + d.j];
+    if (d.type == 0) {
+      if (d.i != d.k || d.j != d.k || sij != d.k || seen_potrf[d.k]) return 3;
+      seen_potrf[d.k] = 1;
+      sij = d.k + 1;
+    } else if (d.type == 1) {
+      if (d.j != d.k || d.i <= d.k || state[(size_t)d.k * T + d.k] != d.k + 1 || sij != d.k) return 4;
+      sij = d.k + 1;
+    } else {
+      if (!(d.k < d.j && d.j <= d.i)) return 5;
+      if (state[(size_t)d.i * T + d.k] != d.k + 1 || state[(size_t)d.j * T + d.k] != d.k + 1 || sij != d.k)
+        return 6;
+      sij = d.k + 1;
+    }
+  }
+  for (int i = 0; i < T; ++i)
+    for (int j = 0; j <= i; ++j)
+      if (state[(size_t)i * T + j] != j + 1) return 7;
+  return 0;
+}
+
+// Workgroups that fit on the device at once for `kernel` (at least one per CU).
+template <typename K>
+static int persistent_grid(K kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return (cus > 0 ? cus : 256) * per_cu;
+}
+
+int64_t chol_task_offsets(int T, std::vector<int64_t>& offs) {
+  offs.assign((size_t)std::max(T, 1), 0);
+  int64_t t = T;
+  for (int k = 0; k + 1 < T; ++k) {
+    offs[k] = t;
+    const int64_t m1 = T - k - 1, m2 = T - k - 2;
+    t += 2 * m1 + m2 * (m2 + 1) / 2;
+  }
+  if (T >= 1) offs[T - 1] = t;
+  return t;
+}
+
+hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
+  const int T = (int)(in.KMp / T64);
+  // counters: state T*T, then head, err
+  const int64_t nctr = (int64_t)T * T + 2;
+  hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nctr, 256), 1024)), dim3(256),
+                     0, s, in.dag, nctr);
+  CholArgs a;
+  a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv;
+  a.state = in.dag; a.head = in.dag + (int64_t)T * T; a.err = a.head + 1; a.info = in.info;
+  a.offs = in.chol_offs; a.ntasks = in.chol_ntasks;
+  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) holds the forward result.
+hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk, int64_t ldW,
+                             hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  const int T = (int)(in.KMp / T64);
+  const int nrt = (int)ceil_div(R, T64);
+  int* flags = in.dag + (int64_t)T * T + 2;           // T * nrt_max flags, then head
+  int* head = flags + (int64_t)T * in.nrt_max;
+  SolveArgs a;
+  a.G = in.G; a.ld = in.KMp; a.T = T; a.Linv = in.Linv; a.R = R; a.nrt = nrt;
+  a.flags = flags; a.head = head; a.info = in.info; a.err = in.dag + (int64_t)T * T + 1;
+  const int64_t nflags = (int64_t)T * in.nrt_max + 1;
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), (int64_t)T * nrt);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)),
+                       dim3(256), 0, s, flags, nflags);
+    a.backward = pass;
+    if (pass == 0) { a.In = Y; a.ldIn = ldY; a.Out = Wk; a.ldOut = ldW; }
+    else { a.In = Wk; a.ldIn = ldW; a.Out = Y; a.ldOut = ldY; }
+    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pc

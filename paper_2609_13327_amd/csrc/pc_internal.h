@@ -32,6 +32,10 @@ struct Inst {
   double* D = nullptr;       // KMp x max_rhs: correction
   double* Rres = nullptr;    // n x max_rhs: least-squares residual x - Z y
   int* info = nullptr;       // device int: first failing pivot column, or -1
+  int* dag = nullptr;        // DAG counters: T*T tile states, queue head, error, solve flags, solve head
+  int nrt_max = 1;           // 64-column tiles of max_rhs
+  int64_t* chol_offs = nullptr;  // first task index of each Cholesky look-ahead iteration
+  int64_t chol_ntasks = 0;
   int* flags = nullptr;      // device per-rhs convergence flags
   double* norms = nullptr;   // device: per-rhs max|delta|, max|y|
   bool factored = false;
@@ -63,5 +67,7 @@ hipError_t launch_nonfinite_check(const double* A, int64_t ld, int64_t rows, int
 hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int64_t ldd,
                                int64_t n, hipStream_t s);
 hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
+int64_t chol_task_offsets(int T, std::vector<int64_t>& offs);
+int check_chol_task_order(int T);
 
 }  // namespace pc

@@ -50,7 +50,8 @@ hipError_t dalloc(T** p, int64_t count) {
 void free_inst(Inst& in) {
   hipFree(in.G); hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
-  hipFree(in.info); hipFree(in.flags); hipFree(in.norms);
+  hipFree(in.info); hipFree(in.flags); hipFree(in.norms); hipFree(in.dag); hipFree(in.chol_offs);
+  in.dag = nullptr; in.chol_offs = nullptr;
   in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = in.norms = nullptr;
   in.pairs = in.qtiles = in.info = in.flags = nullptr;
 }
@@ -96,8 +97,16 @@ pc_status alloc_inst(Inst& in) {
   chk(dalloc(&in.info, 1));
   chk(dalloc(&in.flags, R));
   chk(dalloc(&in.norms, 2 * R));
+  const int64_t T = KMp / pc::NB;
+  in.nrt_max = (int)pc::ceil_div(R, pc::NB);
+  chk(dalloc(&in.dag, T * T + 2 + T * in.nrt_max + 1));
+  std::vector<int64_t> offs;
+  in.chol_ntasks = pc::chol_task_offsets((int)T, offs);
+  chk(dalloc(&in.chol_offs, (int64_t)offs.size()));
   if (e != hipSuccess) return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PC_ERR_OOM : PC_ERR_DEVICE;
   if (hipMemcpy(in.qtiles, qt.data(), qt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return PC_ERR_DEVICE;
+  if (hipMemcpy(in.chol_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
     return PC_ERR_DEVICE;
   // padding rows of the right-hand-side buffers stay zero forever
   if (hipMemset(in.B, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
@@ -247,10 +256,16 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     PhaseTimer t(p, PC_PHASE_CHOLESKY, s);
     PC_TRY(pc::launch_cholesky(in, s));
   }
-  std::vector<int> infos(p->inst.size(), -1);
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    PC_TRY(hipMemcpyAsync(&infos[i], p->inst[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    const Inst& in = p->inst[i];
+    const int64_t T = in.KMp / pc::NB;
+    PC_TRY(hipMemcpyAsync(&infos[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    PC_TRY(hipMemcpyAsync(&errs[i], in.dag + T * T + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   PC_TRY(hipStreamSynchronize(s));
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (errs[i]) return PC_ERR_DEVICE;   // a bounded wait expired: the factor is not trustworthy
   st = PC_OK;
   for (size_t i = 0; i < p->inst.size(); ++i) {
     p->inst[i].factored = infos[i] < 0;
@@ -373,6 +388,11 @@ pc_status pc_sqrt_apply(pc_plan* p, int32_t instance, const double* Yin, int64_t
   hipSetDevice(p->device);
   PC_TRY(pc::launch_zy(in, Yin, ldY, R, nullptr, 0, X, ldX, (hipStream_t)stream));
   return PC_OK;
+}
+
+int32_t pc_selftest_task_order(int32_t T) {
+  if (T < 1) return -1;
+  return pc::check_chol_task_order(T);
 }
 
 pc_status pc_profile_enable(pc_plan* p, int32_t on) {

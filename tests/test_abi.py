@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "pcsqrt.h")).read()
-    return sorted(set(re.findall(r"^(?:pc_status|const char \*)\s*(pc_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:pc_status|const char \*|int32_t)\s*(pc_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_three_hot_path_calls():
@@ -35,3 +35,12 @@ def test_status_strings():
     assert pc.status_string(pc.PC_OK) == "ok"
     assert "rank deficient" in pc.status_string(pc.PC_ERR_NOT_SPD)
     assert pc.status_string(12345) == "unknown status"
+
+
+def test_cholesky_task_order_is_topological():
+    """The persistent Cholesky kernel takes tasks in a fixed order; the host
+    replay checks every task appears once and after everything it waits for."""
+    import paper_2609_13327_amd as pc
+    for T in (1, 2, 3, 5, 8, 33, 64, 256, 512):
+        assert pc.pc_selftest_task_order(T) == 0, T
+    assert pc.pc_selftest_task_order(0) == -1
