@@ -7,14 +7,20 @@
 // factorization of the diagonal tiles) is never held up by kernel launches.
 //
 // Cholesky tasks (T = KMp / 64 tile rows):
-//   POTRF(k)    factor the diagonal tile in registers, and form its inverse
-//   TRSM(i,k)   L_ik = G_ik L_kk^{-T}              (MFMA, with the inverse)
-//   GEMM(i,j,k) G_ij -= L_ik L_jk^T, k < j <= i     (MFMA)
-// Order (look-ahead of one step): POTRF(0), TRSM(*,0); then for every k the
-// updates of tile column k+1, POTRF(k+1) and TRSM(*,k+1), then the rest of
-// step k's trailing update.  Every task appears after the tasks it needs,
-// which makes the waits deadlock-free: a waiting workgroup only waits for a
-// task that another running workgroup has already taken.
+//   POTRF(k)    factor the diagonal tile (blocked by 16, MFMA updates) and form
+//               its inverse; for k >= 1 it first applies the tile's last
+//               update G_kk -= L_{k,k-1} L_{k,k-1}^T itself
+//   TRSM(i,k)   L_ik = G_ik L_kk^{-T} (MFMA, with the inverse); for k >= 1 it
+//               first applies the tile's last update from column k-1
+//   GEMM(i,j,k) G_ij -= L_ik L_jk^T for k <= j - 2 (the earlier updates)
+// Fusing a tile's last update into its POTRF/TRSM keeps the updated tile in
+// the same workgroup, so the critical path (update -> factor -> solve of the
+// next panel) crosses fewer workgroups.
+// Order (look-ahead of one step): POTRF(0), TRSM(*,0); then for every k:
+// POTRF(k+1), TRSM(*,k+1), then the non-final updates GEMM(i,j,k), j >= k+2.
+// Every task appears after the tasks it needs, which makes the waits
+// deadlock-free: a waiting workgroup only waits for a task that another
+// running workgroup has already taken.
 // state[i*T + j] counts the updates applied to tile (i,j); it becomes j + 1
 // once the tile is final (after its TRSM, or its POTRF on the diagonal).
 //
@@ -88,10 +94,10 @@ __device__ __forceinline__ double rdlane(double x, int lane) {
   return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
 
-struct TaskDesc { int type, i, j, k; };   // type 0 POTRF, 1 TRSM, 2 GEMM
+struct TaskDesc { int type, i, j, k; };   // type 0 POTRF(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
 
-// t -> task in the look-ahead order described above; offs[k] is the first
-// index of iteration k (k = 0..T-2) and offs[T-1] the task count.
+// t -> task in the order described above; offs[k] is the first index of
+// iteration k (k = 0..T-2) and offs[T-1] the task count.
 __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) {
   TaskDesc d{0, 0, 0, 0};
   if (t < T) {
@@ -107,14 +113,12 @@ __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) 
   const int k = lo;
   const int64_t u = t - offs[k];
   const int m1 = T - k - 1;
-  if (u < m1) { d.type = 2; d.i = k + 1 + (int)u; d.j = k + 1; d.k = k; return d; }
-  if (u < 2 * m1) {
-    const int v = (int)(u - m1);
-    if (v == 0) { d.type = 0; d.i = d.j = d.k = k + 1; }
-    else { d.type = 1; d.i = k + 1 + v; d.j = d.k = k + 1; }
+  if (u < m1) {
+    if (u == 0) { d.type = 0; d.i = d.j = d.k = k + 1; }
+    else { d.type = 1; d.i = k + 1 + (int)u; d.j = d.k = k + 1; }
     return d;
   }
-  const int64_t w = u - 2 * m1;            // lower triangle (a >= b) of size T-k-2
+  const int64_t w = u - m1;                // lower triangle (a >= b) of size T-k-2
   int64_t a = (int64_t)((sqrt(8.0 * (double)w + 1.0) - 1.0) * 0.5);
   while ((a + 1) * (a + 2) / 2 <= w) ++a;
   while (a * (a + 1) / 2 > w) --a;
@@ -129,6 +133,56 @@ struct CholArgs {
   int* state; int* head; int* info; int* err;
   const int64_t* offs; int64_t ntasks;
 };
+
+// 64 x 64 tile of column-major `M` (rows r0.., cols c0..) into LDS as
+// S[c * 64 + r] (the [k][row] operand layout when the tile's columns are the
+// contraction index), scaled by `scale`.  Each thread issues its 16
+// coherent loads before it writes any of them, so they are in flight together.
+__device__ __forceinline__ void tile_to_lds(const double* M, int64_t ld, int64_t r0, int64_t c0, double* S,
+                                            double scale = 1.0) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {            // two rounds of 8 loads in flight
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * (8 * h + q), r = idx % T64, c = idx / T64;
+      v[q] = ld_c(&M[(r0 + r) + (c0 + c) * ld]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) S[threadIdx.x + 256 * (8 * h + q)] = scale * v[q];
+  }
+}
+
+// Accumulator of a 64x64 tile (2x2 waves of 32x32) <-> column-major memory.
+__device__ __forceinline__ void tile_to_acc(const double* M, int64_t ld, int64_t r0, int64_t c0,
+                                            TileF64<T64, T64, 2, 2>& acc, int64_t ncols_valid) {
+  const int lane = lane_id(), w = wave_id(), wm = w / 2, wn = w % 2;
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm * 32 + fi * 16 + (lane >> 4) + 4 * v;
+        const int c = wn * 32 + fj * 16 + (lane & 15);
+        acc.acc[fi][fj][v] = (c < ncols_valid) ? ld_c(&M[(r0 + r) + (c0 + c) * ld]) : 0.0;
+      }
+}
+
+// Loads of one 64 x 64 column-major tile into registers, 16 per thread, in
+// the order tile_store_lds writes them (S[c * 64 + r] layout).
+struct TileRegs { double v[16]; };
+__device__ __forceinline__ void tile_load(const double* M, int64_t ld, int64_t r0, int64_t c0, TileRegs& t) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+    t.v[q] = ld_c(&M[(r0 + r) + (c0 + c) * ld]);
+  }
+}
+__device__ __forceinline__ void tile_store_lds(const TileRegs& t, double* S, double scale) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) S[threadIdx.x + 256 * q] = scale * t.v[q];
+}
 
 // ---- 16 x 16 MFMA fragments on LDS matrices stored row-major (M[r * ld + c]).
 // A operand A[r][k] = M[r0 + r][c0 + k]; transposed-B operand B[k][n] = M[r0 + n][c0 + k]
@@ -160,10 +214,10 @@ __device__ __forceinline__ d4 fr_load(const double* M, int ld, int r0, int c0) {
 // updated with MFMA.  The inverse of the whole tile is then assembled block
 // by block: Y_pp = X_pp and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq, wave q
 // owning block column q.  LDS: A (64 x 65), X (4 x 16 x 16), scratch (4 x 256).
-__device__ void potrf_task(const CholArgs& a, int k, double* A, double* X, double* Sc, int* sh) {
+__device__ __noinline__ void potrf_task(const CholArgs& a, int k, double* A, double* X, double* Sc, double* Ops, int* sh) {
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int64_t k0 = (int64_t)k * T64;
-  {
+  if (k == 0) {
     double v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -175,6 +229,22 @@ __device__ void potrf_task(const CholArgs& a, int k, double* A, double* X, doubl
       const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
       A[r * LDP + c] = v[q];
     }
+  } else {
+    // the tile's last update, G_kk - L_{k,k-1} L_{k,k-1}^T, computed as
+    // -(-G_kk + L L^T) with one operand buffer (Ops overlaps A's tail)
+    TileF64<T64, T64, 2, 2> acc;
+    TileRegs tl;
+    tile_to_acc(a.G, a.ld, k0, k0, acc, T64);
+    tile_load(a.G, a.ld, k0, k0 - T64, tl);
+    tile_store_lds(tl, Ops, 1.0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc.acc[i][j] = -acc.acc[i][j];
+    __syncthreads();
+    acc.template mma<T64, T64, T64>(Ops, Ops);
+    __syncthreads();
+    acc.for_each([&](int r, int c, double v) { A[r * LDP + c] = (r >= c) ? -v : 0.0; });
   }
   if (t == 0) sh[1] = -1;
   __syncthreads();
@@ -183,43 +253,64 @@ __device__ void potrf_task(const CholArgs& a, int k, double* A, double* X, doubl
   // Sc: 4 x 256 wave scratch, then 64 pivot thresholds, then 64 reciprocal pivots
   if (t < T64) Sc[1024 + t] = a.diag0[k0 + t] * thr_scale;
   __syncthreads();
-  const int er = t >> 4, eq = t & 15;     // this thread's element of a 16 x 16 block
   for (int p = 0; p < 4; ++p) {
     const int c = 16 * p;
-    double* B16 = A + c * LDP + c;        // the diagonal 16 x 16 block, stride LDP
-    // right-looking factorization, one element per thread, two barriers per pivot
-    for (int j = 0; j < 16; ++j) {
-      __syncthreads();                    // the previous update is complete
-      const double piv = B16[j * LDP + j];
-      if (!(piv > Sc[1024 + c + j]) || !isfinite(piv)) {   // uniform decision
-        if (t == 0) sh[1] = (int)(k0 + c + j);
-        break;
+    if (w == 0) {
+      // Factor the 16 x 16 diagonal block and invert it in registers: lane r
+      // (< 16) holds row r.  Branch-free: the pivots are checked once at the end.
+      const int r = lane & 15;
+      double row[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) row[q] = A[(c + r) * LDP + c + q];
+      double worst = 1.0;                 // min over pivots of piv / threshold (NaN-safe below)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double piv = rdlane(row[j], j);
+        const double thr = Sc[1024 + c + j];
+        worst = fmin(worst, (piv > thr && isfinite(piv)) ? 1.0 : -1.0);
+        const double inv = rsqrt(piv);
+        row[j] *= inv;                    // lanes > j: L_rj; lane j: piv / sqrt(piv) = L_jj
+#pragma unroll
+        for (int q = j + 1; q < 16; ++q) row[q] = fma(-row[j], rdlane(row[j], q), row[q]);
       }
-      const double inv = rsqrt(piv);      // 1 / L_jj
-      if (eq == j && er > j) B16[er * LDP + j] *= inv;
-      __syncthreads();                    // the scaled column is visible
-      if (er == j && eq == j) { B16[j * LDP + j] = piv * inv; Sc[1088 + c + j] = inv; }
-      if (eq > j && er >= eq) B16[er * LDP + eq] -= B16[er * LDP + j] * B16[eq * LDP + j];
+      if (worst < 0.0) {
+        if (lane == 0) {
+          // first failing column, for the report
+          int f = 0;
+          for (int j = 0; j < 16; ++j) {
+            if (!(A[(c + j) * LDP + c + j] > Sc[1024 + c + j])) { f = j; break; }
+          }
+          sh[1] = (int)(k0 + c + f);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) row[q] = (q <= r) ? row[q] : 0.0;   // clean upper part
+        const double rdiag = 1.0 / row[r];
+        // forward substitution, all lanes at once; lane r keeps L_rr * X[r][.]
+        double x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = (q == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const double dj = rdlane(rdiag, j);
+          const double lrj = (r == j) ? 0.0 : row[j];
+#pragma unroll
+          for (int q = 0; q <= j; ++q) x[q] = fma(-lrj, rdlane(x[q], j) * dj, x[q]);
+        }
+        if (lane < 16) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            A[(c + r) * LDP + c + q] = row[q];
+            X[p * 256 + r * 16 + q] = (q <= r) ? x[q] * rdiag : 0.0;
+          }
+        }
+      }
     }
     __syncthreads();
     if (sh[1] >= 0) {
       if (t == 0) st_release(a.info, sh[1]);
       return;
     }
-    // inverse X_pp by rows: row j of X is final once rows 0..j-1 are
-    double* Xp = X + p * 256;
-    if (er > eq) Xp[er * 16 + eq] = 0.0;  // placeholders; the upper part stays zero
-    if (er < eq) Xp[er * 16 + eq] = 0.0;
-    for (int j = 0; j < 16; ++j) {
-      __syncthreads();
-      if (er == j && eq <= j) {
-        double acc = (eq == j) ? 1.0 : 0.0;
-        for (int m = eq; m < j; ++m) acc -= B16[j * LDP + m] * Xp[m * 16 + eq];
-        Xp[j * 16 + eq] = acc * Sc[1088 + c + j];
-      }
-    }
-    if (er < eq) B16[er * LDP + eq] = 0.0;   // keep the upper part of the tile clean
-    __syncthreads();
     const int nf = 3 - p;                 // 16-row fragments below the diagonal block
     if (w < nf) {                         // panel: P = A[rows, c:c+16] * X_pp^T
       const int r0 = c + 16 + 16 * w;
@@ -274,6 +365,8 @@ __device__ void potrf_task(const CholArgs& a, int k, double* A, double* X, doubl
     }
   }
   __syncthreads();
+  // the inverse first (the next panel's solves wait for it), then the flag,
+  // then the factor tile itself (read only by later kernels)
   double* Lb = a.Linv + (int64_t)k * T64 * T64;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -283,62 +376,17 @@ __device__ void potrf_task(const CholArgs& a, int k, double* A, double* X, doubl
     if (pr == pc) yv = X[pr * 256 + (r & 15) * 16 + (c & 15)];
     else if (pr > pc) yv = A[c * LDP + r];          // transposed storage of Y_{pr,pc}
     else yv = 0.0;
-    if (r >= c) st_c(&a.G[(k0 + r) + (k0 + c) * a.ld], A[r * LDP + c]);
     st_c(&Lb[r + c * T64], yv);
   }
-}
-
-// 64 x 64 tile of column-major `M` (rows r0.., cols c0..) into LDS as
-// S[c * 64 + r] (the [k][row] operand layout when the tile's columns are the
-// contraction index), scaled by `scale`.  Each thread issues its 16
-// coherent loads before it writes any of them, so they are in flight together.
-__device__ __forceinline__ void tile_to_lds(const double* M, int64_t ld, int64_t r0, int64_t c0, double* S,
-                                            double scale = 1.0) {
+  publish(&a.state[(int64_t)k * a.T + k], k + 1);
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {            // two rounds of 8 loads in flight
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = threadIdx.x + 256 * (8 * h + q), r = idx % T64, c = idx / T64;
-      v[q] = ld_c(&M[(r0 + r) + (c0 + c) * ld]);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) S[threadIdx.x + 256 * (8 * h + q)] = scale * v[q];
+  for (int u = 0; u < 16; ++u) {
+    const int idx = t + 256 * u, r = idx % T64, c = idx / T64;
+    if (r >= c) a.G[(k0 + r) + (k0 + c) * a.ld] = A[r * LDP + c];
   }
 }
 
-// Accumulator of a 64x64 tile (2x2 waves of 32x32) <-> column-major memory.
-__device__ __forceinline__ void tile_to_acc(const double* M, int64_t ld, int64_t r0, int64_t c0,
-                                            TileF64<T64, T64, 2, 2>& acc, int64_t ncols_valid) {
-  const int lane = lane_id(), w = wave_id(), wm = w / 2, wn = w % 2;
-#pragma unroll
-  for (int fi = 0; fi < 2; ++fi)
-#pragma unroll
-    for (int fj = 0; fj < 2; ++fj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wm * 32 + fi * 16 + (lane >> 4) + 4 * v;
-        const int c = wn * 32 + fj * 16 + (lane & 15);
-        acc.acc[fi][fj][v] = (c < ncols_valid) ? ld_c(&M[(r0 + r) + (c0 + c) * ld]) : 0.0;
-      }
-}
-
-// Loads of one 64 x 64 column-major tile into registers, 16 per thread, in
-// the order tile_store_lds writes them (S[c * 64 + r] layout).
-struct TileRegs { double v[16]; };
-__device__ __forceinline__ void tile_load(const double* M, int64_t ld, int64_t r0, int64_t c0, TileRegs& t) {
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
-    t.v[q] = ld_c(&M[(r0 + r) + (c0 + c) * ld]);
-  }
-}
-__device__ __forceinline__ void tile_store_lds(const TileRegs& t, double* S, double scale) {
-#pragma unroll
-  for (int q = 0; q < 16; ++q) S[threadIdx.x + 256 * q] = scale * t.v[q];
-}
-
-__device__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, double* Bs) {
+__device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, double* Bs) {
   const int64_t i0 = (int64_t)i * T64, j0 = (int64_t)j * T64, k0 = (int64_t)k * T64;
   TileF64<T64, T64, 2, 2> acc;
   TileRegs ta, tb;
@@ -355,19 +403,42 @@ __device__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, do
   });
 }
 
-__device__ void trsm_task(const CholArgs& a, int i, int k, double* As, double* Bs) {
+// TRSM(i,k): for k >= 1 the tile's last update from column k-1 comes first
+// (its operands are final once TRSM(i,k-1) and TRSM(k,k-1) are done), then the
+// task waits for POTRF(k) and multiplies by L_kk^{-T}.  Returns false if the
+// DAG was abandoned while waiting.
+__device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* As, double* Bs, int* sh) {
   const int64_t i0 = (int64_t)i * T64, k0 = (int64_t)k * T64;
+  TileF64<T64, T64, 2, 2> upd;
+  if (k >= 1) {
+    TileRegs ta, tb;
+    tile_to_acc(a.G, a.ld, i0, k0, upd, T64);         // G_ik
+    tile_load(a.G, a.ld, i0, k0 - T64, ta);           // L_{i,k-1}
+    tile_load(a.G, a.ld, k0, k0 - T64, tb);           // L_{k,k-1}
+    tile_store_lds(ta, As, -1.0);
+    tile_store_lds(tb, Bs, 1.0);
+    __syncthreads();
+    upd.template mma<T64, T64, T64>(As, Bs);          // G_ik - L_{i,k-1} L_{k,k-1}^T
+    __syncthreads();
+  }
+  if (!wait_ge(&a.state[(int64_t)k * a.T + k], k + 1, a.info, a.err, &sh[2])) return false;
   const double* Lb = a.Linv + (int64_t)k * T64 * T64;
-  TileRegs ta, tb;
-  tile_load(a.G, a.ld, i0, k0, ta);                   // As[c][r] = G[i0+r][k0+c]
+  TileRegs tb;
   tile_load(Lb, T64, 0, 0, tb);                       // Bs[c][r] = Linv[r][c]
-  tile_store_lds(ta, As, 1.0);
+  if (k >= 1) {
+    upd.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+  } else {
+    TileRegs ta;
+    tile_load(a.G, a.ld, i0, k0, ta);                 // As[c][r] = G[i0+r][k0+c]
+    tile_store_lds(ta, As, 1.0);
+  }
   tile_store_lds(tb, Bs, 1.0);
   __syncthreads();
   TileF64<T64, T64, 2, 2> acc;
   acc.zero();
   acc.template mma<T64, T64, T64>(As, Bs);
   acc.for_each([&](int r, int c, double v) { st_c(&a.G[(i0 + r) + (k0 + c) * a.ld], v); });
+  return true;
 }
 
 __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholArgs a) {
@@ -387,16 +458,21 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholArgs a) {
     const TaskDesc d = decode_task(t, T, a.offs);
     int* st = a.state;
     if (d.type == 0) {
-      if (!wait_ge(&st[d.k * T + d.k], d.k, a.info, a.err, &sh[2])) continue;
-      potrf_task(a, d.k, buf, buf + T64 * LDP, buf + T64 * LDP + 1024, sh);
-      __syncthreads();
-      if (sh[1] >= 0) continue;
-      publish(&st[d.k * T + d.k], d.k + 1);
+      const int k = d.k;
+      if (k >= 1) {
+        if (!wait_ge(&st[k * T + k - 1], k, a.info, a.err, &sh[2])) continue;
+        if (!wait_ge(&st[k * T + k], k - 1, a.info, a.err, &sh[2])) continue;
+      }
+      potrf_task(a, k, buf, buf + T64 * LDP, buf + T64 * LDP + 1024, buf + T64 * T64, sh);
     } else if (d.type == 1) {
-      if (!wait_ge(&st[d.k * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
-      if (!wait_ge(&st[d.i * T + d.k], d.k, a.info, a.err, &sh[2])) continue;
-      trsm_task(a, d.i, d.k, As, Bs);
-      publish(&st[d.i * T + d.k], d.k + 1);
+      const int i = d.i, k = d.k;
+      if (k >= 1) {
+        if (!wait_ge(&st[i * T + k - 1], k, a.info, a.err, &sh[2])) continue;
+        if (!wait_ge(&st[k * T + k - 1], k, a.info, a.err, &sh[2])) continue;
+        if (!wait_ge(&st[i * T + k], k - 1, a.info, a.err, &sh[2])) continue;
+      }
+      if (!trsm_task(a, i, k, As, Bs, sh)) continue;
+      publish(&st[i * T + k], k + 1);
     } else {
       if (!wait_ge(&st[d.i * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
       if (d.j != d.i && !wait_ge(&st[d.j * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
@@ -520,32 +596,36 @@ __global__ void dag_reset_kernel(int* p, int64_t count) {
 int check_chol_task_order(int T) {
   std::vector<int64_t> offs;
   const int64_t n = chol_task_offsets(T, offs);
-  std::vector<int> state((size_t)T * T, 0);      // updates applied / final marker, as on the device
-  std::vector<char> seen_potrf(T, 0);
-  int64_t expect = T;                             // POTRF(0) and TRSM(*, 0)
-  for (int k = 0; k + 1 < T; ++k) expect += 2 * (int64_t)(T - k - 1) + (int64_t)(T - k - 2) * (T - k - 1) / 2;
+  int64_t expect = T;
+  for (int k = 0; k + 1 < T; ++k) expect += (int64_t)(T - k - 1) + (int64_t)(T - k - 2) * (T - k - 1) / 2;
   if (n != expect) return 1;
+  std::vector<int> state((size_t)T * T, 0);      // as on the device: updates applied, j + 1 when final
+  auto st = [&](int i, int j) -> int& { return state[(size_t)i * T + j]; };
   for (int64_t t = 0; t < n; ++t) {
     const TaskDesc d = decode_task(t, T, offs.data());
     if (d.i < 0 || d.i >= T || d.j < 0 || d.j >= T || d.k < 0 || d.k >= T) return 2;
-    int& sij = state[(size_t)d.i * T + d.j];
-    if (d.type == 0) {
-      if (d.i != d.k || d.j != d.k || sij != d.k || seen_potrf[d.k]) return 3;
-      seen_potrf[d.k] = 1;
-      sij = d.k + 1;
-    } else if (d.type == 1) {
-      if (d.j != d.k || d.i <= d.k || state[(size_t)d.k * T + d.k] != d.k + 1 || sij != d.k) return 4;
-      sij = d.k + 1;
-    } else {
-      if (!(d.k < d.j && d.j <= d.i)) return 5;
-      if (state[(size_t)d.i * T + d.k] != d.k + 1 || state[(size_t)d.j * T + d.k] != d.k + 1 || sij != d.k)
-        return 6;
-      sij = d.k + 1;
+    if (d.type == 0) {                            // POTRF(k), with the last update when k >= 1
+      const int k = d.k;
+      if (d.i != k || d.j != k) return 3;
+      if (k >= 1 && (st(k, k - 1) < k || st(k, k) < k - 1)) return 3;
+      if (st(k, k) != (k >= 1 ? k - 1 : 0)) return 3;
+      st(k, k) = k + 1;
+    } else if (d.type == 1) {                     // TRSM(i,k), with the last update when k >= 1
+      const int i = d.i, k = d.k;
+      if (i <= k || d.j != k) return 4;
+      if (k >= 1 && (st(i, k - 1) < k || st(k, k - 1) < k || st(i, k) < k - 1)) return 4;
+      if (st(k, k) < k + 1) return 4;
+      if (st(i, k) != (k >= 1 ? k - 1 : 0)) return 4;
+      st(i, k) = k + 1;
+    } else {                                      // GEMM(i,j,k), k <= j - 2
+      if (!(d.k + 2 <= d.j && d.j <= d.i)) return 5;
+      if (st(d.i, d.k) < d.k + 1 || st(d.j, d.k) < d.k + 1 || st(d.i, d.j) != d.k) return 6;
+      st(d.i, d.j) = d.k + 1;
     }
   }
   for (int i = 0; i < T; ++i)
     for (int j = 0; j <= i; ++j)
-      if (state[(size_t)i * T + j] != j + 1) return 7;
+      if (st(i, j) != j + 1) return 7;
   return 0;
 }
 
@@ -566,7 +646,7 @@ int64_t chol_task_offsets(int T, std::vector<int64_t>& offs) {
   for (int k = 0; k + 1 < T; ++k) {
     offs[k] = t;
     const int64_t m1 = T - k - 1, m2 = T - k - 2;
-    t += 2 * m1 + m2 * (m2 + 1) / 2;
+    t += m1 + m2 * (m2 + 1) / 2;
   }
   if (T >= 1) offs[T - 1] = t;
   return t;

@@ -39,7 +39,7 @@ constexpr int CG_JB = 32;
 __global__ __launch_bounds__(256) void column_grams_kernel(const double* __restrict__ E, int64_t ldE,
                                                            int64_t n_h, int64_t n_w, int K, int64_t P,
                                                            const int* __restrict__ pairs, int jb,
-                                                           double* __restrict__ S) {
+                                                           double* __restrict__ S, int64_t ldS) {
   extern __shared__ double Es[];  // jb x K, Es[k * jb + jj]
   const int64_t j0 = (int64_t)blockIdx.x * jb;
   const int64_t p = (int64_t)blockIdx.y * 256 + threadIdx.x;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void column_grams_kernel(const double* __restr
   if (p < P) {
 #pragma unroll
     for (int jj = 0; jj < CG_JB; ++jj)
-      if (jj < jb && j0 + jj < n_h) S[(j0 + jj) * P + p] = acc[jj];
+      if (jj < jb && j0 + jj < n_h) S[(j0 + jj) * ldS + p] = acc[jj];
   }
 }
 
@@ -75,107 +75,188 @@ hipError_t launch_column_grams(const Inst& in, hipStream_t s) {
   dim3 grid((unsigned)ceil_div(in.n_h, jb), (unsigned)ceil_div(in.P, 256));
   size_t shm = (size_t)jb * in.K * sizeof(double);
   hipLaunchKernelGGL(column_grams_kernel, grid, dim3(256), shm, s, in.E, in.ldE, in.n_h, in.n_w,
-                     (int)in.K, in.P, in.pairs, jb, in.S);
+                     (int)in.K, in.P, in.pairs, jb, in.S, in.ldS);
   return hipGetLastError();
 }
 
 // -------------------------------------------------------------- FP64 Gram
 // Tile: 128 pairs p x 128 mode pairs q (8 values of m x 16 values of m').
-struct GramF64Prob {
-  static constexpr int BM = 128, BN = 128, WM = 2, WN = 2, KC = 16;
-  static constexpr int LDA = BM, LDB = BN;
-  const double* S; const double* W; int64_t ldW;
+// Per chunk of 16 grid columns j the workgroup stages the S rows of its
+// 128 pairs and the 24 columns of W its mode pairs use; the T operand
+// W[j,m] W[j,m'] is formed when the MFMA fragment is read from LDS.
+// Four waves own 64 x 64 quadrants (4 x 4 fragments of 16 x 16).
+// When the tiles are too few to fill the device the j range is split in two
+// parts written to G and G2 and summed afterwards (a fixed order, so results
+// are reproducible).  Workgroups are mapped so that each XCD (the hardware
+// places workgroup b on XCD b mod 8) works on a contiguous range of tiles,
+// which then share S rows in its L2.
+constexpr int GB = 128, GKC = 16, GWC = 24;
+
+struct GramArgs {
+  const double* S; int64_t ldS;
+  const double* W; int64_t ldW;
   int64_t n_h, M, P;
   const int* pairs; const int* qtiles;
-  int npt, nq;
-  double* G; int64_t ldG;
-
-  struct Ctx { bool valid; int64_t p0; int m0, mp0; int nchunks; };
-  struct ARegs { double v[8]; };
-  struct BRegs { double v[8]; };
-
-  __device__ Ctx ctx(int tile) const {
-    Ctx c;
-    int pt = tile / nq, qi = tile % nq;
-    c.valid = pt < npt;
-    c.p0 = (int64_t)pt * BM;
-    c.m0 = qtiles[2 * qi];
-    c.mp0 = qtiles[2 * qi + 1];
-    c.nchunks = (int)ceil_div_dev(n_h, KC);
-    return c;
-  }
-  __device__ static int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-  __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
-    const int t = threadIdx.x, pl = t & 127;
-    const int64_t p = c.p0 + pl;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t j = (int64_t)chunk * KC + (t >> 7) + 2 * i;
-      r.v[i] = (j < n_h && p < P) ? S[j * P + p] : 0.0;
-    }
-  }
-  __device__ void storeA(const ARegs& r, double* As) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) As[((t >> 7) + 2 * i) * LDA + (t & 127)] = r.v[i];
-  }
-  __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
-    const int t = threadIdx.x, ql = t & 127;
-    const int64_t m = c.m0 + (ql >> 4), mp = c.mp0 + (ql & 15);
-    const bool ok = m < M && mp < M;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t j = (int64_t)chunk * KC + (t >> 7) + 2 * i;
-      r.v[i] = (ok && j < n_h) ? W[j + m * ldW] * W[j + mp * ldW] : 0.0;
-    }
-  }
-  __device__ void storeB(const BRegs& r, double* Bs) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) Bs[((t >> 7) + 2 * i) * LDB + (t & 127)] = r.v[i];
-  }
-  __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
-    acc.for_each([&](int row, int col, double v) {
-      const int64_t p = c.p0 + row;
-      if (p >= P) return;
-      const int64_t m = c.m0 + (col >> 4), mp = c.mp0 + (col & 15);
-      if (mp >= M || m > mp) return;
-      const int64_t k = pairs[2 * p], kp = pairs[2 * p + 1];
-      G[(kp * M + mp) + (k * M + m) * ldG] = v;
-      if (k != kp && m != mp) G[(kp * M + m) + (k * M + mp) * ldG] = v;
-    });
-  }
+  int npt, nq, ntiles, split;
+  int64_t jlen;
+  double* G; double* G2; int64_t ldG;
 };
 
+__global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
+  __shared__ double As[2][GKC * GB];
+  __shared__ double Ws[2][GKC * GWC];
+  const int64_t units = (int64_t)a.ntiles * a.split;
+  const int64_t per = (units + 7) / 8;
+  const int64_t b = blockIdx.x;
+  const int64_t u = (b % 8) * per + b / 8;
+  if (u >= units) return;
+  const int part = (int)(u / a.ntiles), tile = (int)(u % a.ntiles);
+  const int pt = tile / a.nq, qi = tile % a.nq;
+  const int64_t p0 = (int64_t)pt * GB;
+  const int m0 = a.qtiles[2 * qi], mp0 = a.qtiles[2 * qi + 1];
+  const int64_t jbeg = (int64_t)part * a.jlen;
+  const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
+  const int nchunks = (int)((jend - jbeg + GKC - 1) / GKC);
+  const int t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int wm = w >> 1, wn = w & 1, r = lane & 15, kq = lane >> 4;
+
+  // this thread's staging slots
+  const int sp = (t & 63) * 2, srow = t >> 6;           // S: rows srow + 4i, pairs sp, sp+1
+  int wcol[2], wrow[2];
+  int64_t wm_idx[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = t + 256 * h;
+    wcol[h] = idx / GKC;
+    wrow[h] = idx % GKC;
+    wm_idx[h] = (wcol[h] < 8) ? (int64_t)m0 + wcol[h] : (int64_t)mp0 + wcol[h] - 8;
+  }
+  double sv[8], wv[2];
+  auto load = [&](int chunk) {
+    const int64_t j0 = jbeg + (int64_t)chunk * GKC;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t j = j0 + srow + 4 * i;
+      if (j < jend) {
+        const double2 v = *reinterpret_cast<const double2*>(a.S + j * a.ldS + p0 + sp);
+        sv[2 * i] = v.x; sv[2 * i + 1] = v.y;
+      } else {
+        sv[2 * i] = 0.0; sv[2 * i + 1] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t j = j0 + wrow[h];
+      wv[h] = (wcol[h] < GWC && j < jend && wm_idx[h] < a.M) ? a.W[j + wm_idx[h] * a.ldW] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      As[buf][(srow + 4 * i) * GB + sp] = sv[2 * i];
+      As[buf][(srow + 4 * i) * GB + sp + 1] = sv[2 * i + 1];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (wcol[h] < GWC) Ws[buf][wrow[h] * GWC + wcol[h]] = wv[h];
+  };
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  if (nchunks > 0) {
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const bool more = c + 1 < nchunks;
+      if (more) load(c + 1);
+      const double* Ab = As[c & 1];
+      const double* Wb = Ws[c & 1];
+#pragma unroll
+      for (int kk = 0; kk < GKC; kk += 4) {
+        const int krow = kk + kq;
+        double av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = Ab[krow * GB + wm * 64 + i * 16 + r];
+        const double wmp = Wb[krow * GWC + 8 + r];            // W[j, m0' + r]
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = Wb[krow * GWC + wn * 4 + j] * wmp;   // W[j, m] W[j, m']
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
+      }
+      if (more) store((c + 1) & 1);
+      __syncthreads();
+    }
+  }
+  double* Gout = part == 0 ? a.G : a.G2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * 64 + i * 16 + kq + 4 * v;   // pair
+        const int col = wn * 64 + j * 16 + r;            // mode pair
+        const int64_t p = p0 + row;
+        if (p >= a.P) continue;
+        const int64_t m = m0 + (col >> 4), mp = mp0 + (col & 15);
+        if (mp >= a.M || m > mp) continue;
+        const int64_t k = a.pairs[2 * p], kp = a.pairs[2 * p + 1];
+        const double val = acc[i][j][v];
+        Gout[(kp * a.M + mp) + (k * a.M + m) * a.ldG] = val;
+        if (k != kp && m != mp) Gout[(kp * a.M + m) + (k * a.M + mp) * a.ldG] = val;
+      }
+}
+
+int gram_split_for(const Inst& in) {
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus <= 0) cus = 256;
+  const int64_t tiles = ceil_div(in.P, GB) * (int64_t)in.nq;
+  return (tiles < 2 * (int64_t)cus && in.n_h >= 4 * GKC) ? 2 : 1;
+}
+
 hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
-  GramF64Prob pr;
-  pr.S = in.S; pr.W = in.W; pr.ldW = in.ldW;
-  pr.n_h = in.n_h; pr.M = in.M; pr.P = in.P;
-  pr.pairs = in.pairs; pr.qtiles = in.qtiles;
-  pr.npt = (int)ceil_div(in.P, GramF64Prob::BM); pr.nq = in.nq;
-  pr.G = in.G; pr.ldG = in.KMp;
-  const int64_t tiles = (int64_t)pr.npt * pr.nq;
-  hipLaunchKernelGGL(gemm_f64_kernel<GramF64Prob>, dim3((unsigned)tiles), dim3(256), 0, s, pr);
+  GramArgs a;
+  a.S = in.S; a.ldS = in.ldS; a.W = in.W; a.ldW = in.ldW;
+  a.n_h = in.n_h; a.M = in.M; a.P = in.P;
+  a.pairs = in.pairs; a.qtiles = in.qtiles;
+  a.npt = (int)ceil_div(in.P, GB); a.nq = in.nq; a.ntiles = a.npt * a.nq;
+  a.split = (in.G2 != nullptr) ? 2 : 1;
+  a.jlen = round_up(ceil_div(in.n_h, a.split), GKC);
+  a.G = in.G; a.G2 = in.G2; a.ldG = in.KMp;
+  const int64_t units = (int64_t)a.ntiles * a.split;
+  const int64_t grid = 8 * ((units + 7) / 8);
+  hipLaunchKernelGGL(gram_f64_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 // ------------------------------------ padding of the Gram and its diagonal
 // Rows/cols KM..KMp-1 become the identity so the blocked factorization can
 // run on whole NB blocks; diag0 keeps the pre-factorization diagonal.
-__global__ void gram_pad_diag_kernel(double* G, int64_t ld, int64_t KM, int64_t KMp, double* diag0) {
+__global__ void gram_pad_diag_kernel(double* G, const double* G2, int64_t ld, int64_t KM, int64_t KMp,
+                                     double* diag0) {
   int64_t c = blockIdx.x;  // column
   if (c >= KM) {
     for (int64_t r = threadIdx.x; r < KMp; r += blockDim.x) G[r + c * ld] = (r == c) ? 1.0 : 0.0;
   } else {
+    if (G2)   // second half of a split Gram: lower triangle of this column
+      for (int64_t r = c + threadIdx.x; r < KM; r += blockDim.x) G[r + c * ld] += G2[r + c * ld];
     for (int64_t r = KM + threadIdx.x; r < KMp; r += blockDim.x) G[r + c * ld] = 0.0;
   }
+  __syncthreads();
   if (threadIdx.x == 0) diag0[c] = (c >= KM) ? 1.0 : G[c + c * ld];
 }
 
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s) {
-  hipLaunchKernelGGL(gram_pad_diag_kernel, dim3((unsigned)in.KMp), dim3(64), 0, s, in.G, in.KMp,
-                     in.KM, in.KMp, in.diag0);
+  hipLaunchKernelGGL(gram_pad_diag_kernel, dim3((unsigned)in.KMp), dim3(256), 0, s, in.G,
+                     (const double*)in.G2, in.KMp, in.KM, in.KMp, in.diag0);
   return hipGetLastError();
 }
 

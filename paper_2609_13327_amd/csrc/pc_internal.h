@@ -23,7 +23,9 @@ struct Inst {
   double* G = nullptr;       // KMp x KMp, ld = KMp; Gram then its Cholesky factor (lower)
   double* diag0 = nullptr;   // KMp: diagonal of the Gram before factoring
   double* Linv = nullptr;    // (KMp/NB) blocks of NB x NB: inverses of the diagonal blocks of L
-  double* S = nullptr;       // n_h x P per-column Grams (row j holds the P packed pairs)
+  double* S = nullptr;       // n_h x ldS per-column Grams (row j holds the P packed pairs, zero padded)
+  int64_t ldS = 0;           // P rounded up to the 128-pair Gram tile
+  double* G2 = nullptr;      // second half of a split FP64 Gram (only when the tiles are few)
   int* pairs = nullptr;      // P x 2: (k, k') with k <= k'
   int* qtiles = nullptr;     // nq x 2: (m0, m0') of the mode-pair tiles
   int nq = 0;
@@ -68,6 +70,7 @@ hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int6
                                int64_t n, hipStream_t s);
 hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
 int64_t chol_task_offsets(int T, std::vector<int64_t>& offs);
+int gram_split_for(const Inst& in);
 int check_chol_task_order(int T);
 
 }  // namespace pc

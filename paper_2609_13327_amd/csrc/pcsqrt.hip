@@ -48,7 +48,7 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 void free_inst(Inst& in) {
-  hipFree(in.G); hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
+  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.flags); hipFree(in.norms); hipFree(in.dag); hipFree(in.chol_offs);
   in.dag = nullptr; in.chol_offs = nullptr;
@@ -85,7 +85,8 @@ pc_status alloc_inst(Inst& in) {
   chk(dalloc(&in.G, KMp * KMp));
   chk(dalloc(&in.diag0, KMp));
   chk(dalloc(&in.Linv, nblk * pc::NB * pc::NB));
-  chk(dalloc(&in.S, in.n_h * in.P));
+  in.ldS = pc::round_up(in.P, 128);
+  chk(dalloc(&in.S, in.n_h * in.ldS));
   chk(dalloc(&in.pairs, 2 * in.P));
   std::vector<int> qt = make_qtiles(in.M);
   in.nq = (int)(qt.size() / 2);
@@ -110,6 +111,11 @@ pc_status alloc_inst(Inst& in) {
     return PC_ERR_DEVICE;
   // padding rows of the right-hand-side buffers stay zero forever
   if (hipMemset(in.B, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
+  // S padding columns (pairs P..ldS-1) are read by the Gram tiles and must be zero
+  if (hipMemset(in.S, 0, sizeof(double) * in.n_h * in.ldS) != hipSuccess) return PC_ERR_DEVICE;
+  if (pc::gram_split_for(in) == 2) {
+    if (dalloc(&in.G2, KMp * KMp) != hipSuccess) return PC_ERR_OOM;
+  }
   if (hipMemset(in.Y, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   if (hipMemset(in.D, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   return PC_OK;
