@@ -15,6 +15,8 @@
 #include "gemm_core.h"
 #include "pc_internal.h"
 
+#include <algorithm>
+
 namespace pc {
 
 // ------------------------------------------------------------------ Z^T X
@@ -112,9 +114,147 @@ static hipError_t run_ztx(const Inst& in, const double* X, int64_t ldX, int64_t 
   return hipGetLastError();
 }
 
+// Single level (n_w = 1): b_k = (X^T Z_k)^T with Z_k[j, m] = E[j, k] W[j, m];
+// tile = 64 right-hand sides x 64 modes of one member k.  The member's
+// column of E scales the staged W rows when the MFMA fragment is read.  With
+// few tiles the j range is split in two halves accumulated with two atomic
+// adds onto a zeroed output (two addends onto zero: the same result in either
+// order).
+constexpr int ZT = 64, ZKC = 16, ZLD = ZT + 1;
+
+struct Ztx1Args {
+  const double* E; int64_t ldE;
+  const double* W; int64_t ldW;
+  const double* X; int64_t ldX;
+  double* B; int64_t ldB;
+  int64_t n_h, K, M, R;
+  int ntr, ntm, split;
+  int64_t jlen;
+};
+
+__global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
+  __shared__ double Xs[2][ZKC * ZLD];
+  __shared__ double Ws[2][ZKC * ZLD];
+  __shared__ double Es[2][ZKC];
+  const int64_t ntiles = (int64_t)a.ntr * a.ntm * a.K;
+  const int64_t units = ntiles * a.split;
+  const int64_t per = (units + 7) / 8;
+  const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;     // contiguous ranges per XCD
+  if (u >= units) return;
+  const int part = (int)(u / ntiles);
+  int64_t tile = u % ntiles;
+  const int tr = (int)(tile % a.ntr); tile /= a.ntr;
+  const int tm = (int)(tile % a.ntm);
+  const int64_t k = tile / a.ntm;
+  const int64_t r0 = (int64_t)tr * ZT, m0 = (int64_t)tm * ZT;
+  const int64_t jbeg = (int64_t)part * a.jlen;
+  const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
+  const int nchunks = (int)((jend - jbeg + ZKC - 1) / ZKC);
+  const int t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
+  const double* Ek = a.E + k * a.ldE;
+
+  double xv[4], wv[4], ev = 0.0;
+  auto load = [&](int chunk) {
+    const int64_t j0 = jbeg + (int64_t)chunk * ZKC;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, jj = e % ZKC, col = e / ZKC;
+      const int64_t j = j0 + jj;
+      xv[q] = (j < jend && r0 + col < a.R) ? a.X[j + (r0 + col) * a.ldX] : 0.0;
+      wv[q] = (j < jend && m0 + col < a.M) ? a.W[j + (m0 + col) * a.ldW] : 0.0;
+    }
+    if (t < ZKC) ev = (j0 + t < jend) ? Ek[j0 + t] : 0.0;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, jj = e % ZKC, col = e / ZKC;
+      Xs[buf][jj * ZLD + col] = xv[q];
+      Ws[buf][jj * ZLD + col] = wv[q];
+    }
+    if (t < ZKC) Es[buf][t] = ev;
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  if (nchunks > 0) {
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const bool more = c + 1 < nchunks;
+      if (more) load(c + 1);
+      const double* Xb = Xs[c & 1];
+      const double* Wb = Ws[c & 1];
+      const double* Eb = Es[c & 1];
+#pragma unroll
+      for (int kk = 0; kk < ZKC; kk += 4) {
+        const int krow = kk + kq;
+        const double e = Eb[krow];
+        double av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) av[i] = Xb[krow * ZLD + wm * 32 + i * 16 + rr];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = Wb[krow * ZLD + wn * 32 + j * 16 + rr] * e;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
+      }
+      if (more) store((c + 1) & 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + wm * 32 + i * 16 + kq + 4 * v;
+        const int64_t m = m0 + wn * 32 + j * 16 + rr;
+        if (r >= a.R || m >= a.M) continue;
+        double* dst = &a.B[(k * a.M + m) + r * a.ldB];
+        if (a.split == 1) *dst = acc[i][j][v];
+        else atomicAdd(dst, acc[i][j][v]);
+      }
+}
+
+__global__ void zero_block_kernel(double* B, int64_t ld, int64_t rows, int64_t cols) {
+  const int64_t c = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
+    B[i + c * ld] = 0.0;
+}
+
+static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
+                           hipStream_t s) {
+  Ztx1Args a;
+  a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
+  a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
+  a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT);
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus <= 0) cus = 256;
+  const int64_t ntiles = (int64_t)a.ntr * a.ntm * in.K;
+  a.split = (ntiles < 2 * (int64_t)cus && in.n_h >= 4 * ZKC) ? 2 : 1;
+  a.jlen = round_up(ceil_div(in.n_h, a.split), ZKC);
+  if (a.split == 2) {
+    const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(in.KM, 256), 64);
+    hipLaunchKernelGGL(zero_block_kernel, dim3(gx, (unsigned)R), dim3(256), 0, s, B, ldB, in.KM, R);
+  }
+  const int64_t units = ntiles * a.split;
+  hipLaunchKernelGGL(ztx1_kernel, dim3((unsigned)(8 * ((units + 7) / 8))), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
                       hipStream_t s) {
   if (R <= 0) return hipSuccess;
+  if (in.n_w == 1) return run_ztx1(in, X, ldX, R, B, ldB, s);
   if (in.M <= 32) return run_ztx<ZtxProb<128, 32, 4, 1>>(in, X, ldX, R, B, ldB, s);
   return run_ztx<ZtxProb<64, 64, 2, 2>>(in, X, ldX, R, B, ldB, s);
 }
