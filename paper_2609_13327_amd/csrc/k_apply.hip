@@ -351,9 +351,121 @@ static hipError_t run_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R
   return hipGetLastError();
 }
 
+// Single level (n_w = 1): out[j, r] = (Xs[j, r] -) sum_{k,m} E[j,k] W[j,m] Y[k*M+m, r].
+// Product rows = right-hand sides, columns = grid columns j (coalesced output);
+// the contraction runs over (k, m) in chunks of 16 modes of one member when
+// M is a multiple of 16 (else element by element); the Z operand is formed
+// at fragment time from staged W rows and the member's E values.
+constexpr int YT = 64, YKC = 16, YLD = YT + 1;
+
+struct Zy1Args {
+  const double* E; int64_t ldE;
+  const double* W; int64_t ldW;
+  const double* Y; int64_t ldY;
+  const double* Xs; int64_t ldXs;
+  double* Out; int64_t ldO;
+  int64_t n_h, K, M, KM, R;
+  int ntr, ntj;
+};
+
+__global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
+  __shared__ double Ys[2][YKC * YLD];    // Ys[q][r]
+  __shared__ double Zs[2][YKC * YLD];    // Zs[q][j] = E[j,k(q)] W[j,m(q)]
+  const int64_t ntiles = (int64_t)a.ntr * a.ntj;
+  const int64_t per = (ntiles + 7) / 8;
+  const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (u >= ntiles) return;
+  const int tr = (int)(u % a.ntr), tj = (int)(u / a.ntr);
+  const int64_t r0 = (int64_t)tr * YT, j0 = (int64_t)tj * YT;
+  const int nchunks = (int)((a.KM + YKC - 1) / YKC);
+  const int t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
+  double yv[4], zv[4];
+  auto load = [&](int chunk) {
+    const int64_t q0 = (int64_t)chunk * YKC;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = t + 256 * h;
+      {   // Y: q fastest (contiguous in a column of Y)
+        const int qq = e % YKC, col = e / YKC;
+        const int64_t q = q0 + qq, r = r0 + col;
+        yv[h] = (q < a.KM && r < a.R) ? a.Y[q + r * a.ldY] : 0.0;
+      }
+      {   // Z: j fastest (contiguous in a column of W and of E)
+        const int jj = e % YT, qq = e / YT;
+        const int64_t q = q0 + qq, j = j0 + jj;
+        double z = 0.0;
+        if (q < a.KM && j < a.n_h) {
+          const int64_t k = q / a.M, m = q - k * a.M;
+          z = a.E[j + k * a.ldE] * a.W[j + m * a.ldW];
+        }
+        zv[h] = z;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = t + 256 * h;
+      Ys[buf][(e % YKC) * YLD + e / YKC] = yv[h];
+      Zs[buf][(e / YT) * YLD + e % YT] = zv[h];
+    }
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const bool more = c + 1 < nchunks;
+    if (more) load(c + 1);
+    const double* Yb = Ys[c & 1];
+    const double* Zb = Zs[c & 1];
+#pragma unroll
+    for (int kk = 0; kk < YKC; kk += 4) {
+      const int krow = kk + kq;
+      double av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = Yb[krow * YLD + wm * 32 + i * 16 + rr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Zb[krow * YLD + wn * 32 + j * 16 + rr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
+    }
+    if (more) store((c + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + wm * 32 + i * 16 + kq + 4 * v;
+        const int64_t jj = j0 + wn * 32 + j * 16 + rr;
+        if (r >= a.R || jj >= a.n_h) continue;
+        const double val = acc[i][j][v];
+        a.Out[jj + r * a.ldO] = a.Xs ? a.Xs[jj + r * a.ldXs] - val : val;
+      }
+}
+
 hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs, int64_t ldXs,
                      double* out, int64_t ldOut, hipStream_t s) {
   if (R <= 0) return hipSuccess;
+  if (in.n_w == 1) {
+    Zy1Args a;
+    a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.Y = Y; a.ldY = ldY; a.Xs = Xs; a.ldXs = ldXs;
+    a.Out = out; a.ldO = ldOut; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.KM = in.KM; a.R = R;
+    a.ntr = (int)ceil_div(R, YT); a.ntj = (int)ceil_div(in.n_h, YT);
+    const int64_t ntiles = (int64_t)a.ntr * a.ntj;
+    hipLaunchKernelGGL(zy1_kernel, dim3((unsigned)(8 * ((ntiles + 7) / 8))), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s);
   if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s);
   return run_zy<ZyProb<64, 64, 2, 2>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s);

@@ -26,6 +26,8 @@ struct Inst {
   double* S = nullptr;       // n_h x ldS per-column Grams (row j holds the P packed pairs, zero padded)
   int64_t ldS = 0;           // P rounded up to the 128-pair Gram tile
   double* G2 = nullptr;      // second half of a split FP64 Gram (only when the tiles are few)
+  void* Zt = nullptr;        // reduced precision: the rounded Z, column-major, ldz rows (bf16 or fp32)
+  int64_t ldz = 0;
   int* pairs = nullptr;      // P x 2: (k, k') with k <= k'
   int* qtiles = nullptr;     // nq x 2: (m0, m0') of the mode-pair tiles
   int nq = 0;

@@ -48,7 +48,7 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 void free_inst(Inst& in) {
-  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
+  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.flags); hipFree(in.norms); hipFree(in.dag); hipFree(in.chol_offs);
   in.dag = nullptr; in.chol_offs = nullptr;
@@ -78,7 +78,7 @@ std::vector<int> make_qtiles(int64_t M) {
   return q;
 }
 
-pc_status alloc_inst(Inst& in) {
+pc_status alloc_inst(Inst& in, int precision) {
   const int64_t KMp = in.KMp, nblk = KMp / pc::NB, R = std::max<int64_t>(in.max_rhs, 1);
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
@@ -113,8 +113,13 @@ pc_status alloc_inst(Inst& in) {
   if (hipMemset(in.B, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   // S padding columns (pairs P..ldS-1) are read by the Gram tiles and must be zero
   if (hipMemset(in.S, 0, sizeof(double) * in.n_h * in.ldS) != hipSuccess) return PC_ERR_DEVICE;
-  if (pc::gram_split_for(in) == 2) {
+  if (precision == PC_PREC_FP64 && pc::gram_split_for(in) == 2) {
     if (dalloc(&in.G2, KMp * KMp) != hipSuccess) return PC_ERR_OOM;
+  }
+  if (precision != PC_PREC_FP64) {
+    in.ldz = pc::round_up(in.n, 64);
+    const size_t bytes = (size_t)in.ldz * (size_t)in.KM * (precision == PC_PREC_BF16_REFINE ? 2 : 4);
+    if (hipMalloc(&in.Zt, bytes) != hipSuccess) return PC_ERR_OOM;
   }
   if (hipMemset(in.Y, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   if (hipMemset(in.D, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
@@ -215,7 +220,7 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
     in.P = a.K * (a.K + 1) / 2;
     in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
     p->inst.push_back(in);
-    st = alloc_inst(p->inst.back());
+    st = alloc_inst(p->inst.back(), o.precision);
     max_r = std::max<int64_t>(max_r, a.max_rhs);
   }
   if (st == PC_OK && hipHostMalloc((void**)&p->h_norms, sizeof(double) * 2 * max_r) != hipSuccess)
