@@ -32,6 +32,7 @@ struct ZtxProb {
   double* Bout; int64_t ldB;
   int64_t n_h, n_w, K, M, R, KR;
   int ntr, ntc;   // tiles along rows (k,r) and cols (m)
+  const int* skip;
 
   struct Ctx { bool valid; int64_t c0, m0; int nchunks; };
   struct ARegs { double v[NA]; };
@@ -40,7 +41,7 @@ struct ZtxProb {
   __device__ Ctx ctx(int tile) const {
     Ctx c;
     const int tr = tile % ntr, tc = tile / ntr;
-    c.valid = tc < ntc;
+    c.valid = tc < ntc && !(skip && *skip);
     c.c0 = (int64_t)tr * BM;
     c.m0 = (int64_t)tc * BN;
     c.nchunks = (int)((n_h + KC - 1) / KC);
@@ -102,8 +103,9 @@ struct ZtxProb {
 
 template <class P>
 static hipError_t run_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
-                          hipStream_t s) {
+                          hipStream_t s, const int* skip) {
   P pr;
+  pr.skip = skip;
   pr.E = in.E; pr.ldE = in.ldE; pr.W = in.W; pr.ldW = in.ldW;
   pr.X = X; pr.ldX = ldX; pr.Bout = B; pr.ldB = ldB;
   pr.n_h = in.n_h; pr.n_w = in.n_w; pr.K = in.K; pr.M = in.M; pr.R = R; pr.KR = in.K * R;
@@ -130,9 +132,11 @@ struct Ztx1Args {
   int64_t n_h, K, M, R;
   int ntr, ntm, split;
   int64_t jlen;
+  const int* skip;
 };
 
 __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
+  if (a.skip && *a.skip) return;
   __shared__ double Xs[2][ZKC * ZLD];
   __shared__ double Ws[2][ZKC * ZLD];
   __shared__ double Es[2][ZKC];
@@ -223,28 +227,30 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
       }
 }
 
-__global__ void zero_block_kernel(double* B, int64_t ld, int64_t rows, int64_t cols) {
+__global__ void zero_block_kernel(double* B, int64_t ld, int64_t rows, int64_t cols, const int* skip) {
+  if (skip && *skip) return;
   const int64_t c = blockIdx.y;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
     B[i + c * ld] = 0.0;
 }
 
 static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
-                           hipStream_t s) {
+                           hipStream_t s, const int* skip) {
   Ztx1Args a;
+  a.skip = skip;
   a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
   a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
   a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT);
   int dev = 0, cus = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
   const int64_t ntiles = (int64_t)a.ntr * a.ntm * in.K;
   a.split = (ntiles < 2 * (int64_t)cus && in.n_h >= 4 * ZKC) ? 2 : 1;
   a.jlen = round_up(ceil_div(in.n_h, a.split), ZKC);
   if (a.split == 2) {
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(in.KM, 256), 64);
-    hipLaunchKernelGGL(zero_block_kernel, dim3(gx, (unsigned)R), dim3(256), 0, s, B, ldB, in.KM, R);
+    hipLaunchKernelGGL(zero_block_kernel, dim3(gx, (unsigned)R), dim3(256), 0, s, B, ldB, in.KM, R, skip);
   }
   const int64_t units = ntiles * a.split;
   hipLaunchKernelGGL(ztx1_kernel, dim3((unsigned)(8 * ((units + 7) / 8))), dim3(256), 0, s, a);
@@ -252,11 +258,11 @@ static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t
 }
 
 hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
-                      hipStream_t s) {
+                      hipStream_t s, const int* skip) {
   if (R <= 0) return hipSuccess;
-  if (in.n_w == 1) return run_ztx1(in, X, ldX, R, B, ldB, s);
-  if (in.M <= 32) return run_ztx<ZtxProb<128, 32, 4, 1>>(in, X, ldX, R, B, ldB, s);
-  return run_ztx<ZtxProb<64, 64, 2, 2>>(in, X, ldX, R, B, ldB, s);
+  if (in.n_w == 1) return run_ztx1(in, X, ldX, R, B, ldB, s, skip);
+  if (in.M <= 32) return run_ztx<ZtxProb<128, 32, 4, 1>>(in, X, ldX, R, B, ldB, s, skip);
+  return run_ztx<ZtxProb<64, 64, 2, 2>>(in, X, ldX, R, B, ldB, s, skip);
 }
 
 // ------------------------------------------------------------------- Z Y
@@ -273,6 +279,7 @@ struct ZyProb {
   double* Out; int64_t ldO;
   int64_t n_h, n, K, M, KM, R;
   int ntr, ntc;   // tiles along rows (r) and cols (i)
+  const int* skip;
 
   struct Ctx { bool valid; int64_t r0, i0; int nchunks; };
   struct ARegs { double v[NA]; };
@@ -281,7 +288,7 @@ struct ZyProb {
   __device__ Ctx ctx(int tile) const {
     Ctx c;
     const int tr = tile % ntr, tc = tile / ntr;
-    c.valid = tc < ntc;
+    c.valid = tc < ntc && !(skip && *skip);
     c.r0 = (int64_t)tr * BM;
     c.i0 = (int64_t)tc * BN;
     c.nchunks = (int)((KM + KC - 1) / KC);
@@ -339,8 +346,9 @@ struct ZyProb {
 
 template <class P>
 static hipError_t run_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs,
-                         int64_t ldXs, double* out, int64_t ldOut, hipStream_t s) {
+                         int64_t ldXs, double* out, int64_t ldOut, hipStream_t s, const int* skip) {
   P pr;
+  pr.skip = skip;
   pr.E = in.E; pr.ldE = in.ldE; pr.W = in.W; pr.ldW = in.ldW;
   pr.Y = Y; pr.ldY = ldY; pr.Xs = Xs; pr.ldXs = ldXs; pr.Out = out; pr.ldO = ldOut;
   pr.n_h = in.n_h; pr.n = in.n; pr.K = in.K; pr.M = in.M; pr.KM = in.KM; pr.R = R;
@@ -366,9 +374,11 @@ struct Zy1Args {
   double* Out; int64_t ldO;
   int64_t n_h, K, M, KM, R;
   int ntr, ntj;
+  const int* skip;
 };
 
 __global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
+  if (a.skip && *a.skip) return;
   __shared__ double Ys[2][YKC * YLD];    // Ys[q][r]
   __shared__ double Zs[2][YKC * YLD];    // Zs[q][j] = E[j,k(q)] W[j,m(q)]
   const int64_t ntiles = (int64_t)a.ntr * a.ntj;
@@ -455,10 +465,11 @@ __global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
 }
 
 hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs, int64_t ldXs,
-                     double* out, int64_t ldOut, hipStream_t s) {
+                     double* out, int64_t ldOut, hipStream_t s, const int* skip) {
   if (R <= 0) return hipSuccess;
   if (in.n_w == 1) {
     Zy1Args a;
+    a.skip = skip;
     a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.Y = Y; a.ldY = ldY; a.Xs = Xs; a.ldXs = ldXs;
     a.Out = out; a.ldO = ldOut; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.KM = in.KM; a.R = R;
     a.ntr = (int)ceil_div(R, YT); a.ntj = (int)ceil_div(in.n_h, YT);
@@ -466,9 +477,9 @@ hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, co
     hipLaunchKernelGGL(zy1_kernel, dim3((unsigned)(8 * ((ntiles + 7) / 8))), dim3(256), 0, s, a);
     return hipGetLastError();
   }
-  if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s);
-  if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s);
-  return run_zy<ZyProb<64, 64, 2, 2>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s);
+  if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s, skip);
+  if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s, skip);
+  return run_zy<ZyProb<64, 64, 2, 2>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s, skip);
 }
 
 }  // namespace pc

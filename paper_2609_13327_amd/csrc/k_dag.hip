@@ -496,12 +496,14 @@ struct SolveArgs {
   int64_t R; int nrt;
   int* flags; int* head; const int* info; int* err;
   int backward;
+  const int* skip;
 };
 
 __global__ __launch_bounds__(256, 2) void solve_dag_kernel(SolveArgs a) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
   __shared__ int sh[4];
+  if (a.skip && *a.skip) return;
   const int64_t ntasks = (int64_t)a.T * a.nrt;
   for (;;) {
     if (threadIdx.x == 0) sh[0] = atomicAdd(a.head, 1);
@@ -633,8 +635,8 @@ int check_chol_task_order(int T) {
 template <typename K>
 static int persistent_grid(K kernel) {
   int dev = 0, cus = 0, per_cu = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   return (cus > 0 ? cus : 256) * per_cu;
@@ -668,7 +670,7 @@ hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
 
 // Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) holds the forward result.
 hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk, int64_t ldW,
-                             hipStream_t s) {
+                             hipStream_t s, const int* skip) {
   if (R <= 0) return hipSuccess;
   const int T = (int)(in.KMp / T64);
   const int nrt = (int)ceil_div(R, T64);
@@ -677,6 +679,7 @@ hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, 
   SolveArgs a;
   a.G = in.G; a.ld = in.KMp; a.T = T; a.Linv = in.Linv; a.R = R; a.nrt = nrt;
   a.flags = flags; a.head = head; a.info = in.info; a.err = in.dag + (int64_t)T * T + 1;
+  a.skip = skip;
   const int64_t nflags = (int64_t)T * in.nrt_max + 1;
   const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), (int64_t)T * nrt);
   for (int pass = 0; pass < 2; ++pass) {

@@ -215,8 +215,8 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
 
 int gram_split_for(const Inst& in) {
   int dev = 0, cus = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
   const int64_t tiles = ceil_div(in.P, GB) * (int64_t)in.nq;
   return (tiles < 2 * (int64_t)cus && in.n_h >= 4 * GKC) ? 2 : 1;

@@ -23,12 +23,28 @@ hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t
   return hipGetLastError();
 }
 
-// Y[:, r] += D[:, r] over the first KM rows; norms[2r] = max|D[:, r]|,
-// norms[2r+1] = max|Y_new[:, r]|.  One workgroup per right-hand side.
+__global__ void refine_init_kernel(RefineCtl* ctl, int budget) {
+  ctl->done = budget > 0 ? 0 : 1;
+  ctl->iters = 0;
+  ctl->stall = 0;
+  ctl->worst = 0ULL;
+  ctl->last = 0.0;
+  ctl->prev = 0.0;
+}
+
+hipError_t launch_refine_init(RefineCtl* ctl, int budget, hipStream_t s) {
+  hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(1), 0, s, ctl, budget);
+  return hipGetLastError();
+}
+
+// Y[:, r] += D[:, r] over the first KM rows, and max over r of
+// max|D[:, r]| / max|Y_new[:, r]| into ctl->worst (the bit patterns of
+// non-negative doubles order like the values).  One workgroup per rhs.
 __global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__ Y, int64_t ldY,
                                                             const double* __restrict__ D, int64_t ldD,
-                                                            int64_t KM, double* __restrict__ norms) {
+                                                            int64_t KM, RefineCtl* ctl) {
   __shared__ double red[2][4];
+  if (ctl->done) return;
   const int64_t r = blockIdx.x;
   double md = 0.0, my = 0.0;
   for (int64_t i = threadIdx.x; i < KM; i += 256) {
@@ -45,15 +61,40 @@ __global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__
   if (threadIdx.x == 0) {
     double a = red[0][0], b = red[1][0];
     for (int w = 1; w < 4; ++w) { a = fmax(a, red[0][w]); b = fmax(b, red[1][w]); }
-    norms[2 * r] = a;
-    norms[2 * r + 1] = b;
+    double rel = b > 0.0 ? a / b : (a > 0.0 ? INFINITY : 0.0);
+    if (!(rel >= 0.0)) rel = INFINITY;   // NaN
+    atomicMax(&ctl->worst, (unsigned long long)__double_as_longlong(rel));
   }
 }
 
 hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const double* Dl, int64_t ldD,
-                                int64_t R, double* norms, hipStream_t s) {
+                                int64_t R, RefineCtl* ctl, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(refine_update_kernel, dim3((unsigned)R), dim3(256), 0, s, Y, ldY, Dl, ldD, in.KM, norms);
+  hipLaunchKernelGGL(refine_update_kernel, dim3((unsigned)R), dim3(256), 0, s, Y, ldY, Dl, ldD, in.KM, ctl);
+  return hipGetLastError();
+}
+
+// Stop at the tolerance, or once the updates stop shrinking (two iterations in
+// a row with less than a halving): then the attainable accuracy of the
+// residual has been reached, accepted if the update is below `accept`.
+__global__ void refine_check_kernel(RefineCtl* ctl, double tol, double accept) {
+  if (ctl->done) return;
+  const double worst = __longlong_as_double((long long)ctl->worst);
+  ctl->worst = 0ULL;
+  ctl->iters += 1;
+  ctl->prev = ctl->last;
+  ctl->last = worst;
+  if (worst <= tol) {
+    ctl->done = 1;
+  } else if (ctl->iters >= 2 && worst > 0.5 * ctl->prev) {
+    if (++ctl->stall >= 2) ctl->done = (worst <= accept) ? 1 : 2;
+  } else {
+    ctl->stall = 0;
+  }
+}
+
+hipError_t launch_refine_check(RefineCtl* ctl, double tol, double accept, hipStream_t s) {
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(1), 0, s, ctl, tol, accept);
   return hipGetLastError();
 }
 

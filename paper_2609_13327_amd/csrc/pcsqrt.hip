@@ -24,8 +24,16 @@ struct pc_plan {
   pc_options opt;
   int device = 0;
   int* d_flag = nullptr;        // device scratch int (finiteness check)
-  double* h_norms = nullptr;    // pinned host copy of per-rhs norms
-  int64_t h_norms_cap = 0;
+  pc::RefineCtl* h_ctl = nullptr;   // pinned host copies of the refinement controls
+  // independent instances run on internal streams (fork/join with the caller's stream)
+  std::vector<hipStream_t> aux;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  // hipGraph of the apply sequence, and the arguments it was captured for
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gkey;
   // profiling: recorded (start, stop) event pairs per phase, and a pool
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[PC_NUM_PHASES];
@@ -50,10 +58,10 @@ hipError_t dalloc(T** p, int64_t count) {
 void free_inst(Inst& in) {
   hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
-  hipFree(in.info); hipFree(in.flags); hipFree(in.norms); hipFree(in.dag); hipFree(in.chol_offs);
-  in.dag = nullptr; in.chol_offs = nullptr;
-  in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = in.norms = nullptr;
-  in.pairs = in.qtiles = in.info = in.flags = nullptr;
+  hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
+  in.dag = nullptr; in.chol_offs = nullptr; in.ctl = nullptr;
+  in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = nullptr;
+  in.pairs = in.qtiles = in.info = nullptr;
 }
 
 void free_plan(pc_plan* p) {
@@ -63,8 +71,14 @@ void free_plan(pc_plan* p) {
   for (auto& v : p->rec)
     for (auto& e : v) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
   for (auto e : p->pool) hipEventDestroy(e);
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap) hipStreamDestroy(p->cap);
+  for (auto st : p->aux) hipStreamDestroy(st);
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  for (auto e : p->ev_join) hipEventDestroy(e);
   hipFree(p->d_flag);
-  if (p->h_norms) hipHostFree(p->h_norms);
+  if (p->h_ctl) hipHostFree(p->h_ctl);
   delete p;
 }
 
@@ -96,8 +110,7 @@ pc_status alloc_inst(Inst& in, int precision) {
   chk(dalloc(&in.D, KMp * R));
   chk(dalloc(&in.Rres, in.n * R));
   chk(dalloc(&in.info, 1));
-  chk(dalloc(&in.flags, R));
-  chk(dalloc(&in.norms, 2 * R));
+  chk(dalloc(&in.ctl, 1));
   const int64_t T = KMp / pc::NB;
   in.nrt_max = (int)pc::ceil_div(R, pc::NB);
   chk(dalloc(&in.dag, T * T + 2 + T * in.nrt_max + 1));
@@ -150,19 +163,98 @@ struct PhaseTimer {
   }
 };
 
-pc_status assemble(pc_plan* p, hipStream_t s) {
-  for (auto& in : p->inst) {
-    in.factored = false;
-    PC_TRY(pc::launch_fill_int(in.info, -1, 1, s));
-    if (p->opt.precision == PC_PREC_FP64) {
-      { PhaseTimer t(p, PC_PHASE_COLUMN_GRAMS, s); PC_TRY(pc::launch_column_grams(in, s)); }
-      { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_f64(in, s)); }
-    } else {
-      PhaseTimer t(p, PC_PHASE_GRAM, s);
-      PC_TRY(pc::launch_gram_lowprec(in, p->opt.precision, s));
-    }
-    { PhaseTimer t(p, PC_PHASE_PAD, s); PC_TRY(pc::launch_gram_pad_and_diag(in, s)); }
+hipStream_t stream_for(const pc_plan* p, size_t i, hipStream_t caller) {
+  return p->aux.empty() ? caller : p->aux[i % p->aux.size()];
+}
+
+// Make the internal streams wait for the caller's stream, and back.
+hipError_t fork(pc_plan* p, hipStream_t s) {
+  if (p->aux.empty()) return hipSuccess;
+  hipError_t e = hipEventRecord(p->ev_fork, s);
+  for (auto st : p->aux)
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_fork, 0);
+  return e;
+}
+
+hipError_t join(pc_plan* p, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (size_t j = 0; j < p->aux.size() && e == hipSuccess; ++j) {
+    e = hipEventRecord(p->ev_join[j], p->aux[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[j], 0);
   }
+  return e;
+}
+
+pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
+  in.factored = false;
+  PC_TRY(pc::launch_fill_int(in.info, -1, 1, s));
+  if (p->opt.precision == PC_PREC_FP64) {
+    { PhaseTimer t(p, PC_PHASE_COLUMN_GRAMS, s); PC_TRY(pc::launch_column_grams(in, s)); }
+    { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_f64(in, s)); }
+  } else {
+    PhaseTimer t(p, PC_PHASE_GRAM, s);
+    PC_TRY(pc::launch_gram_lowprec(in, p->opt.precision, s));
+  }
+  { PhaseTimer t(p, PC_PHASE_PAD, s); PC_TRY(pc::launch_gram_pad_and_diag(in, s)); }
+  return PC_OK;
+}
+
+// The apply sequence of every instance on the streams (no host wait when
+// check_every == 0; otherwise the host stops early once every instance's
+// refinement is done, checking every `check_every` iterations).
+pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                        double* const* Y, const int64_t* ldY, hipStream_t s, int check_every) {
+  const size_t cnt = p->inst.size();
+  const int budget = p->opt.max_refine;
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < cnt; ++i) {
+    Inst& in = p->inst[i];
+    if (R[i] == 0) continue;
+    hipStream_t si = stream_for(p, i, s);
+    { PhaseTimer t(p, PC_PHASE_ZTX, si); PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si)); }
+    { PhaseTimer t(p, PC_PHASE_SOLVE, si); PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, si)); }
+    PC_TRY(pc::launch_refine_init(in.ctl, budget, si));
+  }
+  // refinement on the least-squares residual: r = x - Z y, d = G^{-1} Z^T r, y += d;
+  // converged instances skip the remaining iterations on the GPU
+  std::unique_ptr<PhaseTimer> refine_timer;
+  if (budget > 0) refine_timer.reset(new PhaseTimer(p, PC_PHASE_REFINE, s));
+  for (int it = 1; it <= budget; ++it) {
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0) continue;
+      hipStream_t si = stream_for(p, i, s);
+      const int* skip = &in.ctl->done;
+      PC_TRY(pc::launch_zy(in, in.Y, in.KMp, R[i], X[i], ldX[i], in.Rres, in.n, si, skip));
+      PC_TRY(pc::launch_ztx(in, in.Rres, in.n, R[i], in.D, in.KMp, si, skip));
+      PC_TRY(pc::launch_chol_solve(in, in.D, in.KMp, R[i], in.B, in.KMp, si, skip));
+      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.ctl, si));
+      PC_TRY(pc::launch_refine_check(in.ctl, p->opt.tol, kStallAccept, si));
+    }
+    if (check_every > 0 && it % check_every == 0 && it < budget) {
+      bool all = true;
+      for (size_t i = 0; i < cnt; ++i) {
+        if (R[i] == 0) continue;
+        hipStream_t si = stream_for(p, i, s);
+        PC_TRY(hipMemcpyAsync(&p->h_ctl[i], p->inst[i].ctl, sizeof(pc::RefineCtl), hipMemcpyDeviceToHost, si));
+      }
+      for (size_t i = 0; i < cnt; ++i)
+        if (R[i] != 0) PC_TRY(hipStreamSynchronize(stream_for(p, i, s)));
+      for (size_t i = 0; i < cnt; ++i)
+        if (R[i] != 0 && p->h_ctl[i].done == 0) all = false;
+      if (all) break;
+    }
+  }
+  refine_timer.reset();
+  {
+    PhaseTimer copy_timer(p, PC_PHASE_COPYOUT, s);
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0) continue;
+      PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y[i], ldY[i], in.KM, in.KM, R[i], stream_for(p, i, s)));
+    }
+  }
+  PC_TRY(join(p, s));
   return PC_OK;
 }
 
@@ -223,9 +315,24 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
     st = alloc_inst(p->inst.back(), o.precision);
     max_r = std::max<int64_t>(max_r, a.max_rhs);
   }
-  if (st == PC_OK && hipHostMalloc((void**)&p->h_norms, sizeof(double) * 2 * max_r) != hipSuccess)
+  (void)max_r;
+  if (st == PC_OK && hipHostMalloc((void**)&p->h_ctl, sizeof(pc::RefineCtl) * (size_t)count) != hipSuccess)
     st = PC_ERR_OOM;
-  p->h_norms_cap = max_r;
+  if (st == PC_OK && count > 1) {
+    // default-priority streams for independent instances
+    const int ns = std::min<int>(count, 8);
+    for (int j = 0; j < ns && st == PC_OK; ++j) {
+      hipStream_t st_ = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) st = PC_ERR_DEVICE;
+      p->aux.push_back(st_);
+      p->ev_join.push_back(ev);
+    }
+    if (st == PC_OK && hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess) st = PC_ERR_DEVICE;
+  }
+  if (st == PC_OK && o.use_graph && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+    st = PC_ERR_DEVICE;
   if (st == PC_OK) {
     // finiteness of E and W, then the pair tables
     int bad = 0;
@@ -253,7 +360,14 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
 pc_status pc_gram_assemble(pc_plan* p, void* stream) {
   if (!p) return PC_ERR_INVALID_ARG;
   hipSetDevice(p->device);
-  return assemble(p, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    pc_status st = assemble_one(p, p->inst[i], stream_for(p, i, s));
+    if (st != PC_OK) return st;
+  }
+  PC_TRY(join(p, s));
+  return PC_OK;
 }
 
 pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
@@ -261,12 +375,16 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
   if (!p) return PC_ERR_INVALID_ARG;
   hipSetDevice(p->device);
   hipStream_t s = (hipStream_t)stream;
-  pc_status st = assemble(p, s);
-  if (st != PC_OK) return st;
-  for (auto& in : p->inst) {
-    PhaseTimer t(p, PC_PHASE_CHOLESKY, s);
-    PC_TRY(pc::launch_cholesky(in, s));
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    Inst& in = p->inst[i];
+    hipStream_t si = stream_for(p, i, s);
+    pc_status st = assemble_one(p, in, si);
+    if (st != PC_OK) return st;
+    PhaseTimer t(p, PC_PHASE_CHOLESKY, si);
+    PC_TRY(pc::launch_cholesky(in, si));
   }
+  PC_TRY(join(p, s));
   std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
   for (size_t i = 0; i < p->inst.size(); ++i) {
     const Inst& in = p->inst[i];
@@ -277,7 +395,7 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
   PC_TRY(hipStreamSynchronize(s));
   for (size_t i = 0; i < p->inst.size(); ++i)
     if (errs[i]) return PC_ERR_DEVICE;   // a bounded wait expired: the factor is not trustworthy
-  st = PC_OK;
+  pc_status st = PC_OK;
   for (size_t i = 0; i < p->inst.size(); ++i) {
     p->inst[i].factored = infos[i] < 0;
     if (infos[i] >= 0 && st == PC_OK) {
@@ -302,67 +420,48 @@ pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_
     if (R[i] > in.max_rhs) return PC_ERR_TOO_MANY_RHS;
     if (!X[i] || !Y[i] || ldX[i] < in.n || ldY[i] < in.KM) return PC_ERR_INVALID_ARG;
   }
-  // initial solve: Y = G^{-1} Z^T X
-  for (size_t i = 0; i < cnt; ++i) {
-    Inst& in = p->inst[i];
-    in.iters = 0;
-    in.last_rel = 0.0;
-    if (R[i] == 0) continue;
-    { PhaseTimer t(p, PC_PHASE_ZTX, s); PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, s)); }
-    { PhaseTimer t(p, PC_PHASE_SOLVE, s); PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, s)); }
-  }
-  // refinement on the least-squares residual: r = x - Z y, d = G^{-1} Z^T r, y += d
   const int budget = p->opt.max_refine;
-  std::vector<char> done(cnt, 0);   // 0 running, 1 converged, 2 stalled above kStallAccept
-  std::vector<int> stall(cnt, 0);
-  pc_status st = PC_OK;
-  std::unique_ptr<PhaseTimer> refine_timer;
-  if (budget > 0) refine_timer.reset(new PhaseTimer(p, PC_PHASE_REFINE, s));
-  for (int it = 1; it <= budget; ++it) {
-    bool any = false;
+  if (p->opt.use_graph) {
+    // capture once per argument set on the internal stream, then replay on `s`
+    std::vector<int64_t> key;
     for (size_t i = 0; i < cnt; ++i) {
-      Inst& in = p->inst[i];
-      if (R[i] == 0 || done[i]) continue;
-      any = true;
-      PC_TRY(pc::launch_zy(in, in.Y, in.KMp, R[i], X[i], ldX[i], in.Rres, in.n, s));
-      PC_TRY(pc::launch_ztx(in, in.Rres, in.n, R[i], in.D, in.KMp, s));
-      PC_TRY(pc::launch_chol_solve(in, in.D, in.KMp, R[i], in.B, in.KMp, s));
-      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.norms, s));
+      key.push_back((int64_t)(intptr_t)X[i]); key.push_back(ldX[i]); key.push_back(R[i]);
+      key.push_back((int64_t)(intptr_t)Y[i]); key.push_back(ldY[i]);
     }
-    if (!any) break;
-    for (size_t i = 0; i < cnt; ++i) {
-      Inst& in = p->inst[i];
-      if (R[i] == 0 || done[i]) continue;
-      PC_TRY(hipMemcpyAsync(p->h_norms, in.norms, sizeof(double) * 2 * R[i], hipMemcpyDeviceToHost, s));
-      PC_TRY(hipStreamSynchronize(s));
-      double worst = 0.0;
-      for (int64_t r = 0; r < R[i]; ++r) {
-        const double dn = p->h_norms[2 * r], yn = p->h_norms[2 * r + 1];
-        const double rel = yn > 0 ? dn / yn : (dn > 0 ? INFINITY : 0.0);
-        worst = std::max(worst, std::isfinite(rel) ? rel : INFINITY);
-      }
-      // stop at the tolerance, or once the updates stop shrinking (two
-      // iterations in a row with less than a halving): the attainable
-      // accuracy of the residual has been reached
-      const double prev = in.last_rel;
-      in.iters = it;
-      in.last_rel = worst;
-      if (worst <= p->opt.tol) {
-        done[i] = 1;
-      } else if (it >= 2 && worst > 0.5 * prev) {
-        if (++stall[i] >= 2) done[i] = worst <= kStallAccept ? 1 : 2;
-      } else {
-        stall[i] = 0;
-      }
+    if (!p->gexec || key != p->gkey) {
+      if (p->gexec) { hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+      if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+      const bool prof = p->profiling;
+      p->profiling = false;                       // no timing events inside the graph
+      PC_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+      pc_status st = enqueue_apply(p, X, ldX, R, Y, ldY, p->cap, 0);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(p->cap, &g);
+      p->profiling = prof;
+      if (st != PC_OK) { if (g) hipGraphDestroy(g); return st; }
+      if (e != hipSuccess) return PC_ERR_DEVICE;
+      p->graph = g;
+      PC_TRY(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+      p->gkey = key;
     }
+    PC_TRY(hipGraphLaunch(p->gexec, s));
+  } else {
+    pc_status st = enqueue_apply(p, X, ldX, R, Y, ldY, s, budget > 4 ? 2 : 0);
+    if (st != PC_OK) return st;
   }
-  refine_timer.reset();
-  PhaseTimer copy_timer(p, PC_PHASE_COPYOUT, s);
+  for (size_t i = 0; i < cnt; ++i) { p->inst[i].iters = 0; p->inst[i].last_rel = 0.0; }
+  if (budget == 0) return PC_OK;
+  // refinement outcome: one read of every instance's control block
+  for (size_t i = 0; i < cnt; ++i)
+    if (R[i] != 0)
+      PC_TRY(hipMemcpyAsync(&p->h_ctl[i], p->inst[i].ctl, sizeof(pc::RefineCtl), hipMemcpyDeviceToHost, s));
+  PC_TRY(hipStreamSynchronize(s));
+  pc_status st = PC_OK;
   for (size_t i = 0; i < cnt; ++i) {
-    Inst& in = p->inst[i];
     if (R[i] == 0) continue;
-    PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y[i], ldY[i], in.KM, in.KM, R[i], s));
-    if (budget > 0 && p->opt.precision != PC_PREC_FP64 && done[i] != 1) st = PC_ERR_NO_CONVERGENCE;
+    p->inst[i].iters = p->h_ctl[i].iters;
+    p->inst[i].last_rel = p->h_ctl[i].last;
+    if (p->opt.precision != PC_PREC_FP64 && p->h_ctl[i].done != 1) st = PC_ERR_NO_CONVERGENCE;
   }
   return st;
 }

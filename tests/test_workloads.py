@@ -53,4 +53,4 @@ def test_batched_params_constraints():
         n = p["n_lat"] * p["n_lon"]
         assert 32 <= p["n_lat"] <= 96 and p["n_lon"] == 2 * p["n_lat"]
         assert p["K"] in (8, 16, 32, 64) and p["M"] % 32 == 0 and 32 <= p["M"] <= 256
-        assert p["K"] * p["M"] <= n and 8 <= p["R"] <= 128
+        assert 2 * p["K"] * p["M"] <= n and 8 <= p["R"] <= 128
