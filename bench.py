@@ -4,13 +4,16 @@
 One step = the whole hot path on one batch: the Gram of the modulated square
 root (per-column Grams + MFMA Gram), its FP64 Cholesky factorization, b = Z^T x
 and the two triangular solves (plus FP64 refinement in the reduced-precision
-modes), for the 64x128-grid workload (n = 8192, K = 32 members, M = 128 modes,
-Z is 8192 x 4096, 256 right-hand sides).  The plan (validation and workspace
-allocation) is built once before timing, like an FFT plan.
+modes).  The default workload is the 64x128 grid (n = 8192, K = 32 members,
+M = 128 modes, Z is 8192 x 4096, 256 right-hand sides); `--config 3` runs the
+batch of 64 uneven instances (FP32 Gram + FP64 refinement, apply replayed from
+a captured hipGraph).  The plan (validation and workspace allocation) is built
+once before timing, like an FFT plan.
 
 Prints one JSON line.  The oracle (explicit Z + Householder QR in float64) runs
 on the host cores on the same arrays; it supplies the accuracy check and the
-CPU baseline.
+CPU baseline.  Per-kernel durations come from HIP events the library records
+on the stream each kernel is launched on.
 """
 from __future__ import annotations
 
@@ -28,9 +31,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Z⁺x RHS/sec at rel.err≤1e-8 vs FP64 oracle; % HBM/MFMA roofline"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-HBM_PEAK_GBS = 8000.0
-GRAM_SOURCES = ["paper_2609_13327_amd/csrc/k_gram.hip", "paper_2609_13327_amd/csrc/gemm_core.h",
-                "paper_2609_13327_amd/csrc/pc_common.h"]
+CSRC = "paper_2609_13327_amd/csrc/"
+COMMON = [CSRC + "pc_common.h", CSRC + "pc_internal.h"]
+# phase -> (kernel name as the profiler shows it, sources that define it); the
+# solve phase launches its kernel twice (forward, then backward substitution)
+LAUNCHES_PER_PHASE = {"solve": 2}
+KERNELS = {
+    ("gram", "fp64"): ("gram_f64_kernel", [CSRC + "k_gram.hip"]),
+    ("gram", "fp32"): ("gram_f32_kernel", [CSRC + "k_lowprec.hip"]),
+    ("gram", "bf16"): ("gram_bf16_kernel", [CSRC + "k_lowprec.hip"]),
+    ("cholesky", None): ("chol_dag_kernel", [CSRC + "k_dag.hip"]),
+    ("ztx", None): ("ztx1_kernel", [CSRC + "k_apply.hip"]),
+    ("solve", None): ("solve_dag_kernel", [CSRC + "k_dag.hip"]),
+}
+PRECS = {"fp64": (0, 0), "fp32": (1, 10), "bf16": (2, 30)}
 
 
 def parse():
@@ -38,10 +52,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"],
+                    help="default: fp64 for configs 1-2, fp32 for config 3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the reduced-precision variants")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other precisions")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -51,22 +66,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def sources_sha():
+def sources_sha(paths):
     h = hashlib.sha256()
-    for p in GRAM_SOURCES:
+    for p in sorted(set(paths + COMMON)):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def gram_flops(inst):
-    """Algorithmic FP64 Gram work: 2 n_h [K(K+1)/2] [M(M+1)/2] (both symmetries)."""
-    return 2.0 * inst.n_h * (inst.K * (inst.K + 1) / 2) * (inst.M * (inst.M + 1) / 2)
+def kernel_info(phase, prec):
+    return KERNELS.get((phase, prec)) or KERNELS[(phase, None)]
 
 
-def gram_flops_lowprec(inst):
-    """Algorithmic work of the Gram of a rounded Z: n KM (KM+1) (one symmetry)."""
-    return float(inst.n) * inst.KM * (inst.KM + 1)
+def algorithmic_flops(phase, prec, inst, R):
+    """Algorithmic work of one launch of the phase's kernel on one instance."""
+    KM, n, n_h = inst.KM, inst.n, inst.n_h
+    if phase == "gram":
+        if prec == "fp64":   # both symmetries: 2 n_h [K(K+1)/2] [M(M+1)/2]
+            return 2.0 * n_h * (inst.K * (inst.K + 1) / 2) * (inst.M * (inst.M + 1) / 2)
+        return float(n) * KM * (KM + 1)   # Gram of a rounded Z, one symmetry
+    if phase == "cholesky":
+        return KM ** 3 / 3.0
+    if phase == "ztx":   # modulation by e_k, then the W^T projection
+        return 2.0 * n_h * inst.M * inst.K * R + float(n) * inst.K * R
+    if phase == "solve":   # one triangular solve
+        return 1.0 * KM * KM * R
+    raise KeyError(phase)
+
+
+def phase_peak(phase, prec):
+    return PEAK_TFLOPS[prec] if phase == "gram" else PEAK_TFLOPS["fp64"]
 
 
 def copy_probe():
@@ -80,16 +109,25 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
 
 
+def oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        return os.cpu_count()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build; see DESIGN.md for sharding)")
+        log("bench.py: only --gpus 1 is supported (single-GPU build; DESIGN.md says how it would shard)")
         return 2
     if args.copy_probe:
         copy_probe()
         return 0
+    prec_main = args.precision or ("fp32" if args.config == 3 else "fp64")
     import torch
     import paper_2609_13327_amd as pc
     import workloads as wl
@@ -101,25 +139,28 @@ def main():
     torch.cuda.set_device(dev)
 
     log(f"generating config {args.config}")
-    inst = wl.config(args.config)
-    R = inst.R
+    insts = wl.batched_config() if args.config == 3 else [wl.config(args.config)]
+    use_graph = 1 if args.config == 3 else 0
+    total_rhs = sum(i.R for i in insts)
 
     def to_dev(a):
         return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to(dev).t()
 
-    dE, dW, dX = to_dev(inst.E), to_dev(inst.W), to_dev(inst.X)
-    dY = torch.empty((R, inst.KM), dtype=torch.float64, device=dev).t()
-
-    precs = {"fp64": (pc.PC_PREC_FP64, 0), "fp32": (pc.PC_PREC_FP32_REFINE, 10),
-             "bf16": (pc.PC_PREC_BF16_REFINE, 30)}
+    dE = [to_dev(i.E) for i in insts]
+    dW = [to_dev(i.W) for i in insts]
+    dX = [to_dev(i.X) for i in insts]
+    dY = [torch.empty((i.R, i.KM), dtype=torch.float64, device=dev).t() for i in insts]
 
     def measure(prec_name, steps, warmup, profile=True):
-        code, refine = precs[prec_name]
-        plan = pc.Plan([{"E": dE, "W": dW, "n_w": 1, "max_rhs": R}], precision=code,
-                       max_refine=refine, tol=1e-10 if prec_name != "fp64" else 0.0)
+        code, refine = PRECS[prec_name]
+        if args.config == 3 and refine:
+            refine = 20
+        plan = pc.Plan([{"E": e, "W": w, "n_w": 1, "max_rhs": i.R} for e, w, i in zip(dE, dW, insts)],
+                       precision=code, max_refine=refine, tol=1e-10 if refine else 0.0,
+                       use_graph=use_graph)
         for _ in range(warmup):
             plan.factor()
-            plan.apply([dX], [dY])
+            plan.apply(dX, dY)
         torch.cuda.synchronize()
         pc.pc_profile_read(plan.handle)  # drop anything recorded so far
         if profile:
@@ -128,91 +169,115 @@ def main():
         t0 = time.perf_counter()
         for _ in range(steps):
             plan.factor()
-            plan.apply([dX], [dY])
+            plan.apply(dX, dY)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         phases = pc.pc_profile_read(plan.handle)
         pc.pc_profile_enable(plan.handle, False)
         # apply only (factor reused)
-        plan.apply([dX], [dY])
+        plan.apply(dX, dY)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         napply = max(3, steps)
         for _ in range(napply):
-            plan.apply([dX], [dY])
+            plan.apply(dX, dY)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        it, rel = pc.pc_query_info(plan.handle, 0)
-        Y = dY.cpu().numpy()
+        info = [pc.pc_query_info(plan.handle, k) for k in range(len(insts))]
+        Y = [y.cpu().numpy() for y in dY]
         plan.close()
         ms = (t1 - t0) * 1e3 / steps
-        return {"ms_per_step": ms, "rhs_per_s": R / (ms * 1e-3),
-                "apply_only_rhs_per_s": R / ((tb - ta) / napply),
-                "phases_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
-                "phase_counts": {k: v[1] for k, v in phases.items()},
-                "refine_iters": it, "refine_last_rel": rel, "Y": Y}
+        kernels = {}
+        for ph in ("gram", "cholesky", "ztx", "solve"):
+            tot_ms, cnt = phases[ph]
+            if not cnt:
+                continue
+            per = LAUNCHES_PER_PHASE.get(ph, 1)
+            launches_per_step = per * cnt / steps
+            flops = sum(algorithmic_flops(ph, prec_name, i, i.R) for i in insts) / len(insts)
+            avg = tot_ms / (cnt * per)
+            ach = flops / (avg * 1e-3) / 1e12
+            name, _ = kernel_info(ph, prec_name)
+            kernels[ph] = {"kernel": name, "avg_launch_ms": avg, "launches_per_step": launches_per_step,
+                           "flops_per_launch": flops, "achieved_tflops": ach,
+                           "peak_tflops": phase_peak(ph, prec_name),
+                           "frac": ach / phase_peak(ph, prec_name)}
+        return {"ms_per_step": ms, "rhs_per_s": total_rhs / (ms * 1e-3),
+                "apply_only_rhs_per_s": total_rhs / ((tb - ta) / napply),
+                "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
+                "kernels": kernels,
+                "refine_iters_max": max(it for it, _ in info), "Y": Y}
 
-    log(f"timing {args.precision}: {args.warmup} warmup + {args.steps} steps")
-    main_res = measure(args.precision, args.steps, args.warmup)
+    log(f"timing {prec_main}: {args.warmup} warmup + {args.steps} steps")
+    main_res = measure(prec_main, args.steps, args.warmup)
     log(f"  {main_res['ms_per_step']:.3f} ms/step")
 
     # oracle on the host: accuracy reference and CPU baseline
     from oracle import lsq
-    ref = None
+    refs = {}
     cpu = None
-    if args.config in (1, 2) and not args.no_cpu_baseline:
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
-        except Exception:
-            threads = os.cpu_count()
+    if not args.no_cpu_baseline:
+        threads = oracle_threads()
         log("oracle (explicit Z + Householder QR) on the host")
-        t0 = time.perf_counter()
-        ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
-        t_or = time.perf_counter() - t0
+        if args.config == 3:
+            # bounded sample: the cheapest instances until ~10 s of oracle work
+            order = sorted(range(len(insts)), key=lambda k: insts[k].n * insts[k].KM ** 2)
+            t_or, rhs = 0.0, 0
+            for k in order:
+                t0 = time.perf_counter()
+                refs[k] = lsq.left_inverse_apply(insts[k].E, insts[k].W, 1, insts[k].X)
+                t_or += time.perf_counter() - t0
+                rhs += insts[k].R
+                if t_or > 10.0:
+                    break
+            sample = (f"the {len(refs)} cheapest of the 64 instances ({rhs} right-hand sides): form Z, "
+                      f"LAPACK Householder QR, solve")
+        else:
+            t0 = time.perf_counter()
+            refs[0] = lsq.left_inverse_apply(insts[0].E, insts[0].W, 1, insts[0].X)
+            t_or = time.perf_counter() - t0
+            rhs = insts[0].R
+            sample = (f"the full {wl.CONFIG_NAMES[args.config]} step: form Z ({insts[0].n}x{insts[0].KM}), "
+                      f"LAPACK Householder QR, {rhs} right-hand sides")
         log(f"  oracle {t_or:.2f} s")
-        if True:
-            cpu = {"value": R / t_or, "unit": "RHS/s", "cores": int(threads), "kind": "oracle",
-                   "sample": f"the full {wl.CONFIG_NAMES[args.config]} step: form Z "
-                             f"({inst.n}x{inst.KM}), LAPACK Householder QR, {R} right-hand sides"}
+        cpu = {"value": rhs / t_or, "unit": "RHS/s", "cores": int(threads), "kind": "oracle",
+               "sample": sample}
 
     def rel_err(Y):
-        if ref is None:
+        if not refs:
             return None
-        e = np.linalg.norm(Y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        e = np.concatenate([np.linalg.norm(Y[k] - r, axis=0) / np.linalg.norm(r, axis=0)
+                            for k, r in refs.items()])
         return float(e.max()), float(np.median(e))
 
     err = rel_err(main_res["Y"])
     variants = {}
     if not args.no_variants:
         for name in ("bf16", "fp32", "fp64"):
-            if name == args.precision:
+            if name == prec_main:
                 continue
             try:
                 v = measure(name, max(3, args.steps // 4), 2)
                 e = rel_err(v["Y"])
                 variants[name] = {"ms_per_step": v["ms_per_step"], "rhs_per_s": v["rhs_per_s"],
                                   "apply_only_rhs_per_s": v["apply_only_rhs_per_s"],
-                                  "refine_iters": v["refine_iters"],
+                                  "refine_iters_max": v["refine_iters_max"],
                                   "rel_err_max": e[0] if e else None,
-                                  "phases_ms": v["phases_ms"]}
+                                  "phases_ms_per_step": v["phases_ms_per_step"]}
             except Exception as ex:  # a variant that is not available is reported as such
                 variants[name] = {"error": str(ex)}
 
-    gram_ms = main_res["phases_ms"]["gram"]
-    if args.precision == "fp64":
-        flops = gram_flops(inst)
-        peak = PEAK_TFLOPS["fp64"]
-    else:
-        flops = gram_flops_lowprec(inst)
-        peak = PEAK_TFLOPS[args.precision]
-    achieved = flops / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else None
+    # roofline of the kernel that takes the most time per step
+    kern = main_res["kernels"]
+    dom = max(kern, key=lambda ph: kern[ph]["avg_launch_ms"] * kern[ph]["launches_per_step"])
+    d = kern[dom]
+    name, srcs = kernel_info(dom, prec_main)
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"gram_{args.precision}_c{args.config}_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"{name}_c{args.config}_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             t = json.load(f)
-        if t.get("kernel_source_sha") == sources_sha():
+        if t.get("kernel_source_sha") == sources_sha(srcs):
             traffic = t.get("bytes_per_launch")
     out = {
         "metric": METRIC,
@@ -225,19 +290,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[prec_main],
         "data": "synthetic",
-        "config": {"workload": wl.CONFIG_NAMES[args.config], "n": inst.n, "K": inst.K, "M": inst.M,
-                   "rhs": R, "precision": args.precision, "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "kernel": "gram", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
-                     "traffic": traffic, "flops_per_launch": flops,
-                     "avg_launch_ms": gram_ms},
+        "config": {"workload": wl.CONFIG_NAMES[args.config], "instances": len(insts),
+                   "n": [i.n for i in insts] if len(insts) > 1 else insts[0].n,
+                   "KM_max": max(i.KM for i in insts), "rhs": total_rhs, "precision": prec_main,
+                   "hipgraph": bool(use_graph), "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "kernel": d["kernel"], "achieved": d["achieved_tflops"],
+                     "peak": d["peak_tflops"], "unit": "TFLOP/s", "frac": d["frac"],
+                     "traffic": traffic, "flops_per_launch": d["flops_per_launch"],
+                     "avg_launch_ms": d["avg_launch_ms"]},
         "cpu_baseline": cpu,
         "rel_err_max": err[0] if err else None,
         "rel_err_median": err[1] if err else None,
         "apply_only_rhs_per_s": main_res["apply_only_rhs_per_s"],
-        "phases_ms": main_res["phases_ms"],
+        "refine_iters_max": main_res["refine_iters_max"],
+        "kernels": kern,
+        "phases_ms_per_step": main_res["phases_ms_per_step"],
         "variants": variants,
     }
     print(json.dumps(out))

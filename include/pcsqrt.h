@@ -3,7 +3,7 @@
  * localized ensemble covariance, on AMD Instinct MI355X (gfx950).
  *
  * The operation (Sardelli & Bishop, Sec. 2.1, eq. svTransform, with the
- * square root of Sec. 3.8, eq. SQRTofPCModulation):
+ * square root of Sec. 3.7, eq. SQRTofPCModulation):
  *
  *   P^c = C o P^s,  P^s = Z_e Z_e^T (eq. PsAndItsSquareRoot),
  *   C   = equal n_h x n_h blocks C_b = W W^T (eqs. blockStructureCEqualBlocks, SqrtOfC),
@@ -14,7 +14,7 @@
  * E holds the scaled members z_k (eq. zkDefinition; the library uses E as
  * given), rows in the paper's segment order i = l*n_h + j (Sec. 3.4): level or
  * variable kind l (n_w of them), grid column j (n_h of them).  W = V_b
- * Delta_b^{1/2} (Sec. 3.8) holds the M localization square-root modes.  The
+ * Delta_b^{1/2} (Sec. 3.9) holds the M localization square-root modes.  The
  * paper builds a left inverse from per-column SVDs under n_w = K (Sec. 3.9);
  * for the general tall Z (K*M <= n) this library returns the Moore-Penrose
  * (least-squares) left inverse, which agrees with the paper's on range(Z).

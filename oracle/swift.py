@@ -5,7 +5,7 @@ Test infrastructure only (see the package docstring).
 Inputs follow the paper's statement of the problem: the n x K matrix of
 scaled members (its columns z_k, eq. zkDefinition), the n_h x L eigenvectors
 V_b of the localization block and its L non-zero eigenvalues delta_b
-(Sec. 3.8, the economical eigendecomposition C_b = V_b Delta_b V_b^T).
+(Sec. 3.9, the economical eigendecomposition C_b = V_b Delta_b V_b^T).
 
 With n_w = K the matrix A of eq. ADef is square; its per-grid-column blocks
 A_m (n_w x K: the rows of the member matrix that belong to grid column m,

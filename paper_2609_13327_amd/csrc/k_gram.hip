@@ -2,7 +2,7 @@
 //
 // Per grid column j the n_w x K block A_j (the rows of the members in column
 // j, the paper's A_m of Sec. 3.9) gives S_j = A_j^T A_j.  Because the
-// localization is horizontal (equal blocks C_b, Sec. 3.7) every level shares
+// localization is horizontal (equal blocks C_b, Sec. 3.6) every level shares
 // W, so
 //     G_{(k,m),(k',m')} = sum_j S_j[k,k'] * W[j,m] * W[j,m'].
 // G is symmetric in (k,k') and in (m,m') separately; only k <= k' and

@@ -24,7 +24,7 @@ SHAPES = [(4, 8, 1, 3, 5), (4, 8, 2, 4, 6), (3, 6, 3, 2, 9), (4, 8, 4, 8, 7), (2
 @pytest.mark.parametrize("shape", SHAPES)
 def test_modulation_identity(shape):
     """Z Z^T = C o P^s with P^s = E E^T and C built from equal blocks W W^T
-    (the Bishop-Hodyss modulation identity used in Sec. 3.8)."""
+    (the Bishop-Hodyss modulation identity used in Sec. 3.7)."""
     n_lat, n_lon, n_w, K, M = shape
     inst = small_instance(n_lat, n_lon, n_w, K, M)
     Z = lsq.form_z(inst.E, inst.W, n_w)

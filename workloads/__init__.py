@@ -10,7 +10,7 @@ arithmetic.  Everything here is a statement of the workload:
   longitude) structure of an isotropic kernel on a regular lat-lon grid;
 * localization square-root modes W = V_b Delta_b^{1/2}, the leading M
   eigenpairs of a chordal-Gaussian localization block C_b (the paper's choice
-  of square root, Sec. 3.8, truncated to M modes);
+  of square root, Sec. 3.7, truncated to M modes);
 * right-hand sides x ~ N(0, 1).
 
 Layouts (all float64, column-major as the library expects):
