@@ -4,7 +4,8 @@ Test infrastructure only (see the package docstring).
 
 Textbook preconditioned CG (Hestenes & Stiefel 1952) with an optional
 block-Jacobi preconditioner built from the K diagonal M x M blocks G_kk of
-the Gram (one block per ensemble member).  Iteration counts depend on the
+the Gram (one block per ensemble member), or from its consecutive nb x nb
+diagonal blocks (`block_jacobi_tiles`).  Iteration counts depend on the
 inputs; the converged answer is pinned against the direct solve.
 """
 from __future__ import annotations
@@ -22,6 +23,22 @@ def block_jacobi(G: np.ndarray, K: int, M: int):
             s = slice(k * M, (k + 1) * M)
             t = np.linalg.solve(L, r[s])
             out[s] = np.linalg.solve(L.T, t)
+        return out
+    return apply
+
+
+def block_jacobi_tiles(G: np.ndarray, nb: int):
+    """Block-Jacobi with the consecutive nb x nb diagonal blocks of G (the last
+    one smaller when nb does not divide the order): applies the inverse of
+    blockdiag(G[s, s]) via per-block Cholesky."""
+    n = G.shape[0]
+    blocks = [slice(s, min(s + nb, n)) for s in range(0, n, nb)]
+    facs = [np.linalg.cholesky(G[s, s]) for s in blocks]
+
+    def apply(r):
+        out = np.empty_like(r)
+        for s, L in zip(blocks, facs):
+            out[s] = np.linalg.solve(L.T, np.linalg.solve(L, r[s]))
         return out
     return apply
 

@@ -326,3 +326,24 @@ def test_cg_matches_direct_solve():
     # the direct solve is the least-squares answer of the oracle
     y_ls = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X[:, :1])[:, 0]
     assert np.abs(y_direct - y_ls).max() <= 1e-9 * np.abs(y_ls).max()
+
+
+def test_block_jacobi_tiles_inverts_its_blocks():
+    """Applied to a column of G, the tile preconditioner returns the unit
+    vector inside that column's block (it inverts G's diagonal blocks), for a
+    block size that leaves a ragged last block; with one block it is G^{-1}."""
+    inst = small_instance(4, 8, 1, 3, 5)
+    G = lsq.gram(inst.E, inst.W, 1)
+    n = G.shape[0]
+    pre = cg.block_jacobi_tiles(G, 4)
+    for j in range(n):
+        z = pre(G[:, j].copy())
+        s = slice(4 * (j // 4), min(4 * (j // 4) + 4, n))
+        e = np.zeros(n)
+        e[j] = 1.0
+        assert np.abs(z[s] - e[s]).max() <= 1e-10
+    full = cg.block_jacobi_tiles(G, n)
+    b = np.arange(1.0, n + 1)
+    assert np.abs(G @ full(b) - b).max() <= 1e-9 * np.abs(b).max()
+    y, it = cg.pcg(G, b, precond=pre, tol=1e-13, maxiter=200)
+    assert np.abs(G @ y - b).max() <= 1e-10 * np.abs(b).max()
