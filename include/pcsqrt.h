@@ -84,8 +84,13 @@ typedef struct {
   double tol;          /* refinement stops for a right-hand side when
                           max|delta| <= tol * max|y|; <= 0 selects 1e-12 */
   int32_t use_graph;   /* 1: capture the apply sequence in a hipGraph and replay it */
-  int32_t reserved;    /* must be 0 */
+  int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM */
 } pc_options;
+
+/* Keep a symmetric copy of each assembled FP64 Gram and the inverses of its
+ * 64 x 64 diagonal blocks, for pc_cg_solve / pc_learned_apply (extra
+ * 8 (K*M)^2 bytes per instance).  Needs precision PC_PREC_FP64. */
+#define PC_FLAG_KEEP_GRAM 1
 
 typedef struct pc_plan pc_plan;
 
@@ -111,9 +116,10 @@ pc_status pc_gram_factor(pc_plan *plan, void *stream, int32_t *failed_instance);
  * Y[i]: device, K_i*M_i x R[i] with leading dimension ldY[i] >= K_i*M_i.
  * X, ldX, R, Y, ldY are HOST arrays of `count` entries (the build count).
  * R[i] = 0 skips instance i.  Asynchronous in FP64 mode without refinement;
- * with refinement the host reads one convergence flag per iteration (a
- * stream sync each).  Returns PC_ERR_NO_CONVERGENCE (Y holds the last
- * iterate) if the budget ends before the tolerance is met. */
+ * with refinement the convergence test runs on the device and the host
+ * reads its flags every two iterations (without a graph) or once at the
+ * end.  Returns PC_ERR_NO_CONVERGENCE (Y holds the last iterate) if the
+ * budget ends before the tolerance is met. */
 pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int64_t *ldX,
                                 const int64_t *R, double *const *Y, const int64_t *ldY,
                                 void *stream);
@@ -190,6 +196,96 @@ pc_status pc_profile_read(pc_plan *plan, double *total_ms, int64_t *counts);
  * after the tasks it waits for.  Returns 0 when valid, a positive code
  * naming the violated rule otherwise, -1 for T < 1.  Touches no GPU. */
 int32_t pc_selftest_task_order(int32_t T);
+
+/* ------------------------------------------------------------------------
+ * Iterative solve on the normal equations and the learned warm start.
+ * Not part of the paper's method: conjugate gradients on G y = b with
+ * G = Z^T Z, started from the prediction of a small network trained on
+ * (x, Z^+ x) pairs that the direct method produced; the direct solve stays
+ * the fallback and the judge of its error.
+ * ---------------------------------------------------------------------- */
+
+/* pc_cg_solve — block-Jacobi preconditioned CG on G y = b for instance
+ * `instance` of a plan built with PC_FLAG_KEEP_GRAM and factored.
+ * B: device K*M x R (ldB >= K*M), right-hand sides b (e.g. Z^T x).
+ * Y: device K*M x R (ldY >= K*M); read as the starting guess when warm != 0
+ * (else the start is y = 0), overwritten with the result.  A column stops when
+ * ||b - G y||_2 <= tol ||b||_2.  At most maxiter iterations.  Synchronous:
+ * returns after the result is written.  *iterations (host, may be NULL)
+ * receives the largest iteration count over the columns.  Returns
+ * PC_ERR_NO_CONVERGENCE if a column did not reach tol (Y holds the iterate),
+ * PC_ERR_INVALID_ARG if the plan keeps no Gram, PC_ERR_NOT_FACTORED before a
+ * successful pc_gram_factor, PC_ERR_TOO_MANY_RHS if R > max_rhs. */
+pc_status pc_cg_solve(pc_plan *plan, int32_t instance, const double *B, int64_t ldB, int64_t R,
+                      double *Y, int64_t ldY, double tol, int32_t maxiter, int32_t warm,
+                      int32_t *iterations, void *stream);
+
+/* Two-layer network y^ = W2 gelu(W1 x^ + b1) + b2 (gelu(a) = a Phi(a)),
+ * d inputs and outputs, h hidden units.  Parameters and Adam moments are
+ * FP32; every matrix product runs on MFMA with bf16 operands (rounded to
+ * nearest even) or fp32 operands, accumulating in fp32. */
+typedef struct pc_mlp pc_mlp;
+#define PC_MLP_BF16 0
+#define PC_MLP_FP32 1
+
+/* pc_mlp_create — allocate a network for batches of up to max_batch rows on
+ * the current device; parameters start at zero (set them with
+ * pc_mlp_set_params).  operand_type: PC_MLP_BF16 or PC_MLP_FP32. */
+pc_status pc_mlp_create(int64_t d, int64_t h, int64_t max_batch, int32_t operand_type, pc_mlp **out);
+
+/* pc_mlp_destroy — free the network (synchronizes the device).  NULL is accepted. */
+pc_status pc_mlp_destroy(pc_mlp *mlp);
+
+/* Parameter exchange, device FP32 buffers, row-major: W1 h x d, b1 h,
+ * W2 d x h, b2 d.  set also clears the Adam moments and step count. */
+pc_status pc_mlp_set_params(pc_mlp *mlp, const float *W1, const float *b1, const float *W2,
+                            const float *b2, void *stream);
+pc_status pc_mlp_get_params(const pc_mlp *mlp, float *W1, float *b1, float *W2, float *b2,
+                            void *stream);
+
+/* pc_mlp_forward — Y = network(X) for B <= max_batch rows.  X: device FP32
+ * B x d row-major with row stride ldX >= d; Y likewise (ldY >= d).  Asynchronous. */
+pc_status pc_mlp_forward(pc_mlp *mlp, const float *X, int64_t ldX, int64_t B, float *Y, int64_t ldY,
+                         void *stream);
+
+/* pc_mlp_gradients — loss = (1/B) sum_b ||y^_b - t_b||^2 / ||t_b||^2 over
+ * the batch and its gradients, without updating the parameters.  X, T:
+ * device FP32 B x d row-major (strides ldX, ldT >= d).  loss: device, one
+ * float.  dW1 .. db2: device FP32 in the layout of pc_mlp_set_params; any
+ * may be NULL.  Asynchronous. */
+pc_status pc_mlp_gradients(pc_mlp *mlp, const float *X, int64_t ldX, const float *T, int64_t ldT,
+                           int64_t B, float *loss, float *dW1, float *db1, float *dW2, float *db2,
+                           void *stream);
+
+/* pc_mlp_train_step — one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected, learning rate lr) on the batch's loss; loss as above (may
+ * be NULL).  Asynchronous. */
+pc_status pc_mlp_train_step(pc_mlp *mlp, const float *X, int64_t ldX, const float *T, int64_t ldT,
+                            int64_t B, float lr, float *loss, void *stream);
+
+/* pc_mlp_training_pairs — network inputs and targets from N solved systems:
+ * row r of X = b_r / ||b_r||, row r of T = y_r / ||b_r||, where b_r, y_r are
+ * column r of B and Y (device FP64, d x N, ldB, ldY >= d; typically
+ * b = Z^T x and y = Z^+ x from the direct solve).  X, T: device FP32 N x d
+ * row-major (ldX, ldT >= d).  Asynchronous on `stream`. */
+pc_status pc_mlp_training_pairs(const double *B, int64_t ldB, const double *Y, int64_t ldY, int64_t d,
+                                int64_t N, float *X, int64_t ldX, float *T, int64_t ldT, void *stream);
+
+/* pc_mlp_warm_start — y0 = ||b|| network(b / ||b||) per column of B (device
+ * FP64 d x R, ldB >= d) into Y0 (device FP64 d x R, ldY0 >= d), R <= max_batch.
+ * A zero column gives y0 = 0.  Asynchronous. */
+pc_status pc_mlp_warm_start(pc_mlp *mlp, const double *B, int64_t ldB, int64_t R, double *Y0,
+                            int64_t ldY0, void *stream);
+
+/* pc_learned_apply — Y = Z^+ X for instance `instance` by CG from the
+ * network's warm start (mlp may be NULL: cold start), for a plan built with
+ * PC_FLAG_KEEP_GRAM and factored; the network's d must equal K*M.  Columns
+ * that have not reached tol after maxiter iterations are solved directly with
+ * the Cholesky factor (*fallback = 1, else 0).  X: device n x R; Y: device
+ * K*M x R.  Synchronous.  *iterations: largest CG iteration count. */
+pc_status pc_learned_apply(pc_plan *plan, int32_t instance, pc_mlp *mlp, const double *X,
+                           int64_t ldX, int64_t R, double *Y, int64_t ldY, double tol,
+                           int32_t maxiter, int32_t *iterations, int32_t *fallback, void *stream);
 
 #ifdef __cplusplus
 }

@@ -33,11 +33,17 @@ PC_PREC_FP64 = 0
 PC_PREC_FP32_REFINE = 1
 PC_PREC_BF16_REFINE = 2
 
+PC_FLAG_KEEP_GRAM = 1
+PC_MLP_BF16 = 0
+PC_MLP_FP32 = 1
+
 EXPORTED = [
     "pc_sqrt_build", "pc_gram_factor", "pc_left_inverse_apply", "pc_query_info",
     "pc_plan_destroy", "pc_status_string", "pc_sqrt_transpose_apply", "pc_sqrt_apply",
     "pc_gram_assemble", "pc_gram_export", "pc_profile_enable", "pc_profile_read",
-    "pc_selftest_task_order",
+    "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
+    "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
+    "pc_learned_apply", "pc_mlp_training_pairs",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout"]
@@ -51,7 +57,7 @@ class PcInstance(ctypes.Structure):
 
 class PcOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_refine", c_int32), ("tol", c_double),
-                ("use_graph", c_int32), ("reserved", c_int32)]
+                ("use_graph", c_int32), ("flags", c_int32)]
 
 
 class PcError(RuntimeError):
@@ -94,6 +100,22 @@ def load_library(path: str = LIB_PATH):
     lib.pc_profile_enable.argtypes = [c_void_p, c_int32]
     lib.pc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
     lib.pc_selftest_task_order.argtypes = [c_int32]
+    lib.pc_cg_solve.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_double,
+                                c_int32, c_int32, POINTER(c_int32), c_void_p]
+    lib.pc_mlp_create.argtypes = [c_int64, c_int64, c_int64, c_int32, POINTER(c_void_p)]
+    lib.pc_mlp_destroy.argtypes = [c_void_p]
+    lib.pc_mlp_set_params.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.pc_mlp_get_params.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.pc_mlp_forward.argtypes = [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p]
+    lib.pc_mlp_gradients.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.pc_mlp_train_step.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, ctypes.c_float,
+                                      c_void_p, c_void_p]
+    lib.pc_mlp_warm_start.argtypes = [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p]
+    lib.pc_mlp_training_pairs.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_void_p,
+                                          c_int64, c_void_p, c_int64, c_void_p]
+    lib.pc_learned_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
+                                     c_double, c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p]
     for name in EXPORTED:
         if name != "pc_status_string":
             getattr(lib, name).restype = c_int32
@@ -133,6 +155,20 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _fptr(t) -> int:
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise ValueError("expected a float32 device tensor")
+    return t.data_ptr()
+
+
+def _rows(t) -> int:
+    """Row stride of a row-major 2-D tensor (stride (ld, 1))."""
+    if t.dim() != 2 or (t.stride(1) != 1 and t.shape[1] > 1):
+        raise ValueError("expected a row-major 2-D tensor (stride (ld, 1))")
+    return max(int(t.stride(0)), int(t.shape[1]), 1)
+
+
 def _stream(stream) -> int:
     if stream is None:
         import torch
@@ -142,7 +178,7 @@ def _stream(stream) -> int:
 
 # -------------------------------------------------------- C-named functions
 def pc_sqrt_build(instances: Sequence[dict], precision: int = PC_PREC_FP64, max_refine: int = 0,
-                  tol: float = 0.0, use_graph: int = 0, stream=None) -> int:
+                  tol: float = 0.0, use_graph: int = 0, stream=None, flags: int = 0) -> int:
     """instances: dicts with E (n x K), W (n_h x M) column-major float64 device
     tensors, n_w and max_rhs.  Returns the plan handle."""
     lib = load_library()
@@ -155,7 +191,7 @@ def pc_sqrt_build(instances: Sequence[dict], precision: int = PC_PREC_FP64, max_
                             _ld(W), int(d.get("max_rhs", 1)))
         if E.shape[0] != n_h * n_w:
             raise ValueError("E must have n_h * n_w rows")
-    opt = PcOptions(int(precision), int(max_refine), float(tol), int(use_graph), 0)
+    opt = PcOptions(int(precision), int(max_refine), float(tol), int(use_graph), int(flags))
     plan = c_void_p()
     _check(lib.pc_sqrt_build(arr, len(instances), ctypes.byref(opt), c_void_p(_stream(stream)),
                              ctypes.byref(plan)), "pc_sqrt_build")
@@ -252,15 +288,94 @@ def pc_profile_read(plan: int):
     return {PHASES[i]: (tot[i], cnt[i]) for i in range(n)}
 
 
+def pc_cg_solve(plan: int, instance: int, B, Y, tol: float, maxiter: int, warm: bool = False, stream=None,
+                raise_on_error: bool = True):
+    """CG on G y = b (B, Y column-major K*M x R).  Returns (status, iterations)."""
+    it = c_int32(0)
+    st = load_library().pc_cg_solve(c_void_p(plan), int(instance), _ptr(B), _ld(B), int(B.shape[1]), _ptr(Y),
+                                    _ld(Y), float(tol), int(maxiter), int(bool(warm)), ctypes.byref(it),
+                                    c_void_p(_stream(stream)))
+    if raise_on_error and st not in (PC_OK, PC_ERR_NO_CONVERGENCE):
+        _check(st, "pc_cg_solve")
+    return st, it.value
+
+
+def pc_learned_apply(plan: int, instance: int, mlp: Optional[int], X, Y, tol: float, maxiter: int,
+                     stream=None):
+    """Y = Z^+ X by CG from the network's warm start.  Returns (iterations, fallback)."""
+    it = c_int32(0)
+    fb = c_int32(0)
+    _check(load_library().pc_learned_apply(c_void_p(plan), int(instance), c_void_p(mlp), _ptr(X), _ld(X),
+                                           int(X.shape[1]), _ptr(Y), _ld(Y), float(tol), int(maxiter),
+                                           ctypes.byref(it), ctypes.byref(fb), c_void_p(_stream(stream))),
+           "pc_learned_apply")
+    return it.value, fb.value
+
+
+def pc_mlp_create(d: int, h: int, max_batch: int, operand_type: int = PC_MLP_BF16) -> int:
+    m = c_void_p()
+    _check(load_library().pc_mlp_create(int(d), int(h), int(max_batch), int(operand_type), ctypes.byref(m)),
+           "pc_mlp_create")
+    return m.value
+
+
+def pc_mlp_destroy(mlp: Optional[int]):
+    _check(load_library().pc_mlp_destroy(c_void_p(mlp)), "pc_mlp_destroy")
+
+
+def pc_mlp_set_params(mlp: int, W1, b1, W2, b2, stream=None):
+    """Row-major float32 device tensors: W1 (h, d), b1 (h,), W2 (d, h), b2 (d,)."""
+    for t in (W1, b1, W2, b2):
+        if not t.is_contiguous():
+            raise ValueError("parameters must be contiguous")
+    _check(load_library().pc_mlp_set_params(c_void_p(mlp), _fptr(W1), _fptr(b1), _fptr(W2), _fptr(b2),
+                                            c_void_p(_stream(stream))), "pc_mlp_set_params")
+
+
+def pc_mlp_get_params(mlp: int, W1, b1, W2, b2, stream=None):
+    _check(load_library().pc_mlp_get_params(c_void_p(mlp), _fptr(W1), _fptr(b1), _fptr(W2), _fptr(b2),
+                                            c_void_p(_stream(stream))), "pc_mlp_get_params")
+
+
+def pc_mlp_forward(mlp: int, X, Y, stream=None):
+    _check(load_library().pc_mlp_forward(c_void_p(mlp), _fptr(X), _rows(X), int(X.shape[0]), _fptr(Y), _rows(Y),
+                                         c_void_p(_stream(stream))), "pc_mlp_forward")
+
+
+def pc_mlp_gradients(mlp: int, X, T, loss, dW1, db1, dW2, db2, stream=None):
+    _check(load_library().pc_mlp_gradients(c_void_p(mlp), _fptr(X), _rows(X), _fptr(T), _rows(T), int(X.shape[0]),
+                                           _fptr(loss), _fptr(dW1), _fptr(db1), _fptr(dW2), _fptr(db2),
+                                           c_void_p(_stream(stream))), "pc_mlp_gradients")
+
+
+def pc_mlp_train_step(mlp: int, X, T, lr: float, loss=None, stream=None):
+    _check(load_library().pc_mlp_train_step(c_void_p(mlp), _fptr(X), _rows(X), _fptr(T), _rows(T),
+                                            int(X.shape[0]), ctypes.c_float(lr),
+                                            c_void_p(_fptr(loss) if loss is not None else None),
+                                            c_void_p(_stream(stream))), "pc_mlp_train_step")
+
+
+def pc_mlp_warm_start(mlp: int, B, Y0, stream=None):
+    _check(load_library().pc_mlp_warm_start(c_void_p(mlp), _ptr(B), _ld(B), int(B.shape[1]), _ptr(Y0), _ld(Y0),
+                                            c_void_p(_stream(stream))), "pc_mlp_warm_start")
+
+
+def pc_mlp_training_pairs(B, Y, X, T, stream=None):
+    """B, Y: column-major float64 (d, N); X, T: row-major float32 (N, d)."""
+    _check(load_library().pc_mlp_training_pairs(_ptr(B), _ld(B), _ptr(Y), _ld(Y), int(B.shape[0]), int(B.shape[1]),
+                                                _fptr(X), _rows(X), _fptr(T), _rows(T), c_void_p(_stream(stream))),
+           "pc_mlp_training_pairs")
+
+
 # -------------------------------------------------------------- convenience
 class Plan:
     """Owns a plan and keeps its borrowed E/W tensors alive."""
 
     def __init__(self, instances: Sequence[dict], precision: int = PC_PREC_FP64, max_refine: int = 0,
-                 tol: float = 0.0, use_graph: int = 0, stream=None):
+                 tol: float = 0.0, use_graph: int = 0, stream=None, flags: int = 0):
         self._keep = [(d["E"], d["W"]) for d in instances]
         self.instances = list(instances)
-        self.handle = pc_sqrt_build(instances, precision, max_refine, tol, use_graph, stream)
+        self.handle = pc_sqrt_build(instances, precision, max_refine, tol, use_graph, stream, flags)
 
     def factor(self, stream=None, raise_on_error: bool = True):
         return pc_gram_factor(self.handle, stream, raise_on_error)
@@ -278,3 +393,23 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """Owns a warm-start network handle."""
+
+    def __init__(self, d: int, h: int, max_batch: int, operand_type: int = PC_MLP_BF16):
+        self.d, self.h = d, h
+        self.handle = pc_mlp_create(d, h, max_batch, operand_type)
+
+    def close(self):
+        if self.handle:
+            pc_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

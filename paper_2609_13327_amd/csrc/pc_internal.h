@@ -51,6 +51,12 @@ struct Inst {
   int64_t* chol_offs = nullptr;  // first task index of each Cholesky look-ahead iteration
   int64_t chol_ntasks = 0;
   RefineCtl* ctl = nullptr;  // device refinement control
+  // CG on the stored Gram (plans built with PC_FLAG_KEEP_GRAM)
+  double* Gs = nullptr;      // KMp x KMp symmetric copy of the assembled Gram
+  double* Dinv = nullptr;    // (KMp/NB) blocks NB x NB: inverses of the diagonal blocks of Gs
+  double* cg = nullptr;      // four KMp x max_rhs buffers: r, z, p, q
+  struct CgCol* cgcol = nullptr;
+  int* cg_flags = nullptr;   // [0] converged columns, [1] block-Jacobi pivot failure
   bool factored = false;
   int iters = 0;
   double last_rel = 0.0;
@@ -90,4 +96,85 @@ int64_t chol_task_offsets(int T, std::vector<int64_t>& offs);
 int gram_split_for(const Inst& in);
 int check_chol_task_order(int T);
 
+// ---------------------------------------------------------------- learned warm start
+enum { MLP_EPI_STORE = 0, MLP_EPI_BIAS_GELU = 1, MLP_EPI_BIAS = 2, MLP_EPI_GELU_GRAD = 3 };
+// C(m, n) = sum_k A(m, k) B(n, k), fp32 in global memory, MFMA operands bf16 or fp32.
+//   A(m, k) = A[m * sam + k * sak], B(n, k) = B[n * sbn + k * sbk]; a_kcont / b_kcont
+//   say which index is contiguous (sak == 1 / sbk == 1).  Output row-major, ld ldc.
+//   partial (max_splits * M * N floats) allows a split contraction; may be null.
+struct MlpGemm {
+  const float* A; int64_t sam, sak;
+  const float* B; int64_t sbn, sbk;
+  int64_t M, N, K;
+  int a_kcont, b_kcont;
+  int mode;
+  float* C; int64_t ldc;
+  const float* bias;       // per column n (BIAS modes)
+  float* C2;               // gelu(C) (BIAS_GELU), ld ldc
+  const float* aux;        // pre-activation (GELU_GRAD), ld ldc
+  float* partial; int max_splits; int64_t partial_cap;   // partial holds partial_cap floats
+  int64_t kper; int vec;   // set by the launcher
+};
+hipError_t launch_mlp_gemm(const MlpGemm& g, int bf16, hipStream_t s);
+hipError_t launch_mlp_loss(const float* Y, int64_t ldY, const float* T, int64_t ldT, int64_t d, int64_t B,
+                           float* dY, float* row_loss, float* loss, hipStream_t s);
+hipError_t launch_mlp_colsum(const float* G, int64_t ld, int64_t rows, int64_t cols, float* out, hipStream_t s);
+// Adam coefficients: beta1, beta2, 1 - beta1, 1 - beta2, bias corrections 1 - beta^t
+struct AdamCoef { float lr, b1, b2, omb1, omb2, bc1, bc2, eps; };
+hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, const AdamCoef& c,
+                           hipStream_t s);
+hipError_t launch_training_pairs(const double* Bm, int64_t ldB, const double* Ym, int64_t ldY, int64_t d, int64_t N,
+                                 float* X, int64_t ldX, float* T, int64_t ldT, hipStream_t s);
+hipError_t launch_ws_prep(const double* Bm, int64_t ldB, int64_t d, int64_t R, float* Xh, int64_t ldX, double* nrm,
+                          hipStream_t s);
+hipError_t launch_ws_finish(const float* Yh, int64_t ldYh, const double* nrm, int64_t d, int64_t R, double* Y0,
+                            int64_t ldY0, hipStream_t s);
+
+// ---------------------------------------------------------------- CG on the stored Gram
+struct CgCol { double bnorm, rz; int done, iters; };
+// symmetric full copy of the assembled (padded) Gram: Gs = G + tril(G, -1)^T
+hipError_t launch_gram_symmetrize(const Inst& in, double* Gs, hipStream_t s);
+// Dinv[t] = inverse of the t-th 64 x 64 diagonal block of Gs (block-Jacobi); flag set if not SPD
+hipError_t launch_bj_setup(const double* Gs, int64_t ld, int64_t T, double* Dinv, int* flag, hipStream_t s);
+// Z = blockdiag(Dinv) Rm on KMp x R
+hipError_t launch_bj_apply(const double* Dinv, int64_t T, const double* Rm, double* Zm, int64_t ld, int64_t R,
+                           hipStream_t s);
+// Q = Gs P (KMp x KMp times KMp x R), all ld = ld
+hipError_t launch_gram_matmul(const double* Gs, int64_t KMp, const double* P, double* Q, int64_t ld, int64_t R,
+                              hipStream_t s);
+// r = b - Q (Q may be null: cold start, y = 0); a zero column b gives y = 0 and is done
+hipError_t launch_cg_start(const double* Bm, int64_t ldB, const double* Q, double* Rm, double* Y, int64_t ldY,
+                           int64_t ld, int64_t KM, int64_t KMp, int64_t R, double tol, CgCol* col, int* ndone,
+                           hipStream_t s);
+hipError_t launch_cg_dir(const double* Rm, const double* Zm, double* P, int64_t ld, int64_t KMp, int64_t R,
+                         CgCol* col, int first, hipStream_t s);
+hipError_t launch_cg_step(const double* P, const double* Q, double* Y, int64_t ldY, double* Rm, int64_t ld,
+                          int64_t KMp, int64_t R, double tol, CgCol* col, int* ndone, int iter, hipStream_t s);
+
 }  // namespace pc
+
+// The network object behind the C handle pc_mlp (include/pcsqrt.h).
+struct pc_mlp {
+  int device = 0;
+  int64_t d = 0, h = 0, max_batch = 0;
+  int bf16 = 1;
+  int64_t nparams = 0;       // h*d + h + d*h + d
+  float* params = nullptr;   // [W1 (h x d, row-major) | b1 (h) | W2 (d x h, row-major) | b2 (d)]
+  float* grads = nullptr;    // same layout
+  float* m = nullptr;        // Adam moments, same layout
+  float* v = nullptr;
+  int64_t step = 0;          // Adam steps taken
+  // activations for max_batch rows
+  float* Apre = nullptr;     // B x h pre-activation
+  float* H = nullptr;        // B x h
+  float* Y = nullptr;        // B x d output
+  float* dY = nullptr;       // B x d
+  float* dA = nullptr;       // B x h
+  float* row_loss = nullptr; // B
+  float* loss = nullptr;     // 1
+  float* Xh = nullptr;       // B x d normalized warm-start input
+  double* nrm = nullptr;     // B norms of the warm-start inputs
+  float* partial = nullptr;  // split-contraction partials: max_splits x B x max(d, h)
+  int max_splits = 16;
+};
+

@@ -59,6 +59,8 @@ void free_inst(Inst& in) {
   hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
+  hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
+  in.Gs = in.Dinv = in.cg = nullptr; in.cgcol = nullptr; in.cg_flags = nullptr;
   in.dag = nullptr; in.chol_offs = nullptr; in.ctl = nullptr;
   in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = nullptr;
   in.pairs = in.qtiles = in.info = nullptr;
@@ -92,7 +94,7 @@ std::vector<int> make_qtiles(int64_t M) {
   return q;
 }
 
-pc_status alloc_inst(Inst& in, int precision) {
+pc_status alloc_inst(Inst& in, int precision, int flags) {
   const int64_t KMp = in.KMp, nblk = KMp / pc::NB, R = std::max<int64_t>(in.max_rhs, 1);
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
@@ -117,6 +119,13 @@ pc_status alloc_inst(Inst& in, int precision) {
   std::vector<int64_t> offs;
   in.chol_ntasks = pc::chol_task_offsets((int)T, offs);
   chk(dalloc(&in.chol_offs, (int64_t)offs.size()));
+  if (flags & PC_FLAG_KEEP_GRAM) {
+    chk(dalloc(&in.Gs, KMp * KMp));
+    chk(dalloc(&in.Dinv, KMp * pc::NB));
+    chk(dalloc(&in.cg, 4 * KMp * R));
+    chk(dalloc(&in.cgcol, R));
+    chk(dalloc(&in.cg_flags, 2));
+  }
   if (e != hipSuccess) return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PC_ERR_OOM : PC_ERR_DEVICE;
   if (hipMemcpy(in.qtiles, qt.data(), qt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
     return PC_ERR_DEVICE;
@@ -258,6 +267,50 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
   return PC_OK;
 }
 
+
+// CG on G y = b on the plan's KMp-row buffers of one instance.  On entry
+// in.Y holds the start (rows >= KM zero) when warm, b is read from Bm (KM
+// rows).  Runs at most maxiter iterations, checking every 8 whether every
+// column converged.  Returns the largest iteration count in *iters and
+// whether every column converged in *all_ok.
+pc_status run_cg(pc_plan* p, Inst& in, const double* Bm, int64_t ldB, int64_t R, bool warm, double tol,
+                 int maxiter, hipStream_t s, int* iters, bool* all_ok) {
+  const int64_t KMp = in.KMp, ld = KMp, T = KMp / pc::NB, mr = std::max<int64_t>(in.max_rhs, 1);
+  double* r = in.cg;
+  double* z = in.cg + ld * mr;
+  double* pv = in.cg + 2 * ld * mr;
+  double* q = in.cg + 3 * ld * mr;
+  PC_TRY(pc::launch_fill_int(in.cg_flags, 0, 1, s));
+  if (warm) PC_TRY(pc::launch_gram_matmul(in.Gs, KMp, in.Y, q, ld, R, s));
+  PC_TRY(pc::launch_cg_start(Bm, ldB, warm ? q : nullptr, r, in.Y, ld, ld, in.KM, KMp, R, tol, in.cgcol,
+                             in.cg_flags, s));
+  PC_TRY(pc::launch_bj_apply(in.Dinv, T, r, z, ld, R, s));
+  PC_TRY(pc::launch_cg_dir(r, z, pv, ld, KMp, R, in.cgcol, 1, s));
+  int ndone = 0;
+  for (int it = 1; it <= maxiter; ++it) {
+    PC_TRY(pc::launch_gram_matmul(in.Gs, KMp, pv, q, ld, R, s));
+    PC_TRY(pc::launch_cg_step(pv, q, in.Y, ld, r, ld, KMp, R, tol, in.cgcol, in.cg_flags, it, s));
+    if (it % 8 == 0 || it == maxiter) {
+      PC_TRY(hipMemcpyAsync(&ndone, in.cg_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+      PC_TRY(hipStreamSynchronize(s));
+      if (ndone >= R) break;
+    }
+    PC_TRY(pc::launch_bj_apply(in.Dinv, T, r, z, ld, R, s));
+    PC_TRY(pc::launch_cg_dir(r, z, pv, ld, KMp, R, in.cgcol, 0, s));
+  }
+  std::vector<pc::CgCol> cols((size_t)R);
+  PC_TRY(hipMemcpyAsync(cols.data(), in.cgcol, sizeof(pc::CgCol) * (size_t)R, hipMemcpyDeviceToHost, s));
+  PC_TRY(hipStreamSynchronize(s));
+  *iters = 0;
+  *all_ok = true;
+  for (const auto& c : cols) {
+    *iters = std::max(*iters, c.iters);
+    if (c.done != 1) *all_ok = false;
+  }
+  (void)p;
+  return PC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -286,8 +339,9 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   pc_options o{PC_PREC_FP64, 0, 1e-12, 0, 0};
   if (opt) o = *opt;
   if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16_REFINE || o.max_refine < 0 ||
-      o.reserved != 0 || !std::isfinite(o.tol))
+      (o.flags & ~PC_FLAG_KEEP_GRAM) != 0 || !std::isfinite(o.tol))
     return PC_ERR_INVALID_ARG;
+  if ((o.flags & PC_FLAG_KEEP_GRAM) && o.precision != PC_PREC_FP64) return PC_ERR_INVALID_ARG;
   if (o.tol <= 0) o.tol = 1e-12;
   for (int32_t i = 0; i < count; ++i) {
     const pc_instance& a = inst[i];
@@ -312,7 +366,7 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
     in.P = a.K * (a.K + 1) / 2;
     in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
     p->inst.push_back(in);
-    st = alloc_inst(p->inst.back(), o.precision);
+    st = alloc_inst(p->inst.back(), o.precision, o.flags);
     max_r = std::max<int64_t>(max_r, a.max_rhs);
   }
   (void)max_r;
@@ -381,6 +435,11 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     hipStream_t si = stream_for(p, i, s);
     pc_status st = assemble_one(p, in, si);
     if (st != PC_OK) return st;
+    if (in.Gs) {
+      PC_TRY(pc::launch_gram_symmetrize(in, in.Gs, si));
+      PC_TRY(pc::launch_fill_int(in.cg_flags, 0, 2, si));
+      PC_TRY(pc::launch_bj_setup(in.Gs, in.KMp, in.KMp / pc::NB, in.Dinv, in.cg_flags + 1, si));
+    }
     PhaseTimer t(p, PC_PHASE_CHOLESKY, si);
     PC_TRY(pc::launch_cholesky(in, si));
   }
@@ -538,6 +597,70 @@ pc_status pc_gram_export(const pc_plan* p, int32_t instance, double* G, int64_t 
   if (ldG < in.KM) return PC_ERR_INVALID_ARG;
   hipSetDevice(p->device);
   PC_TRY(pc::launch_export_lower(in.G, in.KMp, G, ldG, in.KM, (hipStream_t)stream));
+  return PC_OK;
+}
+
+pc_status pc_cg_solve(pc_plan* p, int32_t instance, const double* Bm, int64_t ldB, int64_t R, double* Y,
+                      int64_t ldY, double tol, int32_t maxiter, int32_t warm, int32_t* iterations, void* stream) {
+  if (iterations) *iterations = 0;
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || R < 0 || maxiter < 0 || !(tol >= 0.0))
+    return PC_ERR_INVALID_ARG;
+  Inst& in = p->inst[instance];
+  if (!in.Gs) return PC_ERR_INVALID_ARG;
+  if (!in.factored) return PC_ERR_NOT_FACTORED;
+  if (R == 0) return PC_OK;
+  if (R > in.max_rhs) return PC_ERR_TOO_MANY_RHS;
+  if (!Bm || !Y || ldB < in.KM || ldY < in.KM) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  PC_TRY(pc::launch_copy_rows(Y, ldY, in.Y, in.KMp, warm ? in.KM : 0, in.KMp, R, s));
+  int it = 0;
+  bool ok = false;
+  pc_status st = run_cg(p, in, Bm, ldB, R, warm != 0, tol, maxiter, s, &it, &ok);
+  if (st != PC_OK) return st;
+  PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y, ldY, in.KM, in.KM, R, s));
+  PC_TRY(hipStreamSynchronize(s));
+  if (iterations) *iterations = it;
+  return ok ? PC_OK : PC_ERR_NO_CONVERGENCE;
+}
+
+pc_status pc_learned_apply(pc_plan* p, int32_t instance, pc_mlp* mlp, const double* X, int64_t ldX, int64_t R,
+                           double* Y, int64_t ldY, double tol, int32_t maxiter, int32_t* iterations,
+                           int32_t* fallback, void* stream) {
+  if (iterations) *iterations = 0;
+  if (fallback) *fallback = 0;
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || R < 0 || maxiter < 0 || !(tol >= 0.0))
+    return PC_ERR_INVALID_ARG;
+  Inst& in = p->inst[instance];
+  if (!in.Gs) return PC_ERR_INVALID_ARG;
+  if (!in.factored) return PC_ERR_NOT_FACTORED;
+  if (R == 0) return PC_OK;
+  if (R > in.max_rhs) return PC_ERR_TOO_MANY_RHS;
+  if (!X || !Y || ldX < in.n || ldY < in.KM) return PC_ERR_INVALID_ARG;
+  if (mlp && (mlp->d != in.KM || R > mlp->max_batch)) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  // b = Z^T x into the plan's right-hand-side buffer
+  PC_TRY(pc::launch_ztx(in, X, ldX, R, in.B, in.KMp, s));
+  // start: the network's prediction, or zero
+  PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, in.Y, in.KMp, 0, in.KMp, R, s));
+  if (mlp) {
+    pc_status st = pc_mlp_warm_start(mlp, in.B, in.KMp, R, in.Y, in.KMp, s);
+    if (st != PC_OK) return st;
+  }
+  int it = 0;
+  bool ok = false;
+  pc_status st = run_cg(p, in, in.B, in.KMp, R, mlp != nullptr, tol, maxiter, s, &it, &ok);
+  if (st != PC_OK) return st;
+  if (!ok) {
+    // the direct solve replaces the iterate
+    PC_TRY(pc::launch_copy_rows(in.B, in.KMp, in.Y, in.KMp, in.KM, in.KMp, R, s));
+    PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R, in.D, in.KMp, s));
+    if (fallback) *fallback = 1;
+  }
+  PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y, ldY, in.KM, in.KM, R, s));
+  PC_TRY(hipStreamSynchronize(s));
+  if (iterations) *iterations = it;
   return PC_OK;
 }
 

@@ -1,0 +1,285 @@
+"""The learned warm start and CG on the normal equations, through the C-ABI:
+network forward, gradients and Adam against the float64 oracle, CG against
+the direct solve and the oracle's CG, and what a trained network saves."""
+import numpy as np
+import pytest
+
+import paper_2609_13327_amd as pc
+import workloads as wl
+from oracle import cg, lsq, mlp
+from tests.gpu_util import dev, empty, host, inst_dict
+
+pytestmark = pytest.mark.gpu
+
+# (d, h, batch): ragged tails in every dimension, a split contraction, and
+# shapes whose strides are not multiples of 4 (scalar loads)
+NET_SHAPES = [(300, 200, 37), (256, 128, 130), (15, 7, 5), (1000, 64, 260)]
+
+
+def _f32(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda:0")
+
+
+def _net(d, h, B, seed, operand):
+    import torch
+    W1, b1, W2, b2 = wl.mlp_init(d, h, seed, bias_scale=0.1)
+    rng = np.random.default_rng(seed + 1)
+    X = rng.standard_normal((B, d)).astype(np.float32)
+    T = rng.standard_normal((B, d)).astype(np.float32)
+    net = pc.Mlp(d, h, B, operand)
+    pc.pc_mlp_set_params(net.handle, _f32(W1), _f32(b1), _f32(W2), _f32(b2))
+    torch.cuda.synchronize()
+    params64 = [np.asarray(p, dtype=np.float64) for p in (W1, b1, W2, b2)]
+    return net, params64, X, T
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# Tolerances.  fp32 operands: each product is exact in fp32 MFMA and the
+# accumulation error is ~sqrt(K) u32 per output, far below 1e-4 normwise.
+# bf16 operands: every operand is rounded once (relative 2^-9), so a product
+# carries at most ~2^-8 relative error; the gradients pass three rounded
+# products in sequence, hence 3e-2 normwise.
+TOL = {pc.PC_MLP_FP32: 1e-4, pc.PC_MLP_BF16: 3e-2}
+
+
+@pytest.mark.parametrize("operand", [pc.PC_MLP_FP32, pc.PC_MLP_BF16])
+@pytest.mark.parametrize("shape", NET_SHAPES)
+def test_mlp_forward_matches_oracle(shape, operand):
+    import torch
+    d, h, B = shape
+    net, params, X, _ = _net(d, h, B, 100 + d, operand)
+    Y = torch.empty((B, d), dtype=torch.float32, device="cuda:0")
+    pc.pc_mlp_forward(net.handle, _f32(X), Y)
+    ref, _ = mlp.forward(params, X.astype(np.float64))
+    assert _rel(host(Y).astype(np.float64), ref) <= TOL[operand] / 3
+    net.close()
+
+
+@pytest.mark.parametrize("operand", [pc.PC_MLP_FP32, pc.PC_MLP_BF16])
+@pytest.mark.parametrize("shape", NET_SHAPES)
+def test_mlp_gradients_match_oracle(shape, operand):
+    import torch
+    d, h, B = shape
+    net, params, X, T = _net(d, h, B, 200 + d, operand)
+    outs = [torch.empty(1, dtype=torch.float32, device="cuda:0"),
+            torch.empty((h, d), dtype=torch.float32, device="cuda:0"),
+            torch.empty(h, dtype=torch.float32, device="cuda:0"),
+            torch.empty((d, h), dtype=torch.float32, device="cuda:0"),
+            torch.empty(d, dtype=torch.float32, device="cuda:0")]
+    pc.pc_mlp_gradients(net.handle, _f32(X), _f32(T), *outs)
+    X64, T64 = X.astype(np.float64), T.astype(np.float64)
+    Yr, cache = mlp.forward(params, X64)
+    grads = mlp.backward(params, cache, Yr, T64)
+    assert abs(float(host(outs[0])[0]) - mlp.loss(Yr, T64)) <= TOL[operand] * mlp.loss(Yr, T64)
+    for got, ref in zip(outs[1:], grads):
+        assert _rel(host(got).astype(np.float64), ref) <= TOL[operand], (got.shape, _rel(host(got), ref))
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    """One training step = the oracle's Adam applied to the library's own
+    gradients (so only the Adam arithmetic is compared), twice in a row."""
+    import torch
+    d, h, B = 300, 200, 37
+    net, params, X, T = _net(d, h, B, 7, pc.PC_MLP_FP32)
+    dX, dT = _f32(X), _f32(T)
+    shapes = [(h, d), (h,), (d, h), (d,)]
+    m = [np.zeros(s) for s in shapes]
+    v = [np.zeros(s) for s in shapes]
+    p = [q.copy() for q in params]
+    lr = 1e-3
+    for t in (1, 2):
+        g = [torch.empty(s, dtype=torch.float32, device="cuda:0") for s in shapes]
+        pc.pc_mlp_gradients(net.handle, dX, dT, torch.empty(1, dtype=torch.float32, device="cuda:0"), *g)
+        pc.pc_mlp_train_step(net.handle, dX, dT, lr)
+        got = [torch.empty(s, dtype=torch.float32, device="cuda:0") for s in shapes]
+        pc.pc_mlp_get_params(net.handle, *got)
+        torch.cuda.synchronize()
+        for i in range(4):
+            gi = host(g[i]).astype(np.float64)
+            p[i], m[i], v[i] = mlp.adam_step(p[i], gi, m[i], v[i], t, lr)
+            diff = np.abs(host(got[i]).astype(np.float64) - p[i])
+            assert np.all(diff <= 1e-6 * lr + 2e-7 * np.abs(p[i])), (t, i, diff.max())
+            p[i] = host(got[i]).astype(np.float64)   # continue from the library's fp32 state
+    net.close()
+
+
+def _cg_instance(seed=9):
+    """n = 288, K*M = 120: two 64-row blocks, the second ragged; kappa(Z) ~ 30."""
+    return wl.make_instance(12, 24, 5, 24, 24, 0.2, 0.5, seed)
+
+
+def _keep_plan(inst, **kw):
+    plan = pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_KEEP_GRAM, **kw)
+    plan.factor()
+    return plan
+
+
+def test_cg_matches_direct_solve_and_oracle_cg():
+    inst = _cg_instance()
+    plan = _keep_plan(inst)
+    B = empty(inst.KM, inst.R)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, dev(inst.X), B)
+    Y = empty(inst.KM, inst.R)
+    st, it = pc.pc_cg_solve(plan.handle, 0, B, Y, tol=1e-13, maxiter=1000)
+    assert st == pc.PC_OK
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    err = np.linalg.norm(host(Y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-9, err.max()
+    # the oracle's CG with the same preconditioner (64 x 64 diagonal blocks)
+    G = lsq.gram(inst.E, inst.W, 1)
+    pre = cg.block_jacobi_tiles(G, 64)
+    b = host(B)
+    its = [cg.pcg(G, b[:, r], precond=pre, tol=1e-13, maxiter=1000)[1] for r in range(inst.R)]
+    assert abs(it - max(its)) <= 2, (it, max(its))
+    plan.close()
+
+
+def test_cg_warm_start_at_solution_needs_no_iteration():
+    inst = _cg_instance(10)
+    plan = _keep_plan(inst)
+    B = empty(inst.KM, inst.R)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, dev(inst.X), B)
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    Y = dev(ref)
+    st, it = pc.pc_cg_solve(plan.handle, 0, B, Y, tol=1e-8, maxiter=50, warm=True)
+    assert st == pc.PC_OK and it == 0
+    assert np.array_equal(host(Y), ref)
+    plan.close()
+
+
+def test_cg_and_learned_apply_argument_checks():
+    inst = _cg_instance(11)
+    plain = pc.Plan([inst_dict(inst)])
+    plain.factor()
+    B = empty(inst.KM, inst.R)
+    st, _ = pc.pc_cg_solve(plain.handle, 0, B, B, 1e-10, 10, raise_on_error=False)
+    assert st == pc.PC_ERR_INVALID_ARG
+    plain.close()
+    with pytest.raises(pc.PcError) as e:
+        pc.Plan([inst_dict(inst)], precision=pc.PC_PREC_FP32_REFINE, max_refine=5, flags=pc.PC_FLAG_KEEP_GRAM)
+    assert e.value.status == pc.PC_ERR_INVALID_ARG
+    keep = pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_KEEP_GRAM)
+    st, _ = pc.pc_cg_solve(keep.handle, 0, B, B, 1e-10, 10, raise_on_error=False)
+    assert st == pc.PC_ERR_NOT_FACTORED
+    keep.factor()
+    net = pc.Mlp(inst.KM + 1, 8, inst.R)
+    with pytest.raises(pc.PcError) as e:
+        pc.pc_learned_apply(keep.handle, 0, net.handle, dev(inst.X), empty(inst.KM, inst.R), 1e-10, 10)
+    assert e.value.status == pc.PC_ERR_INVALID_ARG
+    net.close()
+    keep.close()
+
+
+def test_warm_start_and_training_pairs_match_oracle():
+    import torch
+    inst = _cg_instance(12)
+    d, h = inst.KM, 32
+    W1, b1, W2, b2 = wl.mlp_init(d, h, 5, bias_scale=0.05)
+    net = pc.Mlp(d, h, inst.R, pc.PC_MLP_FP32)
+    pc.pc_mlp_set_params(net.handle, _f32(W1), _f32(b1), _f32(W2), _f32(b2))
+    rng = np.random.default_rng(3)
+    Bn = rng.standard_normal((d, inst.R))
+    Bn[:, 3] = 0.0                                      # a zero column gives a zero start
+    Y0 = empty(d, inst.R)
+    pc.pc_mlp_warm_start(net.handle, dev(Bn), Y0)
+    nb = np.linalg.norm(Bn, axis=0)
+    safe = np.where(nb > 0, nb, 1.0)
+    params = [np.asarray(p, np.float64) for p in (W1, b1, W2, b2)]
+    Yr, _ = mlp.forward(params, (Bn / safe).T.astype(np.float32).astype(np.float64))
+    ref = (Yr * nb[:, None]).T
+    got = host(Y0)
+    assert np.all(got[:, 3] == 0.0)
+    keep = [r for r in range(inst.R) if r != 3]
+    assert _rel(got[:, keep], ref[:, keep]) <= 1e-4
+    # training pairs
+    Ysol = rng.standard_normal((d, inst.R))
+    X = torch.empty((inst.R, d), dtype=torch.float32, device="cuda:0")
+    T = torch.empty_like(X)
+    pc.pc_mlp_training_pairs(dev(Bn), dev(Ysol), X, T)
+    xr = (Bn / safe).T.astype(np.float32)
+    tr = (Ysol / safe).T.astype(np.float32)
+    tr[3, :] = 0.0                                      # b = 0: the pair is defined as zero
+    # one float rounding apart at most (the norm is summed in another order)
+    np.testing.assert_allclose(host(X), xr, rtol=2.4e-7, atol=1e-30)
+    np.testing.assert_allclose(host(T), tr, rtol=2.4e-7, atol=1e-30)
+    net.close()
+
+
+def _train_warm_start(inst, plan, h, n_train, steps, batch, lr, seed):
+    """Pairs (b, Z^+ x) from the direct solve on the GPU, then Adam steps."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    Xtr = torch.randn((n_train, inst.n), generator=g, dtype=torch.float64, device="cuda:0").t()
+    Btr = empty(inst.KM, n_train)
+    Ytr = empty(inst.KM, n_train)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, Xtr, Btr)
+    mr = inst.R
+    for c0 in range(0, n_train, mr):
+        c1 = min(n_train, c0 + mr)
+        plan.apply([Xtr[:, c0:c1]], [Ytr[:, c0:c1]])
+    Xin = torch.empty((n_train, inst.KM), dtype=torch.float32, device="cuda:0")
+    Tin = torch.empty_like(Xin)
+    pc.pc_mlp_training_pairs(Btr, Ytr, Xin, Tin)
+    W1, b1, W2, b2 = wl.mlp_init(inst.KM, h, seed + 1)
+    net = pc.Mlp(inst.KM, h, max(batch, inst.R), pc.PC_MLP_BF16)
+    pc.pc_mlp_set_params(net.handle, _f32(W1), _f32(b1), _f32(W2), _f32(b2))
+    loss = torch.empty(1, dtype=torch.float32, device="cuda:0")
+    losses = []
+    for s in range(steps):
+        r0 = (s * batch) % (n_train - batch + 1)
+        pc.pc_mlp_train_step(net.handle, Xin[r0:r0 + batch], Tin[r0:r0 + batch], lr, loss)
+        if s % 50 == 0 or s == steps - 1:
+            losses.append(float(loss.item()))
+    return net, losses
+
+
+def test_trained_network_saves_cg_iterations():
+    """Train the network on 4096 (b, Z^+ x) pairs from the direct solve, then
+    on held-out right-hand sides: the warm start is closer to the answer
+    than the zero start and CG needs fewer iterations; the answers match the
+    oracle either way."""
+    inst = wl.config(1, R=64)
+    plan = pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_KEEP_GRAM)
+    plan.factor()
+    net, losses = _train_warm_start(inst, plan, h=256, n_train=4096, steps=600, batch=128, lr=2e-3, seed=41)
+    assert losses[-1] < 0.5 * losses[0], losses
+    Xh = dev(inst.X)
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    tol = 1e-12
+    Y_cold = empty(inst.KM, inst.R)
+    it_cold, fb_cold = pc.pc_learned_apply(plan.handle, 0, None, Xh, Y_cold, tol, 500)
+    Y_warm = empty(inst.KM, inst.R)
+    it_warm, fb_warm = pc.pc_learned_apply(plan.handle, 0, net.handle, Xh, Y_warm, tol, 500)
+    for Y in (Y_cold, Y_warm):
+        err = np.linalg.norm(host(Y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert err.max() <= 1e-8, err.max()
+    assert fb_cold == 0 and fb_warm == 0
+    B = empty(inst.KM, inst.R)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, Xh, B)
+    Y0 = empty(inst.KM, inst.R)
+    pc.pc_mlp_warm_start(net.handle, B, Y0)
+    e0 = np.linalg.norm(host(Y0) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    print("losses", losses, "warm-start rel err median", np.median(e0), "CG iterations cold", it_cold,
+          "warm", it_warm)
+    assert np.median(e0) < 0.5
+    assert it_warm < it_cold
+    net.close()
+    plan.close()
+
+
+def test_learned_apply_falls_back_to_direct_solve():
+    inst = _cg_instance(13)
+    plan = _keep_plan(inst)
+    Y = empty(inst.KM, inst.R)
+    it, fb = pc.pc_learned_apply(plan.handle, 0, None, dev(inst.X), Y, 1e-14, 1)
+    assert fb == 1 and it == 1
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    err = np.linalg.norm(host(Y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-10
+    plan.close()

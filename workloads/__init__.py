@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "latlon_points", "circulant_spectrum", "grf_draws", "localization_modes",
-    "Instance", "make_instance", "config", "batched_config", "CONFIG_NAMES",
+    "Instance", "make_instance", "config", "batched_config", "CONFIG_NAMES", "mlp_init",
 ]
 
 
@@ -265,3 +265,16 @@ def batched_config(count: int = 64, seed: int = 3000, scale: float = 1.0) -> Lis
         insts.append(make_instance(n_lat, n_lon, K, M, p["R"], 0.05, 0.2, p["seed"],
                                    W=W, W_info=info))
     return insts
+
+
+def mlp_init(d: int, h: int, seed: int, bias_scale: float = 0.0):
+    """Seeded float32 starting parameters of the warm-start network:
+    W1 (h x d) ~ N(0, 1/d), b1 (h), W2 (d x h) ~ N(0, 1/h), b2 (d); biases
+    N(0, bias_scale^2) (zero by default)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = (rng.standard_normal((h, d)) / math.sqrt(d)).astype(np.float32)
+    b1 = (bias_scale * rng.standard_normal(h)).astype(np.float32)
+    W2 = (rng.standard_normal((d, h)) / math.sqrt(h)).astype(np.float32)
+    b2 = (bias_scale * rng.standard_normal(d)).astype(np.float32)
+    return W1, b1, W2, b2
+
