@@ -184,6 +184,28 @@ __device__ __forceinline__ void tile_store_lds(const TileRegs& t, double* S, dou
   for (int q = 0; q < 16; ++q) S[threadIdx.x + 256 * q] = scale * t.v[q];
 }
 
+// Accumulator tile -> LDS in a swizzled column-major layout (element (r, c)
+// at c * 64 + ((r + c) & 63): conflict-free both for the accumulator's
+// column-strided writes and for the column-contiguous reads below).
+__device__ __forceinline__ int sw64(int r, int c) { return c * T64 + ((r + c) & (T64 - 1)); }
+__device__ __forceinline__ void acc_to_lds_sw(const TileF64<T64, T64, 2, 2>& acc, double* S) {
+  acc.for_each([&](int r, int c, double v) { S[sw64(r, c)] = v; });
+}
+
+// Coherent, coalesced store of an LDS tile (swizzled layout) plus `add`
+// (registers in the tile_load order) to column-major M: each store
+// instruction of a wave writes 64 consecutive doubles of one column.
+// cols_valid limits the columns written; lower_only keeps r >= c.
+__device__ __forceinline__ void lds_sw_to_global(const double* S, const TileRegs* add, double* M, int64_t ld,
+                                                 int64_t r0, int64_t c0, int64_t cols_valid, bool lower_only) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+    const double v = S[sw64(r, c)] + (add ? add->v[q] : 0.0);
+    if (c < cols_valid && (!lower_only || r >= c)) st_c(&M[(r0 + r) + (c0 + c) * ld], v);
+  }
+}
+
 // ---- 16 x 16 MFMA fragments on LDS matrices stored row-major (M[r * ld + c]).
 // A operand A[r][k] = M[r0 + r][c0 + k]; transposed-B operand B[k][n] = M[r0 + n][c0 + k]
 // uses the same addressing; plain B operand B[k][n] = M[r0 + k][c0 + n].
@@ -233,18 +255,21 @@ __device__ __noinline__ void potrf_task(const CholArgs& a, int k, double* A, dou
     // the tile's last update, G_kk - L_{k,k-1} L_{k,k-1}^T, computed as
     // -(-G_kk + L L^T) with one operand buffer (Ops overlaps A's tail)
     TileF64<T64, T64, 2, 2> acc;
-    TileRegs tl;
-    tile_to_acc(a.G, a.ld, k0, k0, acc, T64);
-    tile_load(a.G, a.ld, k0, k0 - T64, tl);
+    TileRegs tl, tc;
+    tile_load(a.G, a.ld, k0, k0, tc);                 // G_kk (coalesced)
+    tile_load(a.G, a.ld, k0, k0 - T64, tl);           // L_{k,k-1}
     tile_store_lds(tl, Ops, 1.0);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc.acc[i][j] = -acc.acc[i][j];
     __syncthreads();
-    acc.template mma<T64, T64, T64>(Ops, Ops);
+    acc.zero();
+    acc.template mma<T64, T64, T64>(Ops, Ops);        // L L^T
     __syncthreads();
-    acc.for_each([&](int r, int c, double v) { A[r * LDP + c] = (r >= c) ? -v : 0.0; });
+    acc.for_each([&](int r, int c, double v) { A[r * LDP + c] = -v; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
+      A[r * LDP + c] = (r >= c) ? A[r * LDP + c] + tc.v[q] : 0.0;
+    }
   }
   if (t == 0) sh[1] = -1;
   __syncthreads();
@@ -389,18 +414,19 @@ __device__ __noinline__ void potrf_task(const CholArgs& a, int k, double* A, dou
 __device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, double* Bs) {
   const int64_t i0 = (int64_t)i * T64, j0 = (int64_t)j * T64, k0 = (int64_t)k * T64;
   TileF64<T64, T64, 2, 2> acc;
-  TileRegs ta, tb;
-  tile_to_acc(a.G, a.ld, i0, j0, acc, T64);          // C = G_ij       (all loads in flight)
+  TileRegs tc, ta, tb;
+  tile_load(a.G, a.ld, i0, j0, tc);                   // G_ij          (all loads in flight)
   tile_load(a.G, a.ld, i0, k0, ta);                   // L_ik
   tile_load(a.G, a.ld, j0, k0, tb);                   // L_jk
   tile_store_lds(ta, As, -1.0);
   tile_store_lds(tb, Bs, 1.0);
   __syncthreads();
-  acc.template mma<T64, T64, T64>(As, Bs);            // C - L_ik L_jk^T
-  const bool diag = i == j;
-  acc.for_each([&](int r, int c, double v) {
-    if (!diag || r >= c) st_c(&a.G[(i0 + r) + (j0 + c) * a.ld], v);
-  });
+  acc.zero();
+  acc.template mma<T64, T64, T64>(As, Bs);            // -L_ik L_jk^T
+  __syncthreads();
+  acc_to_lds_sw(acc, As);
+  __syncthreads();
+  lds_sw_to_global(As, &tc, a.G, a.ld, i0, j0, T64, i == j);   // G_ij - L_ik L_jk^T
 }
 
 // TRSM(i,k): for k >= 1 the tile's last update from column k-1 comes first
@@ -409,35 +435,39 @@ __device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, d
 // DAG was abandoned while waiting.
 __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* As, double* Bs, int* sh) {
   const int64_t i0 = (int64_t)i * T64, k0 = (int64_t)k * T64;
-  TileF64<T64, T64, 2, 2> upd;
+  TileRegs tc;
+  tile_load(a.G, a.ld, i0, k0, tc);                   // G_ik
   if (k >= 1) {
+    TileF64<T64, T64, 2, 2> upd;
     TileRegs ta, tb;
-    tile_to_acc(a.G, a.ld, i0, k0, upd, T64);         // G_ik
     tile_load(a.G, a.ld, i0, k0 - T64, ta);           // L_{i,k-1}
     tile_load(a.G, a.ld, k0, k0 - T64, tb);           // L_{k,k-1}
     tile_store_lds(ta, As, -1.0);
     tile_store_lds(tb, Bs, 1.0);
     __syncthreads();
-    upd.template mma<T64, T64, T64>(As, Bs);          // G_ik - L_{i,k-1} L_{k,k-1}^T
+    upd.zero();
+    upd.template mma<T64, T64, T64>(As, Bs);          // -L_{i,k-1} L_{k,k-1}^T
     __syncthreads();
+    upd.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) As[threadIdx.x + 256 * q] += tc.v[q];   // As[c][r] = updated G_ik
+  } else {
+    tile_store_lds(tc, As, 1.0);                      // As[c][r] = G[i0+r][k0+c]
   }
   if (!wait_ge(&a.state[(int64_t)k * a.T + k], k + 1, a.info, a.err, &sh[2])) return false;
   const double* Lb = a.Linv + (int64_t)k * T64 * T64;
   TileRegs tb;
   tile_load(Lb, T64, 0, 0, tb);                       // Bs[c][r] = Linv[r][c]
-  if (k >= 1) {
-    upd.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
-  } else {
-    TileRegs ta;
-    tile_load(a.G, a.ld, i0, k0, ta);                 // As[c][r] = G[i0+r][k0+c]
-    tile_store_lds(ta, As, 1.0);
-  }
   tile_store_lds(tb, Bs, 1.0);
   __syncthreads();
   TileF64<T64, T64, 2, 2> acc;
   acc.zero();
   acc.template mma<T64, T64, T64>(As, Bs);
-  acc.for_each([&](int r, int c, double v) { st_c(&a.G[(i0 + r) + (k0 + c) * a.ld], v); });
+  __syncthreads();
+  acc_to_lds_sw(acc, As);
+  __syncthreads();
+  lds_sw_to_global(As, nullptr, a.G, a.ld, i0, k0, T64, false);
   return true;
 }
 
@@ -499,7 +529,7 @@ struct SolveArgs {
   const int* skip;
 };
 
-__global__ __launch_bounds__(256, 2) void solve_dag_kernel(SolveArgs a) {
+__global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveArgs a) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
   __shared__ int sh[4];
@@ -579,9 +609,10 @@ __global__ __launch_bounds__(256, 2) void solve_dag_kernel(SolveArgs a) {
     TileF64<T64, T64, 2, 2> res;
     res.zero();
     res.template mma<T64, T64, T64>(As, Bs);
-    res.for_each([&](int r, int c, double v) {
-      if (r0 + c < a.R) st_c(&a.Out[(i0 + r) + (r0 + c) * a.ldOut], v);
-    });
+    __syncthreads();
+    acc_to_lds_sw(res, As);
+    __syncthreads();
+    lds_sw_to_global(As, nullptr, a.Out, a.ldOut, i0, r0, a.R - r0, false);
     publish(&a.flags[i * a.nrt + rt], 1);
     __syncthreads();
   }

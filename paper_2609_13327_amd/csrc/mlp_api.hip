@@ -27,10 +27,10 @@ hipError_t dalloc(T** p, int64_t count) {
 
 void free_mlp(pc_mlp* m) {
   if (!m) return;
-  hipDeviceSynchronize();
-  hipFree(m->params); hipFree(m->grads); hipFree(m->m); hipFree(m->v);
-  hipFree(m->Apre); hipFree(m->H); hipFree(m->Y); hipFree(m->dY); hipFree(m->dA);
-  hipFree(m->row_loss); hipFree(m->loss); hipFree(m->Xh); hipFree(m->nrm); hipFree(m->partial);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(m->params); (void)hipFree(m->grads); (void)hipFree(m->m); (void)hipFree(m->v);
+  (void)hipFree(m->Apre); (void)hipFree(m->H); (void)hipFree(m->Y); (void)hipFree(m->dY); (void)hipFree(m->dA);
+  (void)hipFree(m->row_loss); (void)hipFree(m->loss); (void)hipFree(m->Xh); (void)hipFree(m->nrm); (void)hipFree(m->partial);
   delete m;
 }
 
@@ -105,7 +105,7 @@ pc_status pc_mlp_create(int64_t d, int64_t h, int64_t max_batch, int32_t operand
   if (operand_type != PC_MLP_BF16 && operand_type != PC_MLP_FP32) return PC_ERR_INVALID_ARG;
   pc_mlp* m = new (std::nothrow) pc_mlp();
   if (!m) return PC_ERR_OOM;
-  hipGetDevice(&m->device);
+  (void)hipGetDevice(&m->device);
   m->d = d; m->h = h; m->max_batch = max_batch; m->bf16 = operand_type == PC_MLP_BF16;
   m->nparams = 2 * h * d + h + d;
   hipError_t e = hipSuccess;
@@ -145,7 +145,7 @@ pc_status pc_mlp_destroy(pc_mlp* m) {
 pc_status pc_mlp_set_params(pc_mlp* m, const float* w1, const float* bb1, const float* w2, const float* bb2,
                             void* stream) {
   if (!m || !w1 || !bb1 || !w2 || !bb2) return PC_ERR_INVALID_ARG;
-  hipSetDevice(m->device);
+  (void)hipSetDevice(m->device);
   hipStream_t s = (hipStream_t)stream;
   const int64_t d = m->d, h = m->h;
   PC_TRY(hipMemcpyAsync(W1(m), w1, sizeof(float) * (size_t)(h * d), hipMemcpyDeviceToDevice, s));
@@ -161,7 +161,7 @@ pc_status pc_mlp_set_params(pc_mlp* m, const float* w1, const float* bb1, const 
 pc_status pc_mlp_get_params(const pc_mlp* mc, float* w1, float* bb1, float* w2, float* bb2, void* stream) {
   if (!mc) return PC_ERR_INVALID_ARG;
   pc_mlp* m = const_cast<pc_mlp*>(mc);
-  hipSetDevice(m->device);
+  (void)hipSetDevice(m->device);
   hipStream_t s = (hipStream_t)stream;
   const int64_t d = m->d, h = m->h;
   if (w1) PC_TRY(hipMemcpyAsync(w1, W1(m), sizeof(float) * (size_t)(h * d), hipMemcpyDeviceToDevice, s));
@@ -173,14 +173,14 @@ pc_status pc_mlp_get_params(const pc_mlp* mc, float* w1, float* bb1, float* w2, 
 
 pc_status pc_mlp_forward(pc_mlp* m, const float* X, int64_t ldX, int64_t B, float* Y, int64_t ldY, void* stream) {
   if (!m || !batch_ok(m, X, ldX, B) || !Y || ldY < m->d) return PC_ERR_INVALID_ARG;
-  hipSetDevice(m->device);
+  (void)hipSetDevice(m->device);
   return forward(m, X, ldX, B, Y, ldY, (hipStream_t)stream);
 }
 
 pc_status pc_mlp_gradients(pc_mlp* m, const float* X, int64_t ldX, const float* T, int64_t ldT, int64_t B,
                            float* loss, float* dW1, float* db1, float* dW2, float* db2, void* stream) {
   if (!m || !batch_ok(m, X, ldX, B) || !T || ldT < m->d) return PC_ERR_INVALID_ARG;
-  hipSetDevice(m->device);
+  (void)hipSetDevice(m->device);
   hipStream_t s = (hipStream_t)stream;
   pc_status st = gradients(m, X, ldX, T, ldT, B, s);
   if (st != PC_OK) return st;
@@ -197,7 +197,7 @@ pc_status pc_mlp_gradients(pc_mlp* m, const float* X, int64_t ldX, const float* 
 pc_status pc_mlp_train_step(pc_mlp* m, const float* X, int64_t ldX, const float* T, int64_t ldT, int64_t B,
                             float lr, float* loss, void* stream) {
   if (!m || !batch_ok(m, X, ldX, B) || !T || ldT < m->d || !(lr > 0.f)) return PC_ERR_INVALID_ARG;
-  hipSetDevice(m->device);
+  (void)hipSetDevice(m->device);
   hipStream_t s = (hipStream_t)stream;
   pc_status st = gradients(m, X, ldX, T, ldT, B, s);
   if (st != PC_OK) return st;
@@ -221,7 +221,7 @@ pc_status pc_mlp_warm_start(pc_mlp* m, const double* B, int64_t ldB, int64_t R, 
                             void* stream) {
   if (!m || !B || !Y0 || ldB < m->d || ldY0 < m->d || R < 0 || R > m->max_batch) return PC_ERR_INVALID_ARG;
   if (R == 0) return PC_OK;
-  hipSetDevice(m->device);
+  (void)hipSetDevice(m->device);
   hipStream_t s = (hipStream_t)stream;
   const int64_t d = m->d;
   PC_TRY(pc::launch_ws_prep(B, ldB, d, R, m->Xh, d, m->nrm, s));
