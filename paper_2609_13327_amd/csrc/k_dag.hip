@@ -7,22 +7,26 @@
 // factorization of the diagonal tiles) is never held up by kernel launches.
 //
 // Cholesky tasks (T = KMp / 64 tile rows):
-//   POTRF(k)    factor the diagonal tile (blocked by 16, MFMA updates) and form
-//               its inverse; for k >= 1 it first applies the tile's last
-//               update G_kk -= L_{k,k-1} L_{k,k-1}^T itself
-//   TRSM(i,k)   L_ik = G_ik L_kk^{-T} (MFMA, with the inverse); for k >= 1 it
-//               first applies the tile's last update from column k-1
+//   DIAG(k)     the diagonal step: for k >= 1 first the panel tile below the
+//               previous diagonal, L_{k,k-1} = (G_{k,k-1} - L_{k,k-2}
+//               L_{k-1,k-2}^T) L_{k-1,k-1}^{-T}, then the last update of the
+//               diagonal tile G_kk -= L_{k,k-1} L_{k,k-1}^T, then its
+//               factorization (blocked by 16, MFMA updates) and inverse
+//   TRSM(i,k)   L_ik = (G_ik - L_{i,k-1} L_{k,k-1}^T) L_kk^{-T} for i >= k+2
+//               (MFMA, with the inverse; the update only when k >= 1)
 //   GEMM(i,j,k) G_ij -= L_ik L_jk^T for k <= j - 2 (the earlier updates)
-// Fusing a tile's last update into its POTRF/TRSM keeps the updated tile in
-// the same workgroup, so the critical path (update -> factor -> solve of the
-// next panel) crosses fewer workgroups.
-// Order (look-ahead of one step): POTRF(0), TRSM(*,0); then for every k:
-// POTRF(k+1), TRSM(*,k+1), then the non-final updates GEMM(i,j,k), j >= k+2.
+// Fusing a tile's last update into its TRSM/DIAG keeps the updated tile in
+// the same workgroup, and DIAG chains the whole diagonal step in one
+// workgroup, so the critical path crosses one workgroup hand-over per tile
+// row: DIAG(k) -> DIAG(k+1).  DIAG(k+1) loads and updates its operands before
+// it waits for DIAG(k)'s inverse.
+// Order (look-ahead of one step): DIAG(0); then for every k: DIAG(k+1),
+// TRSM(i,k) for i >= k+2, then the non-final updates GEMM(i,j,k), j >= k+2.
 // Every task appears after the tasks it needs, which makes the waits
 // deadlock-free: a waiting workgroup only waits for a task that another
 // running workgroup has already taken.
 // state[i*T + j] counts the updates applied to tile (i,j); it becomes j + 1
-// once the tile is final (after its TRSM, or its POTRF on the diagonal).
+// once the tile is final.
 //
 // Pivot test: d_j <= 64 * KM * 2^-53 * G_jj or a non-finite pivot marks Z as
 // numerically rank deficient (d_j / G_jj is the squared sine between column
@@ -94,17 +98,13 @@ __device__ __forceinline__ double rdlane(double x, int lane) {
   return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
 
-struct TaskDesc { int type, i, j, k; };   // type 0 POTRF(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
+struct TaskDesc { int type, i, j, k; };   // type 0 DIAG(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
 
 // t -> task in the order described above; offs[k] is the first index of
 // iteration k (k = 0..T-2) and offs[T-1] the task count.
 __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) {
   TaskDesc d{0, 0, 0, 0};
-  if (t < T) {
-    if (t == 0) { d.type = 0; d.i = d.j = d.k = 0; }
-    else { d.type = 1; d.i = (int)t; d.j = d.k = 0; }
-    return d;
-  }
+  if (t == 0) return d;                    // DIAG(0)
   int lo = 0, hi = T - 2;                  // largest k with offs[k] <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) / 2;
@@ -112,10 +112,10 @@ __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) 
   }
   const int k = lo;
   const int64_t u = t - offs[k];
-  const int m1 = T - k - 1;
+  const int m1 = T - k - 1;                // DIAG(k+1) and the T-k-2 TRSM(i,k)
   if (u < m1) {
     if (u == 0) { d.type = 0; d.i = d.j = d.k = k + 1; }
-    else { d.type = 1; d.i = k + 1 + (int)u; d.j = d.k = k + 1; }
+    else { d.type = 1; d.i = k + 1 + (int)u; d.j = d.k = k; }
     return d;
   }
   const int64_t w = u - m1;                // lower triangle (a >= b) of size T-k-2
@@ -236,41 +236,14 @@ __device__ __forceinline__ d4 fr_load(const double* M, int ld, int r0, int c0) {
 // updated with MFMA.  The inverse of the whole tile is then assembled block
 // by block: Y_pp = X_pp and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq, wave q
 // owning block column q.  LDS: A (64 x 65), X (4 x 16 x 16), scratch (4 x 256).
-__device__ __noinline__ void potrf_task(const CholArgs& a, int k, double* A, double* X, double* Sc, double* Ops, int* sh) {
+// Factor the 64 x 64 lower triangle held in A (LDS, row-major, stride LDP)
+// and form its inverse; publish the inverse (Linv) and the factor of tile
+// (k,k).  If pend_flag is set, the flag is published after the first panel
+// (the caller's coherent stores have completed by then).
+__device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, double* X, double* Sc, int* sh,
+                                         int* pend_flag, int pend_val) {
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int64_t k0 = (int64_t)k * T64;
-  if (k == 0) {
-    double v[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
-      v[q] = (r >= c) ? ld_c(&a.G[(k0 + r) + (k0 + c) * a.ld]) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
-      A[r * LDP + c] = v[q];
-    }
-  } else {
-    // the tile's last update, G_kk - L_{k,k-1} L_{k,k-1}^T, computed as
-    // -(-G_kk + L L^T) with one operand buffer (Ops overlaps A's tail)
-    TileF64<T64, T64, 2, 2> acc;
-    TileRegs tl, tc;
-    tile_load(a.G, a.ld, k0, k0, tc);                 // G_kk (coalesced)
-    tile_load(a.G, a.ld, k0, k0 - T64, tl);           // L_{k,k-1}
-    tile_store_lds(tl, Ops, 1.0);
-    __syncthreads();
-    acc.zero();
-    acc.template mma<T64, T64, T64>(Ops, Ops);        // L L^T
-    __syncthreads();
-    acc.for_each([&](int r, int c, double v) { A[r * LDP + c] = -v; });
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
-      A[r * LDP + c] = (r >= c) ? A[r * LDP + c] + tc.v[q] : 0.0;
-    }
-  }
   if (t == 0) sh[1] = -1;
   __syncthreads();
   const double thr_scale = 64.0 * (double)a.KM * 1.1102230246251565e-16;
@@ -358,7 +331,9 @@ __device__ __noinline__ void potrf_task(const CholArgs& a, int k, double* A, dou
         acc = mfma_f64(-fr_a(A, LDP, ri, c, kk), fr_a(A, LDP, rj, c, kk), acc);
       fr_store(A, LDP, ri, rj, acc);
     }
+    if (p == 0 && pend_flag) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (p == 0 && pend_flag && t == 0) st_release(pend_flag, pend_val);
   }
   // block inverse: wave q fills block column q.  The diagonal blocks are X;
   // an off-diagonal block Y_pq (p > q) is kept transposed in the unused upper
@@ -409,6 +384,95 @@ __device__ __noinline__ void potrf_task(const CholArgs& a, int k, double* A, dou
     const int idx = t + 256 * u, r = idx % T64, c = idx / T64;
     if (r >= c) a.G[(k0 + r) + (k0 + c) * a.ld] = A[r * LDP + c];
   }
+}
+
+// DIAG(0): the first diagonal tile as it is.
+__device__ __noinline__ void diag0_task(const CholArgs& a, double* A, double* X, double* Sc, int* sh) {
+  const int t = threadIdx.x;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
+    v[q] = (r >= c) ? ld_c(&a.G[r + c * a.ld]) : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
+    A[r * LDP + c] = v[q];
+  }
+  potrf_factor(a, 0, A, X, Sc, sh, nullptr, 0);
+}
+
+// DIAG(k), k >= 1 (see the top of the file).  Returns false if the DAG was
+// abandoned while waiting.  LDS: As, Bs (two 64 x 64 operands) and then the
+// factorization workspace over the same buffer.
+__device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, int* sh) {
+  double* As = buf;
+  double* Bs = buf + T64 * T64;
+  const int T = a.T;
+  const int64_t k0 = (int64_t)k * T64, p0 = k0 - T64;     // tile rows k and k-1
+  int* st = a.state;
+  // operands that are ready before the previous diagonal step ends
+  if (k >= 3 && !wait_ge(&st[k * T + k - 1], k - 2, a.info, a.err, &sh[2])) return false;
+  if (k >= 2) {
+    if (!wait_ge(&st[k * T + k - 2], k - 1, a.info, a.err, &sh[2])) return false;
+    if (!wait_ge(&st[(k - 1) * T + k - 2], k - 1, a.info, a.err, &sh[2])) return false;
+  }
+  TileRegs tp;                                          // G_{k,k-1}
+  tile_load(a.G, a.ld, k0, p0, tp);
+  if (k >= 2) {                                         // its last update, from column k-2
+    TileF64<T64, T64, 2, 2> upd;
+    TileRegs ta, tb;
+    tile_load(a.G, a.ld, k0, p0 - T64, ta);             // L_{k,k-2}
+    tile_load(a.G, a.ld, p0, p0 - T64, tb);             // L_{k-1,k-2}
+    tile_store_lds(ta, As, -1.0);
+    tile_store_lds(tb, Bs, 1.0);
+    __syncthreads();
+    upd.zero();
+    upd.template mma<T64, T64, T64>(As, Bs);
+    __syncthreads();
+    upd.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) As[threadIdx.x + 256 * q] += tp.v[q];
+  } else {
+    tile_store_lds(tp, As, 1.0);
+  }
+  if (k >= 2 && !wait_ge(&st[k * T + k], k - 1, a.info, a.err, &sh[2])) return false;
+  TileRegs td;                                          // G_kk, updated through column k-2
+  tile_load(a.G, a.ld, k0, k0, td);
+  // the previous diagonal step's inverse
+  if (!wait_ge(&st[(k - 1) * T + k - 1], k, a.info, a.err, &sh[2])) return false;
+  {
+    TileRegs tl;
+    tile_load(a.Linv + (int64_t)(k - 1) * T64 * T64, T64, 0, 0, tl);
+    tile_store_lds(tl, Bs, 1.0);
+  }
+  __syncthreads();
+  TileF64<T64, T64, 2, 2> acc;
+  acc.zero();
+  acc.template mma<T64, T64, T64>(As, Bs);              // L_{k,k-1}
+  __syncthreads();
+  acc.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {                        // L_{k,k-1} out (published later)
+    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+    st_c(&a.G[(k0 + r) + (p0 + c) * a.ld], As[idx]);
+  }
+  acc.zero();
+  acc.template mma<T64, T64, T64>(As, As);              // L_{k,k-1} L_{k,k-1}^T
+  __syncthreads();
+  double* A = buf;
+  acc.for_each([&](int r, int c, double v) { A[r * LDP + c] = -v; });
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+    A[r * LDP + c] = (r >= c) ? A[r * LDP + c] + td.v[q] : 0.0;
+  }
+  potrf_factor(a, k, A, buf + T64 * LDP, buf + T64 * LDP + 1024, sh, &st[k * T + k - 1], k);
+  return true;
 }
 
 __device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, double* Bs) {
@@ -488,12 +552,12 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholArgs a) {
     const TaskDesc d = decode_task(t, T, a.offs);
     int* st = a.state;
     if (d.type == 0) {
-      const int k = d.k;
-      if (k >= 1) {
-        if (!wait_ge(&st[k * T + k - 1], k, a.info, a.err, &sh[2])) continue;
-        if (!wait_ge(&st[k * T + k], k - 1, a.info, a.err, &sh[2])) continue;
-      }
-      potrf_task(a, k, buf, buf + T64 * LDP, buf + T64 * LDP + 1024, buf + T64 * T64, sh);
+      // the diagonal step is the critical path: its waves get the highest
+      // issue priority against the update tasks sharing the CU
+      __builtin_amdgcn_s_setprio(3);
+      if (d.k == 0) diag0_task(a, buf, buf + T64 * LDP, buf + T64 * LDP + 1024, sh);
+      else diag_task(a, d.k, buf, sh);
+      __builtin_amdgcn_s_setprio(0);
     } else if (d.type == 1) {
       const int i = d.i, k = d.k;
       if (k >= 1) {
@@ -501,7 +565,10 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholArgs a) {
         if (!wait_ge(&st[k * T + k - 1], k, a.info, a.err, &sh[2])) continue;
         if (!wait_ge(&st[i * T + k], k - 1, a.info, a.err, &sh[2])) continue;
       }
-      if (!trsm_task(a, i, k, As, Bs, sh)) continue;
+      __builtin_amdgcn_s_setprio(2);
+      const bool done = trsm_task(a, i, k, As, Bs, sh);
+      __builtin_amdgcn_s_setprio(0);
+      if (!done) continue;
       publish(&st[i * T + k], k + 1);
     } else {
       if (!wait_ge(&st[d.i * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
@@ -629,7 +696,7 @@ __global__ void dag_reset_kernel(int* p, int64_t count) {
 int check_chol_task_order(int T) {
   std::vector<int64_t> offs;
   const int64_t n = chol_task_offsets(T, offs);
-  int64_t expect = T;
+  int64_t expect = 1;
   for (int k = 0; k + 1 < T; ++k) expect += (int64_t)(T - k - 1) + (int64_t)(T - k - 2) * (T - k - 1) / 2;
   if (n != expect) return 1;
   std::vector<int> state((size_t)T * T, 0);      // as on the device: updates applied, j + 1 when final
@@ -637,15 +704,21 @@ int check_chol_task_order(int T) {
   for (int64_t t = 0; t < n; ++t) {
     const TaskDesc d = decode_task(t, T, offs.data());
     if (d.i < 0 || d.i >= T || d.j < 0 || d.j >= T || d.k < 0 || d.k >= T) return 2;
-    if (d.type == 0) {                            // POTRF(k), with the last update when k >= 1
+    if (d.type == 0) {                            // DIAG(k)
       const int k = d.k;
       if (d.i != k || d.j != k) return 3;
-      if (k >= 1 && (st(k, k - 1) < k || st(k, k) < k - 1)) return 3;
-      if (st(k, k) != (k >= 1 ? k - 1 : 0)) return 3;
+      if (k >= 1) {
+        // panel tile (k, k-1): every update but the last (from column k-2) applied
+        if (st(k, k - 1) != (k >= 2 ? k - 2 : 0)) return 3;
+        if (k >= 2 && (st(k, k - 2) < k - 1 || st(k - 1, k - 2) < k - 1)) return 3;
+        if (st(k - 1, k - 1) < k) return 3;       // previous diagonal step done
+        st(k, k - 1) = k;
+      }
+      if (st(k, k) != (k >= 1 ? k - 1 : 0)) return 3;   // diagonal tile: all but the last update
       st(k, k) = k + 1;
-    } else if (d.type == 1) {                     // TRSM(i,k), with the last update when k >= 1
+    } else if (d.type == 1) {                     // TRSM(i,k), i >= k+2, with the last update when k >= 1
       const int i = d.i, k = d.k;
-      if (i <= k || d.j != k) return 4;
+      if (i < k + 2 || d.j != k) return 4;
       if (k >= 1 && (st(i, k - 1) < k || st(k, k - 1) < k || st(i, k) < k - 1)) return 4;
       if (st(k, k) < k + 1) return 4;
       if (st(i, k) != (k >= 1 ? k - 1 : 0)) return 4;
@@ -675,7 +748,7 @@ static int persistent_grid(K kernel) {
 
 int64_t chol_task_offsets(int T, std::vector<int64_t>& offs) {
   offs.assign((size_t)std::max(T, 1), 0);
-  int64_t t = T;
+  int64_t t = 1;                                  // DIAG(0)
   for (int k = 0; k + 1 < T; ++k) {
     offs[k] = t;
     const int64_t m1 = T - k - 1, m2 = T - k - 2;
