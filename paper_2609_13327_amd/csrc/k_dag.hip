@@ -535,20 +535,52 @@ __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* 
   return true;
 }
 
-__global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholArgs a) {
-  // POTRF: tile (64 x 65) + X and scratch (2 x 4 x 256) = 6208 doubles;
+// A run of consecutive global task indices that belong to one instance of a
+// batch: global task gstart + u is that instance's task lstart + u.
+struct DagSeg { int64_t gstart, lstart; int inst, pad; };
+
+__device__ __forceinline__ int find_seg(const DagSeg* segs, int n, int64_t g) {
+  int lo = 0, hi = n - 1;                  // largest s with segs[s].gstart <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (segs[mid].gstart <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One instance (inst == null: `one`), or a batch whose instances' task lists
+// are interleaved by the segment table.
+struct CholBatch {
+  const CholArgs* inst; const DagSeg* segs; int nsegs;
+  CholArgs one;
+  int64_t ntasks; int* head; int* err;
+};
+
+__global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
+  // DIAG: tile (64 x 65) + X and scratch (2 x 4 x 256) = 6208 doubles;
   // TRSM/GEMM: two 64 x 64 operands = 8192 doubles
   __shared__ double buf[2 * T64 * T64];
   __shared__ int sh[4];
   double* As = buf;
   double* Bs = buf + T64 * T64;
-  const int T = a.T;
   for (;;) {
-    if (threadIdx.x == 0) sh[0] = atomicAdd(a.head, 1);
+    if (threadIdx.x == 0) sh[0] = atomicAdd(b.head, 1);
     __syncthreads();
-    const int64_t t = sh[0];
+    const int64_t g = sh[0];
     __syncthreads();
-    if (t >= a.ntasks) break;
+    if (g >= b.ntasks) break;
+    CholArgs a;
+    int64_t t;
+    if (b.inst) {
+      const DagSeg sg = b.segs[find_seg(b.segs, b.nsegs, g)];
+      a = b.inst[sg.inst];
+      t = sg.lstart + (g - sg.gstart);
+    } else {
+      a = b.one;
+      t = g;
+    }
+    a.err = b.err;
+    const int T = a.T;
     const TaskDesc d = decode_task(t, T, a.offs);
     int* st = a.state;
     if (d.type == 0) {
@@ -590,42 +622,66 @@ struct SolveArgs {
   const double* Linv;
   const double* In; int64_t ldIn;
   double* Out; int64_t ldOut;
-  int64_t R; int nrt;
-  int* flags; int* head; const int* info; int* err;
-  int backward;
+  int64_t R; const int64_t* Rp;   // right-hand sides: *Rp when Rp is set, else R
+  int nrt;                         // 64-column tiles per block row (task stride, >= ceil(R / 64))
+  int* flags; const int* info;
   const int* skip;
 };
 
-__global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveArgs a) {
+struct SolveBatch {
+  const SolveArgs* inst; const DagSeg* segs; int nsegs;
+  SolveArgs one;
+  int64_t ntasks; int* head; int* err;
+  int backward;
+  int swap_io;      // batch descriptors hold the forward pass: swap In/Out for the backward one
+};
+
+__global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
   __shared__ int sh[4];
-  if (a.skip && *a.skip) return;
-  const int64_t ntasks = (int64_t)a.T * a.nrt;
   for (;;) {
-    if (threadIdx.x == 0) sh[0] = atomicAdd(a.head, 1);
+    if (threadIdx.x == 0) sh[0] = atomicAdd(b.head, 1);
     __syncthreads();
-    const int64_t t = sh[0];
+    const int64_t g = sh[0];
     __syncthreads();
-    if (t >= ntasks) break;
+    if (g >= b.ntasks) break;
+    SolveArgs a;
+    int64_t t;
+    if (b.inst) {
+      const DagSeg sg = b.segs[find_seg(b.segs, b.nsegs, g)];
+      a = b.inst[sg.inst];
+      t = sg.lstart + (g - sg.gstart);
+    } else {
+      a = b.one;
+      t = g;
+    }
+    if (a.skip && *a.skip) continue;
+    if (a.Rp) a.R = *a.Rp;
+    if (b.swap_io && b.backward) {
+      const double* in_ = a.In; const int64_t ldi = a.ldIn;
+      a.In = a.Out; a.ldIn = a.ldOut;
+      a.Out = const_cast<double*>(in_); a.ldOut = ldi;
+    }
     const int step = (int)(t / a.nrt), rt = (int)(t % a.nrt);
-    const int i = a.backward ? a.T - 1 - step : step;
+    if ((int64_t)rt * T64 >= a.R) continue;            // beyond this call's right-hand sides
+    const int i = b.backward ? a.T - 1 - step : step;
     const int64_t i0 = (int64_t)i * T64, r0 = (int64_t)rt * T64;
     TileF64<T64, T64, 2, 2> acc;
     tile_to_acc(a.In, a.ldIn, i0, r0, acc, a.R - r0);    // acc = In[i block, rt]
     bool ok = true;
-    const int nprev = a.backward ? (a.T - 1 - i) : i;
+    const int nprev = b.backward ? (a.T - 1 - i) : i;
     for (int s = 0; s < nprev && ok; ++s) {
-      const int j = a.backward ? a.T - 1 - s : s;       // producers in their own order
+      const int j = b.backward ? a.T - 1 - s : s;       // producers in their own order
       const int64_t j0 = (int64_t)j * T64;
       // operand L block: forward L_ij (As[c][r] = L[i0+r][j0+c]); backward L_ji^T (As[c][r] = L[j0+c][i0+r])
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
-        if (!a.backward) As[q * T64 + p] = a.G[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
+        if (!b.backward) As[q * T64 + p] = a.G[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
         else As[p * T64 + q] = a.G[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
       }
-      if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, a.err, &sh[2])) { ok = false; break; }
+      if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) { ok = false; break; }
       {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -670,7 +726,7 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveArgs a) {
     for (int u = 0; u < 16; ++u) {
       const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
       // forward: As[k][row] = Linv[row][k]; backward: As[k][row] = Linv[k][row]
-      As[q * T64 + p] = a.backward ? Lb[q + p * T64] : Lb[p + q * T64];
+      As[q * T64 + p] = b.backward ? Lb[q + p * T64] : Lb[p + q * T64];
     }
     __syncthreads();
     TileF64<T64, T64, 2, 2> res;
@@ -758,18 +814,37 @@ int64_t chol_task_offsets(int T, std::vector<int64_t>& offs) {
   return t;
 }
 
+static CholArgs chol_args(const Inst& in) {
+  CholArgs a;
+  const int T = (int)(in.KMp / T64);
+  a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv;
+  a.state = in.dag; a.head = in.dag + (int64_t)T * T; a.err = a.head + 1; a.info = in.info;
+  a.offs = in.chol_offs; a.ntasks = in.chol_ntasks;
+  return a;
+}
+
 hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
   const int T = (int)(in.KMp / T64);
   // counters: state T*T, then head, err
   const int64_t nctr = (int64_t)T * T + 2;
   hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nctr, 256), 1024)), dim3(256),
                      0, s, in.dag, nctr);
-  CholArgs a;
-  a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv;
-  a.state = in.dag; a.head = in.dag + (int64_t)T * T; a.err = a.head + 1; a.info = in.info;
-  a.offs = in.chol_offs; a.ntasks = in.chol_ntasks;
-  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, a);
+  CholBatch b{};
+  b.one = chol_args(in);
+  b.ntasks = in.chol_ntasks; b.head = b.one.head; b.err = b.one.err;
+  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, b);
   return hipGetLastError();
+}
+
+static SolveArgs solve_args(const Inst& in, const double* In, double* Out, int64_t R, const int* skip) {
+  SolveArgs a;
+  const int T = (int)(in.KMp / T64);
+  a.G = in.G; a.ld = in.KMp; a.T = T; a.Linv = in.Linv;
+  a.In = In; a.ldIn = in.KMp; a.Out = Out; a.ldOut = in.KMp;
+  a.R = R; a.Rp = nullptr; a.nrt = in.nrt_max;
+  a.flags = in.dag + (int64_t)T * T + 2;               // T * nrt_max flags, then head
+  a.info = in.info; a.skip = skip;
+  return a;
 }
 
 // Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) holds the forward result.
@@ -777,22 +852,182 @@ hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, 
                              hipStream_t s, const int* skip) {
   if (R <= 0) return hipSuccess;
   const int T = (int)(in.KMp / T64);
-  const int nrt = (int)ceil_div(R, T64);
-  int* flags = in.dag + (int64_t)T * T + 2;           // T * nrt_max flags, then head
-  int* head = flags + (int64_t)T * in.nrt_max;
-  SolveArgs a;
-  a.G = in.G; a.ld = in.KMp; a.T = T; a.Linv = in.Linv; a.R = R; a.nrt = nrt;
-  a.flags = flags; a.head = head; a.info = in.info; a.err = in.dag + (int64_t)T * T + 1;
-  a.skip = skip;
+  SolveBatch b{};
+  b.one = solve_args(in, Y, Wk, R, skip);
+  b.one.ldIn = ldY; b.one.ldOut = ldW;
+  b.one.nrt = (int)ceil_div(R, T64);
+  b.ntasks = (int64_t)T * b.one.nrt;
+  b.head = b.one.flags + (int64_t)T * in.nrt_max;
+  b.err = in.dag + (int64_t)T * T + 1;
   const int64_t nflags = (int64_t)T * in.nrt_max + 1;
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), (int64_t)T * nrt);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), b.ntasks);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)),
-                       dim3(256), 0, s, flags, nflags);
-    a.backward = pass;
-    if (pass == 0) { a.In = Y; a.ldIn = ldY; a.Out = Wk; a.ldOut = ldW; }
-    else { a.In = Wk; a.ldIn = ldW; a.Out = Y; a.ldOut = ldY; }
-    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, a);
+                       dim3(256), 0, s, b.one.flags, nflags);
+    b.backward = pass;
+    if (pass == 1) {
+      b.one.In = Wk; b.one.ldIn = ldW; b.one.Out = Y; b.one.ldOut = ldY;
+    }
+    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, b);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batches
+// Every instance of a plan in one persistent launch: the instances' task
+// lists are interleaved round by round (the diagonal and panel tasks of a
+// step before its updates), largest instance first, and each instance keeps
+// its own order, so the waits stay deadlock-free.
+struct DagBatch {
+  int count = 0;
+  CholArgs* chol = nullptr; DagSeg* chol_segs = nullptr; int chol_nsegs = 0; int64_t chol_total = 0;
+  SolveArgs* solve[2] = {nullptr, nullptr};   // solve into Y (initial) or into D (refinement)
+  DagSeg* solve_segs = nullptr; int solve_nsegs = 0; int64_t solve_total = 0;
+  int64_t* R = nullptr;                        // right-hand sides of the current apply, per instance
+  int** rst_ptr = nullptr; int64_t* rst_cnt = nullptr;   // [0, count): Cholesky states, [count, 2 count): solve flags
+  int64_t rst_max[2] = {0, 0};
+  int* ctr = nullptr;                          // [0] Cholesky head, [1] error, [2] solve head
+};
+
+__global__ void batch_reset_kernel(int* const* ptrs, const int64_t* counts) {
+  int* p = ptrs[blockIdx.y];
+  const int64_t n = counts[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+struct RhsPack { int first, n; int64_t v[128]; };
+__global__ void set_rhs_kernel(int64_t* dst, RhsPack pk) {
+  if ((int)threadIdx.x < pk.n) dst[pk.first + threadIdx.x] = pk.v[threadIdx.x];
+}
+
+template <class T>
+static hipError_t upload(T** d, const std::vector<T>& h) {
+  *d = nullptr;
+  if (h.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)d, sizeof(T) * h.size());
+  if (e == hipSuccess) e = hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+void free_dag_batch(DagBatch* b) {
+  if (!b) return;
+  (void)hipFree(b->chol); (void)hipFree(b->chol_segs); (void)hipFree(b->solve[0]); (void)hipFree(b->solve[1]);
+  (void)hipFree(b->solve_segs); (void)hipFree(b->R); (void)hipFree(b->rst_ptr); (void)hipFree(b->rst_cnt);
+  (void)hipFree(b->ctr);
+  delete b;
+}
+
+DagBatch* make_dag_batch(const std::vector<Inst>& insts) {
+  DagBatch* b = new DagBatch();
+  const int n = (int)insts.size();
+  b->count = n;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return insts[x].KMp > insts[y].KMp; });
+  std::vector<CholArgs> ch(n);
+  std::vector<SolveArgs> sv0(n), sv1(n);
+  std::vector<std::vector<int64_t>> offs(n);
+  std::vector<int> Ts(n);
+  std::vector<int*> rp(2 * n);
+  std::vector<int64_t> rc(2 * n);
+  int maxT = 0;
+  hipError_t e = hipMalloc((void**)&b->R, sizeof(int64_t) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->ctr, sizeof(int) * 4);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const Inst& in = insts[i];
+    Ts[i] = (int)(in.KMp / T64);
+    maxT = std::max(maxT, Ts[i]);
+    chol_task_offsets(Ts[i], offs[i]);
+    ch[i] = chol_args(in);
+    sv0[i] = solve_args(in, in.Y, in.B, 0, nullptr);
+    sv1[i] = solve_args(in, in.D, in.B, 0, &in.ctl->done);
+    sv0[i].Rp = sv1[i].Rp = b->R + i;
+    rp[i] = in.dag;
+    rc[i] = (int64_t)Ts[i] * Ts[i];
+    rp[n + i] = sv0[i].flags;
+    rc[n + i] = (int64_t)Ts[i] * in.nrt_max;
+    b->rst_max[0] = std::max(b->rst_max[0], rc[i]);
+    b->rst_max[1] = std::max(b->rst_max[1], rc[n + i]);
+  }
+  // Cholesky segments
+  std::vector<DagSeg> cs;
+  int64_t g = 0;
+  auto add = [&](std::vector<DagSeg>& v, int inst, int64_t lstart, int64_t cnt) {
+    if (cnt <= 0) return;
+    v.push_back(DagSeg{g, lstart, inst, 0});
+    g += cnt;
+  };
+  for (int i : order) add(cs, i, 0, 1);                                      // DIAG(0)
+  for (int r = 0; r + 1 < maxT; ++r) {
+    for (int i : order)
+      if (r + 1 < Ts[i]) add(cs, i, offs[i][r], Ts[i] - r - 1);              // DIAG(r+1), TRSM(., r)
+    for (int i : order)
+      if (r + 1 < Ts[i]) {
+        const int64_t m2 = Ts[i] - r - 2;
+        add(cs, i, offs[i][r] + Ts[i] - r - 1, m2 * (m2 + 1) / 2);          // GEMM(., ., r)
+      }
+  }
+  b->chol_total = g;
+  b->chol_nsegs = (int)cs.size();
+  // solve segments: block row by block row, all column tiles of an instance together
+  std::vector<DagSeg> ss;
+  g = 0;
+  for (int st = 0; st < maxT; ++st)
+    for (int i : order)
+      if (st < Ts[i]) add(ss, i, (int64_t)st * insts[i].nrt_max, insts[i].nrt_max);
+  b->solve_total = g;
+  b->solve_nsegs = (int)ss.size();
+  if (e == hipSuccess) e = upload(&b->chol, ch);
+  if (e == hipSuccess) e = upload(&b->chol_segs, cs);
+  if (e == hipSuccess) e = upload(&b->solve[0], sv0);
+  if (e == hipSuccess) e = upload(&b->solve[1], sv1);
+  if (e == hipSuccess) e = upload(&b->solve_segs, ss);
+  if (e == hipSuccess) e = upload(&b->rst_ptr, rp);
+  if (e == hipSuccess) e = upload(&b->rst_cnt, rc);
+  if (e == hipSuccess) e = hipMemset(b->R, 0, sizeof(int64_t) * n);
+  if (e != hipSuccess) {
+    free_dag_batch(b);
+    return nullptr;
+  }
+  return b;
+}
+
+int* dag_batch_error(const DagBatch* b) { return b->ctr + 1; }
+
+hipError_t launch_cholesky_batch(const DagBatch* b, hipStream_t s) {
+  hipLaunchKernelGGL(dag_reset_kernel, dim3(1), dim3(64), 0, s, b->ctr, (int64_t)4);
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->rst_max[0], 256), 256));
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(gx, (unsigned)b->count), dim3(256), 0, s, b->rst_ptr, b->rst_cnt);
+  CholBatch cb{};
+  cb.inst = b->chol; cb.segs = b->chol_segs; cb.nsegs = b->chol_nsegs;
+  cb.ntasks = b->chol_total; cb.head = b->ctr; cb.err = b->ctr + 1;
+  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, cb);
+  return hipGetLastError();
+}
+
+hipError_t set_batch_rhs(const DagBatch* b, const int64_t* R, hipStream_t s) {
+  for (int first = 0; first < b->count; first += 128) {
+    RhsPack pk;
+    pk.first = first;
+    pk.n = std::min(128, b->count - first);
+    for (int i = 0; i < pk.n; ++i) pk.v[i] = R[first + i];
+    hipLaunchKernelGGL(set_rhs_kernel, dim3(1), dim3(128), 0, s, b->R, pk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s) {
+  SolveBatch sb{};
+  sb.inst = b->solve[refine ? 1 : 0]; sb.segs = b->solve_segs; sb.nsegs = b->solve_nsegs;
+  sb.ntasks = b->solve_total; sb.head = b->ctr + 2; sb.err = b->ctr + 1; sb.swap_io = 1;
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->rst_max[1], 256), 256));
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), b->solve_total);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(dag_reset_kernel, dim3(1), dim3(64), 0, s, b->ctr + 2, (int64_t)1);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(gx, (unsigned)b->count), dim3(256), 0, s, b->rst_ptr + b->count,
+                       b->rst_cnt + b->count);
+    sb.backward = pass;
+    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, sb);
   }
   return hipGetLastError();
 }

@@ -93,6 +93,17 @@ hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int6
                                int64_t n, hipStream_t s);
 hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
 int64_t chol_task_offsets(int T, std::vector<int64_t>& offs);
+// All instances of a plan in one persistent Cholesky launch and one pair of
+// solve launches (task lists interleaved, largest instance first).
+struct DagBatch;
+DagBatch* make_dag_batch(const std::vector<Inst>& insts);   // null on allocation failure
+void free_dag_batch(DagBatch* b);
+int* dag_batch_error(const DagBatch* b);                    // device int: a bounded wait expired
+hipError_t launch_cholesky_batch(const DagBatch* b, hipStream_t s);
+hipError_t set_batch_rhs(const DagBatch* b, const int64_t* R, hipStream_t s);   // R: host, one per instance
+// G^{-1} on the plan buffers of every instance: Y (refine = 0) or D (refine = 1, skipping
+// converged instances), with B as the work buffer
+hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s);
 int gram_split_for(const Inst& in);
 int check_chol_task_order(int T);
 

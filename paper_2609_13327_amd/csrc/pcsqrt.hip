@@ -38,6 +38,8 @@ struct pc_plan {
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[PC_NUM_PHASES];
   std::vector<hipEvent_t> pool;
+  // several instances: one persistent Cholesky launch and one solve pair for all
+  pc::DagBatch* batch = nullptr;
 };
 
 namespace {
@@ -80,6 +82,7 @@ void free_plan(pc_plan* p) {
   if (p->ev_fork) hipEventDestroy(p->ev_fork);
   for (auto e : p->ev_join) hipEventDestroy(e);
   hipFree(p->d_flag);
+  pc::free_dag_batch(p->batch);
   if (p->h_ctl) hipHostFree(p->h_ctl);
   delete p;
 }
@@ -211,8 +214,12 @@ pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
 // The apply sequence of every instance on the streams (no host wait when
 // check_every == 0; otherwise the host stops early once every instance's
 // refinement is done, checking every `check_every` iterations).
+pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                                double* const* Y, const int64_t* ldY, hipStream_t s, int check_every);
+
 pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
                         double* const* Y, const int64_t* ldY, hipStream_t s, int check_every) {
+  if (p->batch) return enqueue_apply_batched(p, X, ldX, R, Y, ldY, s, check_every);
   const size_t cnt = p->inst.size();
   const int budget = p->opt.max_refine;
   PC_TRY(fork(p, s));
@@ -249,6 +256,73 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
       }
       for (size_t i = 0; i < cnt; ++i)
         if (R[i] != 0) PC_TRY(hipStreamSynchronize(stream_for(p, i, s)));
+      for (size_t i = 0; i < cnt; ++i)
+        if (R[i] != 0 && p->h_ctl[i].done == 0) all = false;
+      if (all) break;
+    }
+  }
+  refine_timer.reset();
+  {
+    PhaseTimer copy_timer(p, PC_PHASE_COPYOUT, s);
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0) continue;
+      PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y[i], ldY[i], in.KM, in.KM, R[i], stream_for(p, i, s)));
+    }
+  }
+  PC_TRY(join(p, s));
+  return PC_OK;
+}
+
+
+// The apply sequence with every instance's solves in one batched launch pair:
+// per-instance products on the internal streams, joined before each solve.
+pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                                double* const* Y, const int64_t* ldY, hipStream_t s, int check_every) {
+  const size_t cnt = p->inst.size();
+  const int budget = p->opt.max_refine;
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < cnt; ++i) {
+    Inst& in = p->inst[i];
+    if (R[i] == 0) continue;
+    hipStream_t si = stream_for(p, i, s);
+    PhaseTimer t(p, PC_PHASE_ZTX, si);
+    PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si));
+  }
+  PC_TRY(join(p, s));
+  PC_TRY(pc::set_batch_rhs(p->batch, R, s));
+  { PhaseTimer t(p, PC_PHASE_SOLVE, s); PC_TRY(pc::launch_chol_solve_batch(p->batch, 0, s)); }
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < cnt; ++i)
+    if (R[i] != 0) PC_TRY(pc::launch_refine_init(p->inst[i].ctl, budget, stream_for(p, i, s)));
+  std::unique_ptr<PhaseTimer> refine_timer;
+  if (budget > 0) refine_timer.reset(new PhaseTimer(p, PC_PHASE_REFINE, s));
+  for (int it = 1; it <= budget; ++it) {
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0) continue;
+      hipStream_t si = stream_for(p, i, s);
+      const int* skip = &in.ctl->done;
+      PC_TRY(pc::launch_zy(in, in.Y, in.KMp, R[i], X[i], ldX[i], in.Rres, in.n, si, skip));
+      PC_TRY(pc::launch_ztx(in, in.Rres, in.n, R[i], in.D, in.KMp, si, skip));
+    }
+    PC_TRY(join(p, s));
+    PC_TRY(pc::launch_chol_solve_batch(p->batch, 1, s));
+    PC_TRY(fork(p, s));
+    for (size_t i = 0; i < cnt; ++i) {
+      Inst& in = p->inst[i];
+      if (R[i] == 0) continue;
+      hipStream_t si = stream_for(p, i, s);
+      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.ctl, si));
+      PC_TRY(pc::launch_refine_check(in.ctl, p->opt.tol, kStallAccept, si));
+    }
+    if (check_every > 0 && it % check_every == 0 && it < budget) {
+      for (size_t i = 0; i < cnt; ++i)
+        if (R[i] != 0)
+          PC_TRY(hipMemcpyAsync(&p->h_ctl[i], p->inst[i].ctl, sizeof(pc::RefineCtl), hipMemcpyDeviceToHost,
+                                stream_for(p, i, s)));
+      for (size_t j = 0; j < p->aux.size(); ++j) PC_TRY(hipStreamSynchronize(p->aux[j]));
+      bool all = true;
       for (size_t i = 0; i < cnt; ++i)
         if (R[i] != 0 && p->h_ctl[i].done == 0) all = false;
       if (all) break;
@@ -387,6 +461,7 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   }
   if (st == PC_OK && o.use_graph && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
     st = PC_ERR_DEVICE;
+  if (st == PC_OK && count > 1 && !(p->batch = pc::make_dag_batch(p->inst))) st = PC_ERR_OOM;
   if (st == PC_OK) {
     // finiteness of E and W, then the pair tables
     int bad = 0;
@@ -440,16 +515,23 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
       PC_TRY(pc::launch_fill_int(in.cg_flags, 0, 2, si));
       PC_TRY(pc::launch_bj_setup(in.Gs, in.KMp, in.KMp / pc::NB, in.Dinv, in.cg_flags + 1, si));
     }
-    PhaseTimer t(p, PC_PHASE_CHOLESKY, si);
-    PC_TRY(pc::launch_cholesky(in, si));
+    if (!p->batch) {
+      PhaseTimer t(p, PC_PHASE_CHOLESKY, si);
+      PC_TRY(pc::launch_cholesky(in, si));
+    }
   }
   PC_TRY(join(p, s));
+  if (p->batch) {
+    PhaseTimer t(p, PC_PHASE_CHOLESKY, s);
+    PC_TRY(pc::launch_cholesky_batch(p->batch, s));
+  }
   std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
   for (size_t i = 0; i < p->inst.size(); ++i) {
     const Inst& in = p->inst[i];
     const int64_t T = in.KMp / pc::NB;
     PC_TRY(hipMemcpyAsync(&infos[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
-    PC_TRY(hipMemcpyAsync(&errs[i], in.dag + T * T + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    PC_TRY(hipMemcpyAsync(&errs[i], p->batch ? pc::dag_batch_error(p->batch) : in.dag + T * T + 1, sizeof(int),
+                          hipMemcpyDeviceToHost, s));
   }
   PC_TRY(hipStreamSynchronize(s));
   for (size_t i = 0; i < p->inst.size(); ++i)
