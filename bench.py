@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"],
                     help="default: fp64 for configs 1-2, fp32 for config 3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--tune-cache", default=None, help="tuning cache file (read and updated)")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
@@ -158,6 +160,10 @@ def main():
         plan = pc.Plan([{"E": e, "W": w, "n_w": 1, "max_rhs": i.R} for e, w, i in zip(dE, dW, insts)],
                        precision=code, max_refine=refine, tol=1e-10 if refine else 0.0,
                        use_graph=use_graph)
+        tuning = None
+        if not args.no_tune:   # launch shapes, measured on this plan before timing (like an FFT plan)
+            pc.pc_autotune(plan.handle, args.tune_cache, True)
+            tuning = sorted({pc.pc_query_tuning(plan.handle, k) for k in range(len(insts))})
         for _ in range(warmup):
             plan.factor()
             plan.apply(dX, dY)
@@ -205,7 +211,7 @@ def main():
         return {"ms_per_step": ms, "rhs_per_s": total_rhs / (ms * 1e-3),
                 "apply_only_rhs_per_s": total_rhs / ((tb - ta) / napply),
                 "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
-                "kernels": kernels,
+                "kernels": kernels, "tuning": tuning,
                 "refine_iters_max": max(it for it, _ in info), "Y": Y}
 
     log(f"timing {prec_main}: {args.warmup} warmup + {args.steps} steps")
@@ -305,6 +311,7 @@ def main():
         "rel_err_median": err[1] if err else None,
         "apply_only_rhs_per_s": main_res["apply_only_rhs_per_s"],
         "refine_iters_max": main_res["refine_iters_max"],
+        "tuning": {"shapes (gram_split, ztx_split, chol_wgs_per_cu)": main_res["tuning"]},
         "kernels": kern,
         "phases_ms_per_step": main_res["phases_ms_per_step"],
         "variants": variants,

@@ -166,6 +166,36 @@ pc_status pc_gram_export(const pc_plan *plan, int32_t instance, double *G, int64
                          void *stream);
 
 /* ------------------------------------------------------------------------
+ * Autotuning of launch shapes.
+ * ---------------------------------------------------------------------- */
+
+/* pc_autotune — for every instance, time the candidate launch shapes on the
+ * plan's own data and keep the fastest: the FP64 Gram's contraction split
+ * (1 or 2 parts), the Z^T x contraction split (1 or 2) and the persistent
+ * Cholesky grid (1 or 2 workgroups per compute unit; one choice for a plan
+ * with several instances, whose factorization is one launch).  Choices are
+ * kept in the plan.  cache_path (host string, may be NULL) names a text file
+ * of earlier results keyed by (n_h, n_w, K, M, max_rhs, precision): with
+ * use_cached != 0 an instance found there is not measured; new results are
+ * merged into the file.  Runs the Gram and the factorization several times,
+ * so the plan is left unfactored: call pc_gram_factor afterwards.
+ * Synchronous.  Returns PC_ERR_INVALID_ARG if the cache file cannot be
+ * written. */
+pc_status pc_autotune(pc_plan *plan, const char *cache_path, int32_t use_cached, void *stream);
+
+/* pc_set_tuning — set the launch shapes of instance `instance` by hand
+ * (values as pc_query_tuning reports them; 0 = heuristic).  chol_per_cu
+ * applies to every instance of a plan with several instances.  The plan is
+ * left unfactored.  Returns PC_ERR_INVALID_ARG for values outside 0..2. */
+pc_status pc_set_tuning(pc_plan *plan, int32_t instance, int32_t gram_split, int32_t ztx_split,
+                        int32_t chol_per_cu);
+
+/* pc_query_tuning — the launch shapes in use for instance `instance`
+ * (0 = built-in heuristic, not tuned).  Output pointers may be NULL. */
+pc_status pc_query_tuning(const pc_plan *plan, int32_t instance, int32_t *gram_split,
+                          int32_t *ztx_split, int32_t *chol_per_cu);
+
+/* ------------------------------------------------------------------------
  * Per-phase timing (HIP events recorded on the caller's stream).
  * ---------------------------------------------------------------------- */
 

@@ -43,7 +43,8 @@ EXPORTED = [
     "pc_gram_assemble", "pc_gram_export", "pc_profile_enable", "pc_profile_read",
     "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
-    "pc_learned_apply", "pc_mlp_training_pairs",
+    "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
+    "pc_set_tuning",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout"]
@@ -114,6 +115,9 @@ def load_library(path: str = LIB_PATH):
     lib.pc_mlp_warm_start.argtypes = [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p]
     lib.pc_mlp_training_pairs.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_void_p,
                                           c_int64, c_void_p, c_int64, c_void_p]
+    lib.pc_autotune.argtypes = [c_void_p, ctypes.c_char_p, c_int32, c_void_p]
+    lib.pc_set_tuning.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32]
+    lib.pc_query_tuning.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
     lib.pc_learned_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                      c_double, c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p]
     for name in EXPORTED:
@@ -365,6 +369,25 @@ def pc_mlp_training_pairs(B, Y, X, T, stream=None):
     _check(load_library().pc_mlp_training_pairs(_ptr(B), _ld(B), _ptr(Y), _ld(Y), int(B.shape[0]), int(B.shape[1]),
                                                 _fptr(X), _rows(X), _fptr(T), _rows(T), c_void_p(_stream(stream))),
            "pc_mlp_training_pairs")
+
+
+def pc_autotune(plan: int, cache_path: Optional[str] = None, use_cached: bool = True, stream=None):
+    path = cache_path.encode() if cache_path else None
+    _check(load_library().pc_autotune(c_void_p(plan), path, int(bool(use_cached)), c_void_p(_stream(stream))),
+           "pc_autotune")
+
+
+def pc_set_tuning(plan: int, instance: int, gram_split: int, ztx_split: int, chol_per_cu: int):
+    _check(load_library().pc_set_tuning(c_void_p(plan), int(instance), int(gram_split), int(ztx_split),
+                                        int(chol_per_cu)), "pc_set_tuning")
+
+
+def pc_query_tuning(plan: int, instance: int = 0):
+    """(gram_split, ztx_split, chol_per_cu) of an instance (0 = heuristic)."""
+    g, z, c = c_int32(0), c_int32(0), c_int32(0)
+    _check(load_library().pc_query_tuning(c_void_p(plan), int(instance), ctypes.byref(g), ctypes.byref(z),
+                                          ctypes.byref(c)), "pc_query_tuning")
+    return g.value, z.value, c.value
 
 
 # -------------------------------------------------------------- convenience

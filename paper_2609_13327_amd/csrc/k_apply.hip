@@ -247,6 +247,7 @@ static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t
   if (cus <= 0) cus = 256;
   const int64_t ntiles = (int64_t)a.ntr * a.ntm * in.K;
   a.split = (ntiles < 2 * (int64_t)cus && in.n_h >= 4 * ZKC) ? 2 : 1;
+  if (in.tune_ztx_split == 1 || (in.tune_ztx_split == 2 && in.n_h >= 2 * ZKC)) a.split = in.tune_ztx_split;
   a.jlen = round_up(ceil_div(in.n_h, a.split), ZKC);
   if (a.split == 2) {
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(in.KM, 256), 64);

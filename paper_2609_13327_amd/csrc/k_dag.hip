@@ -791,14 +791,16 @@ int check_chol_task_order(int T) {
   return 0;
 }
 
-// Workgroups that fit on the device at once for `kernel` (at least one per CU).
+// Workgroups that fit on the device at once for `kernel` (at least one per
+// CU), optionally capped at `want` per CU.
 template <typename K>
-static int persistent_grid(K kernel) {
+static int persistent_grid(K kernel, int want = 0) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
+  if (want > 0 && want < per_cu) per_cu = want;
   return (cus > 0 ? cus : 256) * per_cu;
 }
 
@@ -832,7 +834,8 @@ hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
   CholBatch b{};
   b.one = chol_args(in);
   b.ntasks = in.chol_ntasks; b.head = b.one.head; b.err = b.one.err;
-  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel, in.tune_chol_per_cu)), dim3(256),
+                     0, s, b);
   return hipGetLastError();
 }
 
@@ -994,14 +997,14 @@ DagBatch* make_dag_batch(const std::vector<Inst>& insts) {
 
 int* dag_batch_error(const DagBatch* b) { return b->ctr + 1; }
 
-hipError_t launch_cholesky_batch(const DagBatch* b, hipStream_t s) {
+hipError_t launch_cholesky_batch(const DagBatch* b, hipStream_t s, int per_cu) {
   hipLaunchKernelGGL(dag_reset_kernel, dim3(1), dim3(64), 0, s, b->ctr, (int64_t)4);
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->rst_max[0], 256), 256));
   hipLaunchKernelGGL(batch_reset_kernel, dim3(gx, (unsigned)b->count), dim3(256), 0, s, b->rst_ptr, b->rst_cnt);
   CholBatch cb{};
   cb.inst = b->chol; cb.segs = b->chol_segs; cb.nsegs = b->chol_nsegs;
   cb.ntasks = b->chol_total; cb.head = b->ctr; cb.err = b->ctr + 1;
-  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, cb);
+  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel, per_cu)), dim3(256), 0, s, cb);
   return hipGetLastError();
 }
 

@@ -228,9 +228,9 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
   a.n_h = in.n_h; a.M = in.M; a.P = in.P;
   a.pairs = in.pairs; a.qtiles = in.qtiles;
   a.npt = (int)ceil_div(in.P, GB); a.nq = in.nq; a.ntiles = a.npt * a.nq;
-  a.split = (in.G2 != nullptr) ? 2 : 1;
+  a.split = (in.G2 != nullptr && in.tune_gram_split != 1) ? 2 : 1;
   a.jlen = round_up(ceil_div(in.n_h, a.split), GKC);
-  a.G = in.G; a.G2 = in.G2; a.ldG = in.KMp;
+  a.G = in.G; a.G2 = a.split == 2 ? in.G2 : nullptr; a.ldG = in.KMp;
   const int64_t units = (int64_t)a.ntiles * a.split;
   const int64_t grid = 8 * ((units + 7) / 8);
   hipLaunchKernelGGL(gram_f64_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
@@ -256,7 +256,7 @@ __global__ void gram_pad_diag_kernel(double* G, const double* G2, int64_t ld, in
 
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s) {
   hipLaunchKernelGGL(gram_pad_diag_kernel, dim3((unsigned)in.KMp), dim3(256), 0, s, in.G,
-                     (const double*)in.G2, in.KMp, in.KM, in.KMp, in.diag0);
+                     (const double*)(in.tune_gram_split != 1 ? in.G2 : nullptr), in.KMp, in.KM, in.KMp, in.diag0);
   return hipGetLastError();
 }
 

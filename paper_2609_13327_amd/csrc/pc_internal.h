@@ -57,6 +57,10 @@ struct Inst {
   double* cg = nullptr;      // four KMp x max_rhs buffers: r, z, p, q
   struct CgCol* cgcol = nullptr;
   int* cg_flags = nullptr;   // [0] converged columns, [1] block-Jacobi pivot failure
+  // launch-shape choices of the autotuner (0: built-in heuristic)
+  int tune_gram_split = 0;   // FP64 Gram: 1 or 2 contraction parts
+  int tune_ztx_split = 0;    // Z^T x: 1 or 2 contraction parts
+  int tune_chol_per_cu = 0;  // Cholesky DAG: persistent workgroups per compute unit (1 or 2)
   bool factored = false;
   int iters = 0;
   double last_rel = 0.0;
@@ -99,7 +103,7 @@ struct DagBatch;
 DagBatch* make_dag_batch(const std::vector<Inst>& insts);   // null on allocation failure
 void free_dag_batch(DagBatch* b);
 int* dag_batch_error(const DagBatch* b);                    // device int: a bounded wait expired
-hipError_t launch_cholesky_batch(const DagBatch* b, hipStream_t s);
+hipError_t launch_cholesky_batch(const DagBatch* b, hipStream_t s, int per_cu = 0);
 hipError_t set_batch_rhs(const DagBatch* b, const int64_t* R, hipStream_t s);   // R: host, one per instance
 // G^{-1} on the plan buffers of every instance: Y (refine = 0) or D (refine = 1, skipping
 // converged instances), with B as the work buffer

@@ -6,8 +6,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <memory>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "pc_internal.h"
@@ -385,6 +387,76 @@ pc_status run_cg(pc_plan* p, Inst& in, const double* Bm, int64_t ldB, int64_t R,
   return PC_OK;
 }
 
+
+// ------------------------------------------------------------- autotuning
+// Tuning cache: a text file with one line per instance shape,
+//   n_h n_w K M max_rhs precision  gram_split ztx_split chol_per_cu
+// after a first line naming the format.
+const char* kTuneHeader = "pcsqrt-tune-v1";
+
+struct TuneKey {
+  int64_t n_h, n_w, K, M, rhs;
+  int prec;
+  bool operator==(const TuneKey& o) const {
+    return n_h == o.n_h && n_w == o.n_w && K == o.K && M == o.M && rhs == o.rhs && prec == o.prec;
+  }
+};
+struct TuneEntry { TuneKey key; int gram_split, ztx_split, chol_per_cu; };
+
+std::vector<TuneEntry> read_tune_cache(const char* path) {
+  std::vector<TuneEntry> v;
+  if (!path) return v;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return v;
+  char head[64] = {0};
+  if (std::fscanf(f, "%63s", head) == 1 && std::string(head) == kTuneHeader) {
+    TuneEntry e;
+    long long a, b, c, d, r;
+    int pr, g, z, ch;
+    while (std::fscanf(f, "%lld %lld %lld %lld %lld %d %d %d %d", &a, &b, &c, &d, &r, &pr, &g, &z, &ch) == 9) {
+      e.key = TuneKey{a, b, c, d, r, pr};
+      e.gram_split = g; e.ztx_split = z; e.chol_per_cu = ch;
+      v.push_back(e);
+    }
+  }
+  std::fclose(f);
+  return v;
+}
+
+bool write_tune_cache(const char* path, const std::vector<TuneEntry>& v) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "%s\n", kTuneHeader);
+  for (const auto& e : v)
+    std::fprintf(f, "%lld %lld %lld %lld %lld %d %d %d %d\n", (long long)e.key.n_h, (long long)e.key.n_w,
+                 (long long)e.key.K, (long long)e.key.M, (long long)e.key.rhs, e.key.prec, e.gram_split, e.ztx_split,
+                 e.chol_per_cu);
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// Mean milliseconds of `reps` runs of fn on stream s (after one untimed run
+// when `warm`).
+template <class F>
+pc_status time_ms(hipStream_t s, int reps, F&& fn, float* out, bool warm = true) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return PC_ERR_DEVICE;
+  pc_status st = warm ? fn() : PC_OK;
+  float total = 0.f;
+  for (int r = 0; r < reps && st == PC_OK; ++r) {
+    if (hipEventRecord(a, s) != hipSuccess) st = PC_ERR_DEVICE;
+    if (st == PC_OK) st = fn();
+    if (st == PC_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess)) st = PC_ERR_DEVICE;
+    float ms = 0.f;
+    if (st == PC_OK && hipEventElapsedTime(&ms, a, b) != hipSuccess) st = PC_ERR_DEVICE;
+    total += ms;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *out = total / (float)std::max(reps, 1);
+  return st;
+}
 }  // namespace
 
 extern "C" {
@@ -523,7 +595,7 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
   PC_TRY(join(p, s));
   if (p->batch) {
     PhaseTimer t(p, PC_PHASE_CHOLESKY, s);
-    PC_TRY(pc::launch_cholesky_batch(p->batch, s));
+    PC_TRY(pc::launch_cholesky_batch(p->batch, s, p->inst[0].tune_chol_per_cu));
   }
   std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
   for (size_t i = 0; i < p->inst.size(); ++i) {
@@ -743,6 +815,164 @@ pc_status pc_learned_apply(pc_plan* p, int32_t instance, pc_mlp* mlp, const doub
   PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y, ldY, in.KM, in.KM, R, s));
   PC_TRY(hipStreamSynchronize(s));
   if (iterations) *iterations = it;
+  return PC_OK;
+}
+
+pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, void* stream) {
+  if (!p) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<TuneEntry> cache = read_tune_cache(cache_path);
+  const int prec = p->opt.precision;
+  const int reps = 3;
+  bool any_measured = false;
+  int batch_per_cu = 0;
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    Inst& in = p->inst[i];
+    in.factored = false;
+    const TuneKey key{in.n_h, in.n_w, in.K, in.M, in.max_rhs, prec};
+    const TuneEntry* hit = nullptr;
+    for (const auto& e : cache)
+      if (e.key == key) hit = &e;
+    if (hit && use_cached) {
+      in.tune_gram_split = hit->gram_split;
+      in.tune_ztx_split = hit->ztx_split;
+      in.tune_chol_per_cu = hit->chol_per_cu;
+      continue;
+    }
+    any_measured = true;
+    // FP64 Gram: one or two contraction parts (the second part needs G2)
+    in.tune_gram_split = 1;
+    if (prec == PC_PREC_FP64) {
+      if (!in.G2 && hipMalloc((void**)&in.G2, sizeof(double) * (size_t)(in.KMp * in.KMp)) != hipSuccess) {
+        in.G2 = nullptr;
+      }
+      float best = 0.f;
+      int choice = 1;
+      for (int c = 1; c <= (in.G2 ? 2 : 1); ++c) {
+        in.tune_gram_split = c;
+        float ms = 0.f;
+        pc_status st = time_ms(s, reps, [&]() -> pc_status {
+          PC_TRY(pc::launch_column_grams(in, s));
+          PC_TRY(pc::launch_gram_f64(in, s));
+          PC_TRY(pc::launch_gram_pad_and_diag(in, s));
+          return PC_OK;
+        }, &ms);
+        if (st != PC_OK) return st;
+        if (c == 1 || ms < best) { best = ms; choice = c; }
+      }
+      in.tune_gram_split = choice;
+    }
+    // Z^T x at the plan's right-hand-side count, on the residual scratch
+    if (in.max_rhs > 0) {
+      float best = 0.f;
+      int choice = 1;
+      PC_TRY(hipMemsetAsync(in.Rres, 0, sizeof(double) * (size_t)(in.n * in.max_rhs), s));
+      for (int c = 1; c <= 2; ++c) {
+        in.tune_ztx_split = c;
+        float ms = 0.f;
+        pc_status st = time_ms(s, reps, [&]() -> pc_status {
+          PC_TRY(pc::launch_ztx(in, in.Rres, in.n, in.max_rhs, in.D, in.KMp, s));
+          return PC_OK;
+        }, &ms);
+        if (st != PC_OK) return st;
+        if (c == 1 || ms < best) { best = ms; choice = c; }
+      }
+      in.tune_ztx_split = choice;
+    }
+    // Cholesky grid, on the assembled Gram (single-instance plans; a batch is
+    // tuned as a whole below)
+    in.tune_chol_per_cu = 2;
+    if (!p->batch) {
+      float best = 0.f;
+      int choice = 2;
+      for (int c = 2; c >= 1; --c) {
+        in.tune_chol_per_cu = c;
+        float tot = 0.f;
+        for (int r = 0; r < reps; ++r) {
+          pc_status st = assemble_one(p, in, s);
+          if (st != PC_OK) return st;
+          float ms = 0.f;
+          st = time_ms(s, 1, [&]() -> pc_status { PC_TRY(pc::launch_cholesky(in, s)); return PC_OK; }, &ms, false);
+          if (st != PC_OK) return st;
+          tot += ms;
+        }
+        if (c == 2 || tot < best) { best = tot; choice = c; }
+      }
+      in.tune_chol_per_cu = choice;
+    }
+  }
+  if (p->batch && any_measured) {
+    float best = 0.f;
+    for (int c = 2; c >= 1; --c) {
+      float tot = 0.f;
+      for (int r = 0; r < reps; ++r) {
+        for (auto& in : p->inst) {
+          pc_status st = assemble_one(p, in, s);
+          if (st != PC_OK) return st;
+        }
+        hipEvent_t a = nullptr, b = nullptr;
+        float ms = 0.f;
+        PC_TRY(hipEventCreate(&a));
+        PC_TRY(hipEventCreate(&b));
+        PC_TRY(hipEventRecord(a, s));
+        PC_TRY(pc::launch_cholesky_batch(p->batch, s, c));
+        PC_TRY(hipEventRecord(b, s));
+        PC_TRY(hipEventSynchronize(b));
+        PC_TRY(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        tot += ms;
+      }
+      if (c == 2 || tot < best) { best = tot; batch_per_cu = c; }
+    }
+    for (auto& in : p->inst) in.tune_chol_per_cu = batch_per_cu;
+  }
+  // keep the second Gram part only where it was chosen
+  for (auto& in : p->inst)
+    if (in.G2 && in.tune_gram_split == 1) { PC_TRY(hipStreamSynchronize(s)); (void)hipFree(in.G2); in.G2 = nullptr; }
+  PC_TRY(hipStreamSynchronize(s));
+  if (cache_path && any_measured) {
+    for (const auto& in : p->inst) {
+      const TuneKey key{in.n_h, in.n_w, in.K, in.M, in.max_rhs, prec};
+      TuneEntry e{key, in.tune_gram_split, in.tune_ztx_split, in.tune_chol_per_cu};
+      bool found = false;
+      for (auto& c : cache)
+        if (c.key == key) { c = e; found = true; }
+      if (!found) cache.push_back(e);
+    }
+    if (!write_tune_cache(cache_path, cache)) return PC_ERR_INVALID_ARG;
+  }
+  return PC_OK;
+}
+
+pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_t ztx_split, int32_t chol_per_cu) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
+  if (gram_split < 0 || gram_split > 2 || ztx_split < 0 || ztx_split > 2 || chol_per_cu < 0 || chol_per_cu > 2)
+    return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  Inst& in = p->inst[instance];
+  if (gram_split == 2 && p->opt.precision == PC_PREC_FP64 && !in.G2 &&
+      hipMalloc((void**)&in.G2, sizeof(double) * (size_t)(in.KMp * in.KMp)) != hipSuccess) {
+    in.G2 = nullptr;
+    return PC_ERR_OOM;
+  }
+  in.tune_gram_split = gram_split;
+  in.tune_ztx_split = ztx_split;
+  in.tune_chol_per_cu = chol_per_cu;
+  if (p->batch)
+    for (auto& o : p->inst) o.tune_chol_per_cu = chol_per_cu;
+  in.factored = false;
+  return PC_OK;
+}
+
+pc_status pc_query_tuning(const pc_plan* p, int32_t instance, int32_t* gram_split, int32_t* ztx_split,
+                          int32_t* chol_per_cu) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
+  const Inst& in = p->inst[instance];
+  if (gram_split) *gram_split = in.tune_gram_split;
+  if (ztx_split) *ztx_split = in.tune_ztx_split;
+  if (chol_per_cu) *chol_per_cu = in.tune_chol_per_cu;
   return PC_OK;
 }
 

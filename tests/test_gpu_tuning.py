@@ -1,0 +1,64 @@
+"""Launch-shape autotuning through the C-ABI: every shape the tuner can pick
+gives the oracle's answer, and the tuning cache round-trips."""
+import itertools
+
+import numpy as np
+import pytest
+
+import paper_2609_13327_amd as pc
+import workloads as wl
+from oracle import lsq
+from tests.gpu_util import dev, empty, host, inst_dict
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(got, ref):
+    return (np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)).max()
+
+
+@pytest.mark.parametrize("gram,ztx,chol", list(itertools.product([1, 2], [1, 2], [1, 2])))
+def test_every_launch_shape_matches_oracle(gram, ztx, chol):
+    inst = wl.make_instance(12, 24, 5, 24, 70, 0.2, 0.5, 21)
+    plan = pc.Plan([inst_dict(inst)])
+    pc.pc_set_tuning(plan.handle, 0, gram, ztx, chol)
+    assert pc.pc_query_tuning(plan.handle, 0) == (gram, ztx, chol)
+    plan.factor()
+    Y = empty(inst.KM, inst.R)
+    plan.apply([dev(inst.X)], [Y])
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    assert _rel(host(Y), ref) <= 1e-10
+    plan.close()
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    insts = wl.batched_config(count=5, scale=0.3)
+    cache = str(tmp_path / "tune.txt")
+    plan = pc.Plan([inst_dict(i) for i in insts])
+    pc.pc_autotune(plan.handle, cache, use_cached=True)
+    chosen = [pc.pc_query_tuning(plan.handle, k) for k in range(len(insts))]
+    for g, z, c in chosen:
+        assert g in (1, 2) and z in (1, 2) and c in (1, 2)
+    assert len({c for _, _, c in chosen}) == 1            # one grid for the batched factorization
+    plan.factor()
+    Ys = [empty(i.KM, i.R) for i in insts]
+    plan.apply([dev(i.X) for i in insts], Ys)
+    for i, y in zip(insts, Ys):
+        assert _rel(host(y), lsq.left_inverse_apply(i.E, i.W, 1, i.X)) <= 1e-10
+    plan.close()
+    lines = open(cache).read().split("\n")
+    assert lines[0] == "pcsqrt-tune-v1"
+    assert len([ln for ln in lines[1:] if ln.strip()]) == len({(i.n_h, i.K, i.M, i.R) for i in insts})
+    plan2 = pc.Plan([inst_dict(i) for i in insts])
+    pc.pc_autotune(plan2.handle, cache, use_cached=True)
+    assert [pc.pc_query_tuning(plan2.handle, k) for k in range(len(insts))] == chosen
+    plan2.close()
+
+
+def test_set_tuning_rejects_bad_values():
+    inst = wl.make_instance(6, 12, 2, 8, 4, 0.2, 0.5, 22)
+    plan = pc.Plan([inst_dict(inst)])
+    with pytest.raises(pc.PcError) as e:
+        pc.pc_set_tuning(plan.handle, 0, 3, 1, 1)
+    assert e.value.status == pc.PC_ERR_INVALID_ARG
+    plan.close()
