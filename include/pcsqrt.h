@@ -185,15 +185,20 @@ pc_status pc_autotune(pc_plan *plan, const char *cache_path, int32_t use_cached,
 
 /* pc_set_tuning — set the launch shapes of instance `instance` by hand
  * (values as pc_query_tuning reports them; 0 = heuristic).  chol_per_cu
- * applies to every instance of a plan with several instances.  The plan is
- * left unfactored.  Returns PC_ERR_INVALID_ARG for values outside 0..2. */
+ * applies to every instance of a plan with several instances.  chol_block
+ * selects the factorization: 0 keeps the current one, -1 the tile DAG over
+ * the whole Gram, a multiple of 64 that is >= 128 the blocked outer
+ * factorization with block columns of that width (the default for Grams of
+ * order above 8192 uses 1024; not for plans with several instances).  The
+ * plan is left unfactored.  Returns PC_ERR_INVALID_ARG for other values. */
 pc_status pc_set_tuning(pc_plan *plan, int32_t instance, int32_t gram_split, int32_t ztx_split,
-                        int32_t chol_per_cu);
+                        int32_t chol_per_cu, int32_t chol_block);
 
 /* pc_query_tuning — the launch shapes in use for instance `instance`
- * (0 = built-in heuristic, not tuned).  Output pointers may be NULL. */
+ * (0 = built-in heuristic, not tuned; chol_block 0 = tile DAG, else the
+ * block-column width).  Output pointers may be NULL. */
 pc_status pc_query_tuning(const pc_plan *plan, int32_t instance, int32_t *gram_split,
-                          int32_t *ztx_split, int32_t *chol_per_cu);
+                          int32_t *ztx_split, int32_t *chol_per_cu, int32_t *chol_block);
 
 /* ------------------------------------------------------------------------
  * Per-phase timing (HIP events recorded on the caller's stream).

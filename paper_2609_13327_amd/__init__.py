@@ -116,8 +116,9 @@ def load_library(path: str = LIB_PATH):
     lib.pc_mlp_training_pairs.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_void_p,
                                           c_int64, c_void_p, c_int64, c_void_p]
     lib.pc_autotune.argtypes = [c_void_p, ctypes.c_char_p, c_int32, c_void_p]
-    lib.pc_set_tuning.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32]
-    lib.pc_query_tuning.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
+    lib.pc_set_tuning.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32]
+    lib.pc_query_tuning.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                    POINTER(c_int32)]
     lib.pc_learned_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                      c_double, c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p]
     for name in EXPORTED:
@@ -377,17 +378,18 @@ def pc_autotune(plan: int, cache_path: Optional[str] = None, use_cached: bool = 
            "pc_autotune")
 
 
-def pc_set_tuning(plan: int, instance: int, gram_split: int, ztx_split: int, chol_per_cu: int):
+def pc_set_tuning(plan: int, instance: int, gram_split: int, ztx_split: int, chol_per_cu: int,
+                  chol_block: int = 0):
     _check(load_library().pc_set_tuning(c_void_p(plan), int(instance), int(gram_split), int(ztx_split),
-                                        int(chol_per_cu)), "pc_set_tuning")
+                                        int(chol_per_cu), int(chol_block)), "pc_set_tuning")
 
 
-def pc_query_tuning(plan: int, instance: int = 0):
-    """(gram_split, ztx_split, chol_per_cu) of an instance (0 = heuristic)."""
-    g, z, c = c_int32(0), c_int32(0), c_int32(0)
+def pc_query_tuning(plan: int, instance: int = 0, with_block: bool = False):
+    """(gram_split, ztx_split, chol_per_cu[, chol_block]) of an instance (0 = heuristic)."""
+    g, z, c, b = c_int32(0), c_int32(0), c_int32(0), c_int32(0)
     _check(load_library().pc_query_tuning(c_void_p(plan), int(instance), ctypes.byref(g), ctypes.byref(z),
-                                          ctypes.byref(c)), "pc_query_tuning")
-    return g.value, z.value, c.value
+                                          ctypes.byref(c), ctypes.byref(b)), "pc_query_tuning")
+    return (g.value, z.value, c.value, b.value) if with_block else (g.value, z.value, c.value)
 
 
 # -------------------------------------------------------------- convenience

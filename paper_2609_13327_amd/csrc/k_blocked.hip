@@ -1,0 +1,136 @@
+// FP64 MFMA products of column-major panels for the blocked outer
+// factorization of large Grams:
+//   C(i, j) = alpha sum_k A(i, k) B(j, k)            (overwrite), or
+//   C(i, j) = C(i, j) + alpha sum_k A(i, k) B(j, k)  (accumulate),
+// optionally on the lower triangle only (tiles with i >= j; inside a
+// diagonal tile only i >= j is written).  128 x 128 workgroup tiles, four
+// waves of 64 x 64, contraction staged through LDS 16 columns at a time;
+// both operands are read along their columns (coalesced).
+#include "pc_common.h"
+#include "pc_internal.h"
+#include "gemm_core.h"
+
+#include <algorithm>
+
+namespace pc {
+
+struct NtGemmProb {
+  static constexpr int BM = 128, BN = 128, WM = 2, WN = 2, KC = 16;
+  static constexpr int LDA = BM + 8, LDB = BN + 8;
+  static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  double* C; int64_t ldc;
+  int64_t M, N, K;
+  double alpha;
+  int accumulate, lower;
+  int64_t tm, tn, ntiles;
+
+  struct Ctx { bool valid; int64_t i0, j0; int nchunks; };
+  struct ARegs { double v[NA]; };
+  struct BRegs { double v[NB_]; };
+
+  __device__ Ctx ctx(int b) const {
+    Ctx c;
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t u = (b % 8) * per + b / 8;      // consecutive tiles on one XCD
+    c.valid = u < ntiles;
+    int64_t ti, tj;
+    if (lower) {
+      ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+      while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
+      while (ti * (ti + 1) / 2 > u) --ti;
+      tj = u - ti * (ti + 1) / 2;
+    } else {
+      ti = u % tm;
+      tj = u / tm;
+    }
+    c.i0 = ti * BM;
+    c.j0 = tj * BN;
+    c.nchunks = (int)((K + KC - 1) / KC);
+    return c;
+  }
+  __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q, row = e % BM, kk = e / BM;
+      const int64_t i = c.i0 + row, k = (int64_t)chunk * KC + kk;
+      r.v[q] = (i < M && k < K) ? A[i + k * lda] : 0.0;
+    }
+  }
+  __device__ void storeA(const ARegs& r, double* As) const {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[(e / BM) * LDA + e % BM] = r.v[q];
+    }
+  }
+  __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
+#pragma unroll
+    for (int q = 0; q < NB_; ++q) {
+      const int e = threadIdx.x + 256 * q, col = e % BN, kk = e / BN;
+      const int64_t j = c.j0 + col, k = (int64_t)chunk * KC + kk;
+      r.v[q] = (j < N && k < K) ? B[j + k * ldb] : 0.0;
+    }
+  }
+  __device__ void storeB(const BRegs& r, double* Bs) const {
+#pragma unroll
+    for (int q = 0; q < NB_; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      Bs[(e / BN) * LDB + e % BN] = r.v[q];
+    }
+  }
+  __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
+    acc.for_each([&](int row, int col, double v) {
+      const int64_t i = c.i0 + row, j = c.j0 + col;
+      if (i >= M || j >= N || (lower && i < j)) return;
+      double* p = C + i + j * ldc;
+      *p = accumulate ? *p + alpha * v : alpha * v;
+    });
+  }
+};
+
+hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                          int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  NtGemmProb g;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower;
+  g.tm = ceil_div(M, NtGemmProb::BM);
+  g.tn = ceil_div(N, NtGemmProb::BN);
+  g.ntiles = lower ? g.tm * (g.tm + 1) / 2 : g.tm * g.tn;
+  const int64_t grid = 8 * ((g.ntiles + 7) / 8);
+  hipLaunchKernelGGL(gemm_f64_kernel<NtGemmProb>, dim3((unsigned)grid), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// dst (rows x cols, ld ldd) = src (ld lds)
+__global__ void copy_panel_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd,
+                                  int64_t rows) {
+  const int64_t c = blockIdx.y;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x)
+    dst[r + c * ldd] = src[r + c * lds];
+}
+
+hipError_t launch_copy_panel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
+                             hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(rows, 256), 128);
+  hipLaunchKernelGGL(copy_panel_kernel, dim3(gx, (unsigned)cols), dim3(256), 0, s, src, lds, dst, ldd, rows);
+  return hipGetLastError();
+}
+
+// n x n identity (ld n)
+__global__ void identity_kernel(double* __restrict__ I, int64_t n) {
+  const int64_t c = blockIdx.y;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    I[r + c * n] = (r == c) ? 1.0 : 0.0;
+}
+
+hipError_t launch_identity(double* I, int64_t n, hipStream_t s) {
+  const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 16);
+  hipLaunchKernelGGL(identity_kernel, dim3(gx, (unsigned)n), dim3(256), 0, s, I, n);
+  return hipGetLastError();
+}
+
+}  // namespace pc

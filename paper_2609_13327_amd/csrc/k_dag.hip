@@ -132,6 +132,7 @@ struct CholArgs {
   const double* diag0; double* Linv;
   int* state; int* head; int* info; int* err;
   const int64_t* offs; int64_t ntasks;
+  int64_t col_off;          // column of G's first row/column in the whole matrix (failure reports)
 };
 
 // 64 x 64 tile of column-major `M` (rows r0.., cols c0..) into LDS as
@@ -278,7 +279,7 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
           for (int j = 0; j < 16; ++j) {
             if (!(A[(c + j) * LDP + c + j] > Sc[1024 + c + j])) { f = j; break; }
           }
-          sh[1] = (int)(k0 + c + f);
+          sh[1] = (int)(a.col_off + k0 + c + f);
         }
       } else {
 #pragma unroll
@@ -822,10 +823,74 @@ static CholArgs chol_args(const Inst& in) {
   a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv;
   a.state = in.dag; a.head = in.dag + (int64_t)T * T; a.err = a.head + 1; a.info = in.info;
   a.offs = in.chol_offs; a.ntasks = in.chol_ntasks;
+  a.col_off = 0;
   return a;
 }
 
+// Blocked outer factorization for large Grams: for every block column of
+// NO = 1024 (16 tiles), factor the diagonal block with the tile DAG, form
+// its inverse by a forward solve on the identity, solve the panel below as
+// G_panel L_kk^{-T} and apply the symmetric update to the trailing lower
+// triangle with FP64 MFMA products.  The critical path is then 16 diagonal
+// steps per block column instead of one per 64-tile row.
+// Counters of the blocked path: [0] error flag for the whole factorization,
+// then the diagonal block's states and queue head, then the flags and head
+// of its inverse (2 (NO/64)^2 + 3 ints in all).
+static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
+  const int64_t ld = in.KMp, NO = in.blk_NO;
+  int* err = in.dag;
+  hipLaunchKernelGGL(dag_reset_kernel, dim3(1), dim3(64), 0, s, err, (int64_t)1);
+  for (int64_t k0 = 0; k0 < in.KMp; k0 += NO) {
+    const int64_t nb = std::min<int64_t>(NO, in.KMp - k0), m = in.KMp - k0 - nb;
+    const int Ts = (int)(nb / T64);
+    const bool tail = nb != NO;
+    // 1. the diagonal block, with the tile DAG on the sub-matrix
+    CholBatch b{};
+    CholArgs& a = b.one;
+    a.G = in.G + k0 + k0 * ld; a.ld = ld; a.T = Ts; a.KM = in.KM;
+    a.diag0 = in.diag0 + k0; a.Linv = in.Linv + (k0 / T64) * T64 * T64;
+    a.state = in.dag + 1; a.head = a.state + (int64_t)Ts * Ts; a.err = err; a.info = in.info;
+    a.offs = tail ? in.blk_offs_tail : in.blk_offs; a.ntasks = tail ? in.blk_ntasks_tail : in.blk_ntasks;
+    a.col_off = k0;
+    b.ntasks = a.ntasks; b.head = a.head; b.err = a.err;
+    const int64_t nctr = (int64_t)Ts * Ts + 1;
+    hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nctr, 256), 1024)), dim3(256), 0, s,
+                       a.state, nctr);
+    hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel, in.tune_chol_per_cu)),
+                       dim3(256), 0, s, b);
+    if (m <= 0) break;
+    // 2. X = L_kk^{-1}: forward solve on the identity (only the lower triangle of X is nonzero)
+    SolveBatch sb{};
+    SolveArgs& v = sb.one;
+    v.G = a.G; v.ld = ld; v.T = Ts; v.Linv = a.Linv;
+    v.In = in.blk_I; v.ldIn = NO; v.Out = in.blk_X; v.ldOut = NO;
+    v.R = nb; v.Rp = nullptr; v.nrt = Ts;
+    v.flags = a.head + 1; v.info = in.info; v.skip = nullptr;
+    sb.ntasks = (int64_t)Ts * Ts; sb.head = v.flags + (int64_t)Ts * Ts; sb.err = a.err; sb.backward = 0;
+    const int64_t nflags = (int64_t)Ts * Ts + 1;
+    hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)), dim3(256), 0, s,
+                       v.flags, nflags);
+    hipLaunchKernelGGL(solve_dag_kernel, dim3((unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), sb.ntasks)),
+                       dim3(256), 0, s, sb);
+    // 3. panel: L_panel = G_panel X^T (from a copy of G_panel)
+    double* panel = in.G + (k0 + nb) + k0 * ld;
+    hipError_t e = launch_copy_panel(panel, ld, in.blk_P, m, m, nb, s);
+    if (e == hipSuccess) e = launch_nt_gemm(in.blk_P, m, in.blk_X, NO, panel, ld, m, nb, nb, 1.0, 0, 0, s);
+    // 4. trailing lower triangle: G_22 -= L_panel L_panel^T
+    if (e == hipSuccess)
+      e = launch_nt_gemm(panel, ld, panel, ld, in.G + (k0 + nb) + (k0 + nb) * ld, ld, m, m, nb, -1.0, 1, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+int* chol_error_flag(const Inst& in) {
+  const int64_t T = in.KMp / T64;
+  return in.blk_NO > 0 ? in.dag : in.dag + T * T + 1;
+}
+
 hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
+  if (in.blk_NO > 0) return launch_cholesky_blocked(in, s);
   const int T = (int)(in.KMp / T64);
   // counters: state T*T, then head, err
   const int64_t nctr = (int64_t)T * T + 2;

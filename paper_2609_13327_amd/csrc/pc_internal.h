@@ -61,6 +61,13 @@ struct Inst {
   int tune_gram_split = 0;   // FP64 Gram: 1 or 2 contraction parts
   int tune_ztx_split = 0;    // Z^T x: 1 or 2 contraction parts
   int tune_chol_per_cu = 0;  // Cholesky DAG: persistent workgroups per compute unit (1 or 2)
+  // blocked outer factorization (large Grams): block columns of blk_NO (0: tile DAG only)
+  int64_t blk_NO = 0;
+  double* blk_P = nullptr;   // KMp x blk_NO copy of a panel
+  double* blk_X = nullptr;   // blk_NO x blk_NO inverse of a diagonal block
+  double* blk_I = nullptr;   // blk_NO x blk_NO identity
+  int64_t* blk_offs = nullptr; int64_t blk_ntasks = 0;            // DAG order of a full diagonal block
+  int64_t* blk_offs_tail = nullptr; int64_t blk_ntasks_tail = 0;  // and of the last, smaller one
   bool factored = false;
   int iters = 0;
   double last_rel = 0.0;
@@ -73,6 +80,7 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s);
 hipError_t launch_cholesky(const Inst& in, hipStream_t s);
+int* chol_error_flag(const Inst& in);   // device int set when a bounded wait of the factorization expired
 // `skip` (device int, may be null): when nonzero at run time the kernels exit
 // at once; the refinement loop uses it to stop converged instances on the GPU.
 hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B,
@@ -96,6 +104,13 @@ hipError_t launch_nonfinite_check(const double* A, int64_t ld, int64_t rows, int
 hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int64_t ldd,
                                int64_t n, hipStream_t s);
 hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
+// C = alpha A B^T (or C += alpha A B^T when accumulate), column-major, FP64 MFMA;
+// lower != 0 writes only the lower triangle (i >= j) of a square C
+hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                          int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s);
+hipError_t launch_copy_panel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
+                             hipStream_t s);
+hipError_t launch_identity(double* I, int64_t n, hipStream_t s);
 int64_t chol_task_offsets(int T, std::vector<int64_t>& offs);
 // All instances of a plan in one persistent Cholesky launch and one pair of
 // solve launches (task lists interleaved, largest instance first).

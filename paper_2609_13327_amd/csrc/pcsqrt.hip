@@ -21,6 +21,11 @@ using pc::Inst;
 // reduced-precision modes); otherwise the apply reports no convergence.
 static constexpr double kStallAccept = 1e-9;
 
+// Grams of order above this are factored by block columns of 1024, each block
+// by the tile DAG (the DAG alone has one diagonal step per 64 rows on its
+// critical path).
+static constexpr int64_t kBlockedAbove = 8192;
+
 struct pc_plan {
   std::vector<Inst> inst;
   pc_options opt;
@@ -64,6 +69,8 @@ void free_inst(Inst& in) {
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
+  hipFree(in.blk_P); hipFree(in.blk_X); hipFree(in.blk_I); hipFree(in.blk_offs); hipFree(in.blk_offs_tail);
+  in.blk_P = in.blk_X = in.blk_I = nullptr; in.blk_offs = in.blk_offs_tail = nullptr;
   in.Gs = in.Dinv = in.cg = nullptr; in.cgcol = nullptr; in.cg_flags = nullptr;
   in.dag = nullptr; in.chol_offs = nullptr; in.ctl = nullptr;
   in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = nullptr;
@@ -99,6 +106,40 @@ std::vector<int> make_qtiles(int64_t M) {
   return q;
 }
 
+// Buffers of the blocked outer factorization with block columns of NO
+// (a multiple of 64); NO = 0 frees them (tile DAG only).
+pc_status alloc_blocked(Inst& in, int64_t NO) {
+  (void)hipFree(in.blk_P); (void)hipFree(in.blk_X); (void)hipFree(in.blk_I);
+  (void)hipFree(in.blk_offs); (void)hipFree(in.blk_offs_tail);
+  in.blk_P = in.blk_X = in.blk_I = nullptr;
+  in.blk_offs = in.blk_offs_tail = nullptr;
+  in.blk_NO = 0;
+  in.blk_ntasks = in.blk_ntasks_tail = 0;
+  if (NO <= 0) return PC_OK;
+  const int64_t KMp = in.KMp;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  chk(dalloc(&in.blk_P, KMp * NO));
+  chk(dalloc(&in.blk_X, NO * NO));
+  chk(dalloc(&in.blk_I, NO * NO));
+  std::vector<int64_t> bo;
+  in.blk_ntasks = pc::chol_task_offsets((int)(NO / pc::NB), bo);
+  chk(dalloc(&in.blk_offs, (int64_t)bo.size()));
+  if (e == hipSuccess) chk(hipMemcpy(in.blk_offs, bo.data(), sizeof(int64_t) * bo.size(), hipMemcpyHostToDevice));
+  const int64_t tail = KMp % NO;
+  if (tail) {
+    std::vector<int64_t> bt;
+    in.blk_ntasks_tail = pc::chol_task_offsets((int)(tail / pc::NB), bt);
+    chk(dalloc(&in.blk_offs_tail, (int64_t)bt.size()));
+    if (e == hipSuccess) chk(hipMemcpy(in.blk_offs_tail, bt.data(), sizeof(int64_t) * bt.size(), hipMemcpyHostToDevice));
+  }
+  if (e == hipSuccess) chk(pc::launch_identity(in.blk_I, NO, nullptr));
+  if (e == hipSuccess) chk(hipDeviceSynchronize());
+  if (e != hipSuccess) return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PC_ERR_OOM : PC_ERR_DEVICE;
+  in.blk_NO = NO;
+  return PC_OK;
+}
+
 pc_status alloc_inst(Inst& in, int precision, int flags) {
   const int64_t KMp = in.KMp, nblk = KMp / pc::NB, R = std::max<int64_t>(in.max_rhs, 1);
   hipError_t e = hipSuccess;
@@ -120,10 +161,16 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   chk(dalloc(&in.ctl, 1));
   const int64_t T = KMp / pc::NB;
   in.nrt_max = (int)pc::ceil_div(R, pc::NB);
-  chk(dalloc(&in.dag, T * T + 2 + T * in.nrt_max + 1));
+  // counters: Cholesky states, head, error, solve flags, solve head; the blocked
+  // factorization reuses them for a diagonal block and its inverse (2 T^2 + 3)
+  chk(dalloc(&in.dag, std::max<int64_t>(T * T + 2 + T * in.nrt_max + 1, 2 * T * T + 3)));
   std::vector<int64_t> offs;
   in.chol_ntasks = pc::chol_task_offsets((int)T, offs);
   chk(dalloc(&in.chol_offs, (int64_t)offs.size()));
+  if (KMp > kBlockedAbove && e == hipSuccess) {
+    const pc_status bs = alloc_blocked(in, 1024);
+    if (bs != PC_OK) return bs;
+  }
   if (flags & PC_FLAG_KEEP_GRAM) {
     chk(dalloc(&in.Gs, KMp * KMp));
     chk(dalloc(&in.Dinv, KMp * pc::NB));
@@ -533,7 +580,9 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   }
   if (st == PC_OK && o.use_graph && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
     st = PC_ERR_DEVICE;
-  if (st == PC_OK && count > 1 && !(p->batch = pc::make_dag_batch(p->inst))) st = PC_ERR_OOM;
+  bool any_blocked = false;
+  for (auto& in : p->inst) any_blocked = any_blocked || in.blk_NO > 0;
+  if (st == PC_OK && count > 1 && !any_blocked && !(p->batch = pc::make_dag_batch(p->inst))) st = PC_ERR_OOM;
   if (st == PC_OK) {
     // finiteness of E and W, then the pair tables
     int bad = 0;
@@ -602,7 +651,7 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     const Inst& in = p->inst[i];
     const int64_t T = in.KMp / pc::NB;
     PC_TRY(hipMemcpyAsync(&infos[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
-    PC_TRY(hipMemcpyAsync(&errs[i], p->batch ? pc::dag_batch_error(p->batch) : in.dag + T * T + 1, sizeof(int),
+    PC_TRY(hipMemcpyAsync(&errs[i], p->batch ? pc::dag_batch_error(p->batch) : pc::chol_error_flag(in), sizeof(int),
                           hipMemcpyDeviceToHost, s));
   }
   PC_TRY(hipStreamSynchronize(s));
@@ -946,16 +995,24 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
   return PC_OK;
 }
 
-pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_t ztx_split, int32_t chol_per_cu) {
+pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_t ztx_split, int32_t chol_per_cu,
+                        int32_t chol_block) {
   if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
   if (gram_split < 0 || gram_split > 2 || ztx_split < 0 || ztx_split > 2 || chol_per_cu < 0 || chol_per_cu > 2)
     return PC_ERR_INVALID_ARG;
+  if (chol_block < -1 || (chol_block > 0 && (chol_block < 128 || chol_block % pc::NB != 0)))
+    return PC_ERR_INVALID_ARG;
+  if (chol_block != 0 && p->batch) return PC_ERR_INVALID_ARG;   // a batch factors every instance in one launch
   hipSetDevice(p->device);
   Inst& in = p->inst[instance];
   if (gram_split == 2 && p->opt.precision == PC_PREC_FP64 && !in.G2 &&
       hipMalloc((void**)&in.G2, sizeof(double) * (size_t)(in.KMp * in.KMp)) != hipSuccess) {
     in.G2 = nullptr;
     return PC_ERR_OOM;
+  }
+  if (chol_block != 0) {
+    const pc_status bs = alloc_blocked(in, chol_block > 0 ? chol_block : 0);
+    if (bs != PC_OK) return bs;
   }
   in.tune_gram_split = gram_split;
   in.tune_ztx_split = ztx_split;
@@ -967,12 +1024,13 @@ pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_
 }
 
 pc_status pc_query_tuning(const pc_plan* p, int32_t instance, int32_t* gram_split, int32_t* ztx_split,
-                          int32_t* chol_per_cu) {
+                          int32_t* chol_per_cu, int32_t* chol_block) {
   if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
   const Inst& in = p->inst[instance];
   if (gram_split) *gram_split = in.tune_gram_split;
   if (ztx_split) *ztx_split = in.tune_ztx_split;
   if (chol_per_cu) *chol_per_cu = in.tune_chol_per_cu;
+  if (chol_block) *chol_block = (int32_t)in.blk_NO;
   return PC_OK;
 }
 

@@ -62,3 +62,28 @@ def test_set_tuning_rejects_bad_values():
         pc.pc_set_tuning(plan.handle, 0, 3, 1, 1)
     assert e.value.status == pc.PC_ERR_INVALID_ARG
     plan.close()
+
+
+@pytest.mark.parametrize("block", [128, 192, -1])
+def test_blocked_factorization_matches_oracle(block):
+    """Block columns of 128 / 192 (with a narrower last block) and the plain
+    tile DAG give the oracle's answer; K*M = 420 (7 tiles, ragged)."""
+    inst = wl.make_instance(20, 40, 6, 70, 33, 0.15, 0.4, 23)
+    plan = pc.Plan([inst_dict(inst)])
+    pc.pc_set_tuning(plan.handle, 0, 0, 0, 0, block)
+    assert pc.pc_query_tuning(plan.handle, 0, with_block=True)[3] == (block if block > 0 else 0)
+    plan.factor()
+    Y = empty(inst.KM, inst.R)
+    plan.apply([dev(inst.X)], [Y])
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    assert _rel(host(Y), ref) <= 1e-10
+    plan.close()
+
+
+def test_blocked_factorization_reports_rank_deficiency():
+    inst = wl.make_instance(10, 20, 4, 40, 3, 0.3, 0.5, 5, centring="sample")
+    plan = pc.Plan([inst_dict(inst)])
+    pc.pc_set_tuning(plan.handle, 0, 0, 0, 0, 128)
+    st, failed = plan.factor(raise_on_error=False)
+    assert st == pc.PC_ERR_NOT_SPD and failed == 0
+    plan.close()
