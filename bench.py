@@ -52,9 +52,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--train", type=int, default=20000, help="config 5: training pairs")
+    ap.add_argument("--epochs", type=int, default=3, help="config 5: passes over the training pairs")
+    ap.add_argument("--heldout", type=int, default=256, help="config 5: held-out right-hand sides")
+    ap.add_argument("--cg-maxiter", type=int, default=400, help="config 5: CG iteration cap")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16"],
-                    help="default: fp64 for configs 1-2, fp32 for config 3")
+                    help="default: fp64 for configs 1-2, fp32 for config 3, bf16 for config 4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--tune-cache", default=None, help="tuning cache file (read and updated)")
@@ -129,7 +133,7 @@ def main():
     if args.copy_probe:
         copy_probe()
         return 0
-    prec_main = args.precision or ("fp32" if args.config == 3 else "fp64")
+    prec_main = args.precision or {3: "fp32", 4: "bf16"}.get(args.config, "fp64")
     import torch
     import paper_2609_13327_amd as pc
     import workloads as wl
@@ -140,6 +144,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.config == 5:
+        return learned(args, torch, pc, wl, dev)
     log(f"generating config {args.config}")
     insts = wl.batched_config() if args.config == 3 else [wl.config(args.config)]
     use_graph = 1 if args.config == 3 else 0
@@ -222,7 +228,9 @@ def main():
     from oracle import lsq
     refs = {}
     cpu = None
-    if not args.no_cpu_baseline:
+    if args.config == 4:
+        log("no oracle run for the 131072 x 32768 instance (its explicit QR is out of reach on the host)")
+    if not args.no_cpu_baseline and args.config != 4:
         threads = oracle_threads()
         log("oracle (explicit Z + Householder QR) on the host")
         if args.config == 3:
@@ -316,6 +324,107 @@ def main():
         "phases_ms_per_step": main_res["phases_ms_per_step"],
         "variants": variants,
     }
+    print(json.dumps(out))
+    return 0
+
+
+def learned(args, torch, pc, wl, dev):
+    """The learned warm start on the 131072 x 32768 instance: train the
+    network on pairs (b = Z^T x, Z^+ x) from the direct solve, then solve
+    held-out right-hand sides by CG from zero and from the network's
+    prediction (direct solve as fallback and as the reference)."""
+    inst = wl.config(5, R=args.heldout)
+    KM = inst.KM
+
+    def to_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to(dev).t()
+
+    E, W = to_dev(inst.E), to_dev(inst.W)
+    chunk = 1024
+    plan = pc.Plan([{"E": E, "W": W, "n_w": 1, "max_rhs": chunk}],
+                   flags=pc.PC_FLAG_KEEP_GRAM | pc.PC_FLAG_CG_MEMBER_BLOCKS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.factor()
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    log(f"factor (FP64 Gram and Cholesky, kept Gram, member-block inverses) {t_factor:.2f} s")
+    # training pairs from the direct solve
+    g = torch.Generator(device=dev)
+    g.manual_seed(5000)
+    N = args.train
+    Xin = torch.empty((N, KM), dtype=torch.float32, device=dev)
+    Tin = torch.empty_like(Xin)
+    Bc = torch.empty((chunk, KM), dtype=torch.float64, device=dev).t()
+    Yc = torch.empty((chunk, KM), dtype=torch.float64, device=dev).t()
+    t0 = time.perf_counter()
+    for c0 in range(0, N, chunk):
+        c1 = min(N, c0 + chunk)
+        Xc = torch.randn((c1 - c0, inst.n), generator=g, dtype=torch.float64, device=dev).t()
+        pc.pc_sqrt_transpose_apply(plan.handle, 0, Xc, Bc[:, :c1 - c0])
+        plan.apply([Xc], [Yc[:, :c1 - c0]])
+        pc.pc_mlp_training_pairs(Bc[:, :c1 - c0], Yc[:, :c1 - c0], Xin[c0:c1], Tin[c0:c1])
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    log(f"{N} training pairs {t_pairs:.2f} s")
+    h, batch, lr = 1024, 256, 1e-3
+    W1, b1, W2, b2 = wl.mlp_init(KM, h, 5001)
+    net = pc.Mlp(KM, h, max(batch, args.heldout), pc.PC_MLP_BF16)
+    f32 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    pc.pc_mlp_set_params(net.handle, f32(W1), f32(b1), f32(W2), f32(b2))
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    losses = []
+    steps = args.epochs * (N // batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(steps):
+        r0 = (st * batch) % (N - batch + 1)
+        pc.pc_mlp_train_step(net.handle, Xin[r0:r0 + batch], Tin[r0:r0 + batch], lr, loss)
+        if st % max(1, steps // 10) == 0 or st == steps - 1:
+            losses.append(round(float(loss.item()), 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    train_flops = 6.0 * 2 * batch * KM * h * steps
+    log(f"training {steps} steps {t_train:.2f} s, losses {losses}")
+    del Xin, Tin
+    # held-out right-hand sides
+    R = inst.R
+    X = to_dev(inst.X)
+    Yd = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.apply([X], [Yd])
+    torch.cuda.synchronize()
+    t_direct = time.perf_counter() - t0
+    ref = Yd.cpu().numpy()
+    res = {}
+    for name, m in (("cold", None), ("warm", net.handle)):
+        Y = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, fb = pc.pc_learned_apply(plan.handle, 0, m, X, Y, 1e-11, args.cg_maxiter)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        e = np.linalg.norm(Y.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        res[name] = {"seconds": t, "rhs_per_s": R / t, "cg_iterations": it, "fallback_to_direct": bool(fb),
+                     "rel_err_vs_direct_max": float(e.max())}
+        log(f"CG {name}: {it} iterations, fallback {fb}, {t:.2f} s, max rel err vs direct {e.max():.2e}")
+    B = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, X, B)
+    Y0 = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
+    pc.pc_mlp_warm_start(net.handle, B, Y0)
+    e0 = np.linalg.norm(Y0.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    net.close()
+    plan.close()
+    out = {"metric": "learned warm start + CG: RHS/s at rel.err<=1e-8 vs the direct solve", "unit": "RHS/s",
+           "value": res["warm"]["rhs_per_s"], "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "dtype": "bf16 network, f64 CG",
+           "config": {"workload": wl.CONFIG_NAMES[5], "n": inst.n, "KM": KM, "heldout_rhs": R, "train_pairs": N,
+                      "hidden": h, "batch": batch, "epochs": args.epochs},
+           "factor_s": t_factor, "pairs_s": t_pairs, "train_s": t_train,
+           "train_tflops": train_flops / t_train / 1e12, "losses": losses,
+           "warm_start_rel_err_median": float(np.median(e0)),
+           "direct_apply_rhs_per_s": R / t_direct, "cg": res}
     print(json.dumps(out))
     return 0
 

@@ -84,13 +84,19 @@ typedef struct {
   double tol;          /* refinement stops for a right-hand side when
                           max|delta| <= tol * max|y|; <= 0 selects 1e-12 */
   int32_t use_graph;   /* 1: capture the apply sequence in a hipGraph and replay it */
-  int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM */
+  int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM, optionally with PC_FLAG_CG_MEMBER_BLOCKS */
 } pc_options;
 
 /* Keep a symmetric copy of each assembled FP64 Gram and the inverses of its
  * 64 x 64 diagonal blocks, for pc_cg_solve / pc_learned_apply (extra
  * 8 (K*M)^2 bytes per instance).  Needs precision PC_PREC_FP64. */
 #define PC_FLAG_KEEP_GRAM 1
+
+/* With PC_FLAG_KEEP_GRAM: precondition CG by the inverses of the K diagonal
+ * M x M member blocks G_kk of the Gram (one block per ensemble member; each
+ * factored by the tile DAG and inverted at pc_gram_factor, K M^2 doubles)
+ * instead of its 64 x 64 diagonal blocks. */
+#define PC_FLAG_CG_MEMBER_BLOCKS 2
 
 typedef struct pc_plan pc_plan;
 

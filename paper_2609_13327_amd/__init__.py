@@ -34,6 +34,7 @@ PC_PREC_FP32_REFINE = 1
 PC_PREC_BF16_REFINE = 2
 
 PC_FLAG_KEEP_GRAM = 1
+PC_FLAG_CG_MEMBER_BLOCKS = 2
 PC_MLP_BF16 = 0
 PC_MLP_FP32 = 1
 

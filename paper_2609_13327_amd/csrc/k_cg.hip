@@ -330,4 +330,93 @@ hipError_t launch_cg_step(const double* P, const double* Q, double* Y, int64_t l
   return hipGetLastError();
 }
 
+
+// ---------------------------------------- member block-Jacobi application
+// z[o_k + i] = sum_c Dinv_k[i, c] r[o_k + c] for every member block k
+// (o_k = k M), all right-hand sides; Dinv_k is Mp x Mp (ld Mp).
+struct MemberApply {
+  static constexpr int BM = 64, BN = 64, WM = 2, WN = 2, KC = 16;
+  static constexpr int LDA = BM + 16, LDB = BN + 1;
+  static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
+  const double* Dinv; const double* Rm; double* Zm;
+  int64_t ld, M, Mp, R;
+  int ntr, ntc, nblk;
+  struct Ctx { bool valid; int64_t kb, i0, c0; int nchunks; };
+  struct ARegs { double v[NA]; };
+  struct BRegs { double v[NB_]; };
+  __device__ Ctx ctx(int tile) const {
+    Ctx c;
+    const int per = ntr * ntc;
+    c.kb = tile / per;
+    const int u = tile % per, tr = u % ntr, tc = u / ntr;
+    c.valid = c.kb < nblk;
+    c.i0 = (int64_t)tr * BM;
+    c.c0 = (int64_t)tc * BN;
+    c.nchunks = (int)((M + KC - 1) / KC);
+    return c;
+  }
+  __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {   // As[k][row] = Dinv_k(i0 + row, k)
+    const double* A = Dinv + c.kb * Mp * Mp;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q, row = e % BM, kk = e / BM;
+      const int64_t i = c.i0 + row, k = (int64_t)chunk * KC + kk;
+      r.v[q] = (i < M && k < M) ? A[i + k * Mp] : 0.0;
+    }
+  }
+  __device__ void storeA(const ARegs& r, double* As) const {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[(e / BM) * LDA + e % BM] = r.v[q];
+    }
+  }
+  __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {   // Bs[k][col] = r(o_k + k, c0 + col)
+    const double* B = Rm + c.kb * M;
+#pragma unroll
+    for (int q = 0; q < NB_; ++q) {
+      const int e = threadIdx.x + 256 * q, kk = e % KC, col = e / KC;
+      const int64_t k = (int64_t)chunk * KC + kk, cc = c.c0 + col;
+      r.v[q] = (k < M && cc < R) ? B[k + cc * ld] : 0.0;
+    }
+  }
+  __device__ void storeB(const BRegs& r, double* Bs) const {
+#pragma unroll
+    for (int q = 0; q < NB_; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      Bs[(e % KC) * LDB + e / KC] = r.v[q];
+    }
+  }
+  __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
+    acc.for_each([&](int row, int col, double v) {
+      const int64_t i = c.i0 + row, cc = c.c0 + col;
+      if (i < M && cc < R) Zm[(c.kb * M + i) + cc * ld] = v;
+    });
+  }
+};
+
+hipError_t launch_member_apply(const double* Dinv, int64_t K, int64_t M, int64_t Mp, const double* Rm, double* Zm,
+                               int64_t ld, int64_t R, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  MemberApply g;
+  g.Dinv = Dinv; g.Rm = Rm; g.Zm = Zm; g.ld = ld; g.M = M; g.Mp = Mp; g.R = R;
+  g.ntr = (int)ceil_div(M, MemberApply::BM);
+  g.ntc = (int)ceil_div(R, MemberApply::BN);
+  g.nblk = (int)K;
+  hipLaunchKernelGGL(gemm_f64_kernel<MemberApply>, dim3((unsigned)(K * g.ntr * g.ntc)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// rows [from, to) of every column set to zero
+__global__ void zero_rows_kernel(double* __restrict__ Z, int64_t ld, int64_t from, int64_t to) {
+  const int64_t c = blockIdx.y;
+  for (int64_t i = from + threadIdx.x; i < to; i += blockDim.x) Z[i + c * ld] = 0.0;
+}
+
+hipError_t launch_zero_rows(double* Z, int64_t ld, int64_t from, int64_t to, int64_t R, hipStream_t s) {
+  if (R <= 0 || to <= from) return hipSuccess;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3(1, (unsigned)R), dim3(64), 0, s, Z, ld, from, to);
+  return hipGetLastError();
+}
+
 }  // namespace pc

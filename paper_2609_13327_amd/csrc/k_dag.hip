@@ -1100,4 +1100,57 @@ hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s)
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------- member-block inverses
+// The inverse of one diagonal member block G_kk (rows and columns o..o+M of
+// the symmetric Gram copy Gs) for the block-Jacobi preconditioner of CG:
+// the block is copied to D (Mp x Mp, identity padding), factored by the tile
+// DAG and inverted by a forward and a backward solve on the identity.
+// ctr: [0] error flag, then the DAG states and head, then the solve flags and
+// head (2 (Mp/64)^2 + 3 ints).
+__global__ void member_block_copy_kernel(const double* __restrict__ Gs, int64_t ld, int64_t o, int64_t M, int64_t Mp,
+                                         double* __restrict__ D, double* __restrict__ d0) {
+  const int64_t c = blockIdx.y;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < Mp; r += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (r < M && c < M) ? Gs[(o + r) + (o + c) * ld] : (r == c ? 1.0 : 0.0);
+    D[r + c * Mp] = v;
+    if (r == c) d0[r] = v;
+  }
+}
+
+hipError_t launch_member_block_inverse(const double* Gs, int64_t ld, int64_t o, int64_t M, int64_t Mp, double* D,
+                                       double* d0, double* Linv, int* ctr, const int64_t* offs, int64_t ntasks,
+                                       const double* I, double* Wk, double* Dinv, int* info, hipStream_t s) {
+  const int Tb = (int)(Mp / T64);
+  hipLaunchKernelGGL(member_block_copy_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(Mp, 256), 8), (unsigned)Mp),
+                     dim3(256), 0, s, Gs, ld, o, M, Mp, D, d0);
+  const int64_t nctr = 2 * (int64_t)Tb * Tb + 3;
+  hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nctr, 256), 64)), dim3(256), 0, s, ctr,
+                     nctr);
+  CholBatch b{};
+  CholArgs& a = b.one;
+  a.G = D; a.ld = Mp; a.T = Tb; a.KM = M; a.diag0 = d0; a.Linv = Linv;
+  a.state = ctr + 1; a.head = a.state + (int64_t)Tb * Tb; a.err = ctr; a.info = info;
+  a.offs = offs; a.ntasks = ntasks; a.col_off = o;
+  b.ntasks = ntasks; b.head = a.head; b.err = a.err;
+  hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, b);
+  SolveBatch sb{};
+  SolveArgs& v = sb.one;
+  v.G = D; v.ld = Mp; v.T = Tb; v.Linv = Linv;
+  v.R = Mp; v.Rp = nullptr; v.nrt = Tb;
+  v.flags = a.head + 1; v.info = info; v.skip = nullptr;
+  sb.ntasks = (int64_t)Tb * Tb; sb.head = v.flags + (int64_t)Tb * Tb; sb.err = ctr;
+  const int64_t nflags = (int64_t)Tb * Tb + 1;
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), sb.ntasks);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 64)), dim3(256), 0, s,
+                       v.flags, nflags);
+    sb.backward = pass;
+    if (pass == 0) { v.In = I; v.ldIn = Mp; v.Out = Wk; v.ldOut = Mp; }
+    else { v.In = Wk; v.ldIn = Mp; v.Out = Dinv; v.ldOut = Mp; }
+    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, sb);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace pc

@@ -57,6 +57,15 @@ struct Inst {
   double* cg = nullptr;      // four KMp x max_rhs buffers: r, z, p, q
   struct CgCol* cgcol = nullptr;
   int* cg_flags = nullptr;   // [0] converged columns, [1] block-Jacobi pivot failure
+  // member block-Jacobi (PC_FLAG_CG_MEMBER_BLOCKS): inverses of the K diagonal M x M blocks
+  int64_t cgm_Mp = 0;        // M rounded up to 64
+  double* cgm_Dinv = nullptr;   // K x Mp x Mp
+  double* cgm_work = nullptr;   // 2 x Mp x Mp: block copy, forward-solve result
+  double* cgm_I = nullptr;      // Mp x Mp identity
+  double* cgm_d0 = nullptr;     // Mp: diagonal of the block copy
+  double* cgm_Linv = nullptr;   // (Mp/64) x 64 x 64
+  int* cgm_ctr = nullptr;       // DAG and solve counters of one block
+  int64_t* cgm_offs = nullptr; int64_t cgm_ntasks = 0;
   // launch-shape choices of the autotuner (0: built-in heuristic)
   int tune_gram_split = 0;   // FP64 Gram: 1 or 2 contraction parts
   int tune_ztx_split = 0;    // Z^T x: 1 or 2 contraction parts
@@ -170,6 +179,12 @@ hipError_t launch_bj_setup(const double* Gs, int64_t ld, int64_t T, double* Dinv
 hipError_t launch_bj_apply(const double* Dinv, int64_t T, const double* Rm, double* Zm, int64_t ld, int64_t R,
                            hipStream_t s);
 // Q = Gs P (KMp x KMp times KMp x R), all ld = ld
+hipError_t launch_member_apply(const double* Dinv, int64_t K, int64_t M, int64_t Mp, const double* Rm, double* Zm,
+                               int64_t ld, int64_t R, hipStream_t s);
+hipError_t launch_zero_rows(double* Z, int64_t ld, int64_t from, int64_t to, int64_t R, hipStream_t s);
+hipError_t launch_member_block_inverse(const double* Gs, int64_t ld, int64_t o, int64_t M, int64_t Mp, double* D,
+                                       double* d0, double* Linv, int* ctr, const int64_t* offs, int64_t ntasks,
+                                       const double* I, double* Wk, double* Dinv, int* info, hipStream_t s);
 hipError_t launch_gram_matmul(const double* Gs, int64_t KMp, const double* P, double* Q, int64_t ld, int64_t R,
                               hipStream_t s);
 // r = b - Q (Q may be null: cold start, y = 0); a zero column b gives y = 0 and is done

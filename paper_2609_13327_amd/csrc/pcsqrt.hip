@@ -70,6 +70,10 @@ void free_inst(Inst& in) {
   hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
   hipFree(in.blk_P); hipFree(in.blk_X); hipFree(in.blk_I); hipFree(in.blk_offs); hipFree(in.blk_offs_tail);
+  hipFree(in.cgm_Dinv); hipFree(in.cgm_work); hipFree(in.cgm_I); hipFree(in.cgm_d0); hipFree(in.cgm_Linv);
+  hipFree(in.cgm_ctr); hipFree(in.cgm_offs);
+  in.cgm_Dinv = in.cgm_work = in.cgm_I = in.cgm_d0 = in.cgm_Linv = nullptr;
+  in.cgm_ctr = nullptr; in.cgm_offs = nullptr;
   in.blk_P = in.blk_X = in.blk_I = nullptr; in.blk_offs = in.blk_offs_tail = nullptr;
   in.Gs = in.Dinv = in.cg = nullptr; in.cgcol = nullptr; in.cg_flags = nullptr;
   in.dag = nullptr; in.chol_offs = nullptr; in.ctl = nullptr;
@@ -170,6 +174,22 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   if (KMp > kBlockedAbove && e == hipSuccess) {
     const pc_status bs = alloc_blocked(in, 1024);
     if (bs != PC_OK) return bs;
+  }
+  if (flags & PC_FLAG_CG_MEMBER_BLOCKS) {
+    const int64_t Mp = pc::round_up(in.M, pc::NB), Tb = Mp / pc::NB;
+    in.cgm_Mp = Mp;
+    chk(dalloc(&in.cgm_Dinv, in.K * Mp * Mp));
+    chk(dalloc(&in.cgm_work, 2 * Mp * Mp));
+    chk(dalloc(&in.cgm_I, Mp * Mp));
+    chk(dalloc(&in.cgm_d0, Mp));
+    chk(dalloc(&in.cgm_Linv, Tb * pc::NB * pc::NB));
+    chk(dalloc(&in.cgm_ctr, 2 * Tb * Tb + 3));
+    std::vector<int64_t> mo;
+    in.cgm_ntasks = pc::chol_task_offsets((int)Tb, mo);
+    chk(dalloc(&in.cgm_offs, (int64_t)mo.size()));
+    if (e == hipSuccess) chk(hipMemcpy(in.cgm_offs, mo.data(), sizeof(int64_t) * mo.size(), hipMemcpyHostToDevice));
+    if (e == hipSuccess) chk(pc::launch_identity(in.cgm_I, Mp, nullptr));
+    if (e == hipSuccess) chk(hipDeviceSynchronize());
   }
   if (flags & PC_FLAG_KEEP_GRAM) {
     chk(dalloc(&in.Gs, KMp * KMp));
@@ -407,7 +427,12 @@ pc_status run_cg(pc_plan* p, Inst& in, const double* Bm, int64_t ldB, int64_t R,
   if (warm) PC_TRY(pc::launch_gram_matmul(in.Gs, KMp, in.Y, q, ld, R, s));
   PC_TRY(pc::launch_cg_start(Bm, ldB, warm ? q : nullptr, r, in.Y, ld, ld, in.KM, KMp, R, tol, in.cgcol,
                              in.cg_flags, s));
-  PC_TRY(pc::launch_bj_apply(in.Dinv, T, r, z, ld, R, s));
+  auto precond = [&]() -> hipError_t {
+    return in.cgm_Dinv ? pc::launch_member_apply(in.cgm_Dinv, in.K, in.M, in.cgm_Mp, r, z, ld, R, s)
+                       : pc::launch_bj_apply(in.Dinv, T, r, z, ld, R, s);
+  };
+  if (in.cgm_Dinv) PC_TRY(pc::launch_zero_rows(z, ld, in.KM, KMp, R, s));   // padding rows stay zero
+  PC_TRY(precond());
   PC_TRY(pc::launch_cg_dir(r, z, pv, ld, KMp, R, in.cgcol, 1, s));
   int ndone = 0;
   for (int it = 1; it <= maxiter; ++it) {
@@ -418,7 +443,7 @@ pc_status run_cg(pc_plan* p, Inst& in, const double* Bm, int64_t ldB, int64_t R,
       PC_TRY(hipStreamSynchronize(s));
       if (ndone >= R) break;
     }
-    PC_TRY(pc::launch_bj_apply(in.Dinv, T, r, z, ld, R, s));
+    PC_TRY(precond());
     PC_TRY(pc::launch_cg_dir(r, z, pv, ld, KMp, R, in.cgcol, 0, s));
   }
   std::vector<pc::CgCol> cols((size_t)R);
@@ -532,9 +557,10 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   pc_options o{PC_PREC_FP64, 0, 1e-12, 0, 0};
   if (opt) o = *opt;
   if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16_REFINE || o.max_refine < 0 ||
-      (o.flags & ~PC_FLAG_KEEP_GRAM) != 0 || !std::isfinite(o.tol))
+      (o.flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS)) != 0 || !std::isfinite(o.tol))
     return PC_ERR_INVALID_ARG;
   if ((o.flags & PC_FLAG_KEEP_GRAM) && o.precision != PC_PREC_FP64) return PC_ERR_INVALID_ARG;
+  if ((o.flags & PC_FLAG_CG_MEMBER_BLOCKS) && !(o.flags & PC_FLAG_KEEP_GRAM)) return PC_ERR_INVALID_ARG;
   if (o.tol <= 0) o.tol = 1e-12;
   for (int32_t i = 0; i < count; ++i) {
     const pc_instance& a = inst[i];
@@ -634,7 +660,18 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     if (in.Gs) {
       PC_TRY(pc::launch_gram_symmetrize(in, in.Gs, si));
       PC_TRY(pc::launch_fill_int(in.cg_flags, 0, 2, si));
-      PC_TRY(pc::launch_bj_setup(in.Gs, in.KMp, in.KMp / pc::NB, in.Dinv, in.cg_flags + 1, si));
+      if (in.cgm_Dinv) {
+        // member block-Jacobi: the inverse of every diagonal M x M block
+        PC_TRY(pc::launch_fill_int(in.cg_flags + 1, -1, 1, si));
+        const int64_t Mp = in.cgm_Mp;
+        for (int64_t k = 0; k < in.K; ++k)
+          PC_TRY(pc::launch_member_block_inverse(in.Gs, in.KMp, k * in.M, in.M, Mp, in.cgm_work, in.cgm_d0,
+                                                 in.cgm_Linv, in.cgm_ctr, in.cgm_offs, in.cgm_ntasks, in.cgm_I,
+                                                 in.cgm_work + Mp * Mp, in.cgm_Dinv + k * Mp * Mp, in.cg_flags + 1,
+                                                 si));
+      } else {
+        PC_TRY(pc::launch_bj_setup(in.Gs, in.KMp, in.KMp / pc::NB, in.Dinv, in.cg_flags + 1, si));
+      }
     }
     if (!p->batch) {
       PhaseTimer t(p, PC_PHASE_CHOLESKY, si);

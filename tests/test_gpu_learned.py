@@ -283,3 +283,33 @@ def test_learned_apply_falls_back_to_direct_solve():
     err = np.linalg.norm(host(Y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert err.max() <= 1e-10
     plan.close()
+
+
+def test_cg_member_block_jacobi_matches_oracle():
+    """Preconditioning by the inverses of the K diagonal member blocks G_kk
+    (M = 24, padded to 64): same iteration count as the oracle's CG with
+    blockdiag(G_kk)^{-1}, and the direct solve's answer."""
+    inst = _cg_instance(14)
+    plan = pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_KEEP_GRAM | pc.PC_FLAG_CG_MEMBER_BLOCKS)
+    plan.factor()
+    B = empty(inst.KM, inst.R)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, dev(inst.X), B)
+    Y = empty(inst.KM, inst.R)
+    st, it = pc.pc_cg_solve(plan.handle, 0, B, Y, tol=1e-13, maxiter=1000)
+    assert st == pc.PC_OK
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    err = np.linalg.norm(host(Y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-9, err.max()
+    G = lsq.gram(inst.E, inst.W, 1)
+    pre = cg.block_jacobi(G, inst.K, inst.M)
+    b = host(B)
+    its = [cg.pcg(G, b[:, r], precond=pre, tol=1e-13, maxiter=1000)[1] for r in range(inst.R)]
+    assert abs(it - max(its)) <= 2, (it, max(its))
+    plan.close()
+
+
+def test_member_blocks_need_kept_gram():
+    inst = _cg_instance(15)
+    with pytest.raises(pc.PcError) as e:
+        pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_CG_MEMBER_BLOCKS)
+    assert e.value.status == pc.PC_ERR_INVALID_ARG
