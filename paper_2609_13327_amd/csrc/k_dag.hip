@@ -45,22 +45,31 @@ constexpr int T64 = 64;
 constexpr int LDP = T64 + 1;          // padded LDS stride
 constexpr long long kSpinLimit = 1LL << 22;   // about 0.2 s of polling
 
+// Every buffer these kernels touch is in device (global) memory.  Task
+// arguments are read from LDS or device memory, which leaves their pointers
+// generic; casting them to the global address space keeps the accesses
+// global_load/store instead of flat ones.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) int gint;
+__device__ __forceinline__ gdouble* gp(const double* p) { return (gdouble*)p; }
+__device__ __forceinline__ gint* gp(const int* p) { return (gint*)p; }
+
 __device__ __forceinline__ int ld_acquire(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void st_release(int* p, int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Tile data that other workgroups read while the kernel runs is moved with
 // device-coherent accesses (relaxed atomics at agent scope: they go past the
 // per-XCD L2 caches), so that no cache-wide write-back or invalidate is needed.
 __device__ __forceinline__ double ld_c(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_c(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // All threads: wait until this workgroup's coherent stores have completed,
@@ -80,7 +89,7 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info,
     long long spins = 0;
     while (ld_acquire(flag) < v) {
       if (ld_acquire(info) >= 0 || ld_acquire(err) != 0) { ok = 0; break; }
-      if (++spins > kSpinLimit) { atomicOr(err, 1); ok = 0; break; }
+      if (++spins > kSpinLimit) { atomicOr((int*)gp(err), 1); ok = 0; break; }
       __builtin_amdgcn_s_sleep(2);
     }
     *sh = ok;
@@ -250,7 +259,7 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
   const double thr_scale = 64.0 * (double)a.KM * 1.1102230246251565e-16;
   // pivot thresholds of the 64 columns, read once
   // Sc: 4 x 256 wave scratch, then 64 pivot thresholds, then 64 reciprocal pivots
-  if (t < T64) Sc[1024 + t] = a.diag0[k0 + t] * thr_scale;
+  if (t < T64) Sc[1024 + t] = gp(a.diag0)[k0 + t] * thr_scale;
   __syncthreads();
   for (int p = 0; p < 4; ++p) {
     const int c = 16 * p;
@@ -383,7 +392,7 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int idx = t + 256 * u, r = idx % T64, c = idx / T64;
-    if (r >= c) a.G[(k0 + r) + (k0 + c) * a.ld] = A[r * LDP + c];
+    if (r >= c) gp(a.G)[(k0 + r) + (k0 + c) * a.ld] = A[r * LDP + c];
   }
 }
 
@@ -562,25 +571,31 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
   // TRSM/GEMM: two 64 x 64 operands = 8192 doubles
   __shared__ double buf[2 * T64 * T64];
   __shared__ int sh[4];
+  __shared__ CholArgs sa;
   double* As = buf;
   double* Bs = buf + T64 * T64;
   for (;;) {
     if (threadIdx.x == 0) sh[0] = atomicAdd(b.head, 1);
     __syncthreads();
-    const int64_t g = sh[0];
+    // the task index is the same for the whole workgroup: keep it (and all
+    // that is derived from it) in scalar registers
+    const int64_t g = __builtin_amdgcn_readfirstlane(sh[0]);
     __syncthreads();
     if (g >= b.ntasks) break;
-    CholArgs a;
+    // this task's instance arguments, shared through LDS (a private copy
+    // would live in scratch memory, since the task functions take a reference)
     int64_t t;
     if (b.inst) {
       const DagSeg sg = b.segs[find_seg(b.segs, b.nsegs, g)];
-      a = b.inst[sg.inst];
+      if (threadIdx.x == 0) sa = b.inst[sg.inst];
       t = sg.lstart + (g - sg.gstart);
     } else {
-      a = b.one;
+      if (threadIdx.x == 0) sa = b.one;
       t = g;
     }
-    a.err = b.err;
+    if (threadIdx.x == 0) sa.err = b.err;
+    __syncthreads();
+    const CholArgs& a = sa;
     const int T = a.T;
     const TaskDesc d = decode_task(t, T, a.offs);
     int* st = a.state;
@@ -641,29 +656,39 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
   __shared__ int sh[4];
+  __shared__ SolveArgs sa;
   for (;;) {
     if (threadIdx.x == 0) sh[0] = atomicAdd(b.head, 1);
     __syncthreads();
-    const int64_t g = sh[0];
+    // the task index is the same for the whole workgroup: keep it (and all
+    // that is derived from it) in scalar registers
+    const int64_t g = __builtin_amdgcn_readfirstlane(sh[0]);
     __syncthreads();
     if (g >= b.ntasks) break;
-    SolveArgs a;
     int64_t t;
-    if (b.inst) {
-      const DagSeg sg = b.segs[find_seg(b.segs, b.nsegs, g)];
-      a = b.inst[sg.inst];
-      t = sg.lstart + (g - sg.gstart);
-    } else {
-      a = b.one;
-      t = g;
+    if (threadIdx.x == 0) {
+      if (b.inst) {
+        const DagSeg sg = b.segs[find_seg(b.segs, b.nsegs, g)];
+        sa = b.inst[sg.inst];
+        t = sg.lstart + (g - sg.gstart);
+      } else {
+        sa = b.one;
+        t = g;
+      }
+      if (sa.Rp) sa.R = *sa.Rp;
+      if (b.swap_io && b.backward) {
+        const double* in_ = sa.In; const int64_t ldi = sa.ldIn;
+        sa.In = sa.Out; sa.ldIn = sa.ldOut;
+        sa.Out = const_cast<double*>(in_); sa.ldOut = ldi;
+      }
+      sh[1] = (int)t;
+      sh[3] = (sa.skip && *sa.skip) ? 1 : 0;
     }
-    if (a.skip && *a.skip) continue;
-    if (a.Rp) a.R = *a.Rp;
-    if (b.swap_io && b.backward) {
-      const double* in_ = a.In; const int64_t ldi = a.ldIn;
-      a.In = a.Out; a.ldIn = a.ldOut;
-      a.Out = const_cast<double*>(in_); a.ldOut = ldi;
-    }
+    __syncthreads();
+    t = __builtin_amdgcn_readfirstlane(sh[1]);
+    const bool skipped = sh[3] != 0;
+    const SolveArgs& a = sa;
+    if (skipped) { __syncthreads(); continue; }
     const int step = (int)(t / a.nrt), rt = (int)(t % a.nrt);
     if ((int64_t)rt * T64 >= a.R) continue;            // beyond this call's right-hand sides
     const int i = b.backward ? a.T - 1 - step : step;
@@ -679,8 +704,8 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
-        if (!b.backward) As[q * T64 + p] = a.G[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
-        else As[p * T64 + q] = a.G[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
+        if (!b.backward) As[q * T64 + p] = gp(a.G)[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
+        else As[p * T64 + q] = gp(a.G)[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
       }
       if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) { ok = false; break; }
       {
@@ -721,7 +746,7 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     }
     if (!ok) continue;
     // Out_i = Linv_i (or its transpose) * acc
-    const double* Lb = a.Linv + (int64_t)i * T64 * T64;
+    const gdouble* Lb = gp(a.Linv + (int64_t)i * T64 * T64);
     acc.for_each([&](int r, int c, double v) { Bs[r * T64 + c] = v; });
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
