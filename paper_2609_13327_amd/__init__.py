@@ -82,6 +82,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run __graft_entry__.build() or paper_2609_13327_amd/build.py)")
+    # PyTorch brings its own HIP runtime; importing it first makes the library
+    # bind to that one, so that one runtime owns the device in this process
+    # (a second runtime loaded before it cannot allocate device memory).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     lib.pc_sqrt_build.argtypes = [POINTER(PcInstance), c_int32, POINTER(PcOptions), c_void_p,
                                   POINTER(c_void_p)]

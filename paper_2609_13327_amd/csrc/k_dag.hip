@@ -100,13 +100,6 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info,
   return ok;
 }
 
-__device__ __forceinline__ double rdlane(double x, int lane) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
-}
-
 struct TaskDesc { int type, i, j, k; };   // type 0 DIAG(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
 
 // t -> task in the order described above; offs[k] is the first index of
@@ -139,6 +132,7 @@ __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) 
 struct CholArgs {
   double* G; int64_t ld; int T; int64_t KM;
   const double* diag0; double* Linv;
+  double* Lt;               // final strictly-lower tiles, tile-major (null: read them from G)
   int* state; int* head; int* info; int* err;
   const int64_t* offs; int64_t ntasks;
   int64_t col_off;          // column of G's first row/column in the whole matrix (failure reports)
@@ -216,6 +210,41 @@ __device__ __forceinline__ void lds_sw_to_global(const double* S, const TileRegs
   }
 }
 
+// Final tiles L_ik (i > k) are also written once, tile-major, to a buffer
+// that nothing reads before its producer has published the tile: those reads
+// can go through the caches (no stale line can exist), unlike the tiles of G,
+// which change while the kernel runs.
+__device__ __forceinline__ int64_t lt_off(int i, int k) {
+  return ((int64_t)i * (i - 1) / 2 + k) * (T64 * T64);
+}
+__device__ __forceinline__ void ltile_load(const CholArgs& a, int i, int k, TileRegs& t) {
+  if (a.Lt) {
+    const gdouble* p = gp(a.Lt) + lt_off(i, k);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t.v[q] = p[threadIdx.x + 256 * q];
+  } else {
+    tile_load(a.G, a.ld, (int64_t)i * T64, (int64_t)k * T64, t);
+  }
+}
+
+// X Linv^T for a 64 x 64 tile X (As[c * 64 + r] = X[r][c]) and the inverse of
+// a diagonal tile (Bs[c * 64 + r] = Linv[r][c]).  Linv is lower triangular,
+// so output columns 16 f.. need only the first 16 (f + 1) contraction
+// indices.  Wave w computes rows 16 w.. of the four 16-column fragments:
+// acc4[f][v] is element (16 w + (lane >> 4) + 4 v, 16 f + (lane & 15)).
+__device__ __forceinline__ void mul_linv_t(const double* As, const double* Bs, d4 acc4[4]) {
+  const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
+#pragma unroll
+  for (int f = 0; f < 4; ++f) acc4[f] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < T64; kk += 4) {
+    const double av = As[(kk + (l >> 4)) * T64 + 16 * w + (l & 15)];
+#pragma unroll
+    for (int f = kk / 16; f < 4; ++f)
+      acc4[f] = mfma_f64(av, Bs[(kk + (l >> 4)) * T64 + 16 * f + (l & 15)], acc4[f]);
+  }
+}
+
 // ---- 16 x 16 MFMA fragments on LDS matrices stored row-major (M[r * ld + c]).
 // A operand A[r][k] = M[r0 + r][c0 + k]; transposed-B operand B[k][n] = M[r0 + n][c0 + k]
 // uses the same addressing; plain B operand B[k][n] = M[r0 + k][c0 + n].
@@ -240,12 +269,29 @@ __device__ __forceinline__ d4 fr_load(const double* M, int ld, int r0, int c0) {
   return acc;
 }
 
-// Diagonal tile, blocked by 16: for each 16-column panel, one wave factors the
-// 16 x 16 diagonal block in registers (row per lane) and inverts it; the
-// panel below is solved with that inverse and the trailing lower part is
-// updated with MFMA.  The inverse of the whole tile is then assembled block
-// by block: Y_pp = X_pp and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq, wave q
-// owning block column q.  LDS: A (64 x 65), X (4 x 16 x 16), scratch (4 x 256).
+// Broadcast of lane l of each row of 16 lanes to the whole row (DPP
+// row_newbcast: one VALU move, no scalar round trip).  `l` must fold to a
+// constant after unrolling.
+__device__ __forceinline__ double bcast16(double v, int l) {
+#define PC_BC(n) case n: return __builtin_amdgcn_mov_dpp(v, 0x150 + n, 0xf, 0xf, false);
+  switch (l) {
+    PC_BC(0) PC_BC(1) PC_BC(2) PC_BC(3) PC_BC(4) PC_BC(5) PC_BC(6) PC_BC(7)
+    PC_BC(8) PC_BC(9) PC_BC(10) PC_BC(11) PC_BC(12) PC_BC(13) PC_BC(14)
+    default: return __builtin_amdgcn_mov_dpp(v, 0x15f, 0xf, 0xf, false);
+  }
+#undef PC_BC
+}
+
+// Diagonal tile, blocked by 16.  For each 16-column panel one wave factors
+// the whole column panel (rows c..63) right-looking, column by column: every
+// row of 16 lanes holds a copy of the 16 x 16 diagonal block (lane r: row r)
+// and up to 16 rows of the panel below it, so the broadcasts of L_qj that
+// the updates need stay inside a row (DPP) and the panel is solved in the
+// same sweep.  The trailing lower part is then updated with MFMA.  After the
+// last panel the four waves invert the four 16 x 16 diagonal blocks in
+// parallel, and the inverse of the whole tile is assembled block by block:
+// Y_pp = X_pp and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq, wave q owning block
+// column q.  LDS: A (64 x 65), X (4 x 16 x 16), scratch (4 x 256).
 // Factor the 64 x 64 lower triangle held in A (LDS, row-major, stride LDP)
 // and form its inverse; publish the inverse (Linv) and the factor of tile
 // (k,k).  If pend_flag is set, the flag is published after the first panel
@@ -255,64 +301,55 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int64_t k0 = (int64_t)k * T64;
   if (t == 0) sh[1] = -1;
-  __syncthreads();
   const double thr_scale = 64.0 * (double)a.KM * 1.1102230246251565e-16;
   // pivot thresholds of the 64 columns, read once
-  // Sc: 4 x 256 wave scratch, then 64 pivot thresholds, then 64 reciprocal pivots
+  // Sc: 4 x 256 wave scratch, then 64 pivot thresholds
   if (t < T64) Sc[1024 + t] = gp(a.diag0)[k0 + t] * thr_scale;
   __syncthreads();
   for (int p = 0; p < 4; ++p) {
     const int c = 16 * p;
     if (w == 0) {
-      // Factor the 16 x 16 diagonal block and invert it in registers: lane r
-      // (< 16) holds row r.  Branch-free: the pivots are checked once at the end.
-      const int r = lane & 15;
-      double row[16];
+      // lane 16 s + r: diagonal-block row c + r (dg) and panel row
+      // c + 16 + 16 s + r (pr) when that row exists.  Branch-free: the
+      // pivots are checked once at the end.
+      const int r = lane & 15, s = lane >> 4;
+      const int prow = c + 16 + 16 * s + r;
+      const bool has = prow < T64;
+      const int lrow = has ? prow : c + r;      // rows past the tile compute on a copy, never stored
+      double dg[16], pr[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) row[q] = A[(c + r) * LDP + c + q];
-      double worst = 1.0;                 // min over pivots of piv / threshold (NaN-safe below)
+      for (int q = 0; q < 16; ++q) dg[q] = A[(c + r) * LDP + c + q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pr[q] = A[lrow * LDP + c + q];
+      int fail = 16;                      // first failing pivot of this panel
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double piv = rdlane(row[j], j);
+        const double piv = bcast16(dg[j], j);
         const double thr = Sc[1024 + c + j];
-        worst = fmin(worst, (piv > thr && isfinite(piv)) ? 1.0 : -1.0);
+        if (!(piv > thr && isfinite(piv))) fail = fail < j ? fail : j;
         const double inv = rsqrt(piv);
-        row[j] *= inv;                    // lanes > j: L_rj; lane j: piv / sqrt(piv) = L_jj
+        dg[j] *= inv;                     // lanes r > j: L_rj; lane j: piv / sqrt(piv) = L_jj
+        pr[j] *= inv;
 #pragma unroll
-        for (int q = j + 1; q < 16; ++q) row[q] = fma(-row[j], rdlane(row[j], q), row[q]);
+        for (int q = j + 1; q < 16; ++q) {
+          const double lqj = bcast16(dg[j], q);
+          dg[q] = fma(-dg[j], lqj, dg[q]);
+          pr[q] = fma(-pr[j], lqj, pr[q]);
+        }
+        // finish the panel rows' updates in this step (the instruction
+        // selector would otherwise defer them and keep every broadcast live)
+#pragma unroll
+        for (int q = j; q < 16; ++q) asm volatile("" : "+v"(pr[q]));
       }
-      if (worst < 0.0) {
-        if (lane == 0) {
-          // first failing column, for the report
-          int f = 0;
-          for (int j = 0; j < 16; ++j) {
-            if (!(A[(c + j) * LDP + c + j] > Sc[1024 + c + j])) { f = j; break; }
-          }
-          sh[1] = (int)(a.col_off + k0 + c + f);
-        }
-      } else {
+      // Stores are unconditional (lanes without a panel row write to the
+      // wave scratch), so no part of the sweep is sunk into a branch.
+      // Every row of 16 lanes writes the same diagonal block.
+      double* pdst = has ? A + prow * LDP + c : Sc + lane * 16;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) row[q] = (q <= r) ? row[q] : 0.0;   // clean upper part
-        const double rdiag = 1.0 / row[r];
-        // forward substitution, all lanes at once; lane r keeps L_rr * X[r][.]
-        double x[16];
+      for (int q = 0; q < 16; ++q) A[(c + r) * LDP + c + q] = (q <= r) ? dg[q] : 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) x[q] = (q == r) ? 1.0 : 0.0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const double dj = rdlane(rdiag, j);
-          const double lrj = (r == j) ? 0.0 : row[j];
-#pragma unroll
-          for (int q = 0; q <= j; ++q) x[q] = fma(-lrj, rdlane(x[q], j) * dj, x[q]);
-        }
-        if (lane < 16) {
-#pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            A[(c + r) * LDP + c + q] = row[q];
-            X[p * 256 + r * 16 + q] = (q <= r) ? x[q] * rdiag : 0.0;
-          }
-        }
-      }
+      for (int q = 0; q < 16; ++q) pdst[q] = pr[q];
+      if (fail < 16 && lane == 0) sh[1] = (int)(a.col_off + k0 + c + fail);
     }
     __syncthreads();
     if (sh[1] >= 0) {
@@ -320,15 +357,6 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
       return;
     }
     const int nf = 3 - p;                 // 16-row fragments below the diagonal block
-    if (w < nf) {                         // panel: P = A[rows, c:c+16] * X_pp^T
-      const int r0 = c + 16 + 16 * w;
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4)
-        acc = mfma_f64(fr_a(A, LDP, r0, c, kk), fr_a(X + p * 256, 16, 0, 0, kk), acc);
-      fr_store(A, LDP, r0, c, acc);
-    }
-    __syncthreads();
     // trailing lower fragments (fi >= fj) of A[c+16:, c+16:] -= P P^T
     for (int f = w; f < nf * (nf + 1) / 2; f += 4) {
       int fi = 0;
@@ -345,6 +373,32 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
     __syncthreads();
     if (p == 0 && pend_flag && t == 0) st_release(pend_flag, pend_val);
   }
+  // inverses of the diagonal blocks, wave q block q, by forward substitution
+  // (lane r: row r; row j of X is final at step j, X_jq = x_j[q] / L_jj)
+  {
+    const int r = lane & 15, c = 16 * w;
+    double row[16], x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) row[q] = (q <= r) ? A[(c + r) * LDP + c + q] : 0.0;
+    const double rdiag = 1.0 / A[(c + r) * LDP + c + r];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = (q == r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      // -L_rj / L_jj for rows below j (row[j] is 0 above the diagonal).  The
+      // broadcast runs on all lanes: a DPP move reading a lane that is
+      // switched off does not return that lane's value.
+      const double dj = bcast16(rdiag, j);
+      const double f = (r == j) ? 0.0 : -row[j] * dj;
+#pragma unroll
+      for (int q = 0; q <= j; ++q) x[q] = fma(f, bcast16(x[q], j), x[q]);
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) X[w * 256 + r * 16 + q] = (q <= r) ? x[q] * rdiag : 0.0;
+    }
+  }
+  __syncthreads();
   // block inverse: wave q fills block column q.  The diagonal blocks are X;
   // an off-diagonal block Y_pq (p > q) is kept transposed in the unused upper
   // triangle of A (rows 16q.., columns 16p..), which L never touches.
@@ -433,8 +487,8 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
   if (k >= 2) {                                         // its last update, from column k-2
     TileF64<T64, T64, 2, 2> upd;
     TileRegs ta, tb;
-    tile_load(a.G, a.ld, k0, p0 - T64, ta);             // L_{k,k-2}
-    tile_load(a.G, a.ld, p0, p0 - T64, tb);             // L_{k-1,k-2}
+    ltile_load(a, k, k - 2, ta);                        // L_{k,k-2}
+    ltile_load(a, k - 1, k - 2, tb);                    // L_{k-1,k-2}
     tile_store_lds(ta, As, -1.0);
     tile_store_lds(tb, Bs, 1.0);
     __syncthreads();
@@ -459,22 +513,56 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
     tile_store_lds(tl, Bs, 1.0);
   }
   __syncthreads();
-  TileF64<T64, T64, 2, 2> acc;
-  acc.zero();
-  acc.template mma<T64, T64, T64>(As, Bs);              // L_{k,k-1}
-  __syncthreads();
-  acc.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+  {
+    // L_{k,k-1} = G' Linv_{k-1}^T
+    const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
+    d4 acc4[4];
+    mul_linv_t(As, Bs, acc4);
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) As[(16 * f + (l & 15)) * T64 + 16 * w + (l >> 4) + 4 * v] = acc4[f][v];
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 16; ++q) {                        // L_{k,k-1} out (published later)
     const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
     st_c(&a.G[(k0 + r) + (p0 + c) * a.ld], As[idx]);
   }
-  acc.zero();
-  acc.template mma<T64, T64, T64>(As, As);              // L_{k,k-1} L_{k,k-1}^T
-  __syncthreads();
+  if (a.Lt) {
+    double* lt = a.Lt + lt_off(k, k - 1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) st_c(&lt[threadIdx.x + 256 * q], As[threadIdx.x + 256 * q]);
+  }
   double* A = buf;
-  acc.for_each([&](int r, int c, double v) { A[r * LDP + c] = -v; });
+  {
+    // L_{k,k-1} L_{k,k-1}^T on the ten lower 16 x 16 fragments, three or two
+    // per wave: w0 (0,0) (3,0) (3,1), w1 (1,0) (1,1) (3,2), w2 (2,0) (2,1),
+    // w3 (2,2) (3,3)
+    const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
+    const int nf = w < 2 ? 3 : 2;
+    int fi[3], fj[3];
+    fi[0] = w < 2 ? w : 2;  fj[0] = w == 3 ? 2 : (w == 1 ? 0 : 0);
+    fi[1] = w == 0 ? 3 : (w == 1 ? 1 : (w == 2 ? 2 : 3));  fj[1] = w == 0 ? 0 : (w == 1 ? 1 : (w == 2 ? 1 : 3));
+    fi[2] = 3;  fj[2] = w == 0 ? 1 : 2;
+    d4 sy[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) sy[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < T64; kk += 4) {
+      const double* col = As + (kk + (l >> 4)) * T64 + (l & 15);
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+        if (u < nf) sy[u] = mfma_f64(col[16 * fi[u]], col[16 * fj[u]], sy[u]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (u < nf)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(16 * fi[u] + (l >> 4) + 4 * v) * LDP + 16 * fj[u] + (l & 15)] = -sy[u][v];
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -489,9 +577,11 @@ __device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, d
   const int64_t i0 = (int64_t)i * T64, j0 = (int64_t)j * T64, k0 = (int64_t)k * T64;
   TileF64<T64, T64, 2, 2> acc;
   TileRegs tc, ta, tb;
-  tile_load(a.G, a.ld, i0, j0, tc);                   // G_ij          (all loads in flight)
-  tile_load(a.G, a.ld, i0, k0, ta);                   // L_ik
-  tile_load(a.G, a.ld, j0, k0, tb);                   // L_jk
+  // all loads in flight; the operands first, so that the product can start
+  // while G_ij is still arriving (loads complete in order)
+  ltile_load(a, i, k, ta);                            // L_ik
+  ltile_load(a, j, k, tb);                            // L_jk
+  tile_load(a.G, a.ld, i0, j0, tc);                   // G_ij
   tile_store_lds(ta, As, -1.0);
   tile_store_lds(tb, Bs, 1.0);
   __syncthreads();
@@ -510,12 +600,12 @@ __device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, d
 __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* As, double* Bs, int* sh) {
   const int64_t i0 = (int64_t)i * T64, k0 = (int64_t)k * T64;
   TileRegs tc;
-  tile_load(a.G, a.ld, i0, k0, tc);                   // G_ik
   if (k >= 1) {
     TileF64<T64, T64, 2, 2> upd;
     TileRegs ta, tb;
-    tile_load(a.G, a.ld, i0, k0 - T64, ta);           // L_{i,k-1}
-    tile_load(a.G, a.ld, k0, k0 - T64, tb);           // L_{k,k-1}
+    ltile_load(a, i, k - 1, ta);                      // L_{i,k-1}
+    ltile_load(a, k, k - 1, tb);                      // L_{k,k-1}
+    tile_load(a.G, a.ld, i0, k0, tc);                 // G_ik (arrives while the product runs)
     tile_store_lds(ta, As, -1.0);
     tile_store_lds(tb, Bs, 1.0);
     __syncthreads();
@@ -527,6 +617,7 @@ __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* 
 #pragma unroll
     for (int q = 0; q < 16; ++q) As[threadIdx.x + 256 * q] += tc.v[q];   // As[c][r] = updated G_ik
   } else {
+    tile_load(a.G, a.ld, i0, k0, tc);                 // G_ik
     tile_store_lds(tc, As, 1.0);                      // As[c][r] = G[i0+r][k0+c]
   }
   if (!wait_ge(&a.state[(int64_t)k * a.T + k], k + 1, a.info, a.err, &sh[2])) return false;
@@ -535,13 +626,26 @@ __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* 
   tile_load(Lb, T64, 0, 0, tb);                       // Bs[c][r] = Linv[r][c]
   tile_store_lds(tb, Bs, 1.0);
   __syncthreads();
-  TileF64<T64, T64, 2, 2> acc;
-  acc.zero();
-  acc.template mma<T64, T64, T64>(As, Bs);
-  __syncthreads();
-  acc_to_lds_sw(acc, As);
+  {
+    const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
+    d4 acc4[4];
+    mul_linv_t(As, Bs, acc4);                         // L_ik = G'_ik Linv_k^T
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) As[sw64(16 * w + (l >> 4) + 4 * v, 16 * f + (l & 15))] = acc4[f][v];
+  }
   __syncthreads();
   lds_sw_to_global(As, nullptr, a.G, a.ld, i0, k0, T64, false);
+  if (a.Lt) {
+    double* lt = a.Lt + lt_off(i, k);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      st_c(&lt[idx], As[sw64(idx % T64, idx / T64)]);
+    }
+  }
   return true;
 }
 
@@ -574,6 +678,9 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
   __shared__ CholArgs sa;
   double* As = buf;
   double* Bs = buf + T64 * T64;
+  // Final tiles are read through the caches: drop whatever lines this
+  // compute unit's caches still hold from before the launch.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   for (;;) {
     if (threadIdx.x == 0) sh[0] = atomicAdd(b.head, 1);
     __syncthreads();
@@ -633,9 +740,15 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
 // Forward: task (i, rt) in order i ascending: acc = B_i - sum_{j<i} L_ij Z_j,
 // Z_i = Linv_i acc.  Backward: i descending: acc = Z_i - sum_{j>i} L_ji^T Y_j,
 // Y_i = Linv_i^T acc.  flag[i * nrt + rt] = 1 once the block row is written.
+// With the folded products (Mf, Mb) the update from the previous block row
+// comes last and after the multiplication by the inverse:
+//   Z_i = Linv_i (B_i - sum_{j<i-1} L_ij Z_j) - Mf_i Z_{i-1},   Mf_i = Linv_i L_{i,i-1}
+//   Y_i = Linv_i^T (Z_i - sum_{j>i+1} L_ji^T Y_j) - Mb_i Y_{i+1}, Mb_i = Linv_i^T L_{i+1,i}^T
+// so that the chain from one block row to the next crosses one product.
 struct SolveArgs {
   const double* G; int64_t ld; int T;
   const double* Linv;
+  const double* Mf; const double* Mb;   // folded products (column-major, 64 x 64 per block row) or null
   const double* In; int64_t ldIn;
   double* Out; int64_t ldOut;
   int64_t R; const int64_t* Rp;   // right-hand sides: *Rp when Rp is set, else R
@@ -697,7 +810,10 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     tile_to_acc(a.In, a.ldIn, i0, r0, acc, a.R - r0);    // acc = In[i block, rt]
     bool ok = true;
     const int nprev = b.backward ? (a.T - 1 - i) : i;
-    for (int s = 0; s < nprev && ok; ++s) {
+    const double* Mfold = b.backward ? a.Mb : a.Mf;
+    const bool fold = Mfold != nullptr && nprev > 0;
+    const int nloop = fold ? nprev - 1 : nprev;         // the previous block row is folded
+    for (int s = 0; s < nloop && ok; ++s) {
       const int j = b.backward ? a.T - 1 - s : s;       // producers in their own order
       const int64_t j0 = (int64_t)j * T64;
       // operand L block: forward L_ij (As[c][r] = L[i0+r][j0+c]); backward L_ji^T (As[c][r] = L[j0+c][i0+r])
@@ -759,6 +875,32 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     res.zero();
     res.template mma<T64, T64, T64>(As, Bs);
     __syncthreads();
+    if (fold) {
+      // res -= M_i Out_j for the previous block row j (As[k][row] = -M[row][k])
+      const int j = b.backward ? i + 1 : i - 1;
+      const int64_t j0 = (int64_t)j * T64;
+      const gdouble* Mi = gp(Mfold + (int64_t)i * T64 * T64);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) As[threadIdx.x + 256 * u] = -Mi[threadIdx.x + 256 * u];
+      if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
+          v[u] = (r0 + q < a.R) ? ld_c(&a.Out[(j0 + p) + (r0 + q) * a.ldOut]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
+          Bs[p * T64 + q] = v[u];
+        }
+      }
+      __syncthreads();
+      res.template mma<T64, T64, T64>(As, Bs);
+      __syncthreads();
+    }
     acc_to_lds_sw(res, As);
     __syncthreads();
     lds_sw_to_global(As, nullptr, a.Out, a.ldOut, i0, r0, a.R - r0, false);
@@ -845,7 +987,7 @@ int64_t chol_task_offsets(int T, std::vector<int64_t>& offs) {
 static CholArgs chol_args(const Inst& in) {
   CholArgs a;
   const int T = (int)(in.KMp / T64);
-  a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv;
+  a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv; a.Lt = in.Lt;
   a.state = in.dag; a.head = in.dag + (int64_t)T * T; a.err = a.head + 1; a.info = in.info;
   a.offs = in.chol_offs; a.ntasks = in.chol_ntasks;
   a.col_off = 0;
@@ -873,7 +1015,7 @@ static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
     CholBatch b{};
     CholArgs& a = b.one;
     a.G = in.G + k0 + k0 * ld; a.ld = ld; a.T = Ts; a.KM = in.KM;
-    a.diag0 = in.diag0 + k0; a.Linv = in.Linv + (k0 / T64) * T64 * T64;
+    a.diag0 = in.diag0 + k0; a.Linv = in.Linv + (k0 / T64) * T64 * T64; a.Lt = in.Lt;
     a.state = in.dag + 1; a.head = a.state + (int64_t)Ts * Ts; a.err = err; a.info = in.info;
     a.offs = tail ? in.blk_offs_tail : in.blk_offs; a.ntasks = tail ? in.blk_ntasks_tail : in.blk_ntasks;
     a.col_off = k0;
@@ -915,7 +1057,10 @@ int* chol_error_flag(const Inst& in) {
 }
 
 hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
-  if (in.blk_NO > 0) return launch_cholesky_blocked(in, s);
+  if (in.blk_NO > 0) {
+    const hipError_t e = launch_cholesky_blocked(in, s);
+    return e != hipSuccess ? e : launch_solve_fold(in, s);
+  }
   const int T = (int)(in.KMp / T64);
   // counters: state T*T, then head, err
   const int64_t nctr = (int64_t)T * T + 2;
@@ -926,6 +1071,45 @@ hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
   b.ntasks = in.chol_ntasks; b.head = b.one.head; b.err = b.one.err;
   hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel, in.tune_chol_per_cu)), dim3(256),
                      0, s, b);
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_solve_fold(in, s);
+}
+
+// The folded products of the block solves: block (i, 0) forms Mf_i =
+// Linv_i L_{i,i-1} (i >= 1), block (i, 1) forms Mb_i = Linv_i^T L_{i+1,i}^T
+// (i <= T - 2); both column-major.
+__global__ __launch_bounds__(256) void solve_fold_kernel(const double* G, int64_t ld, const double* Linv, int T,
+                                                         double* Mf, double* Mb) {
+  __shared__ double As[T64 * T64];
+  __shared__ double Bs[T64 * T64];
+  const int i = blockIdx.x, dir = blockIdx.y;
+  if ((dir == 0 && i == 0) || (dir == 1 && i == T - 1)) return;
+  const gdouble* Lb = gp(Linv + (int64_t)i * T64 * T64);
+  const int64_t i0 = (int64_t)i * T64;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = threadIdx.x + 256 * u, p = idx % T64, c = idx / T64;
+    if (dir == 0) {
+      As[idx] = Lb[idx];                                            // A[p][c] = Linv[p][c]
+      Bs[p * T64 + c] = gp(G)[(i0 + p) + (i0 - T64 + c) * ld];     // B[p][c] = L_{i,i-1}[p][c]
+    } else {
+      As[p * T64 + c] = Lb[idx];                                    // A[c][p] = Linv[p][c]
+      Bs[idx] = gp(G)[(i0 + T64 + p) + (i0 + c) * ld];             // B[c][p] = L_{i+1,i}[p][c]
+    }
+  }
+  __syncthreads();
+  TileF64<T64, T64, 2, 2> acc;
+  acc.zero();
+  acc.template mma<T64, T64, T64>(As, Bs);
+  double* M = (dir == 0 ? Mf : Mb) + (int64_t)i * T64 * T64;
+  acc.for_each([&](int r, int c, double v) { M[r + c * T64] = v; });
+}
+
+hipError_t launch_solve_fold(const Inst& in, hipStream_t s) {
+  const int T = (int)(in.KMp / T64);
+  if (!in.Msol || T < 2) return hipSuccess;
+  hipLaunchKernelGGL(solve_fold_kernel, dim3((unsigned)T, 2), dim3(256), 0, s, in.G, in.KMp, in.Linv, T, in.Msol,
+                     in.Msol + (int64_t)T * T64 * T64);
   return hipGetLastError();
 }
 
@@ -933,6 +1117,7 @@ static SolveArgs solve_args(const Inst& in, const double* In, double* Out, int64
   SolveArgs a;
   const int T = (int)(in.KMp / T64);
   a.G = in.G; a.ld = in.KMp; a.T = T; a.Linv = in.Linv;
+  a.Mf = in.Msol; a.Mb = in.Msol ? in.Msol + (int64_t)T * T64 * T64 : nullptr;
   a.In = In; a.ldIn = in.KMp; a.Out = Out; a.ldOut = in.KMp;
   a.R = R; a.Rp = nullptr; a.nrt = in.nrt_max;
   a.flags = in.dag + (int64_t)T * T + 2;               // T * nrt_max flags, then head
@@ -1154,7 +1339,7 @@ hipError_t launch_member_block_inverse(const double* Gs, int64_t ld, int64_t o, 
                      nctr);
   CholBatch b{};
   CholArgs& a = b.one;
-  a.G = D; a.ld = Mp; a.T = Tb; a.KM = M; a.diag0 = d0; a.Linv = Linv;
+  a.G = D; a.ld = Mp; a.T = Tb; a.KM = M; a.diag0 = d0; a.Linv = Linv; a.Lt = nullptr;
   a.state = ctr + 1; a.head = a.state + (int64_t)Tb * Tb; a.err = ctr; a.info = info;
   a.offs = offs; a.ntasks = ntasks; a.col_off = o;
   b.ntasks = ntasks; b.head = a.head; b.err = a.err;

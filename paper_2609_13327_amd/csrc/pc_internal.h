@@ -33,6 +33,9 @@ struct Inst {
   double* G = nullptr;       // KMp x KMp, ld = KMp; Gram then its Cholesky factor (lower)
   double* diag0 = nullptr;   // KMp: diagonal of the Gram before factoring
   double* Linv = nullptr;    // (KMp/NB) blocks of NB x NB: inverses of the diagonal blocks of L
+  double* Lt = nullptr;      // final strictly-lower tiles of L, tile-major, written once per factorization
+  double* Msol = nullptr;    // 2 x (KMp/NB) blocks NB x NB: the block solves' folded last updates
+  int64_t lt_tiles = 0;      // capacity of Lt in 64 x 64 tiles
   double* S = nullptr;       // n_h x ldS per-column Grams (row j holds the P packed pairs, zero padded)
   int64_t ldS = 0;           // P rounded up to the 128-pair Gram tile
   double* G2 = nullptr;      // second half of a split FP64 Gram (only when the tiles are few)
@@ -89,6 +92,7 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s);
 hipError_t launch_cholesky(const Inst& in, hipStream_t s);
+hipError_t launch_solve_fold(const Inst& in, hipStream_t s);
 int* chol_error_flag(const Inst& in);   // device int set when a bounded wait of the factorization expired
 // `skip` (device int, may be null): when nonzero at run time the kernels exit
 // at once; the refinement loop uses it to stop converged instances on the GPU.

@@ -65,7 +65,7 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 void free_inst(Inst& in) {
-  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.S); hipFree(in.pairs);
+  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
@@ -110,6 +110,18 @@ std::vector<int> make_qtiles(int64_t M) {
   return q;
 }
 
+// Final-L tile buffer for a tile DAG of T tile rows (T (T - 1) / 2 tiles).
+hipError_t ensure_lt(Inst& in, int64_t T) {
+  const int64_t need = T * (T - 1) / 2;
+  if (need <= in.lt_tiles) return hipSuccess;
+  (void)hipFree(in.Lt);
+  in.Lt = nullptr;
+  in.lt_tiles = 0;
+  const hipError_t e = dalloc(&in.Lt, need * pc::NB * pc::NB);
+  if (e == hipSuccess) in.lt_tiles = need;
+  return e;
+}
+
 // Buffers of the blocked outer factorization with block columns of NO
 // (a multiple of 64); NO = 0 frees them (tile DAG only).
 pc_status alloc_blocked(Inst& in, int64_t NO) {
@@ -119,13 +131,14 @@ pc_status alloc_blocked(Inst& in, int64_t NO) {
   in.blk_offs = in.blk_offs_tail = nullptr;
   in.blk_NO = 0;
   in.blk_ntasks = in.blk_ntasks_tail = 0;
-  if (NO <= 0) return PC_OK;
+  if (NO <= 0) return ensure_lt(in, in.KMp / pc::NB) == hipSuccess ? PC_OK : PC_ERR_OOM;
   const int64_t KMp = in.KMp;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
   chk(dalloc(&in.blk_P, KMp * NO));
   chk(dalloc(&in.blk_X, NO * NO));
   chk(dalloc(&in.blk_I, NO * NO));
+  chk(ensure_lt(in, NO / pc::NB));
   std::vector<int64_t> bo;
   in.blk_ntasks = pc::chol_task_offsets((int)(NO / pc::NB), bo);
   chk(dalloc(&in.blk_offs, (int64_t)bo.size()));
@@ -151,6 +164,7 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   chk(dalloc(&in.G, KMp * KMp));
   chk(dalloc(&in.diag0, KMp));
   chk(dalloc(&in.Linv, nblk * pc::NB * pc::NB));
+  chk(dalloc(&in.Msol, 2 * nblk * pc::NB * pc::NB));
   in.ldS = pc::round_up(in.P, 128);
   chk(dalloc(&in.S, in.n_h * in.ldS));
   chk(dalloc(&in.pairs, 2 * in.P));
@@ -174,6 +188,8 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   if (KMp > kBlockedAbove && e == hipSuccess) {
     const pc_status bs = alloc_blocked(in, 1024);
     if (bs != PC_OK) return bs;
+  } else {
+    chk(ensure_lt(in, T));
   }
   if (flags & PC_FLAG_CG_MEMBER_BLOCKS) {
     const int64_t Mp = pc::round_up(in.M, pc::NB), Tb = Mp / pc::NB;
@@ -682,6 +698,7 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
   if (p->batch) {
     PhaseTimer t(p, PC_PHASE_CHOLESKY, s);
     PC_TRY(pc::launch_cholesky_batch(p->batch, s, p->inst[0].tune_chol_per_cu));
+    for (const Inst& in : p->inst) PC_TRY(pc::launch_solve_fold(in, s));
   }
   std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
   for (size_t i = 0; i < p->inst.size(); ++i) {

@@ -217,3 +217,26 @@ def test_deterministic_bitwise():
         outs.append(host(Y))
         plan.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("shape", [(16, 32, 1, 8, 32, 16), (20, 40, 1, 16, 40, 33)])
+def test_refactor_after_operand_change(shape):
+    """The FP64 plan borrows E and W: after they change in place, a new
+    factorization uses the new values everywhere (no tile of the previous
+    factor survives in any buffer or cache).  Each result is checked like a
+    fresh plan's, with refinement for the ill-conditioned shape."""
+    a = _inst(shape, seed=21)
+    b = _inst(shape, seed=22)
+    kappa = max(lsq.cond(a.E, a.W, a.n_w), lsq.cond(b.E, b.W, b.n_w))
+    d = inst_dict(a)
+    plan = pc.Plan([d], max_refine=0 if kappa <= 1e4 else 40, tol=1e-14)
+    for inst in (a, b, a):
+        d["E"].copy_(dev(inst.E))
+        d["W"].copy_(dev(inst.W))
+        plan.factor()
+        Y = empty(inst.KM, inst.R)
+        plan.apply([dev(inst.X)], [Y])
+        ref = lsq.left_inverse_apply(inst.E, inst.W, inst.n_w, inst.X)
+        err = _rel_err(host(Y), ref)
+        assert np.all(err <= _ls_tol(inst, inst.X, ref)), err.max()
+    plan.close()
