@@ -233,10 +233,12 @@ pc_status pc_profile_enable(pc_plan *plan, int32_t on);
 pc_status pc_profile_read(pc_plan *plan, double *total_ms, int64_t *counts);
 
 /* pc_selftest_task_order — host-only check of the task order used by the
- * Cholesky DAG kernel for T tile rows of 64: every task exactly once and
- * after the tasks it waits for.  Returns 0 when valid, a positive code
- * naming the violated rule otherwise, -1 for T < 1.  Touches no GPU. */
-int32_t pc_selftest_task_order(int32_t T);
+ * Cholesky DAG kernel for T tile rows of 64 with update tasks that apply
+ * `group` consecutive columns each (group <= 0: the library's default):
+ * every task exactly once and after the tasks it waits for.  Returns 0 when
+ * valid, a positive code naming the violated rule otherwise, -1 for T < 1 or
+ * group > T.  Touches no GPU. */
+int32_t pc_selftest_task_order(int32_t T, int32_t group);
 
 /* ------------------------------------------------------------------------
  * Iterative solve on the normal equations and the learned warm start.

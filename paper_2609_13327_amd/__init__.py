@@ -108,7 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.pc_gram_export.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p]
     lib.pc_profile_enable.argtypes = [c_void_p, c_int32]
     lib.pc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
-    lib.pc_selftest_task_order.argtypes = [c_int32]
+    lib.pc_selftest_task_order.argtypes = [c_int32, c_int32]
     lib.pc_cg_solve.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_double,
                                 c_int32, c_int32, POINTER(c_int32), c_void_p]
     lib.pc_mlp_create.argtypes = [c_int64, c_int64, c_int64, c_int32, POINTER(c_void_p)]
@@ -283,9 +283,10 @@ def pc_gram_export(plan: int, instance: int, G, stream=None):
                                          c_void_p(_stream(stream))), "pc_gram_export")
 
 
-def pc_selftest_task_order(T: int) -> int:
-    """0 when the Cholesky DAG task order for T tile rows is valid (host only)."""
-    return int(load_library().pc_selftest_task_order(int(T)))
+def pc_selftest_task_order(T: int, group: int = 0) -> int:
+    """0 when the Cholesky DAG task order for T tile rows, with update tasks
+    of `group` columns (0: the default), is valid (host only)."""
+    return int(load_library().pc_selftest_task_order(int(T), int(group)))
 
 
 def pc_profile_enable(plan: int, on: bool = True):

@@ -14,14 +14,19 @@
 //               factorization (blocked by 16, MFMA updates) and inverse
 //   TRSM(i,k)   L_ik = (G_ik - L_{i,k-1} L_{k,k-1}^T) L_kk^{-T} for i >= k+2
 //               (MFMA, with the inverse; the update only when k >= 1)
-//   GEMM(i,j,k) G_ij -= L_ik L_jk^T for k <= j - 2 (the earlier updates)
+//   GEMM(i,j,k) G_ij -= sum_{kk = kb..k} L_i,kk L_j,kk^T for k <= j - 2 (the
+//               earlier updates), kb = G floor(k / G): the updates come in
+//               groups of G consecutive columns, one task per tile and group,
+//               so that G_ij makes one round trip to memory per group
 // Fusing a tile's last update into its TRSM/DIAG keeps the updated tile in
 // the same workgroup, and DIAG chains the whole diagonal step in one
 // workgroup, so the critical path crosses one workgroup hand-over per tile
 // row: DIAG(k) -> DIAG(k+1).  DIAG(k+1) loads and updates its operands before
 // it waits for DIAG(k)'s inverse.
 // Order (look-ahead of one step): DIAG(0); then for every k: DIAG(k+1),
-// TRSM(i,k) for i >= k+2, then the non-final updates GEMM(i,j,k), j >= k+2.
+// TRSM(i,k) for i >= k+2, then the non-final update tasks ending at column k:
+// GEMM(i,j,k) for all j >= k+2 when k closes a group ((k + 1) % G == 0),
+// else only for j = k + 2 (a tile whose last non-final update is k).
 // Every task appears after the tasks it needs, which makes the waits
 // deadlock-free: a waiting workgroup only waits for a task that another
 // running workgroup has already taken.
@@ -102,9 +107,18 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info,
 
 struct TaskDesc { int type, i, j, k; };   // type 0 DIAG(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
 
+constexpr int kGemmGroup = 4;   // columns of updates per GEMM task
+
+// Whether iteration k closes a group of updates, and its GEMM task count.
+__host__ __device__ inline bool gemm_group_end(int k, int G) { return (k + 1) % G == 0; }
+__host__ __device__ inline int64_t gemm_task_count(int T, int k, int G) {
+  const int64_t m2 = T - k - 2;
+  return gemm_group_end(k, G) ? m2 * (m2 + 1) / 2 : m2;
+}
+
 // t -> task in the order described above; offs[k] is the first index of
 // iteration k (k = 0..T-2) and offs[T-1] the task count.
-__host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) {
+__host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs, int G) {
   TaskDesc d{0, 0, 0, 0};
   if (t == 0) return d;                    // DIAG(0)
   int lo = 0, hi = T - 2;                  // largest k with offs[k] <= t
@@ -120,7 +134,12 @@ __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs) 
     else { d.type = 1; d.i = k + 1 + (int)u; d.j = d.k = k; }
     return d;
   }
-  const int64_t w = u - m1;                // lower triangle (a >= b) of size T-k-2
+  const int64_t w = u - m1;
+  if (!gemm_group_end(k, G)) {             // column j = k + 2 only
+    d.type = 2; d.i = k + 2 + (int)w; d.j = k + 2; d.k = k;
+    return d;
+  }
+  // lower triangle (a >= b) of size T-k-2
   int64_t a = (int64_t)((sqrt(8.0 * (double)w + 1.0) - 1.0) * 0.5);
   while ((a + 1) * (a + 2) / 2 <= w) ++a;
   while (a * (a + 1) / 2 > w) --a;
@@ -135,6 +154,7 @@ struct CholArgs {
   double* Lt;               // final strictly-lower tiles, tile-major (null: read them from G)
   int* state; int* head; int* info; int* err;
   const int64_t* offs; int64_t ntasks;
+  int grp;                  // update columns per GEMM task (the order in offs was built for it)
   int64_t col_off;          // column of G's first row/column in the whole matrix (failure reports)
 };
 
@@ -573,24 +593,58 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
   return true;
 }
 
-__device__ __noinline__ void gemm_task(const CholArgs& a, int i, int j, int k, double* As, double* Bs) {
-  const int64_t i0 = (int64_t)i * T64, j0 = (int64_t)j * T64, k0 = (int64_t)k * T64;
+// GEMM(i,j,k) with its group: G_ij -= L_i,kk L_j,kk^T for kk = kb..k.  Each
+// update is rounded into the tile on its own, in column order, so the result
+// is the same for every group size.
+__device__ __forceinline__ void gemm_task(const CholArgs& a, int i, int j, int kb, int k, double* As, double* Bs) {
+  const int64_t i0 = (int64_t)i * T64, j0 = (int64_t)j * T64;
+  // The product is formed transposed, acc(m, n) = -(L_jk L_ik^T)(m, n), so
+  // that a lane's accumulator entries run down the columns of G_ij: the tile
+  // is read in the accumulator layout and written back from it directly,
+  // each wave instruction touching four 128-byte column segments.
   TileF64<T64, T64, 2, 2> acc;
-  TileRegs tc, ta, tb;
-  // all loads in flight; the operands first, so that the product can start
-  // while G_ij is still arriving (loads complete in order)
-  ltile_load(a, i, k, ta);                            // L_ik
-  ltile_load(a, j, k, tb);                            // L_jk
-  tile_load(a.G, a.ld, i0, j0, tc);                   // G_ij
-  tile_store_lds(ta, As, -1.0);
-  tile_store_lds(tb, Bs, 1.0);
-  __syncthreads();
-  acc.zero();
-  acc.template mma<T64, T64, T64>(As, Bs);            // -L_ik L_jk^T
-  __syncthreads();
-  acc_to_lds_sw(acc, As);
-  __syncthreads();
-  lds_sw_to_global(As, &tc, a.G, a.ld, i0, j0, T64, i == j);   // G_ij - L_ik L_jk^T
+  TileRegs ta, tb;
+  // operands first (loads complete in order), G_ij arrives during the product
+  ltile_load(a, i, kb, ta);                           // L_i,kb
+  ltile_load(a, j, kb, tb);                           // L_j,kb
+  const int lane = lane_id(), w = wave_id(), wm = w / 2, wn = w % 2;
+  double cr[2][2][4];                                 // G_ij(n, m) at accumulator (m, n)
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = wm * 32 + fi * 16 + (lane >> 4) + 4 * v, n = wn * 32 + fj * 16 + (lane & 15);
+        cr[fi][fj][v] = ld_c(&a.G[(i0 + n) + (j0 + m) * a.ld]);
+      }
+  for (int kk = kb; kk <= k; ++kk) {
+    if (kk > kb) __syncthreads();                     // the previous product has read As, Bs
+    tile_store_lds(tb, As, -1.0);                     // As[c][m] = -L_j,kk[m][c]
+    tile_store_lds(ta, Bs, 1.0);                      // Bs[c][n] = L_i,kk[n][c]
+    __syncthreads();
+    if (kk < k) {                                     // next operands, in flight during the product
+      ltile_load(a, i, kk + 1, ta);
+      ltile_load(a, j, kk + 1, tb);
+    }
+    acc.zero();
+    acc.template mma<T64, T64, T64>(As, Bs);
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+      for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cr[fi][fj][v] += acc.acc[fi][fj][v];
+  }
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = wm * 32 + fi * 16 + (lane >> 4) + 4 * v, n = wn * 32 + fj * 16 + (lane & 15);
+        if (i != j || n >= m) st_c(&a.G[(i0 + n) + (j0 + m) * a.ld], cr[fi][fj][v]);
+      }
 }
 
 // TRSM(i,k): for k >= 1 the tile's last update from column k-1 comes first
@@ -704,7 +758,7 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
     __syncthreads();
     const CholArgs& a = sa;
     const int T = a.T;
-    const TaskDesc d = decode_task(t, T, a.offs);
+    const TaskDesc d = decode_task(t, T, a.offs, a.grp);
     int* st = a.state;
     if (d.type == 0) {
       // the diagonal step is the critical path: its waves get the highest
@@ -726,10 +780,13 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
       if (!done) continue;
       publish(&st[i * T + k], k + 1);
     } else {
+      // L_i,kk is final for every kk <= k once L_ik is (each TRSM waits for
+      // the one before it in its tile row)
+      const int kb = d.k - d.k % a.grp;
       if (!wait_ge(&st[d.i * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
       if (d.j != d.i && !wait_ge(&st[d.j * T + d.k], d.k + 1, a.info, a.err, &sh[2])) continue;
-      if (!wait_ge(&st[d.i * T + d.j], d.k, a.info, a.err, &sh[2])) continue;
-      gemm_task(a, d.i, d.j, d.k, As, Bs);
+      if (!wait_ge(&st[d.i * T + d.j], kb, a.info, a.err, &sh[2])) continue;
+      gemm_task(a, d.i, d.j, kb, d.k, As, Bs);
       publish(&st[d.i * T + d.j], d.k + 1);
     }
     __syncthreads();
@@ -917,16 +974,17 @@ __global__ void dag_reset_kernel(int* p, int64_t count) {
 
 // Host check of the task order for T tile rows: every task exactly once, and
 // each task after all the tasks it waits for.  Returns 0 when valid.
-int check_chol_task_order(int T) {
+int check_chol_task_order(int T, int G) {
+  if (G <= 0) G = kGemmGroup;
   std::vector<int64_t> offs;
-  const int64_t n = chol_task_offsets(T, offs);
+  const int64_t n = chol_task_offsets(T, offs, G);
   int64_t expect = 1;
-  for (int k = 0; k + 1 < T; ++k) expect += (int64_t)(T - k - 1) + (int64_t)(T - k - 2) * (T - k - 1) / 2;
+  for (int k = 0; k + 1 < T; ++k) expect += (int64_t)(T - k - 1) + gemm_task_count(T, k, G);
   if (n != expect) return 1;
   std::vector<int> state((size_t)T * T, 0);      // as on the device: updates applied, j + 1 when final
   auto st = [&](int i, int j) -> int& { return state[(size_t)i * T + j]; };
   for (int64_t t = 0; t < n; ++t) {
-    const TaskDesc d = decode_task(t, T, offs.data());
+    const TaskDesc d = decode_task(t, T, offs.data(), G);
     if (d.i < 0 || d.i >= T || d.j < 0 || d.j >= T || d.k < 0 || d.k >= T) return 2;
     if (d.type == 0) {                            // DIAG(k)
       const int k = d.k;
@@ -947,9 +1005,14 @@ int check_chol_task_order(int T) {
       if (st(k, k) < k + 1) return 4;
       if (st(i, k) != (k >= 1 ? k - 1 : 0)) return 4;
       st(i, k) = k + 1;
-    } else {                                      // GEMM(i,j,k), k <= j - 2
+    } else {                                      // GEMM(i,j,k): updates kb..k, k <= j - 2
+      const int kb = d.k - d.k % G;
       if (!(d.k + 2 <= d.j && d.j <= d.i)) return 5;
-      if (st(d.i, d.k) < d.k + 1 || st(d.j, d.k) < d.k + 1 || st(d.i, d.j) != d.k) return 6;
+      // the kernel waits for L_ik, L_jk only: the earlier columns must be final by then
+      if (st(d.i, d.k) < d.k + 1 || st(d.j, d.k) < d.k + 1) return 6;
+      for (int kk = kb; kk <= d.k; ++kk)
+        if (st(d.i, kk) < kk + 1 || st(d.j, kk) < kk + 1) return 6;
+      if (st(d.i, d.j) != kb) return 6;
       st(d.i, d.j) = d.k + 1;
     }
   }
@@ -972,13 +1035,13 @@ static int persistent_grid(K kernel, int want = 0) {
   return (cus > 0 ? cus : 256) * per_cu;
 }
 
-int64_t chol_task_offsets(int T, std::vector<int64_t>& offs) {
+int64_t chol_task_offsets(int T, std::vector<int64_t>& offs, int G) {
+  if (G <= 0) G = kGemmGroup;
   offs.assign((size_t)std::max(T, 1), 0);
   int64_t t = 1;                                  // DIAG(0)
   for (int k = 0; k + 1 < T; ++k) {
     offs[k] = t;
-    const int64_t m1 = T - k - 1, m2 = T - k - 2;
-    t += m1 + m2 * (m2 + 1) / 2;
+    t += (T - k - 1) + gemm_task_count(T, k, G);
   }
   if (T >= 1) offs[T - 1] = t;
   return t;
@@ -989,7 +1052,7 @@ static CholArgs chol_args(const Inst& in) {
   const int T = (int)(in.KMp / T64);
   a.G = in.G; a.ld = in.KMp; a.T = T; a.KM = in.KM; a.diag0 = in.diag0; a.Linv = in.Linv; a.Lt = in.Lt;
   a.state = in.dag; a.head = in.dag + (int64_t)T * T; a.err = a.head + 1; a.info = in.info;
-  a.offs = in.chol_offs; a.ntasks = in.chol_ntasks;
+  a.offs = in.chol_offs; a.ntasks = in.chol_ntasks; a.grp = kGemmGroup;
   a.col_off = 0;
   return a;
 }
@@ -1018,6 +1081,7 @@ static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
     a.diag0 = in.diag0 + k0; a.Linv = in.Linv + (k0 / T64) * T64 * T64; a.Lt = in.Lt;
     a.state = in.dag + 1; a.head = a.state + (int64_t)Ts * Ts; a.err = err; a.info = in.info;
     a.offs = tail ? in.blk_offs_tail : in.blk_offs; a.ntasks = tail ? in.blk_ntasks_tail : in.blk_ntasks;
+    a.grp = kGemmGroup;
     a.col_off = k0;
     b.ntasks = a.ntasks; b.head = a.head; b.err = a.err;
     const int64_t nctr = (int64_t)Ts * Ts + 1;
@@ -1215,7 +1279,7 @@ DagBatch* make_dag_batch(const std::vector<Inst>& insts) {
     const Inst& in = insts[i];
     Ts[i] = (int)(in.KMp / T64);
     maxT = std::max(maxT, Ts[i]);
-    chol_task_offsets(Ts[i], offs[i]);
+    chol_task_offsets(Ts[i], offs[i], kGemmGroup);
     ch[i] = chol_args(in);
     sv0[i] = solve_args(in, in.Y, in.B, 0, nullptr);
     sv1[i] = solve_args(in, in.D, in.B, 0, &in.ctl->done);
@@ -1240,10 +1304,7 @@ DagBatch* make_dag_batch(const std::vector<Inst>& insts) {
     for (int i : order)
       if (r + 1 < Ts[i]) add(cs, i, offs[i][r], Ts[i] - r - 1);              // DIAG(r+1), TRSM(., r)
     for (int i : order)
-      if (r + 1 < Ts[i]) {
-        const int64_t m2 = Ts[i] - r - 2;
-        add(cs, i, offs[i][r] + Ts[i] - r - 1, m2 * (m2 + 1) / 2);          // GEMM(., ., r)
-      }
+      if (r + 1 < Ts[i]) add(cs, i, offs[i][r] + Ts[i] - r - 1, gemm_task_count(Ts[i], r, kGemmGroup));   // GEMM(., ., r)
   }
   b->chol_total = g;
   b->chol_nsegs = (int)cs.size();
@@ -1341,7 +1402,7 @@ hipError_t launch_member_block_inverse(const double* Gs, int64_t ld, int64_t o, 
   CholArgs& a = b.one;
   a.G = D; a.ld = Mp; a.T = Tb; a.KM = M; a.diag0 = d0; a.Linv = Linv; a.Lt = nullptr;
   a.state = ctr + 1; a.head = a.state + (int64_t)Tb * Tb; a.err = ctr; a.info = info;
-  a.offs = offs; a.ntasks = ntasks; a.col_off = o;
+  a.offs = offs; a.ntasks = ntasks; a.grp = kGemmGroup; a.col_off = o;
   b.ntasks = ntasks; b.head = a.head; b.err = a.err;
   hipLaunchKernelGGL(chol_dag_kernel, dim3((unsigned)persistent_grid(chol_dag_kernel)), dim3(256), 0, s, b);
   SolveBatch sb{};

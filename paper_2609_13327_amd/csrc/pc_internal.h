@@ -124,7 +124,7 @@ hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t
 hipError_t launch_copy_panel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
                              hipStream_t s);
 hipError_t launch_identity(double* I, int64_t n, hipStream_t s);
-int64_t chol_task_offsets(int T, std::vector<int64_t>& offs);
+int64_t chol_task_offsets(int T, std::vector<int64_t>& offs, int G = 0);   // G <= 0: the default group
 // All instances of a plan in one persistent Cholesky launch and one pair of
 // solve launches (task lists interleaved, largest instance first).
 struct DagBatch;
@@ -137,7 +137,7 @@ hipError_t set_batch_rhs(const DagBatch* b, const int64_t* R, hipStream_t s);   
 // converged instances), with B as the work buffer
 hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s);
 int gram_split_for(const Inst& in);
-int check_chol_task_order(int T);
+int check_chol_task_order(int T, int G = 0);
 
 // ---------------------------------------------------------------- learned warm start
 enum { MLP_EPI_STORE = 0, MLP_EPI_BIAS_GELU = 1, MLP_EPI_BIAS = 2, MLP_EPI_GELU_GRAD = 3 };

@@ -816,9 +816,9 @@ pc_status pc_sqrt_apply(pc_plan* p, int32_t instance, const double* Yin, int64_t
   return PC_OK;
 }
 
-int32_t pc_selftest_task_order(int32_t T) {
-  if (T < 1) return -1;
-  return pc::check_chol_task_order(T);
+int32_t pc_selftest_task_order(int32_t T, int32_t group) {
+  if (T < 1 || group > T) return -1;
+  return pc::check_chol_task_order(T, group);
 }
 
 pc_status pc_profile_enable(pc_plan* p, int32_t on) {

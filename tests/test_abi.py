@@ -43,4 +43,8 @@ def test_cholesky_task_order_is_topological():
     import paper_2609_13327_amd as pc
     for T in (1, 2, 3, 5, 8, 33, 64, 256, 512):
         assert pc.pc_selftest_task_order(T) == 0, T
+        for G in (1, 2, 3, 4):
+            if G <= T:
+                assert pc.pc_selftest_task_order(T, G) == 0, (T, G)
     assert pc.pc_selftest_task_order(0) == -1
+    assert pc.pc_selftest_task_order(4, 5) == -1
