@@ -865,6 +865,17 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     const int64_t i0 = (int64_t)i * T64, r0 = (int64_t)rt * T64;
     TileF64<T64, T64, 2, 2> acc;
     tile_to_acc(a.In, a.ldIn, i0, r0, acc, a.R - r0);    // acc = In[i block, rt]
+    // the diagonal block's inverse is static: it travels while the task waits
+    // forward: As[k][row] = Linv[row][k]; backward: As[k][row] = Linv[k][row]
+    TileRegs linv;
+    {
+      const gdouble* Lb = gp(a.Linv + (int64_t)i * T64 * T64);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
+        linv.v[u] = b.backward ? Lb[q + p * T64] : Lb[idx];
+      }
+    }
     bool ok = true;
     const int nprev = b.backward ? (a.T - 1 - i) : i;
     const double* Mfold = b.backward ? a.Mb : a.Mf;
@@ -919,14 +930,9 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     }
     if (!ok) continue;
     // Out_i = Linv_i (or its transpose) * acc
-    const gdouble* Lb = gp(a.Linv + (int64_t)i * T64 * T64);
     acc.for_each([&](int r, int c, double v) { Bs[r * T64 + c] = v; });
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
-      // forward: As[k][row] = Linv[row][k]; backward: As[k][row] = Linv[k][row]
-      As[q * T64 + p] = b.backward ? Lb[q + p * T64] : Lb[p + q * T64];
-    }
+    for (int u = 0; u < 16; ++u) As[threadIdx.x + 256 * u] = linv.v[u];
     __syncthreads();
     TileF64<T64, T64, 2, 2> res;
     res.zero();
@@ -1200,12 +1206,14 @@ hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, 
   b.one.nrt = (int)ceil_div(R, T64);
   b.ntasks = (int64_t)T * b.one.nrt;
   b.head = b.one.flags + (int64_t)T * in.nrt_max;
-  b.err = in.dag + (int64_t)T * T + 1;
-  const int64_t nflags = (int64_t)T * in.nrt_max + 1;
+  b.err = in.dag + (int64_t)T * T + 1;                        // just before the flags
+  // the error flag, the flags and the head are reset before each pass (after
+  // a blocked factorization nothing else clears the error flag)
+  const int64_t nflags = (int64_t)T * in.nrt_max + 2;
   const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), b.ntasks);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)),
-                       dim3(256), 0, s, b.one.flags, nflags);
+                       dim3(256), 0, s, b.err, nflags);
     b.backward = pass;
     if (pass == 1) {
       b.one.In = Wk; b.one.ldIn = ldW; b.one.Out = Y; b.one.ldOut = ldY;

@@ -87,3 +87,27 @@ def test_blocked_factorization_reports_rank_deficiency():
     st, failed = plan.factor(raise_on_error=False)
     assert st == pc.PC_ERR_NOT_SPD and failed == 0
     plan.close()
+
+
+def test_blocked_after_batch_plan_reuses_memory():
+    """A blocked factorization's solves must not depend on what freed device
+    memory held before the plan was built: here a batch plan (one instance
+    without right-hand sides) is built and freed first, whose memory the
+    blocked plan's counters then reuse."""
+    batch = wl.batched_config(count=4, scale=0.3)
+    bp = pc.Plan([inst_dict(i) for i in batch])
+    bp.factor()
+    Xs = [dev(i.X) for i in batch]
+    Ys = [empty(i.KM, i.R) for i in batch]
+    Xs[1] = None
+    bp.apply(Xs, Ys)
+    bp.close()
+    inst = wl.make_instance(20, 40, 6, 70, 33, 0.15, 0.4, 23)
+    plan = pc.Plan([inst_dict(inst)])
+    pc.pc_set_tuning(plan.handle, 0, 0, 0, 0, 192)
+    plan.factor()
+    Y = empty(inst.KM, inst.R)
+    plan.apply([dev(inst.X)], [Y])
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    assert _rel(host(Y), ref) <= 1e-10
+    plan.close()
