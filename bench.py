@@ -206,10 +206,14 @@ def main():
                 continue
             per = LAUNCHES_PER_PHASE.get(ph, 1)
             launches_per_step = per * cnt / steps
-            flops = sum(algorithmic_flops(ph, prec_name, i, i.R) for i in insts) / len(insts)
+            # every instance's work is done once per step, by one launch per
+            # instance or by one launch for the whole batch
+            flops = sum(algorithmic_flops(ph, prec_name, i, i.R) for i in insts) * per / launches_per_step
             avg = tot_ms / (cnt * per)
             ach = flops / (avg * 1e-3) / 1e12
             name, _ = kernel_info(ph, prec_name)
+            if ph == "gram" and prec_name != "fp64" and len(insts) > 1:
+                name = "gram_lowprec_batch_kernel"     # all instances' Grams in one launch
             kernels[ph] = {"kernel": name, "avg_launch_ms": avg, "launches_per_step": launches_per_step,
                            "flops_per_launch": flops, "achieved_tflops": ach,
                            "peak_tflops": phase_peak(ph, prec_name),

@@ -52,17 +52,11 @@ __device__ __forceinline__ void lower_tile(int64_t t, int64_t& ta, int64_t& tb) 
 // ---------------------------------------------------------------- bf16
 constexpr int BKC = 32, BST = BKC + 8;   // k per stage, padded LDS row stride (bf16 elements)
 
-__global__ __launch_bounds__(256) void gram_bf16_kernel(const unsigned short* __restrict__ Zt, int64_t ldz,
-                                                        int64_t KM, int64_t ntile_pairs, double* __restrict__ G,
-                                                        int64_t ldG) {
+// One 128 x 128 tile (a0.., b0..) of the lower triangle, a0 >= b0.
+__device__ __forceinline__ void gram_bf16_tile(const unsigned short* __restrict__ Zt, int64_t ldz, int64_t KM,
+                                               int64_t a0, int64_t b0, double* __restrict__ G, int64_t ldG) {
   __shared__ __attribute__((aligned(16))) unsigned short As[2][LT * BST];   // rows b (lower index block)
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][LT * BST];   // cols a
-  const int64_t per = (ntile_pairs + 7) / 8;
-  const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (u >= ntile_pairs) return;
-  int64_t ta, tb;
-  lower_tile(u, ta, tb);                         // ta >= tb
-  const int64_t a0 = ta * LT, b0 = tb * LT;
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 1, wn = w & 1, r = lane & 15, kq = lane >> 4;
   const int seg = t & 3, row = t >> 2;           // 16-byte segment of a 64-byte row chunk
@@ -122,19 +116,24 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const unsigned short* __
       }
 }
 
-// ---------------------------------------------------------------- fp32
-constexpr int FKC = 16, FST = FKC + 1;
-
-__global__ __launch_bounds__(256) void gram_f32_kernel(const float* __restrict__ Zt, int64_t ldz, int64_t KM,
-                                                       int64_t ntile_pairs, double* __restrict__ G, int64_t ldG) {
-  __shared__ float As[2][LT * FST];
-  __shared__ float Bs[2][LT * FST];
+__global__ __launch_bounds__(256) void gram_bf16_kernel(const unsigned short* __restrict__ Zt, int64_t ldz,
+                                                        int64_t KM, int64_t ntile_pairs, double* __restrict__ G,
+                                                        int64_t ldG) {
   const int64_t per = (ntile_pairs + 7) / 8;
   const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (u >= ntile_pairs) return;
   int64_t ta, tb;
-  lower_tile(u, ta, tb);
-  const int64_t a0 = ta * LT, b0 = tb * LT;
+  lower_tile(u, ta, tb);                         // ta >= tb
+  gram_bf16_tile(Zt, ldz, KM, ta * LT, tb * LT, G, ldG);
+}
+
+// ---------------------------------------------------------------- fp32
+constexpr int FKC = 16, FST = FKC + 1;
+
+__device__ __forceinline__ void gram_f32_tile(const float* __restrict__ Zt, int64_t ldz, int64_t KM, int64_t a0,
+                                              int64_t b0, double* __restrict__ G, int64_t ldG) {
+  __shared__ float As[2][LT * FST];
+  __shared__ float Bs[2][LT * FST];
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 1, wn = w & 1, r = lane & 15, kq = lane >> 4;
   const int seg = t & 3, row = t >> 2;           // 4 floats of a 16-float row chunk
@@ -197,6 +196,88 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float* __restrict__
         const int64_t a = a0 + wn * 64 + j * 16 + r;
         if (a < KM && b < KM && a >= b) G[a + b * ldG] = (double)acc[i][j][v];
       }
+}
+
+__global__ __launch_bounds__(256) void gram_f32_kernel(const float* __restrict__ Zt, int64_t ldz, int64_t KM,
+                                                       int64_t ntile_pairs, double* __restrict__ G, int64_t ldG) {
+  const int64_t per = (ntile_pairs + 7) / 8;
+  const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (u >= ntile_pairs) return;
+  int64_t ta, tb;
+  lower_tile(u, ta, tb);
+  gram_f32_tile(Zt, ldz, KM, ta * LT, tb * LT, G, ldG);
+}
+
+// Several instances in one launch: workgroup b takes tiles[b] (instance,
+// tile row, tile column); the host lists the tiles longest contraction first,
+// so the short ones fill the end of the launch.
+template <typename T>
+__global__ __launch_bounds__(256) void gram_lowprec_batch_kernel(const LowGramTile* __restrict__ tiles,
+                                                                 const LowGramInst* __restrict__ insts) {
+  const LowGramTile tl = tiles[blockIdx.x];
+  const LowGramInst in = insts[tl.inst];
+  if constexpr (sizeof(T) == 2)
+    gram_bf16_tile(reinterpret_cast<const unsigned short*>(in.Zt), in.ldz, in.KM, (int64_t)tl.ta * LT,
+                   (int64_t)tl.tb * LT, in.G, in.ldG);
+  else
+    gram_f32_tile(reinterpret_cast<const float*>(in.Zt), in.ldz, in.KM, (int64_t)tl.ta * LT, (int64_t)tl.tb * LT,
+                  in.G, in.ldG);
+}
+
+hipError_t launch_stage_z(const Inst& in, int precision, hipStream_t s) {
+  if (!in.Zt) return hipErrorInvalidValue;
+  const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(in.ldz, 256), 64);
+  if (precision == 2)
+    hipLaunchKernelGGL(stage_z_kernel<unsigned short>, dim3(gx, (unsigned)in.KM), dim3(256), 0, s, in.E, in.ldE,
+                       in.W, in.ldW, in.n, in.n_h, in.M, in.ldz, reinterpret_cast<unsigned short*>(in.Zt));
+  else
+    hipLaunchKernelGGL(stage_z_kernel<float>, dim3(gx, (unsigned)in.KM), dim3(256), 0, s, in.E, in.ldE, in.W,
+                       in.ldW, in.n, in.n_h, in.M, in.ldz, reinterpret_cast<float*>(in.Zt));
+  return hipGetLastError();
+}
+
+LowGramBatch* make_lowgram_batch(const std::vector<Inst>& insts) {
+  std::vector<LowGramInst> hi(insts.size());
+  std::vector<LowGramTile> ht;
+  for (size_t i = 0; i < insts.size(); ++i) {
+    const Inst& in = insts[i];
+    hi[i] = LowGramInst{in.Zt, in.ldz, in.KM, in.G, in.KMp};
+    const int64_t nt = ceil_div(in.KM, LT);
+    for (int64_t a = 0; a < nt; ++a)
+      for (int64_t b = 0; b <= a; ++b) ht.push_back(LowGramTile{(int)i, (int)a, (int)b, 0});
+  }
+  std::stable_sort(ht.begin(), ht.end(), [&](const LowGramTile& x, const LowGramTile& y) {
+    return insts[x.inst].ldz > insts[y.inst].ldz;
+  });
+  LowGramBatch* b = new LowGramBatch{};
+  b->ntiles = (int64_t)ht.size();
+  hipError_t e = hipMalloc((void**)&b->tiles, sizeof(LowGramTile) * ht.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&b->insts, sizeof(LowGramInst) * hi.size());
+  if (e == hipSuccess) e = hipMemcpy(b->tiles, ht.data(), sizeof(LowGramTile) * ht.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->insts, hi.data(), sizeof(LowGramInst) * hi.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_lowgram_batch(b);
+    return nullptr;
+  }
+  return b;
+}
+
+void free_lowgram_batch(LowGramBatch* b) {
+  if (!b) return;
+  (void)hipFree(b->tiles);
+  (void)hipFree(b->insts);
+  delete b;
+}
+
+hipError_t launch_gram_lowprec_batch(const LowGramBatch* b, int precision, hipStream_t s) {
+  if (b->ntiles <= 0) return hipSuccess;
+  if (precision == 2)
+    hipLaunchKernelGGL(gram_lowprec_batch_kernel<unsigned short>, dim3((unsigned)b->ntiles), dim3(256), 0, s,
+                       b->tiles, b->insts);
+  else
+    hipLaunchKernelGGL(gram_lowprec_batch_kernel<float>, dim3((unsigned)b->ntiles), dim3(256), 0, s, b->tiles,
+                       b->insts);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s) {

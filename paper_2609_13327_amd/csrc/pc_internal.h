@@ -90,6 +90,15 @@ hipError_t launch_pairs_init(const Inst& in, hipStream_t s);
 hipError_t launch_column_grams(const Inst& in, hipStream_t s);
 hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
+// reduced-precision Grams of several instances in one launch (after each
+// instance's rounded Z has been staged)
+struct LowGramInst { const void* Zt; int64_t ldz, KM; double* G; int64_t ldG; };
+struct LowGramTile { int inst, ta, tb, pad; };
+struct LowGramBatch { LowGramTile* tiles = nullptr; LowGramInst* insts = nullptr; int64_t ntiles = 0; };
+hipError_t launch_stage_z(const Inst& in, int precision, hipStream_t s);
+LowGramBatch* make_lowgram_batch(const std::vector<Inst>& insts);
+void free_lowgram_batch(LowGramBatch* b);
+hipError_t launch_gram_lowprec_batch(const LowGramBatch* b, int precision, hipStream_t s);
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s);
 hipError_t launch_cholesky(const Inst& in, hipStream_t s);
 hipError_t launch_solve_fold(const Inst& in, hipStream_t s);

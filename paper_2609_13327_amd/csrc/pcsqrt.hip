@@ -47,6 +47,8 @@ struct pc_plan {
   std::vector<hipEvent_t> pool;
   // several instances: one persistent Cholesky launch and one solve pair for all
   pc::DagBatch* batch = nullptr;
+  // several instances in reduced precision: their Grams in one launch
+  pc::LowGramBatch* lowgram = nullptr;
 };
 
 namespace {
@@ -96,6 +98,7 @@ void free_plan(pc_plan* p) {
   for (auto e : p->ev_join) hipEventDestroy(e);
   hipFree(p->d_flag);
   pc::free_dag_batch(p->batch);
+  pc::free_lowgram_batch(p->lowgram);
   if (p->h_ctl) hipHostFree(p->h_ctl);
   delete p;
 }
@@ -280,6 +283,30 @@ hipError_t join(pc_plan* p, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[j], 0);
   }
   return e;
+}
+
+// Reduced-precision Grams of a batch: every instance's rounded Z is staged on
+// its stream, then all the Grams are one launch, then the padding per stream.
+pc_status assemble_lowgram_batch(pc_plan* p, hipStream_t s) {
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    Inst& in = p->inst[i];
+    hipStream_t si = stream_for(p, i, s);
+    in.factored = false;
+    PC_TRY(pc::launch_fill_int(in.info, -1, 1, si));
+    PC_TRY(pc::launch_stage_z(in, p->opt.precision, si));
+  }
+  PC_TRY(join(p, s));
+  { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_lowprec_batch(p->lowgram, p->opt.precision, s)); }
+  PC_TRY(fork(p, s));
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    Inst& in = p->inst[i];
+    hipStream_t si = stream_for(p, i, s);
+    PhaseTimer t(p, PC_PHASE_PAD, si);
+    PC_TRY(pc::launch_gram_pad_and_diag(in, si));
+  }
+  PC_TRY(join(p, s));
+  return PC_OK;
 }
 
 pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
@@ -625,6 +652,9 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   bool any_blocked = false;
   for (auto& in : p->inst) any_blocked = any_blocked || in.blk_NO > 0;
   if (st == PC_OK && count > 1 && !any_blocked && !(p->batch = pc::make_dag_batch(p->inst))) st = PC_ERR_OOM;
+  if (st == PC_OK && p->batch && o.precision != PC_PREC_FP64 && !(o.flags & PC_FLAG_KEEP_GRAM) &&
+      !(p->lowgram = pc::make_lowgram_batch(p->inst)))
+    st = PC_ERR_OOM;
   if (st == PC_OK) {
     // finiteness of E and W, then the pair tables
     int bad = 0;
@@ -653,6 +683,7 @@ pc_status pc_gram_assemble(pc_plan* p, void* stream) {
   if (!p) return PC_ERR_INVALID_ARG;
   hipSetDevice(p->device);
   hipStream_t s = (hipStream_t)stream;
+  if (p->lowgram) return assemble_lowgram_batch(p, s);
   PC_TRY(fork(p, s));
   for (size_t i = 0; i < p->inst.size(); ++i) {
     pc_status st = assemble_one(p, p->inst[i], stream_for(p, i, s));
@@ -667,12 +698,18 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
   if (!p) return PC_ERR_INVALID_ARG;
   hipSetDevice(p->device);
   hipStream_t s = (hipStream_t)stream;
+  if (p->lowgram) {
+    const pc_status st = assemble_lowgram_batch(p, s);
+    if (st != PC_OK) return st;
+  }
   PC_TRY(fork(p, s));
   for (size_t i = 0; i < p->inst.size(); ++i) {
     Inst& in = p->inst[i];
     hipStream_t si = stream_for(p, i, s);
-    pc_status st = assemble_one(p, in, si);
-    if (st != PC_OK) return st;
+    if (!p->lowgram) {
+      const pc_status st = assemble_one(p, in, si);
+      if (st != PC_OK) return st;
+    }
     if (in.Gs) {
       PC_TRY(pc::launch_gram_symmetrize(in, in.Gs, si));
       PC_TRY(pc::launch_fill_int(in.cg_flags, 0, 2, si));
