@@ -48,7 +48,7 @@ namespace pc {
 
 constexpr int T64 = 64;
 constexpr int LDP = T64 + 1;          // padded LDS stride
-constexpr long long kSpinLimit = 1LL << 22;   // about 0.2 s of polling
+constexpr long long kSpinLimit = 1LL << 22;   // polls: a few seconds at most
 
 // Every buffer these kernels touch is in device (global) memory.  Task
 // arguments are read from LDS or device memory, which leaves their pointers
@@ -93,9 +93,11 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info,
     int ok = 1;
     long long spins = 0;
     while (ld_acquire(flag) < v) {
-      if (ld_acquire(info) >= 0 || ld_acquire(err) != 0) { ok = 0; break; }
-      if (++spins > kSpinLimit) { atomicOr((int*)gp(err), 1); ok = 0; break; }
-      __builtin_amdgcn_s_sleep(2);
+      // the abandon conditions are polled every 8th time, so that a poll
+      // costs one round trip to memory
+      if ((++spins & 7) == 0 && (ld_acquire(info) >= 0 || ld_acquire(err) != 0)) { ok = 0; break; }
+      if (spins > kSpinLimit) { atomicOr((int*)gp(err), 1); ok = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
     }
     *sh = ok;
   }
@@ -302,16 +304,71 @@ __device__ __forceinline__ double bcast16(double v, int l) {
 #undef PC_BC
 }
 
+// Inverse of the 16 x 16 diagonal block b of the factor in A, by one wave,
+// into X + 256 b (row-major), by forward substitution: lane r holds row r
+// (every row of 16 lanes a copy), and row j of the inverse is final at
+// step j (X_jq = x_j[q] / L_jj).
+__device__ __forceinline__ void inv_diag_block(const double* A, double* X, int b) {
+  const int lane = lane_id(), r = lane & 15, c = 16 * b;
+  double row[16], x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) row[q] = (q <= r) ? A[(c + r) * LDP + c + q] : 0.0;
+  const double rdiag = 1.0 / A[(c + r) * LDP + c + r];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = (q == r) ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    // -L_rj / L_jj for rows below j (row[j] is 0 above the diagonal).  The
+    // broadcast runs on all lanes: a DPP move reading a lane that is
+    // switched off does not return that lane's value.
+    const double dj = bcast16(rdiag, j);
+    const double f = (r == j) ? 0.0 : -row[j] * dj;
+#pragma unroll
+    for (int q = 0; q <= j; ++q) x[q] = fma(f, bcast16(x[q], j), x[q]);
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) X[b * 256 + r * 16 + q] = (q <= r) ? x[q] * rdiag : 0.0;
+  }
+}
+
+// Off-diagonal block (p, q), p > q, of the inverse, by one wave:
+// Y_pq = -X_pp (L_pq X_qq + sum_{q<m<p} L_pm Y_mq).  Y blocks are kept
+// transposed in the upper triangle of A (rows 16q.., columns 16p..), which
+// the factor never touches.  Sw: 16 x 16 scratch of this wave.
+__device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, double* Sw, int p, int q) {
+  d4 s4 = {0.0, 0.0, 0.0, 0.0};
+  // B[k][n] = Y_mq[k][n] = A[16q + n][16m + k]
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4)
+    s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * q, kk), fr_b(X + q * 256, 16, 0, 0, kk), s4);
+  for (int m = q + 1; m < p; ++m)
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4)
+      s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * m, kk), fr_a(A, LDP, 16 * q, 16 * m, kk), s4);
+  fr_store(Sw, 16, 0, 0, s4);
+  d4 y4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4)
+    y4 = mfma_f64(-fr_a(X + p * 256, 16, 0, 0, kk), fr_b(Sw, 16, 0, 0, kk), y4);
+  const int l = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[(16 * q + (l & 15)) * LDP + 16 * p + (l >> 4) + 4 * v] = y4[v];
+}
+
 // Diagonal tile, blocked by 16.  For each 16-column panel one wave factors
 // the whole column panel (rows c..63) right-looking, column by column: every
 // row of 16 lanes holds a copy of the 16 x 16 diagonal block (lane r: row r)
 // and up to 16 rows of the panel below it, so the broadcasts of L_qj that
 // the updates need stay inside a row (DPP) and the panel is solved in the
-// same sweep.  The trailing lower part is then updated with MFMA.  After the
-// last panel the four waves invert the four 16 x 16 diagonal blocks in
-// parallel, and the inverse of the whole tile is assembled block by block:
-// Y_pp = X_pp and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq, wave q owning block
-// column q.  LDS: A (64 x 65), X (4 x 16 x 16), scratch (4 x 256).
+// same sweep.  The trailing lower part is then updated with MFMA.
+// The inverse of the tile is assembled block by block, Y_pp = X_pp (the
+// inverse of the diagonal block) and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq,
+// by the waves that the sweeps leave idle: X_pp while the next panel is
+// swept, Y_10 with the last panel, then X_33, Y_21 and Y_20, and last the
+// three blocks of block row 3.
+// LDS: A (64 x 65), X (4 x 16 x 16), sweep scratch (64 x 16) and pivot
+// thresholds (64), then the inverse's scratch (4 x 256).
 // Factor the 64 x 64 lower triangle held in A (LDS, row-major, stride LDP)
 // and form its inverse; publish the inverse (Linv) and the factor of tile
 // (k,k).  If pend_flag is set, the flag is published after the first panel
@@ -320,10 +377,10 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
                                          int* pend_flag, int pend_val) {
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int64_t k0 = (int64_t)k * T64;
+  double* Sy = Sc + 1024 + T64;          // inverse scratch, 256 per wave
   if (t == 0) sh[1] = -1;
   const double thr_scale = 64.0 * (double)a.KM * 1.1102230246251565e-16;
   // pivot thresholds of the 64 columns, read once
-  // Sc: 4 x 256 wave scratch, then 64 pivot thresholds
   if (t < T64) Sc[1024 + t] = gp(a.diag0)[k0 + t] * thr_scale;
   __syncthreads();
   for (int p = 0; p < 4; ++p) {
@@ -362,7 +419,7 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
         for (int q = j; q < 16; ++q) asm volatile("" : "+v"(pr[q]));
       }
       // Stores are unconditional (lanes without a panel row write to the
-      // wave scratch), so no part of the sweep is sunk into a branch.
+      // sweep scratch), so no part of the sweep is sunk into a branch.
       // Every row of 16 lanes writes the same diagonal block.
       double* pdst = has ? A + prow * LDP + c : Sc + lane * 16;
 #pragma unroll
@@ -370,6 +427,10 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
 #pragma unroll
       for (int q = 0; q < 16; ++q) pdst[q] = pr[q];
       if (fail < 16 && lane == 0) sh[1] = (int)(a.col_off + k0 + c + fail);
+    } else if (w == 1 && p >= 1) {
+      inv_diag_block(A, X, p - 1);        // L_{p-1,p-1} is final since the last sweep
+    } else if (w == 2 && p == 3) {
+      inv_offdiag_block(A, X, Sy + 2 * 256, 1, 0);
     }
     __syncthreads();
     if (sh[1] >= 0) {
@@ -390,64 +451,15 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
       fr_store(A, LDP, ri, rj, acc);
     }
     if (p == 0 && pend_flag) __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    if (p < 3) __syncthreads();           // the last panel has no trailing part
     if (p == 0 && pend_flag && t == 0) st_release(pend_flag, pend_val);
   }
-  // inverses of the diagonal blocks, wave q block q, by forward substitution
-  // (lane r: row r; row j of X is final at step j, X_jq = x_j[q] / L_jj)
-  {
-    const int r = lane & 15, c = 16 * w;
-    double row[16], x[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) row[q] = (q <= r) ? A[(c + r) * LDP + c + q] : 0.0;
-    const double rdiag = 1.0 / A[(c + r) * LDP + c + r];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = (q == r) ? 1.0 : 0.0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      // -L_rj / L_jj for rows below j (row[j] is 0 above the diagonal).  The
-      // broadcast runs on all lanes: a DPP move reading a lane that is
-      // switched off does not return that lane's value.
-      const double dj = bcast16(rdiag, j);
-      const double f = (r == j) ? 0.0 : -row[j] * dj;
-#pragma unroll
-      for (int q = 0; q <= j; ++q) x[q] = fma(f, bcast16(x[q], j), x[q]);
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) X[w * 256 + r * 16 + q] = (q <= r) ? x[q] * rdiag : 0.0;
-    }
-  }
+  // the rest of the inverse: X_33, Y_21, Y_20, then block row 3
+  if (w == 1) inv_diag_block(A, X, 3);
+  else if (w == 2) inv_offdiag_block(A, X, Sy + 2 * 256, 2, 1);
+  else if (w == 3) inv_offdiag_block(A, X, Sy + 3 * 256, 2, 0);
   __syncthreads();
-  // block inverse: wave q fills block column q.  The diagonal blocks are X;
-  // an off-diagonal block Y_pq (p > q) is kept transposed in the unused upper
-  // triangle of A (rows 16q.., columns 16p..), which L never touches.
-  {
-    const int q = w;
-    double* Sw = Sc + q * 256;            // wave-private 16 x 16 scratch
-    for (int pp = q + 1; pp < 4; ++pp) {
-      d4 s4 = {0.0, 0.0, 0.0, 0.0};
-      // S = L_pq X_qq + sum_{q<m<p} L_pm Y_mq   (B[k][n] = Y_mq[k][n] = A[16q + n][16m + k])
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4)
-        s4 = mfma_f64(fr_a(A, LDP, 16 * pp, 16 * q, kk), fr_b(X + q * 256, 16, 0, 0, kk), s4);
-      for (int m = q + 1; m < pp; ++m)
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4)
-          s4 = mfma_f64(fr_a(A, LDP, 16 * pp, 16 * m, kk), fr_a(A, LDP, 16 * q, 16 * m, kk), s4);
-      fr_store(Sw, 16, 0, 0, s4);
-      d4 y4 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4)
-        y4 = mfma_f64(-fr_a(X + pp * 256, 16, 0, 0, kk), fr_b(Sw, 16, 0, 0, kk), y4);
-      // store Y_pq transposed: A[16q + n][16pp + r] = Y_pq[r][n]
-      {
-        const int l = lane_id();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) A[(16 * q + (l & 15)) * LDP + 16 * pp + (l >> 4) + 4 * v] = y4[v];
-      }
-    }
-  }
+  if (w >= 1) inv_offdiag_block(A, X, Sy + w * 256, 3, 3 - w);
   __syncthreads();
   // the inverse first (the next panel's solves wait for it), then the flag,
   // then the factor tile itself (read only by later kernels)
@@ -725,7 +737,8 @@ struct CholBatch {
 };
 
 __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
-  // DIAG: tile (64 x 65) + X and scratch (2 x 4 x 256) = 6208 doubles;
+  // DIAG: tile (64 x 65) + X (4 x 256) + sweep scratch and thresholds
+  // (1024 + 64) + inverse scratch (4 x 256) = 7296 doubles;
   // TRSM/GEMM: two 64 x 64 operands = 8192 doubles
   __shared__ double buf[2 * T64 * T64];
   __shared__ int sh[4];
