@@ -210,6 +210,12 @@ __device__ __forceinline__ void tile_store_lds(const TileRegs& t, double* S, dou
   for (int q = 0; q < 16; ++q) S[threadIdx.x + 256 * q] = scale * t.v[q];
 }
 
+// Row-XOR layout of a 64 x 64 operand: element (k, n) at k * 64 + (n ^ k).
+// Writing it from a column of the source (k runs across the lanes) and
+// reading MFMA fragments (n runs across 16 lanes, four rows of k) both spread
+// over all LDS banks, which a transposing store into the plain layout does
+// not (every lane of the wave on one bank).
+__device__ __forceinline__ int xs64(int k, int n) { return k * T64 + (n ^ k); }
 // Accumulator tile -> LDS in a swizzled column-major layout (element (r, c)
 // at c * 64 + ((r + c) & 63): conflict-free both for the accumulator's
 // column-strided writes and for the column-contiguous reads below).
@@ -835,6 +841,34 @@ struct SolveBatch {
   int swap_io;      // batch descriptors hold the forward pass: swap In/Out for the backward one
 };
 
+// acc += (sa A) B for 64 x 64 operands in LDS, A[k][m] and B[k][n] in the
+// plain layout (k * 64 + m) or, with XA / XB, in the row-XOR layout.
+template <bool XA, bool XB>
+__device__ __forceinline__ void mma64_lds(TileF64<T64, T64, 2, 2>& acc, const double* As, const double* Bs,
+                                          double sa) {
+  const int lane = lane_id(), w = wave_id();
+  const int wm = w / 2, wn = w % 2, rr = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < T64; kk += 4) {
+    const int k = kk + kq;
+    double av[2], bv[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int m = wm * 32 + f * 16 + rr;
+      av[f] = sa * As[XA ? xs64(k, m) : k * T64 + m];
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int n = wn * 32 + f * 16 + rr;
+      bv[f] = Bs[XB ? xs64(k, n) : k * T64 + n];
+    }
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+      for (int fj = 0; fj < 2; ++fj) acc.acc[fi][fj] = mfma_f64(av[fi], bv[fj], acc.acc[fi][fj]);
+  }
+}
+
 __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
@@ -897,12 +931,13 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     for (int s = 0; s < nloop && ok; ++s) {
       const int j = b.backward ? a.T - 1 - s : s;       // producers in their own order
       const int64_t j0 = (int64_t)j * T64;
-      // operand L block: forward L_ij (As[c][r] = L[i0+r][j0+c]); backward L_ji^T (As[c][r] = L[j0+c][i0+r])
+      // operand L block (row-XOR layout): forward L_ij (A[c][r] = L[i0+r][j0+c]); backward L_ji^T
+      // (A[c][r] = L[j0+c][i0+r]); Out_j also row-XOR (B[p][q] = Out[j0+p][r0+q])
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
-        if (!b.backward) As[q * T64 + p] = gp(a.G)[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
-        else As[p * T64 + q] = gp(a.G)[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
+        if (!b.backward) As[xs64(q, p)] = gp(a.G)[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
+        else As[xs64(p, q)] = gp(a.G)[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
       }
       if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) { ok = false; break; }
       {
@@ -917,28 +952,12 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
-            Bs[p * T64 + q] = v[u];
+            Bs[xs64(p, q)] = v[u];
           }
         }
       }
       __syncthreads();
-      // acc -= Lop * Out_j
-      {
-        const int lane = lane_id(), w = wave_id();
-        const int wm = w / 2, wn = w % 2, rr = lane & 15, kq = lane >> 4;
-#pragma unroll 4
-        for (int kk = 0; kk < T64; kk += 4) {
-          double av[2], bv[2];
-#pragma unroll
-          for (int f = 0; f < 2; ++f) av[f] = -As[(kk + kq) * T64 + wm * 32 + f * 16 + rr];
-#pragma unroll
-          for (int f = 0; f < 2; ++f) bv[f] = Bs[(kk + kq) * T64 + wn * 32 + f * 16 + rr];
-#pragma unroll
-          for (int fi = 0; fi < 2; ++fi)
-#pragma unroll
-            for (int fj = 0; fj < 2; ++fj) acc.acc[fi][fj] = mfma_f64(av[fi], bv[fj], acc.acc[fi][fj]);
-        }
-      }
+      mma64_lds<true, true>(acc, As, Bs, -1.0);       // acc -= Lop * Out_j
       __syncthreads();
     }
     if (!ok) continue;
@@ -970,11 +989,11 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
-          Bs[p * T64 + q] = v[u];
+          Bs[xs64(p, q)] = v[u];
         }
       }
       __syncthreads();
-      res.template mma<T64, T64, T64>(As, Bs);
+      mma64_lds<false, true>(res, As, Bs, 1.0);
       __syncthreads();
     }
     acc_to_lds_sw(res, As);
