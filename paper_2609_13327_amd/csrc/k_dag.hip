@@ -821,10 +821,15 @@ __global__ __launch_bounds__(256, 2) void chol_dag_kernel(CholBatch b) {
 //   Z_i = Linv_i (B_i - sum_{j<i-1} L_ij Z_j) - Mf_i Z_{i-1},   Mf_i = Linv_i L_{i,i-1}
 //   Y_i = Linv_i^T (Z_i - sum_{j>i+1} L_ji^T Y_j) - Mb_i Y_{i+1}, Mb_i = Linv_i^T L_{i+1,i}^T
 // so that the chain from one block row to the next crosses one product.
+// With the second folds (Mf2_i = Linv_i L_{i,i-2}, Mb2_i = Linv_i^T L_{i+2,i}^T)
+// the block row before that is folded the same way, just before the previous
+// one, so that the rest of the task (the older block rows and the product
+// with the inverse) runs one step ahead of the chain.
 struct SolveArgs {
   const double* G; int64_t ld; int T;
   const double* Linv;
   const double* Mf; const double* Mb;   // folded products (column-major, 64 x 64 per block row) or null
+  const double* Mf2; const double* Mb2; // second folds (same layout) or null
   const double* In; int64_t ldIn;
   double* Out; int64_t ldOut;
   int64_t R; const int64_t* Rp;   // right-hand sides: *Rp when Rp is set, else R
@@ -926,8 +931,10 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     bool ok = true;
     const int nprev = b.backward ? (a.T - 1 - i) : i;
     const double* Mfold = b.backward ? a.Mb : a.Mf;
+    const double* Mfold2 = b.backward ? a.Mb2 : a.Mf2;
     const bool fold = Mfold != nullptr && nprev > 0;
-    const int nloop = fold ? nprev - 1 : nprev;         // the previous block row is folded
+    const bool fold2 = fold && Mfold2 != nullptr && nprev > 1;
+    const int nloop = nprev - (fold ? 1 : 0) - (fold2 ? 1 : 0);   // the folded block rows come last
     for (int s = 0; s < nloop && ok; ++s) {
       const int j = b.backward ? a.T - 1 - s : s;       // producers in their own order
       const int64_t j0 = (int64_t)j * T64;
@@ -970,14 +977,17 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     res.zero();
     res.template mma<T64, T64, T64>(As, Bs);
     __syncthreads();
-    if (fold) {
-      // res -= M_i Out_j for the previous block row j (As[k][row] = -M[row][k])
-      const int j = b.backward ? i + 1 : i - 1;
+    // res -= M_i Out_j for the block row j two steps back, then the previous
+    // one (As[k][row] = -M[row][k])
+    bool fok = true;
+#pragma unroll 1
+    for (int d = fold2 ? 2 : 1; d >= 1 && fold; --d) {
+      const int j = b.backward ? i + d : i - d;
       const int64_t j0 = (int64_t)j * T64;
-      const gdouble* Mi = gp(Mfold + (int64_t)i * T64 * T64);
+      const gdouble* Mi = gp((d == 2 ? Mfold2 : Mfold) + (int64_t)i * T64 * T64);
 #pragma unroll
       for (int u = 0; u < 16; ++u) As[threadIdx.x + 256 * u] = -Mi[threadIdx.x + 256 * u];
-      if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) continue;
+      if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) { fok = false; break; }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         double v[8];
@@ -996,6 +1006,7 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
       mma64_lds<false, true>(res, As, Bs, 1.0);
       __syncthreads();
     }
+    if (!fok) continue;
     acc_to_lds_sw(res, As);
     __syncthreads();
     lds_sw_to_global(As, nullptr, a.Out, a.ldOut, i0, r0, a.R - r0, false);
@@ -1177,41 +1188,42 @@ hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
   return e != hipSuccess ? e : launch_solve_fold(in, s);
 }
 
-// The folded products of the block solves: block (i, 0) forms Mf_i =
-// Linv_i L_{i,i-1} (i >= 1), block (i, 1) forms Mb_i = Linv_i^T L_{i+1,i}^T
-// (i <= T - 2); both column-major.
+// The folded products of the block solves: block (i, y) forms, for the
+// distance d = 1 + y / 2, Mf_i = Linv_i L_{i,i-d} (y even, i >= d) or
+// Mb_i = Linv_i^T L_{i+d,i}^T (y odd, i + d <= T - 1); column-major, in M
+// at block (y T + i) (Mf, Mb, Mf2, Mb2).
 __global__ __launch_bounds__(256) void solve_fold_kernel(const double* G, int64_t ld, const double* Linv, int T,
-                                                         double* Mf, double* Mb) {
+                                                         double* M) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
-  const int i = blockIdx.x, dir = blockIdx.y;
-  if ((dir == 0 && i == 0) || (dir == 1 && i == T - 1)) return;
+  const int i = blockIdx.x, y = blockIdx.y, dir = y & 1, dist = 1 + y / 2;
+  if ((dir == 0 && i < dist) || (dir == 1 && i + dist > T - 1)) return;
   const gdouble* Lb = gp(Linv + (int64_t)i * T64 * T64);
-  const int64_t i0 = (int64_t)i * T64;
+  const int64_t i0 = (int64_t)i * T64, o = (int64_t)dist * T64;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int idx = threadIdx.x + 256 * u, p = idx % T64, c = idx / T64;
     if (dir == 0) {
       As[idx] = Lb[idx];                                            // A[p][c] = Linv[p][c]
-      Bs[p * T64 + c] = gp(G)[(i0 + p) + (i0 - T64 + c) * ld];     // B[p][c] = L_{i,i-1}[p][c]
+      Bs[xs64(p, c)] = gp(G)[(i0 + p) + (i0 - o + c) * ld];         // B[p][c] = L_{i,i-d}[p][c]
     } else {
-      As[p * T64 + c] = Lb[idx];                                    // A[c][p] = Linv[p][c]
-      Bs[idx] = gp(G)[(i0 + T64 + p) + (i0 + c) * ld];             // B[c][p] = L_{i+1,i}[p][c]
+      As[xs64(p, c)] = Lb[idx];                                     // A[c][p] = Linv[p][c]
+      Bs[idx] = gp(G)[(i0 + o + p) + (i0 + c) * ld];                // B[c][p] = L_{i+d,i}[p][c]
     }
   }
   __syncthreads();
   TileF64<T64, T64, 2, 2> acc;
   acc.zero();
-  acc.template mma<T64, T64, T64>(As, Bs);
-  double* M = (dir == 0 ? Mf : Mb) + (int64_t)i * T64 * T64;
-  acc.for_each([&](int r, int c, double v) { M[r + c * T64] = v; });
+  if (dir == 0) mma64_lds<false, true>(acc, As, Bs, 1.0);
+  else mma64_lds<true, false>(acc, As, Bs, 1.0);
+  double* Mo = M + ((int64_t)y * T + i) * T64 * T64;
+  acc.for_each([&](int r, int c, double v) { Mo[r + c * T64] = v; });
 }
 
 hipError_t launch_solve_fold(const Inst& in, hipStream_t s) {
   const int T = (int)(in.KMp / T64);
   if (!in.Msol || T < 2) return hipSuccess;
-  hipLaunchKernelGGL(solve_fold_kernel, dim3((unsigned)T, 2), dim3(256), 0, s, in.G, in.KMp, in.Linv, T, in.Msol,
-                     in.Msol + (int64_t)T * T64 * T64);
+  hipLaunchKernelGGL(solve_fold_kernel, dim3((unsigned)T, 4), dim3(256), 0, s, in.G, in.KMp, in.Linv, T, in.Msol);
   return hipGetLastError();
 }
 
@@ -1219,7 +1231,9 @@ static SolveArgs solve_args(const Inst& in, const double* In, double* Out, int64
   SolveArgs a;
   const int T = (int)(in.KMp / T64);
   a.G = in.G; a.ld = in.KMp; a.T = T; a.Linv = in.Linv;
-  a.Mf = in.Msol; a.Mb = in.Msol ? in.Msol + (int64_t)T * T64 * T64 : nullptr;
+  const int64_t bs = (int64_t)T * T64 * T64;
+  a.Mf = in.Msol; a.Mb = in.Msol ? in.Msol + bs : nullptr;
+  a.Mf2 = in.Msol ? in.Msol + 2 * bs : nullptr; a.Mb2 = in.Msol ? in.Msol + 3 * bs : nullptr;
   a.In = In; a.ldIn = in.KMp; a.Out = Out; a.ldOut = in.KMp;
   a.R = R; a.Rp = nullptr; a.nrt = in.nrt_max;
   a.flags = in.dag + (int64_t)T * T + 2;               // T * nrt_max flags, then head

@@ -34,7 +34,7 @@ struct Inst {
   double* diag0 = nullptr;   // KMp: diagonal of the Gram before factoring
   double* Linv = nullptr;    // (KMp/NB) blocks of NB x NB: inverses of the diagonal blocks of L
   double* Lt = nullptr;      // final strictly-lower tiles of L, tile-major, written once per factorization
-  double* Msol = nullptr;    // 2 x (KMp/NB) blocks NB x NB: the block solves' folded last updates
+  double* Msol = nullptr;    // 4 x (KMp/NB) blocks NB x NB: the block solves' folded last two updates
   int64_t lt_tiles = 0;      // capacity of Lt in 64 x 64 tiles
   double* S = nullptr;       // n_h x ldS per-column Grams (row j holds the P packed pairs, zero padded)
   int64_t ldS = 0;           // P rounded up to the 128-pair Gram tile

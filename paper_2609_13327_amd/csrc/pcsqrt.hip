@@ -167,7 +167,7 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   chk(dalloc(&in.G, KMp * KMp));
   chk(dalloc(&in.diag0, KMp));
   chk(dalloc(&in.Linv, nblk * pc::NB * pc::NB));
-  chk(dalloc(&in.Msol, 2 * nblk * pc::NB * pc::NB));
+  chk(dalloc(&in.Msol, 4 * nblk * pc::NB * pc::NB));
   in.ldS = pc::round_up(in.P, 128);
   chk(dalloc(&in.S, in.n_h * in.ldS));
   chk(dalloc(&in.pairs, 2 * in.P));
