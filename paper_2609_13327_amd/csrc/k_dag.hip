@@ -258,24 +258,23 @@ __device__ __forceinline__ void ltile_load(const CholArgs& a, int i, int k, Tile
 // X Linv^T for a 64 x 64 tile X (As[c * 64 + r] = X[r][c]) and the inverse of
 // a diagonal tile (Bs[c * 64 + r] = Linv[r][c]).  Linv is lower triangular,
 // so output columns 16 f.. need only the first 16 (f + 1) contraction
-// indices.  Wave w computes rows 16 w.. of the four 16-column fragments:
-// acc4[f][v] is element (16 w + (lane >> 4) + 4 v, 16 f + (lane & 15)).
+// indices.  The product is formed transposed: wave w computes rows 16 w.. of
+// the four 16-column fragments, acc4[f][v] being element
+// (16 w + (lane & 15), 16 f + (lane >> 4) + 4 v), so that 16 lanes hold 16
+// consecutive rows of a column (coalesced column-major stores, and
+// conflict-free LDS stores into a column-major tile).
 __device__ __forceinline__ void mul_linv_t(const double* As, const double* Bs, d4 acc4[4]) {
   const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
 #pragma unroll
   for (int f = 0; f < 4; ++f) acc4[f] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < T64; kk += 4) {
-    const double av = As[(kk + (l >> 4)) * T64 + 16 * w + (l & 15)];
+    const double xv = As[(kk + (l >> 4)) * T64 + 16 * w + (l & 15)];
 #pragma unroll
     for (int f = kk / 16; f < 4; ++f)
-      acc4[f] = mfma_f64(av, Bs[(kk + (l >> 4)) * T64 + 16 * f + (l & 15)], acc4[f]);
+      acc4[f] = mfma_f64(Bs[(kk + (l >> 4)) * T64 + 16 * f + (l & 15)], xv, acc4[f]);
   }
 }
-
-// ---- 16 x 16 MFMA fragments on LDS matrices stored row-major (M[r * ld + c]).
-// A operand A[r][k] = M[r0 + r][c0 + k]; transposed-B operand B[k][n] = M[r0 + n][c0 + k]
-// uses the same addressing; plain B operand B[k][n] = M[r0 + k][c0 + n].
 __device__ __forceinline__ double fr_a(const double* M, int ld, int r0, int c0, int kk) {
   const int l = lane_id();
   return M[(r0 + (l & 15)) * ld + c0 + kk + (l >> 4)];
@@ -531,9 +530,9 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
     tile_store_lds(tb, Bs, 1.0);
     __syncthreads();
     upd.zero();
-    upd.template mma<T64, T64, T64>(As, Bs);
+    upd.template mma<T64, T64, T64>(Bs, As);          // transposed: accumulator (c, r)
     __syncthreads();
-    upd.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+    upd.for_each([&](int c, int r, double v) { As[c * T64 + r] = v; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) As[threadIdx.x + 256 * q] += tp.v[q];
@@ -552,27 +551,27 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
   }
   __syncthreads();
   {
-    // L_{k,k-1} = G' Linv_{k-1}^T
+    // L_{k,k-1} = G' Linv_{k-1}^T, out from the accumulators (published
+    // later) and into As as a column-major tile for the SYRK
     const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
     d4 acc4[4];
     mul_linv_t(As, Bs, acc4);
+    double* lt = a.Lt ? a.Lt + lt_off(k, k - 1) : nullptr;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + (l & 15), c = 16 * f + (l >> 4) + 4 * v;
+        st_c(&a.G[(k0 + r) + (p0 + c) * a.ld], acc4[f][v]);
+        if (lt) st_c(&lt[c * T64 + r], acc4[f][v]);
+      }
     __syncthreads();
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) As[(16 * f + (l & 15)) * T64 + 16 * w + (l >> 4) + 4 * v] = acc4[f][v];
+      for (int v = 0; v < 4; ++v) As[(16 * f + (l >> 4) + 4 * v) * T64 + 16 * w + (l & 15)] = acc4[f][v];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {                        // L_{k,k-1} out (published later)
-    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
-    st_c(&a.G[(k0 + r) + (p0 + c) * a.ld], As[idx]);
-  }
-  if (a.Lt) {
-    double* lt = a.Lt + lt_off(k, k - 1);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) st_c(&lt[threadIdx.x + 256 * q], As[threadIdx.x + 256 * q]);
-  }
   double* A = buf;
   {
     // L_{k,k-1} L_{k,k-1}^T on the ten lower 16 x 16 fragments, three or two
@@ -682,9 +681,9 @@ __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* 
     tile_store_lds(tb, Bs, 1.0);
     __syncthreads();
     upd.zero();
-    upd.template mma<T64, T64, T64>(As, Bs);          // -L_{i,k-1} L_{k,k-1}^T
+    upd.template mma<T64, T64, T64>(Bs, As);          // -L_{i,k-1} L_{k,k-1}^T, transposed
     __syncthreads();
-    upd.for_each([&](int r, int c, double v) { As[c * T64 + r] = v; });
+    upd.for_each([&](int c, int r, double v) { As[c * T64 + r] = v; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) As[threadIdx.x + 256 * q] += tc.v[q];   // As[c][r] = updated G_ik
@@ -699,24 +698,19 @@ __device__ __noinline__ bool trsm_task(const CholArgs& a, int i, int k, double* 
   tile_store_lds(tb, Bs, 1.0);
   __syncthreads();
   {
+    // L_ik = G'_ik Linv_k^T, out straight from the accumulators
     const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
     d4 acc4[4];
-    mul_linv_t(As, Bs, acc4);                         // L_ik = G'_ik Linv_k^T
-    __syncthreads();
+    mul_linv_t(As, Bs, acc4);
+    double* lt = a.Lt ? a.Lt + lt_off(i, k) : nullptr;
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) As[sw64(16 * w + (l >> 4) + 4 * v, 16 * f + (l & 15))] = acc4[f][v];
-  }
-  __syncthreads();
-  lds_sw_to_global(As, nullptr, a.G, a.ld, i0, k0, T64, false);
-  if (a.Lt) {
-    double* lt = a.Lt + lt_off(i, k);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = threadIdx.x + 256 * q;
-      st_c(&lt[idx], As[sw64(idx % T64, idx / T64)]);
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + (l & 15), c = 16 * f + (l >> 4) + 4 * v;
+        st_c(&a.G[(i0 + r) + (k0 + c) * a.ld], acc4[f][v]);
+        if (lt) st_c(&lt[c * T64 + r], acc4[f][v]);
+      }
   }
   return true;
 }
