@@ -122,7 +122,8 @@ static hipError_t run_ztx(const Inst& in, const double* X, int64_t ldX, int64_t 
 // few tiles the j range is split in two halves accumulated with two atomic
 // adds onto a zeroed output (two addends onto zero: the same result in either
 // order).
-constexpr int ZT = 64, ZKC = 16, ZLD = ZT + 1;
+constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1;
+constexpr int ZNQ = ZKC * ZT / 256;     // X and W values staged per thread and chunk
 
 struct Ztx1Args {
   const double* E; int64_t ldE;
@@ -158,11 +159,11 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
   const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
   const double* Ek = a.E + k * a.ldE;
 
-  double xv[4], wv[4], ev = 0.0;
+  double xv[ZNQ], wv[ZNQ], ev = 0.0;
   auto load = [&](int chunk) {
     const int64_t j0 = jbeg + (int64_t)chunk * ZKC;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ZNQ; ++q) {
       const int e = t + 256 * q, jj = e % ZKC, col = e / ZKC;
       const int64_t j = j0 + jj;
       xv[q] = (j < jend && r0 + col < a.R) ? a.X[j + (r0 + col) * a.ldX] : 0.0;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ZNQ; ++q) {
       const int e = t + 256 * q, jj = e % ZKC, col = e / ZKC;
       Xs[buf][jj * ZLD + col] = xv[q];
       Ws[buf][jj * ZLD + col] = wv[q];
