@@ -117,12 +117,12 @@ static hipError_t run_ztx(const Inst& in, const double* X, int64_t ldX, int64_t 
 }
 
 // Single level (n_w = 1): b_k = (X^T Z_k)^T with Z_k[j, m] = E[j, k] W[j, m];
-// tile = 64 right-hand sides x 64 modes of one member k.  The member's
-// column of E scales the staged W rows when the MFMA fragment is read.  With
-// few tiles the j range is split in two halves accumulated with two atomic
-// adds onto a zeroed output (two addends onto zero: the same result in either
-// order).
-constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1;
+// tile = 64 right-hand sides x 64 modes of ZKB consecutive members k.  The
+// staged X and W rows serve all of the tile's members: each member's column
+// of E scales the W rows when the MFMA fragment is read.  With few tiles the
+// j range is split in two halves accumulated with two atomic adds onto a
+// zeroed output (two addends onto zero: the same result in either order).
+constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1, ZKB = 2;
 constexpr int ZNQ = ZKC * ZT / 256;     // X and W values staged per thread and chunk
 
 struct Ztx1Args {
@@ -131,7 +131,7 @@ struct Ztx1Args {
   const double* X; int64_t ldX;
   double* B; int64_t ldB;
   int64_t n_h, K, M, R;
-  int ntr, ntm, split;
+  int ntr, ntm, ntk, split;
   int64_t jlen;
   const int* skip;
 };
@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
   if (a.skip && *a.skip) return;
   __shared__ double Xs[2][ZKC * ZLD];
   __shared__ double Ws[2][ZKC * ZLD];
-  __shared__ double Es[2][ZKC];
-  const int64_t ntiles = (int64_t)a.ntr * a.ntm * a.K;
+  __shared__ double Es[2][ZKC * ZKB];
+  const int64_t ntiles = (int64_t)a.ntr * a.ntm * a.ntk;
   const int64_t units = ntiles * a.split;
   const int64_t per = (units + 7) / 8;
   const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;     // contiguous ranges per XCD
@@ -150,16 +150,20 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
   int64_t tile = u % ntiles;
   const int tr = (int)(tile % a.ntr); tile /= a.ntr;
   const int tm = (int)(tile % a.ntm);
-  const int64_t k = tile / a.ntm;
+  const int64_t k0 = (tile / a.ntm) * ZKB;                         // first member of the tile
   const int64_t r0 = (int64_t)tr * ZT, m0 = (int64_t)tm * ZT;
   const int64_t jbeg = (int64_t)part * a.jlen;
   const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
   const int nchunks = (int)((jend - jbeg + ZKC - 1) / ZKC);
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
-  const double* Ek = a.E + k * a.ldE;
 
   double xv[ZNQ], wv[ZNQ], ev = 0.0;
+  // E: thread t < ZKC * ZKB stages member t / ZKC, row t % ZKC (zero past K)
+  const int ej = t % ZKC, ek = t / ZKC;
+  const bool estage = t < ZKC * ZKB;
+  const double* Ek = a.E + (k0 + ek) * a.ldE;
+  const bool evalid = estage && k0 + ek < a.K;
   auto load = [&](int chunk) {
     const int64_t j0 = jbeg + (int64_t)chunk * ZKC;
 #pragma unroll
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
       xv[q] = (j < jend && r0 + col < a.R) ? a.X[j + (r0 + col) * a.ldX] : 0.0;
       wv[q] = (j < jend && m0 + col < a.M) ? a.W[j + (m0 + col) * a.ldW] : 0.0;
     }
-    if (t < ZKC) ev = (j0 + t < jend) ? Ek[j0 + t] : 0.0;
+    if (estage) ev = (evalid && j0 + ej < jend) ? Ek[j0 + ej] : 0.0;
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -178,13 +182,15 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
       Xs[buf][jj * ZLD + col] = xv[q];
       Ws[buf][jj * ZLD + col] = wv[q];
     }
-    if (t < ZKC) Es[buf][t] = ev;
+    if (estage) Es[buf][ej * ZKB + ek] = ev;
   };
-  d4 acc[2][2];
+  d4 acc[ZKB][2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int b = 0; b < ZKB; ++b)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[b][i][j] = d4{0.0, 0.0, 0.0, 0.0};
   if (nchunks > 0) {
     load(0);
     store(0);
@@ -198,34 +204,42 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
 #pragma unroll
       for (int kk = 0; kk < ZKC; kk += 4) {
         const int krow = kk + kq;
-        const double e = Eb[krow];
-        double av[2], bv[2];
+        double av[2], wr[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) av[i] = Xb[krow * ZLD + wm * 32 + i * 16 + rr];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bv[j] = Wb[krow * ZLD + wn * 32 + j * 16 + rr] * e;
+        for (int j = 0; j < 2; ++j) wr[j] = Wb[krow * ZLD + wn * 32 + j * 16 + rr];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int b = 0; b < ZKB; ++b) {
+          const double e = Eb[krow * ZKB + b];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[b][i][j] = mfma_f64(av[i], wr[j] * e, acc[b][i][j]);
+        }
       }
       if (more) store((c + 1) & 1);
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int b = 0; b < ZKB; ++b) {
+    const int64_t k = k0 + b;
+    if (k >= a.K) break;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = r0 + wm * 32 + i * 16 + kq + 4 * v;
-        const int64_t m = m0 + wn * 32 + j * 16 + rr;
-        if (r >= a.R || m >= a.M) continue;
-        double* dst = &a.B[(k * a.M + m) + r * a.ldB];
-        if (a.split == 1) *dst = acc[i][j][v];
-        else atomicAdd(dst, acc[i][j][v]);
-      }
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = r0 + wm * 32 + i * 16 + kq + 4 * v;
+          const int64_t m = m0 + wn * 32 + j * 16 + rr;
+          if (r >= a.R || m >= a.M) continue;
+          double* dst = &a.B[(k * a.M + m) + r * a.ldB];
+          if (a.split == 1) *dst = acc[b][i][j][v];
+          else atomicAdd(dst, acc[b][i][j][v]);
+        }
+  }
 }
 
 __global__ void zero_block_kernel(double* B, int64_t ld, int64_t rows, int64_t cols, const int* skip) {
@@ -241,12 +255,12 @@ static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t
   a.skip = skip;
   a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
   a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
-  a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT);
+  a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT); a.ntk = (int)ceil_div(in.K, ZKB);
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
-  const int64_t ntiles = (int64_t)a.ntr * a.ntm * in.K;
+  const int64_t ntiles = (int64_t)a.ntr * a.ntm * a.ntk;
   a.split = (ntiles < 2 * (int64_t)cus && in.n_h >= 4 * ZKC) ? 2 : 1;
   if (in.tune_ztx_split == 1 || (in.tune_ztx_split == 2 && in.n_h >= 2 * ZKC)) a.split = in.tune_ztx_split;
   a.jlen = round_up(ceil_div(in.n_h, a.split), ZKC);
