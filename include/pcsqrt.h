@@ -130,6 +130,20 @@ pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int
                                 const int64_t *R, double *const *Y, const int64_t *ldY,
                                 void *stream);
 
+/* pc_factor_apply — pc_gram_factor followed by pc_left_inverse_apply, with
+ * the same arguments, ownership and statuses (failed_instance as in
+ * pc_gram_factor; X need not be ready before the call, only ordered before
+ * it on `stream`).  For a plan of one instance without a graph, the
+ * products b = Z^T x (Sec. 3.9: they use E, W and X only) run on an
+ * internal stream while the factorization runs, which the two separate
+ * calls cannot do: pc_gram_factor waits for the pivot status before
+ * returning.  Synchronizes `stream` once, at the end.  If the Gram is not
+ * positive definite the result Y is undefined and PC_ERR_NOT_SPD is
+ * returned; the plan then rejects apply until a successful factorization. */
+pc_status pc_factor_apply(pc_plan *plan, const double *const *X, const int64_t *ldX,
+                          const int64_t *R, double *const *Y, const int64_t *ldY,
+                          void *stream, int32_t *failed_instance);
+
 /* pc_query_info — after an apply and a stream sync: iterations used by the
  * last apply (max over its right-hand sides) and its final max|delta|/max|y|,
  * for instance `instance`.  Either output pointer may be NULL. */

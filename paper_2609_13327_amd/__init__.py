@@ -45,7 +45,7 @@ EXPORTED = [
     "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
-    "pc_set_tuning",
+    "pc_set_tuning", "pc_factor_apply",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout"]
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.pc_left_inverse_apply.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
                                           POINTER(c_int64), POINTER(c_void_p), POINTER(c_int64),
                                           c_void_p]
+    lib.pc_factor_apply.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64), POINTER(c_int64),
+                                    POINTER(c_void_p), POINTER(c_int64), c_void_p, POINTER(c_int32)]
     lib.pc_query_info.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_double)]
     lib.pc_plan_destroy.argtypes = [c_void_p]
     lib.pc_status_string.argtypes = [c_int32]
@@ -224,6 +226,36 @@ def pc_gram_factor(plan: int, stream=None, raise_on_error: bool = True):
 def pc_gram_assemble(plan: int, stream=None):
     _check(load_library().pc_gram_assemble(c_void_p(plan), c_void_p(_stream(stream))),
            "pc_gram_assemble")
+
+
+def _apply_args(X: Sequence, Y: Sequence):
+    n = len(X)
+    xp = (c_void_p * n)()
+    ldx = (c_int64 * n)()
+    rr = (c_int64 * n)()
+    yp = (c_void_p * n)()
+    ldy = (c_int64 * n)()
+    for i in range(n):
+        if X[i] is None:
+            xp[i], ldx[i], rr[i], yp[i], ldy[i] = None, 1, 0, None, 1
+            continue
+        if X[i].shape[1] != Y[i].shape[1]:
+            raise ValueError("X and Y must have the same number of columns")
+        xp[i], ldx[i], rr[i] = _ptr(X[i]), _ld(X[i]), int(X[i].shape[1])
+        yp[i], ldy[i] = _ptr(Y[i]), _ld(Y[i])
+    return xp, ldx, rr, yp, ldy
+
+
+def pc_factor_apply(plan: int, X: Sequence, Y: Sequence, stream=None, raise_on_error: bool = True):
+    """Factor and apply in one call (Y[i] <- Z_i^+ X[i]); returns (status, failed_instance)."""
+    lib = load_library()
+    xp, ldx, rr, yp, ldy = _apply_args(X, Y)
+    failed = c_int32(-1)
+    st = lib.pc_factor_apply(c_void_p(plan), xp, ldx, rr, yp, ldy, c_void_p(_stream(stream)),
+                             ctypes.byref(failed))
+    if raise_on_error:
+        _check(st, "pc_factor_apply", f"(instance {failed.value})")
+    return st, failed.value
 
 
 def pc_left_inverse_apply(plan: int, X: Sequence, Y: Sequence, stream=None,
@@ -416,6 +448,9 @@ class Plan:
 
     def apply(self, X: Sequence, Y: Sequence, stream=None, raise_on_error: bool = True):
         return pc_left_inverse_apply(self.handle, X, Y, stream, raise_on_error)
+
+    def factor_apply(self, X: Sequence, Y: Sequence, stream=None, raise_on_error: bool = True):
+        return pc_factor_apply(self.handle, X, Y, stream, raise_on_error)
 
     def close(self):
         if self.handle:

@@ -91,6 +91,8 @@ hipError_t launch_column_grams(const Inst& in, hipStream_t s) {
 // places workgroup b on XCD b mod 8) works on a contiguous range of tiles,
 // which then share S rows in its L2.
 constexpr int GB = 128, GKC = 16, GWC = 24;
+constexpr int GSR = GKC / 4;                      // S rows staged per thread and chunk (two pairs each)
+constexpr int GWH = (GKC * GWC + 255) / 256;      // W values staged per thread and chunk
 
 struct GramArgs {
   const double* S; int64_t ldS;
@@ -122,20 +124,20 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
 
   // this thread's staging slots
   const int sp = (t & 63) * 2, srow = t >> 6;           // S: rows srow + 4i, pairs sp, sp+1
-  int wcol[2], wrow[2];
-  int64_t wm_idx[2];
+  int wcol[GWH], wrow[GWH];
+  int64_t wm_idx[GWH];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < GWH; ++h) {
     const int idx = t + 256 * h;
     wcol[h] = idx / GKC;
     wrow[h] = idx % GKC;
     wm_idx[h] = (wcol[h] < 8) ? (int64_t)m0 + wcol[h] : (int64_t)mp0 + wcol[h] - 8;
   }
-  double sv[8], wv[2];
+  double sv[2 * GSR], wv[GWH];
   auto load = [&](int chunk) {
     const int64_t j0 = jbeg + (int64_t)chunk * GKC;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < GSR; ++i) {
       const int64_t j = j0 + srow + 4 * i;
       if (j < jend) {
         const double2 v = *reinterpret_cast<const double2*>(a.S + j * a.ldS + p0 + sp);
@@ -145,19 +147,19 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
       }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < GWH; ++h) {
       const int64_t j = j0 + wrow[h];
       wv[h] = (wcol[h] < GWC && j < jend && wm_idx[h] < a.M) ? a.W[j + wm_idx[h] * a.ldW] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < GSR; ++i) {
       As[buf][(srow + 4 * i) * GB + sp] = sv[2 * i];
       As[buf][(srow + 4 * i) * GB + sp + 1] = sv[2 * i + 1];
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < GWH; ++h)
       if (wcol[h] < GWC) Ws[buf][wrow[h] * GWC + wcol[h]] = wv[h];
   };
 

@@ -49,6 +49,9 @@ struct pc_plan {
   pc::DagBatch* batch = nullptr;
   // several instances in reduced precision: their Grams in one launch
   pc::LowGramBatch* lowgram = nullptr;
+  // factor-and-apply: the products Z^T x on their own stream during the factorization
+  hipStream_t ovl = nullptr;
+  hipEvent_t ev_gram = nullptr, ev_ztx = nullptr;
 };
 
 namespace {
@@ -93,6 +96,9 @@ void free_plan(pc_plan* p) {
   if (p->gexec) hipGraphExecDestroy(p->gexec);
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->cap) hipStreamDestroy(p->cap);
+  if (p->ovl) hipStreamDestroy(p->ovl);
+  if (p->ev_gram) hipEventDestroy(p->ev_gram);
+  if (p->ev_ztx) hipEventDestroy(p->ev_ztx);
   for (auto st : p->aux) hipStreamDestroy(st);
   if (p->ev_fork) hipEventDestroy(p->ev_fork);
   for (auto e : p->ev_join) hipEventDestroy(e);
@@ -330,7 +336,8 @@ pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_
                                 double* const* Y, const int64_t* ldY, hipStream_t s, int check_every);
 
 pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
-                        double* const* Y, const int64_t* ldY, hipStream_t s, int check_every) {
+                        double* const* Y, const int64_t* ldY, hipStream_t s, int check_every,
+                        bool ztx_done = false) {
   if (p->batch) return enqueue_apply_batched(p, X, ldX, R, Y, ldY, s, check_every);
   const size_t cnt = p->inst.size();
   const int budget = p->opt.max_refine;
@@ -339,7 +346,7 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
     Inst& in = p->inst[i];
     if (R[i] == 0) continue;
     hipStream_t si = stream_for(p, i, s);
-    { PhaseTimer t(p, PC_PHASE_ZTX, si); PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si)); }
+    if (!ztx_done) { PhaseTimer t(p, PC_PHASE_ZTX, si); PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si)); }
     { PhaseTimer t(p, PC_PHASE_SOLVE, si); PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, si)); }
     PC_TRY(pc::launch_refine_init(in.ctl, budget, si));
   }
@@ -693,11 +700,9 @@ pc_status pc_gram_assemble(pc_plan* p, void* stream) {
   return PC_OK;
 }
 
-pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
-  if (failed_instance) *failed_instance = -1;
-  if (!p) return PC_ERR_INVALID_ARG;
-  hipSetDevice(p->device);
-  hipStream_t s = (hipStream_t)stream;
+// The factorization of every instance on the streams; `after_gram`, if set,
+// is recorded once the (single, unbatched) instance's Gram is assembled.
+static pc_status enqueue_factor(pc_plan* p, hipStream_t s, hipEvent_t after_gram) {
   if (p->lowgram) {
     const pc_status st = assemble_lowgram_batch(p, s);
     if (st != PC_OK) return st;
@@ -709,6 +714,7 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     if (!p->lowgram) {
       const pc_status st = assemble_one(p, in, si);
       if (st != PC_OK) return st;
+      if (after_gram) PC_TRY(hipEventRecord(after_gram, si));
     }
     if (in.Gs) {
       PC_TRY(pc::launch_gram_symmetrize(in, in.Gs, si));
@@ -737,10 +743,14 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     PC_TRY(pc::launch_cholesky_batch(p->batch, s, p->inst[0].tune_chol_per_cu));
     for (const Inst& in : p->inst) PC_TRY(pc::launch_solve_fold(in, s));
   }
+  return PC_OK;
+}
+
+// Pivot status of every instance after the factorization (one stream sync).
+static pc_status finish_factor(pc_plan* p, hipStream_t s, int32_t* failed_instance) {
   std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
   for (size_t i = 0; i < p->inst.size(); ++i) {
     const Inst& in = p->inst[i];
-    const int64_t T = in.KMp / pc::NB;
     PC_TRY(hipMemcpyAsync(&infos[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
     PC_TRY(hipMemcpyAsync(&errs[i], p->batch ? pc::dag_batch_error(p->batch) : pc::chol_error_flag(in), sizeof(int),
                           hipMemcpyDeviceToHost, s));
@@ -757,6 +767,35 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
     }
   }
   return st;
+}
+
+// Refinement outcome of an apply: one read of every instance's control block.
+static pc_status finish_apply(pc_plan* p, const int64_t* R, hipStream_t s) {
+  const size_t cnt = p->inst.size();
+  for (size_t i = 0; i < cnt; ++i) { p->inst[i].iters = 0; p->inst[i].last_rel = 0.0; }
+  if (p->opt.max_refine == 0) return PC_OK;
+  for (size_t i = 0; i < cnt; ++i)
+    if (R[i] != 0)
+      PC_TRY(hipMemcpyAsync(&p->h_ctl[i], p->inst[i].ctl, sizeof(pc::RefineCtl), hipMemcpyDeviceToHost, s));
+  PC_TRY(hipStreamSynchronize(s));
+  pc_status st = PC_OK;
+  for (size_t i = 0; i < cnt; ++i) {
+    if (R[i] == 0) continue;
+    p->inst[i].iters = p->h_ctl[i].iters;
+    p->inst[i].last_rel = p->h_ctl[i].last;
+    if (p->opt.precision != PC_PREC_FP64 && p->h_ctl[i].done != 1) st = PC_ERR_NO_CONVERGENCE;
+  }
+  return st;
+}
+
+pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
+  if (failed_instance) *failed_instance = -1;
+  if (!p) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  const pc_status st = enqueue_factor(p, s, nullptr);
+  if (st != PC_OK) return st;
+  return finish_factor(p, s, failed_instance);
 }
 
 pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
@@ -802,21 +841,50 @@ pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_
     pc_status st = enqueue_apply(p, X, ldX, R, Y, ldY, s, budget > 4 ? 2 : 0);
     if (st != PC_OK) return st;
   }
-  for (size_t i = 0; i < cnt; ++i) { p->inst[i].iters = 0; p->inst[i].last_rel = 0.0; }
-  if (budget == 0) return PC_OK;
-  // refinement outcome: one read of every instance's control block
-  for (size_t i = 0; i < cnt; ++i)
-    if (R[i] != 0)
-      PC_TRY(hipMemcpyAsync(&p->h_ctl[i], p->inst[i].ctl, sizeof(pc::RefineCtl), hipMemcpyDeviceToHost, s));
-  PC_TRY(hipStreamSynchronize(s));
-  pc_status st = PC_OK;
+  return finish_apply(p, R, s);
+}
+
+pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                          double* const* Y, const int64_t* ldY, void* stream, int32_t* failed_instance) {
+  if (failed_instance) *failed_instance = -1;
+  if (!p || !X || !ldX || !R || !Y || !ldY) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t cnt = p->inst.size();
   for (size_t i = 0; i < cnt; ++i) {
+    const Inst& in = p->inst[i];
+    if (R[i] < 0) return PC_ERR_INVALID_ARG;
     if (R[i] == 0) continue;
-    p->inst[i].iters = p->h_ctl[i].iters;
-    p->inst[i].last_rel = p->h_ctl[i].last;
-    if (p->opt.precision != PC_PREC_FP64 && p->h_ctl[i].done != 1) st = PC_ERR_NO_CONVERGENCE;
+    if (R[i] > in.max_rhs) return PC_ERR_TOO_MANY_RHS;
+    if (!X[i] || !Y[i] || ldX[i] < in.n || ldY[i] < in.KM) return PC_ERR_INVALID_ARG;
   }
-  return st;
+  // The overlap: one unbatched instance in FP64 or with refinement, no graph
+  // (the products Z^T x depend on E, W and X only, which the caller's stream
+  // has made ready when the Gram is assembled).
+  const bool overlap = cnt == 1 && R[0] > 0 && !p->batch && !p->lowgram && !p->opt.use_graph;
+  if (!overlap) {
+    const pc_status st = pc_gram_factor(p, stream, failed_instance);
+    if (st != PC_OK) return st;
+    return pc_left_inverse_apply(p, X, ldX, R, Y, ldY, stream);
+  }
+  if (!p->ovl) {
+    if (hipStreamCreateWithFlags(&p->ovl, hipStreamNonBlocking) != hipSuccess) { p->ovl = nullptr; return PC_ERR_DEVICE; }
+    if (hipEventCreateWithFlags(&p->ev_gram, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_ztx, hipEventDisableTiming) != hipSuccess)
+      return PC_ERR_DEVICE;
+  }
+  Inst& in = p->inst[0];
+  pc_status st = enqueue_factor(p, s, p->ev_gram);
+  if (st != PC_OK) return st;
+  PC_TRY(hipStreamWaitEvent(p->ovl, p->ev_gram, 0));
+  { PhaseTimer t(p, PC_PHASE_ZTX, p->ovl); PC_TRY(pc::launch_ztx(in, X[0], ldX[0], R[0], in.Y, in.KMp, p->ovl)); }
+  PC_TRY(hipEventRecord(p->ev_ztx, p->ovl));
+  PC_TRY(hipStreamWaitEvent(s, p->ev_ztx, 0));
+  st = enqueue_apply(p, X, ldX, R, Y, ldY, s, p->opt.max_refine > 4 ? 2 : 0, true);
+  const pc_status fst = finish_factor(p, s, failed_instance);
+  if (st != PC_OK) return st;
+  if (fst != PC_OK) return fst;
+  return finish_apply(p, R, s);
 }
 
 pc_status pc_query_info(const pc_plan* p, int32_t instance, int32_t* iterations, double* last_rel_update) {
