@@ -824,6 +824,10 @@ struct SolveArgs {
   const double* Linv;
   const double* Mf; const double* Mb;   // folded products (column-major, 64 x 64 per block row) or null
   const double* Mf2; const double* Mb2; // second folds (same layout) or null
+  // forward pass run while the factorization runs: the tile states of the
+  // factorization (T x T, row-major) and its final tiles; L blocks and the
+  // inverses are read once their tiles are published
+  const int* cstate; int cT; const double* Lt;
   const double* In; int64_t ldIn;
   double* Out; int64_t ldOut;
   int64_t R; const int64_t* Rp;   // right-hand sides: *Rp when Rp is set, else R
@@ -839,6 +843,34 @@ struct SolveBatch {
   int backward;
   int swap_io;      // batch descriptors hold the forward pass: swap In/Out for the backward one
 };
+
+// The number of leading tiles L_i0, L_i1, .. of tile row i that the running
+// factorization has published, at least `need` + 1 once this returns true
+// (tiles of a row become final in column order).  Wave 0 reads up to 64
+// states per round; the abandon conditions are read every 8th round.
+__device__ __forceinline__ bool row_ready(const int* st_row, int i, int need, int* ready, const int* info, int* err,
+                                          int* sh) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int have = *ready, ok = 1;
+    long long spins = 0;
+    while (have <= need) {
+      const int jj = have + lane;
+      const bool fin = jj >= i || ld_acquire(&st_row[jj]) >= jj + 1;
+      const unsigned long long notfin = __ballot(!fin);
+      have += notfin ? __builtin_ctzll(notfin) : 64;
+      if (have > need) break;
+      if ((++spins & 7) == 0 && (ld_acquire(info) >= 0 || ld_acquire(err) != 0)) { ok = 0; break; }
+      if (spins > kSpinLimit) { if (lane == 0) atomicOr((int*)gp(err), 1); ok = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) { *sh = ok; *ready = have; }
+  }
+  __syncthreads();
+  const bool ok = *sh != 0;
+  __syncthreads();
+  return ok;
+}
 
 // acc += (sa A) B for 64 x 64 operands in LDS, A[k][m] and B[k][n] in the
 // plain layout (k * 64 + m) or, with XA / XB, in the row-XOR layout.
@@ -868,11 +900,20 @@ __device__ __forceinline__ void mma64_lds(TileF64<T64, T64, 2, 2>& acc, const do
   }
 }
 
-__global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
+// CONC: the forward pass alongside the factorization (forward only, no
+// folded products, tiles and inverses read once published); a variant of its
+// own so that it needs no more registers than two waves per SIMD allow and
+// shares the compute units with the factorization's workgroups.
+template <bool CONC>
+__global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBatch b) {
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
-  __shared__ int sh[4];
+  __shared__ int sh[8];
   __shared__ SolveArgs sa;
+  // final tiles (and inverses) of a factorization that runs alongside are
+  // read through the caches once published: drop whatever lines this
+  // compute unit's caches still hold from before the launch
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   for (;;) {
     if (threadIdx.x == 0) sh[0] = atomicAdd(b.head, 1);
     __syncthreads();
@@ -892,7 +933,7 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
         t = g;
       }
       if (sa.Rp) sa.R = *sa.Rp;
-      if (b.swap_io && b.backward) {
+      if (!CONC && b.swap_io && b.backward) {
         const double* in_ = sa.In; const int64_t ldi = sa.ldIn;
         sa.In = sa.Out; sa.ldIn = sa.ldOut;
         sa.Out = const_cast<double*>(in_); sa.ldOut = ldi;
@@ -907,38 +948,50 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     if (skipped) { __syncthreads(); continue; }
     const int step = (int)(t / a.nrt), rt = (int)(t % a.nrt);
     if ((int64_t)rt * T64 >= a.R) continue;            // beyond this call's right-hand sides
-    const int i = b.backward ? a.T - 1 - step : step;
+    const bool bwd = !CONC && b.backward;
+    const int i = bwd ? a.T - 1 - step : step;
     const int64_t i0 = (int64_t)i * T64, r0 = (int64_t)rt * T64;
     TileF64<T64, T64, 2, 2> acc;
     tile_to_acc(a.In, a.ldIn, i0, r0, acc, a.R - r0);    // acc = In[i block, rt]
     // the diagonal block's inverse is static: it travels while the task waits
     // forward: As[k][row] = Linv[row][k]; backward: As[k][row] = Linv[k][row]
     TileRegs linv;
-    {
+    if (!CONC) {
       const gdouble* Lb = gp(a.Linv + (int64_t)i * T64 * T64);
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
-        linv.v[u] = b.backward ? Lb[q + p * T64] : Lb[idx];
+        linv.v[u] = bwd ? Lb[q + p * T64] : Lb[idx];
       }
     }
+    if (threadIdx.x == 0) sh[4] = 0;                  // leading final tiles of row i (with a.cstate)
     bool ok = true;
-    const int nprev = b.backward ? (a.T - 1 - i) : i;
-    const double* Mfold = b.backward ? a.Mb : a.Mf;
-    const double* Mfold2 = b.backward ? a.Mb2 : a.Mf2;
-    const bool fold = Mfold != nullptr && nprev > 0;
+    const int nprev = bwd ? (a.T - 1 - i) : i;
+    const double* Mfold = bwd ? a.Mb : a.Mf;
+    const double* Mfold2 = bwd ? a.Mb2 : a.Mf2;
+    const bool fold = !CONC && Mfold != nullptr && nprev > 0;
     const bool fold2 = fold && Mfold2 != nullptr && nprev > 1;
     const int nloop = nprev - (fold ? 1 : 0) - (fold2 ? 1 : 0);   // the folded block rows come last
     for (int s = 0; s < nloop && ok; ++s) {
-      const int j = b.backward ? a.T - 1 - s : s;       // producers in their own order
+      const int j = bwd ? a.T - 1 - s : s;               // producers in their own order
       const int64_t j0 = (int64_t)j * T64;
       // operand L block (row-XOR layout): forward L_ij (A[c][r] = L[i0+r][j0+c]); backward L_ji^T
       // (A[c][r] = L[j0+c][i0+r]); Out_j also row-XOR (B[p][q] = Out[j0+p][r0+q])
+      if (CONC) {
+        if (!row_ready(a.cstate + (int64_t)i * a.cT, i, j, &sh[4], a.info, b.err, &sh[2])) { ok = false; break; }
+        const gdouble* lt = gp(a.Lt + lt_off(i, j));   // final tile, column-major
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
-        if (!b.backward) As[xs64(q, p)] = gp(a.G)[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
-        else As[xs64(p, q)] = gp(a.G)[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
+        for (int u = 0; u < 16; ++u) {
+          const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
+          As[xs64(q, p)] = lt[idx];                     // A[p][q] = L[i0+p][j0+q]
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
+          if (!bwd) As[xs64(q, p)] = gp(a.G)[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
+          else As[xs64(p, q)] = gp(a.G)[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
+        }
       }
       if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) { ok = false; break; }
       {
@@ -962,6 +1015,13 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
       __syncthreads();
     }
     if (!ok) continue;
+    if (CONC) {
+      // the diagonal step's inverse, once published
+      if (!wait_ge(&a.cstate[(int64_t)i * a.cT + i], i + 1, a.info, b.err, &sh[2])) continue;
+      const double* Lb = a.Linv + (int64_t)i * T64 * T64;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) linv.v[u] = ld_c(&Lb[threadIdx.x + 256 * u]);
+    }
     // Out_i = Linv_i (or its transpose) * acc
     acc.for_each([&](int r, int c, double v) { Bs[r * T64 + c] = v; });
 #pragma unroll
@@ -976,7 +1036,7 @@ __global__ __launch_bounds__(256, 1) void solve_dag_kernel(SolveBatch b) {
     bool fok = true;
 #pragma unroll 1
     for (int d = fold2 ? 2 : 1; d >= 1 && fold; --d) {
-      const int j = b.backward ? i + d : i - d;
+      const int j = bwd ? i + d : i - d;
       const int64_t j0 = (int64_t)j * T64;
       const gdouble* Mi = gp((d == 2 ? Mfold2 : Mfold) + (int64_t)i * T64 * T64);
 #pragma unroll
@@ -1144,7 +1204,7 @@ static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
     const int64_t nflags = (int64_t)Ts * Ts + 1;
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)), dim3(256), 0, s,
                        v.flags, nflags);
-    hipLaunchKernelGGL(solve_dag_kernel, dim3((unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), sb.ntasks)),
+    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3((unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), sb.ntasks)),
                        dim3(256), 0, s, sb);
     // 3. panel: L_panel = G_panel X^T (from a copy of G_panel)
     double* panel = in.G + (k0 + nb) + k0 * ld;
@@ -1163,7 +1223,7 @@ int* chol_error_flag(const Inst& in) {
   return in.blk_NO > 0 ? in.dag : in.dag + T * T + 1;
 }
 
-hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
+hipError_t launch_cholesky(const Inst& in, hipStream_t s, hipEvent_t after_reset) {
   if (in.blk_NO > 0) {
     const hipError_t e = launch_cholesky_blocked(in, s);
     return e != hipSuccess ? e : launch_solve_fold(in, s);
@@ -1173,6 +1233,10 @@ hipError_t launch_cholesky(const Inst& in, hipStream_t s) {
   const int64_t nctr = (int64_t)T * T + 2;
   hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nctr, 256), 1024)), dim3(256),
                      0, s, in.dag, nctr);
+  if (after_reset) {
+    const hipError_t e = hipEventRecord(after_reset, s);
+    if (e != hipSuccess) return e;
+  }
   CholBatch b{};
   b.one = chol_args(in);
   b.ntasks = in.chol_ntasks; b.head = b.one.head; b.err = b.one.err;
@@ -1235,9 +1299,44 @@ static SolveArgs solve_args(const Inst& in, const double* In, double* Out, int64
   return a;
 }
 
+// The forward pass of the solve, Wk <- L^{-1} B (B = in.Y, Wk = in.B, R
+// right-hand sides), on stream s while the factorization runs on another
+// stream: its tasks read each L block and diagonal inverse once the
+// factorization has published it.  `s` must be ordered after the reset of
+// the factorization's tile states (its tasks would read the last
+// factorization's states otherwise).  The error flag is its own (the last
+// int of the counters).
+hipError_t launch_chol_solve_fwd_concurrent(const Inst& in, int64_t R, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  const int T = (int)(in.KMp / T64);
+  if (in.blk_NO > 0 || !in.Lt) return hipErrorInvalidValue;
+  SolveBatch b{};
+  b.one = solve_args(in, in.Y, in.B, R, nullptr);
+  b.one.Mf = b.one.Mb = b.one.Mf2 = b.one.Mb2 = nullptr;   // formed after the factorization
+  b.one.cstate = in.dag; b.one.cT = T; b.one.Lt = in.Lt;
+  b.one.nrt = (int)ceil_div(R, T64);
+  b.ntasks = (int64_t)T * b.one.nrt;
+  b.head = b.one.flags + (int64_t)T * in.nrt_max;
+  b.err = b.head + 1;
+  b.backward = 0;
+  const int64_t nflags = (int64_t)T * in.nrt_max + 2;       // flags, head, err
+  hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)), dim3(256), 0,
+                     s, b.one.flags, nflags);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<true>, 1), b.ntasks);
+  hipLaunchKernelGGL(solve_dag_kernel_t<true>, dim3(g), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+int* chol_solve_fwd_error_flag(const Inst& in) {
+  const int64_t T = in.KMp / T64;
+  return in.dag + T * T + 2 + T * in.nrt_max + 1;
+}
+
 // Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) holds the forward result.
+// With first_pass = 1 only the backward pass runs (Wk already holds the
+// forward result).
 hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk, int64_t ldW,
-                             hipStream_t s, const int* skip) {
+                             hipStream_t s, const int* skip, int first_pass) {
   if (R <= 0) return hipSuccess;
   const int T = (int)(in.KMp / T64);
   SolveBatch b{};
@@ -1250,15 +1349,15 @@ hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, 
   // the error flag, the flags and the head are reset before each pass (after
   // a blocked factorization nothing else clears the error flag)
   const int64_t nflags = (int64_t)T * in.nrt_max + 2;
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), b.ntasks);
-  for (int pass = 0; pass < 2; ++pass) {
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), b.ntasks);
+  for (int pass = first_pass; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)),
                        dim3(256), 0, s, b.err, nflags);
     b.backward = pass;
     if (pass == 1) {
       b.one.In = Wk; b.one.ldIn = ldW; b.one.Out = Y; b.one.ldOut = ldY;
     }
-    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3(g), dim3(256), 0, s, b);
   }
   return hipGetLastError();
 }
@@ -1408,13 +1507,13 @@ hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s)
   sb.inst = b->solve[refine ? 1 : 0]; sb.segs = b->solve_segs; sb.nsegs = b->solve_nsegs;
   sb.ntasks = b->solve_total; sb.head = b->ctr + 2; sb.err = b->ctr + 1; sb.swap_io = 1;
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->rst_max[1], 256), 256));
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), b->solve_total);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), b->solve_total);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3(1), dim3(64), 0, s, b->ctr + 2, (int64_t)1);
     hipLaunchKernelGGL(batch_reset_kernel, dim3(gx, (unsigned)b->count), dim3(256), 0, s, b->rst_ptr + b->count,
                        b->rst_cnt + b->count);
     sb.backward = pass;
-    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3(g), dim3(256), 0, s, sb);
   }
   return hipGetLastError();
 }
@@ -1460,14 +1559,14 @@ hipError_t launch_member_block_inverse(const double* Gs, int64_t ld, int64_t o, 
   v.flags = a.head + 1; v.info = info; v.skip = nullptr;
   sb.ntasks = (int64_t)Tb * Tb; sb.head = v.flags + (int64_t)Tb * Tb; sb.err = ctr;
   const int64_t nflags = (int64_t)Tb * Tb + 1;
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel), sb.ntasks);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), sb.ntasks);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 64)), dim3(256), 0, s,
                        v.flags, nflags);
     sb.backward = pass;
     if (pass == 0) { v.In = I; v.ldIn = Mp; v.Out = Wk; v.ldOut = Mp; }
     else { v.In = Wk; v.ldIn = Mp; v.Out = Dinv; v.ldOut = Mp; }
-    hipLaunchKernelGGL(solve_dag_kernel, dim3(g), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3(g), dim3(256), 0, s, sb);
   }
   return hipGetLastError();
 }

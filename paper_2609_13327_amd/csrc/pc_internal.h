@@ -100,7 +100,9 @@ LowGramBatch* make_lowgram_batch(const std::vector<Inst>& insts);
 void free_lowgram_batch(LowGramBatch* b);
 hipError_t launch_gram_lowprec_batch(const LowGramBatch* b, int precision, hipStream_t s);
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s);
-hipError_t launch_cholesky(const Inst& in, hipStream_t s);
+// after_reset (may be null) is recorded once the tile states are reset,
+// before the factorization starts (unblocked factorizations only)
+hipError_t launch_cholesky(const Inst& in, hipStream_t s, hipEvent_t after_reset = nullptr);
 hipError_t launch_solve_fold(const Inst& in, hipStream_t s);
 int* chol_error_flag(const Inst& in);   // device int set when a bounded wait of the factorization expired
 // `skip` (device int, may be null): when nonzero at run time the kernels exit
@@ -111,8 +113,12 @@ hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, d
 hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xsub,
                      int64_t ldXs, double* out, int64_t ldOut, hipStream_t s, const int* skip = nullptr);
 // in-place Y <- L^{-T} L^{-1} Y on the KMp x R block (ld = ldY), using work buffer Wk
+// (first_pass = 1: Wk already holds L^{-1} Y, only the backward pass runs)
 hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk,
-                             int64_t ldW, hipStream_t s, const int* skip = nullptr);
+                             int64_t ldW, hipStream_t s, const int* skip = nullptr, int first_pass = 0);
+// in.B <- L^{-1} in.Y (R right-hand sides) while the unblocked factorization runs on another stream
+hipError_t launch_chol_solve_fwd_concurrent(const Inst& in, int64_t R, hipStream_t s);
+int* chol_solve_fwd_error_flag(const Inst& in);   // device int set when one of its bounded waits expired
 hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                             int64_t rows_zero_to, int64_t R, hipStream_t s);
 hipError_t launch_refine_init(RefineCtl* ctl, int budget, hipStream_t s);

@@ -32,6 +32,8 @@ struct pc_plan {
   int device = 0;
   int* d_flag = nullptr;        // device scratch int (finiteness check)
   pc::RefineCtl* h_ctl = nullptr;   // pinned host copies of the refinement controls
+  int* h_status = nullptr;          // pinned host copies of each instance's pivot status and error flag,
+                                    // then the error flag of a forward pass run during the factorization
   // independent instances run on internal streams (fork/join with the caller's stream)
   std::vector<hipStream_t> aux;
   hipEvent_t ev_fork = nullptr;
@@ -51,7 +53,7 @@ struct pc_plan {
   pc::LowGramBatch* lowgram = nullptr;
   // factor-and-apply: the products Z^T x on their own stream during the factorization
   hipStream_t ovl = nullptr;
-  hipEvent_t ev_gram = nullptr, ev_ztx = nullptr;
+  hipEvent_t ev_gram = nullptr, ev_reset = nullptr, ev_ztx = nullptr;
 };
 
 namespace {
@@ -99,6 +101,7 @@ void free_plan(pc_plan* p) {
   if (p->ovl) hipStreamDestroy(p->ovl);
   if (p->ev_gram) hipEventDestroy(p->ev_gram);
   if (p->ev_ztx) hipEventDestroy(p->ev_ztx);
+  if (p->ev_reset) hipEventDestroy(p->ev_reset);
   for (auto st : p->aux) hipStreamDestroy(st);
   if (p->ev_fork) hipEventDestroy(p->ev_fork);
   for (auto e : p->ev_join) hipEventDestroy(e);
@@ -106,6 +109,7 @@ void free_plan(pc_plan* p) {
   pc::free_dag_batch(p->batch);
   pc::free_lowgram_batch(p->lowgram);
   if (p->h_ctl) hipHostFree(p->h_ctl);
+  if (p->h_status) hipHostFree(p->h_status);
   delete p;
 }
 
@@ -188,9 +192,10 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   chk(dalloc(&in.ctl, 1));
   const int64_t T = KMp / pc::NB;
   in.nrt_max = (int)pc::ceil_div(R, pc::NB);
-  // counters: Cholesky states, head, error, solve flags, solve head; the blocked
+  // counters: Cholesky states, head, error, solve flags, solve head, and the
+  // error flag of a forward pass run during the factorization; the blocked
   // factorization reuses them for a diagonal block and its inverse (2 T^2 + 3)
-  chk(dalloc(&in.dag, std::max<int64_t>(T * T + 2 + T * in.nrt_max + 1, 2 * T * T + 3)));
+  chk(dalloc(&in.dag, std::max<int64_t>(T * T + 2 + T * in.nrt_max + 2, 2 * T * T + 3)));
   std::vector<int64_t> offs;
   in.chol_ntasks = pc::chol_task_offsets((int)T, offs);
   chk(dalloc(&in.chol_offs, (int64_t)offs.size()));
@@ -335,9 +340,11 @@ pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
 pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
                                 double* const* Y, const int64_t* ldY, hipStream_t s, int check_every);
 
+// done_ahead: 0, or 1 when b = Z^T x is already in in.Y, or 2 when the
+// forward pass of the first solve is also done (in in.B).
 pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
                         double* const* Y, const int64_t* ldY, hipStream_t s, int check_every,
-                        bool ztx_done = false) {
+                        int done_ahead = 0) {
   if (p->batch) return enqueue_apply_batched(p, X, ldX, R, Y, ldY, s, check_every);
   const size_t cnt = p->inst.size();
   const int budget = p->opt.max_refine;
@@ -346,8 +353,14 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
     Inst& in = p->inst[i];
     if (R[i] == 0) continue;
     hipStream_t si = stream_for(p, i, s);
-    if (!ztx_done) { PhaseTimer t(p, PC_PHASE_ZTX, si); PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si)); }
-    { PhaseTimer t(p, PC_PHASE_SOLVE, si); PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, si)); }
+    if (done_ahead < 1) {
+      PhaseTimer t(p, PC_PHASE_ZTX, si);
+      PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si));
+    }
+    {
+      PhaseTimer t(p, PC_PHASE_SOLVE, si);
+      PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, si, nullptr, done_ahead >= 2 ? 1 : 0));
+    }
     PC_TRY(pc::launch_refine_init(in.ctl, budget, si));
   }
   // refinement on the least-squares residual: r = x - Z y, d = G^{-1} Z^T r, y += d;
@@ -641,6 +654,8 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   (void)max_r;
   if (st == PC_OK && hipHostMalloc((void**)&p->h_ctl, sizeof(pc::RefineCtl) * (size_t)count) != hipSuccess)
     st = PC_ERR_OOM;
+  if (st == PC_OK && hipHostMalloc((void**)&p->h_status, sizeof(int) * (2 * (size_t)count + 1)) != hipSuccess)
+    st = PC_ERR_OOM;
   if (st == PC_OK && count > 1) {
     // default-priority streams for independent instances
     const int ns = std::min<int>(count, 8);
@@ -701,8 +716,10 @@ pc_status pc_gram_assemble(pc_plan* p, void* stream) {
 }
 
 // The factorization of every instance on the streams; `after_gram`, if set,
-// is recorded once the (single, unbatched) instance's Gram is assembled.
-static pc_status enqueue_factor(pc_plan* p, hipStream_t s, hipEvent_t after_gram) {
+// is recorded once the (single, unbatched) instance's Gram is assembled, and
+// `after_reset` once its tile states are reset (unblocked factorization).
+static pc_status enqueue_factor(pc_plan* p, hipStream_t s, hipEvent_t after_gram,
+                                hipEvent_t after_reset = nullptr) {
   if (p->lowgram) {
     const pc_status st = assemble_lowgram_batch(p, s);
     if (st != PC_OK) return st;
@@ -734,7 +751,7 @@ static pc_status enqueue_factor(pc_plan* p, hipStream_t s, hipEvent_t after_gram
     }
     if (!p->batch) {
       PhaseTimer t(p, PC_PHASE_CHOLESKY, si);
-      PC_TRY(pc::launch_cholesky(in, si));
+      PC_TRY(pc::launch_cholesky(in, si, after_reset));
     }
   }
   PC_TRY(join(p, s));
@@ -746,27 +763,42 @@ static pc_status enqueue_factor(pc_plan* p, hipStream_t s, hipEvent_t after_gram
   return PC_OK;
 }
 
-// Pivot status of every instance after the factorization (one stream sync).
-static pc_status finish_factor(pc_plan* p, hipStream_t s, int32_t* failed_instance) {
-  std::vector<int> infos(p->inst.size(), -1), errs(p->inst.size(), 0);
-  for (size_t i = 0; i < p->inst.size(); ++i) {
+// Copies of every instance's pivot status and error flag after the
+// factorization, into pinned memory (read after a later stream sync; the
+// solves reuse the error flag, so the copies go right after the factor).
+static pc_status read_factor_status(pc_plan* p, hipStream_t s) {
+  const size_t n = p->inst.size();
+  for (size_t i = 0; i < n; ++i) {
     const Inst& in = p->inst[i];
-    PC_TRY(hipMemcpyAsync(&infos[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
-    PC_TRY(hipMemcpyAsync(&errs[i], p->batch ? pc::dag_batch_error(p->batch) : pc::chol_error_flag(in), sizeof(int),
-                          hipMemcpyDeviceToHost, s));
+    PC_TRY(hipMemcpyAsync(&p->h_status[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    PC_TRY(hipMemcpyAsync(&p->h_status[n + i], p->batch ? pc::dag_batch_error(p->batch) : pc::chol_error_flag(in),
+                          sizeof(int), hipMemcpyDeviceToHost, s));
   }
-  PC_TRY(hipStreamSynchronize(s));
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    if (errs[i]) return PC_ERR_DEVICE;   // a bounded wait expired: the factor is not trustworthy
+  return PC_OK;
+}
+
+// The factorization's outcome from those copies (after the stream sync).
+static pc_status factor_outcome(pc_plan* p, int32_t* failed_instance) {
+  const size_t n = p->inst.size();
+  for (size_t i = 0; i < n; ++i)
+    if (p->h_status[n + i]) return PC_ERR_DEVICE;   // a bounded wait expired: the factor is not trustworthy
   pc_status st = PC_OK;
-  for (size_t i = 0; i < p->inst.size(); ++i) {
-    p->inst[i].factored = infos[i] < 0;
-    if (infos[i] >= 0 && st == PC_OK) {
+  for (size_t i = 0; i < n; ++i) {
+    p->inst[i].factored = p->h_status[i] < 0;
+    if (p->h_status[i] >= 0 && st == PC_OK) {
       st = PC_ERR_NOT_SPD;
       if (failed_instance) *failed_instance = (int32_t)i;
     }
   }
   return st;
+}
+
+// Pivot status of every instance after the factorization (one stream sync).
+static pc_status finish_factor(pc_plan* p, hipStream_t s, int32_t* failed_instance) {
+  const pc_status st = read_factor_status(p, s);
+  if (st != PC_OK) return st;
+  PC_TRY(hipStreamSynchronize(s));
+  return factor_outcome(p, failed_instance);
 }
 
 // Refinement outcome of an apply: one read of every instance's control block.
@@ -870,20 +902,35 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   if (!p->ovl) {
     if (hipStreamCreateWithFlags(&p->ovl, hipStreamNonBlocking) != hipSuccess) { p->ovl = nullptr; return PC_ERR_DEVICE; }
     if (hipEventCreateWithFlags(&p->ev_gram, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_reset, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_ztx, hipEventDisableTiming) != hipSuccess)
       return PC_ERR_DEVICE;
   }
   Inst& in = p->inst[0];
-  pc_status st = enqueue_factor(p, s, p->ev_gram);
+  // The forward pass of the first solve also runs during an unblocked
+  // factorization, behind it: its tasks wait for the L blocks they read.
+  const bool fwd = in.blk_NO == 0 && in.Lt != nullptr;
+  pc_status st = enqueue_factor(p, s, p->ev_gram, fwd ? p->ev_reset : nullptr);
+  if (st != PC_OK) return st;
+  st = read_factor_status(p, s);
   if (st != PC_OK) return st;
   PC_TRY(hipStreamWaitEvent(p->ovl, p->ev_gram, 0));
   { PhaseTimer t(p, PC_PHASE_ZTX, p->ovl); PC_TRY(pc::launch_ztx(in, X[0], ldX[0], R[0], in.Y, in.KMp, p->ovl)); }
+  if (fwd) {
+    PC_TRY(hipStreamWaitEvent(p->ovl, p->ev_reset, 0));
+    PhaseTimer t(p, PC_PHASE_SOLVE, p->ovl);
+    PC_TRY(pc::launch_chol_solve_fwd_concurrent(in, R[0], p->ovl));
+  }
   PC_TRY(hipEventRecord(p->ev_ztx, p->ovl));
   PC_TRY(hipStreamWaitEvent(s, p->ev_ztx, 0));
-  st = enqueue_apply(p, X, ldX, R, Y, ldY, s, p->opt.max_refine > 4 ? 2 : 0, true);
-  const pc_status fst = finish_factor(p, s, failed_instance);
+  if (fwd)
+    PC_TRY(hipMemcpyAsync(&p->h_status[2], pc::chol_solve_fwd_error_flag(in), sizeof(int), hipMemcpyDeviceToHost, s));
+  st = enqueue_apply(p, X, ldX, R, Y, ldY, s, p->opt.max_refine > 4 ? 2 : 0, fwd ? 2 : 1);
+  PC_TRY(hipStreamSynchronize(s));
+  const pc_status fst = factor_outcome(p, failed_instance);
   if (st != PC_OK) return st;
   if (fst != PC_OK) return fst;
+  if (fwd && p->h_status[2]) return PC_ERR_DEVICE;   // a bounded wait of the forward pass expired
   return finish_apply(p, R, s);
 }
 
