@@ -42,7 +42,7 @@ KERNELS = {
     ("gram", "bf16"): ("gram_bf16_kernel", [CSRC + "k_lowprec.hip"]),
     ("cholesky", None): ("chol_dag_kernel", [CSRC + "k_dag.hip"]),
     ("ztx", None): ("ztx1_kernel", [CSRC + "k_apply.hip"]),
-    ("solve", None): ("solve_dag_kernel", [CSRC + "k_dag.hip"]),
+    ("solve", None): ("solve_dag_kernel_t", [CSRC + "k_dag.hip"]),
 }
 PRECS = {"fp64": (0, 0), "fp32": (1, 10), "bf16": (2, 30)}
 
@@ -203,6 +203,8 @@ def main():
             if not cnt:
                 continue
             per = LAUNCHES_PER_PHASE.get(ph, 1)
+            if ph == "solve" and phases["solve_alongside"][1]:
+                per = 1   # the forward pass ran alongside the factorization: only the backward pass here
             launches_per_step = per * cnt / steps
             # every instance's work is done once per step, by one launch per
             # instance or by one launch for the whole batch

@@ -233,7 +233,9 @@ pc_status pc_query_tuning(const pc_plan *plan, int32_t instance, int32_t *gram_s
 #define PC_PHASE_SOLVE 5         /* the two triangular solves of the initial solve */
 #define PC_PHASE_REFINE 6        /* the whole refinement loop */
 #define PC_PHASE_COPYOUT 7       /* copy of the solution to the caller's Y */
-#define PC_NUM_PHASES 8
+#define PC_PHASE_SOLVE_ALONGSIDE 8  /* pc_factor_apply: the forward pass run during the
+                                       factorization, from its launch to its end */
+#define PC_NUM_PHASES 9
 
 /* pc_profile_enable — on != 0: every later call records a pair of HIP
  * events around each phase it runs, per instance.  Costs a few microseconds

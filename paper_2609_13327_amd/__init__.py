@@ -48,7 +48,7 @@ EXPORTED = [
     "pc_set_tuning", "pc_factor_apply",
 ]
 
-PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout"]
+PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout", "solve_alongside"]
 
 
 class PcInstance(ctypes.Structure):

@@ -918,7 +918,7 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   { PhaseTimer t(p, PC_PHASE_ZTX, p->ovl); PC_TRY(pc::launch_ztx(in, X[0], ldX[0], R[0], in.Y, in.KMp, p->ovl)); }
   if (fwd) {
     PC_TRY(hipStreamWaitEvent(p->ovl, p->ev_reset, 0));
-    PhaseTimer t(p, PC_PHASE_SOLVE, p->ovl);
+    PhaseTimer t(p, PC_PHASE_SOLVE_ALONGSIDE, p->ovl);
     PC_TRY(pc::launch_chol_solve_fwd_concurrent(in, R[0], p->ovl));
   }
   PC_TRY(hipEventRecord(p->ev_ztx, p->ovl));
