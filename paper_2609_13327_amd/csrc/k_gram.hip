@@ -86,8 +86,9 @@ hipError_t launch_column_grams(const Inst& in, hipStream_t s) {
 // W[j,m] W[j,m'] is formed when the MFMA fragment is read from LDS.
 // Four waves own 64 x 64 quadrants (4 x 4 fragments of 16 x 16).
 // When the tiles are too few to fill the device the j range is split in two
-// parts written to G and G2 and summed afterwards (a fixed order, so results
-// are reproducible).  Workgroups are mapped so that each XCD (the hardware
+// or four parts written to G and G2 and summed afterwards in a fixed order
+// (results are reproducible); four when two would leave the last round of
+// workgroups mostly empty.  Workgroups are mapped so that each XCD (the hardware
 // places workgroup b on XCD b mod 8) works on a contiguous range of tiles,
 // which then share S rows in its L2.
 constexpr int GB = 128, GKC = 16, GWC = 24;
@@ -101,7 +102,7 @@ struct GramArgs {
   const int* pairs; const int* qtiles;
   int npt, nq, ntiles, split;
   int64_t jlen;
-  double* G; double* G2; int64_t ldG;
+  double* G; double* G2; int64_t ldG;     // part q >= 1 goes to G2 + (q - 1) ldG^2
 };
 
 __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
       __syncthreads();
     }
   }
-  double* Gout = part == 0 ? a.G : a.G2;
+  double* Gout = part == 0 ? a.G : a.G2 + (int64_t)(part - 1) * a.ldG * a.ldG;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -215,13 +216,29 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
       }
 }
 
+// Contraction parts for the untuned FP64 Gram: one when the tiles fill the
+// device twice over, else two or four, whichever leaves the last round of
+// workgroups (two per compute unit) fuller.
 int gram_split_for(const Inst& in) {
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
   const int64_t tiles = ceil_div(in.P, GB) * (int64_t)in.nq;
-  return (tiles < 2 * (int64_t)cus && in.n_h >= 4 * GKC) ? 2 : 1;
+  const int64_t slots = 2 * (int64_t)cus;
+  if (tiles >= slots || in.n_h < 4 * GKC) return 1;
+  auto fill = [&](int parts) {
+    const int64_t units = tiles * parts;
+    return (double)units / (double)(ceil_div(units, slots) * slots);
+  };
+  return (in.n_h >= 8 * GKC && fill(4) > fill(2) + 0.05) ? 4 : 2;
+}
+
+int gram_parts_used(const Inst& in) {
+  int want = in.tune_gram_split > 0 ? in.tune_gram_split : gram_split_for(in);
+  if (!in.G2) return 1;
+  while (want > 1 && want - 1 > in.g2_parts) want /= 2;
+  return want;
 }
 
 hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
@@ -230,9 +247,9 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
   a.n_h = in.n_h; a.M = in.M; a.P = in.P;
   a.pairs = in.pairs; a.qtiles = in.qtiles;
   a.npt = (int)ceil_div(in.P, GB); a.nq = in.nq; a.ntiles = a.npt * a.nq;
-  a.split = (in.G2 != nullptr && in.tune_gram_split != 1) ? 2 : 1;
+  a.split = gram_parts_used(in);
   a.jlen = round_up(ceil_div(in.n_h, a.split), GKC);
-  a.G = in.G; a.G2 = a.split == 2 ? in.G2 : nullptr; a.ldG = in.KMp;
+  a.G = in.G; a.G2 = a.split > 1 ? in.G2 : nullptr; a.ldG = in.KMp;
   const int64_t units = (int64_t)a.ntiles * a.split;
   const int64_t grid = 8 * ((units + 7) / 8);
   hipLaunchKernelGGL(gram_f64_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
@@ -242,14 +259,19 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
 // ------------------------------------ padding of the Gram and its diagonal
 // Rows/cols KM..KMp-1 become the identity so the blocked factorization can
 // run on whole NB blocks; diag0 keeps the pre-factorization diagonal.
-__global__ void gram_pad_diag_kernel(double* G, const double* G2, int64_t ld, int64_t KM, int64_t KMp,
+__global__ void gram_pad_diag_kernel(double* G, const double* G2, int nextra, int64_t ld, int64_t KM, int64_t KMp,
                                      double* diag0) {
   int64_t c = blockIdx.x;  // column
   if (c >= KM) {
     for (int64_t r = threadIdx.x; r < KMp; r += blockDim.x) G[r + c * ld] = (r == c) ? 1.0 : 0.0;
   } else {
-    if (G2)   // second half of a split Gram: lower triangle of this column
-      for (int64_t r = c + threadIdx.x; r < KM; r += blockDim.x) G[r + c * ld] += G2[r + c * ld];
+    // the other parts of a split Gram, in part order: lower triangle of this column
+    if (nextra > 0)
+      for (int64_t r = c + threadIdx.x; r < KM; r += blockDim.x) {
+        double v = G[r + c * ld];
+        for (int q = 0; q < nextra; ++q) v += G2[(int64_t)q * ld * ld + r + c * ld];
+        G[r + c * ld] = v;
+      }
     for (int64_t r = KM + threadIdx.x; r < KMp; r += blockDim.x) G[r + c * ld] = 0.0;
   }
   __syncthreads();
@@ -257,8 +279,9 @@ __global__ void gram_pad_diag_kernel(double* G, const double* G2, int64_t ld, in
 }
 
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s) {
+  const int parts = gram_parts_used(in);
   hipLaunchKernelGGL(gram_pad_diag_kernel, dim3((unsigned)in.KMp), dim3(256), 0, s, in.G,
-                     (const double*)(in.tune_gram_split != 1 ? in.G2 : nullptr), in.KMp, in.KM, in.KMp, in.diag0);
+                     (const double*)(parts > 1 ? in.G2 : nullptr), parts - 1, in.KMp, in.KM, in.KMp, in.diag0);
   return hipGetLastError();
 }
 

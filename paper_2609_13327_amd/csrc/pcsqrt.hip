@@ -72,7 +72,7 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 void free_inst(Inst& in) {
-  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
+  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; in.g2_parts = 0; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
@@ -121,6 +121,18 @@ std::vector<int> make_qtiles(int64_t M) {
     for (int64_t c = 0; c * 8 < M; ++c)
       if (8 * c <= 16 * d + 15) { q.push_back((int)(8 * c)); q.push_back((int)(16 * d)); }
   return q;
+}
+
+// Room in G2 for the contraction parts 2..parts of a split FP64 Gram.
+hipError_t ensure_gram_parts(Inst& in, int parts) {
+  if (parts - 1 <= in.g2_parts) return hipSuccess;
+  (void)hipFree(in.G2);
+  in.G2 = nullptr;
+  in.g2_parts = 0;
+  const hipError_t e = hipMalloc((void**)&in.G2, sizeof(double) * (size_t)(parts - 1) * (size_t)(in.KMp * in.KMp));
+  if (e != hipSuccess) { in.G2 = nullptr; return e; }
+  in.g2_parts = parts - 1;
+  return hipSuccess;
 }
 
 // Final-L tile buffer for a tile DAG of T tile rows (T (T - 1) / 2 tiles).
@@ -237,8 +249,8 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   if (hipMemset(in.B, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   // S padding columns (pairs P..ldS-1) are read by the Gram tiles and must be zero
   if (hipMemset(in.S, 0, sizeof(double) * in.n_h * in.ldS) != hipSuccess) return PC_ERR_DEVICE;
-  if (precision == PC_PREC_FP64 && pc::gram_split_for(in) == 2) {
-    if (dalloc(&in.G2, KMp * KMp) != hipSuccess) return PC_ERR_OOM;
+  if (precision == PC_PREC_FP64 && pc::gram_split_for(in) > 1) {
+    if (ensure_gram_parts(in, pc::gram_split_for(in)) != hipSuccess) return PC_ERR_OOM;
   }
   if (precision != PC_PREC_FP64) {
     in.ldz = pc::round_up(in.n, 64);
@@ -1096,15 +1108,16 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
       continue;
     }
     any_measured = true;
-    // FP64 Gram: one or two contraction parts (the second part needs G2)
+    // FP64 Gram: one, two or four contraction parts (the others need G2)
     in.tune_gram_split = 1;
     if (prec == PC_PREC_FP64) {
-      if (!in.G2 && hipMalloc((void**)&in.G2, sizeof(double) * (size_t)(in.KMp * in.KMp)) != hipSuccess) {
-        in.G2 = nullptr;
-      }
+      // four parts only where the tiles are few (the large Grams fill the device)
+      const int most = pc::gram_split_for(in) > 1 ? 4 : 2;
+      if (ensure_gram_parts(in, most) != hipSuccess) (void)ensure_gram_parts(in, 2);
       float best = 0.f;
       int choice = 1;
-      for (int c = 1; c <= (in.G2 ? 2 : 1); ++c) {
+      for (int c = 1; c <= most; c *= 2) {
+        if (c - 1 > in.g2_parts) break;
         in.tune_gram_split = c;
         float ms = 0.f;
         pc_status st = time_ms(s, reps, [&]() -> pc_status {
@@ -1185,7 +1198,12 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
   }
   // keep the second Gram part only where it was chosen
   for (auto& in : p->inst)
-    if (in.G2 && in.tune_gram_split == 1) { PC_TRY(hipStreamSynchronize(s)); (void)hipFree(in.G2); in.G2 = nullptr; }
+    if (in.G2 && in.tune_gram_split == 1) {
+      PC_TRY(hipStreamSynchronize(s));
+      (void)hipFree(in.G2);
+      in.G2 = nullptr;
+      in.g2_parts = 0;
+    }
   PC_TRY(hipStreamSynchronize(s));
   if (cache_path && any_measured) {
     for (const auto& in : p->inst) {
@@ -1204,18 +1222,16 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
 pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_t ztx_split, int32_t chol_per_cu,
                         int32_t chol_block) {
   if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
-  if (gram_split < 0 || gram_split > 2 || ztx_split < 0 || ztx_split > 2 || chol_per_cu < 0 || chol_per_cu > 2)
+  if (gram_split < 0 || gram_split > 4 || gram_split == 3 || ztx_split < 0 || ztx_split > 2 || chol_per_cu < 0 ||
+      chol_per_cu > 2)
     return PC_ERR_INVALID_ARG;
   if (chol_block < -1 || (chol_block > 0 && (chol_block < 128 || chol_block % pc::NB != 0)))
     return PC_ERR_INVALID_ARG;
   if (chol_block != 0 && p->batch) return PC_ERR_INVALID_ARG;   // a batch factors every instance in one launch
   hipSetDevice(p->device);
   Inst& in = p->inst[instance];
-  if (gram_split == 2 && p->opt.precision == PC_PREC_FP64 && !in.G2 &&
-      hipMalloc((void**)&in.G2, sizeof(double) * (size_t)(in.KMp * in.KMp)) != hipSuccess) {
-    in.G2 = nullptr;
+  if (gram_split >= 2 && p->opt.precision == PC_PREC_FP64 && ensure_gram_parts(in, gram_split) != hipSuccess)
     return PC_ERR_OOM;
-  }
   if (chol_block != 0) {
     const pc_status bs = alloc_blocked(in, chol_block > 0 ? chol_block : 0);
     if (bs != PC_OK) return bs;
