@@ -48,6 +48,7 @@ namespace pc {
 
 constexpr int T64 = 64;
 constexpr int LDP = T64 + 1;          // padded LDS stride
+constexpr int kSolveWaves = 8;        // waves per workgroup of the solves (not the one run alongside)
 constexpr long long kSpinLimit = 1LL << 22;   // polls: a few seconds at most
 
 // Every buffer these kernels touch is in device (global) memory.  Task
@@ -180,17 +181,19 @@ __device__ __forceinline__ void tile_to_lds(const double* M, int64_t ld, int64_t
 }
 
 // Accumulator of a 64x64 tile (2x2 waves of 32x32) <-> column-major memory.
+template <int WM, int WN>
 __device__ __forceinline__ void tile_to_acc(const double* M, int64_t ld, int64_t r0, int64_t c0,
-                                            TileF64<T64, T64, 2, 2>& acc, int64_t ncols_valid) {
-  const int lane = lane_id(), w = wave_id(), wm = w / 2, wn = w % 2;
+                                            TileF64<T64, T64, WM, WN>& acc, int64_t ncols_valid) {
+  using Tile = TileF64<T64, T64, WM, WN>;
+  const int lane = lane_id(), w = wave_id(), wm = w / WN, wn = w % WN;
 #pragma unroll
-  for (int fi = 0; fi < 2; ++fi)
+  for (int fi = 0; fi < Tile::FM; ++fi)
 #pragma unroll
-    for (int fj = 0; fj < 2; ++fj)
+    for (int fj = 0; fj < Tile::FN; ++fj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = wm * 32 + fi * 16 + (lane >> 4) + 4 * v;
-        const int c = wn * 32 + fj * 16 + (lane & 15);
+        const int r = wm * Tile::TM + fi * 16 + (lane >> 4) + 4 * v;
+        const int c = wn * Tile::TN + fj * 16 + (lane & 15);
         acc.acc[fi][fj][v] = (c < ncols_valid) ? ld_c(&M[(r0 + r) + (c0 + c) * ld]) : 0.0;
       }
 }
@@ -220,7 +223,8 @@ __device__ __forceinline__ int xs64(int k, int n) { return k * T64 + (n ^ k); }
 // at c * 64 + ((r + c) & 63): conflict-free both for the accumulator's
 // column-strided writes and for the column-contiguous reads below).
 __device__ __forceinline__ int sw64(int r, int c) { return c * T64 + ((r + c) & (T64 - 1)); }
-__device__ __forceinline__ void acc_to_lds_sw(const TileF64<T64, T64, 2, 2>& acc, double* S) {
+template <int WM, int WN>
+__device__ __forceinline__ void acc_to_lds_sw(const TileF64<T64, T64, WM, WN>& acc, double* S) {
   acc.for_each([&](int r, int c, double v) { S[sw64(r, c)] = v; });
 }
 
@@ -228,11 +232,12 @@ __device__ __forceinline__ void acc_to_lds_sw(const TileF64<T64, T64, 2, 2>& acc
 // (registers in the tile_load order) to column-major M: each store
 // instruction of a wave writes 64 consecutive doubles of one column.
 // cols_valid limits the columns written; lower_only keeps r >= c.
+template <int NT = 256>
 __device__ __forceinline__ void lds_sw_to_global(const double* S, const TileRegs* add, double* M, int64_t ld,
                                                  int64_t r0, int64_t c0, int64_t cols_valid, bool lower_only) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+  for (int q = 0; q < T64 * T64 / NT; ++q) {
+    const int idx = threadIdx.x + NT * q, r = idx % T64, c = idx / T64;
     const double v = S[sw64(r, c)] + (add ? add->v[q] : 0.0);
     if (c < cols_valid && (!lower_only || r >= c)) st_c(&M[(r0 + r) + (c0 + c) * ld], v);
   }
@@ -878,29 +883,31 @@ __device__ __forceinline__ bool row_ready(const int* st_row, int i, int need, in
 
 // acc += (sa A) B for 64 x 64 operands in LDS, A[k][m] and B[k][n] in the
 // plain layout (k * 64 + m) or, with XA / XB, in the row-XOR layout.
-template <bool XA, bool XB>
-__device__ __forceinline__ void mma64_lds(TileF64<T64, T64, 2, 2>& acc, const double* As, const double* Bs,
+template <bool XA, bool XB, int WM = 2, int WN = 2>
+__device__ __forceinline__ void mma64_lds(TileF64<T64, T64, WM, WN>& acc, const double* As, const double* Bs,
                                           double sa) {
+  using Tile = TileF64<T64, T64, WM, WN>;
+  constexpr int FM = Tile::FM, FN = Tile::FN;
   const int lane = lane_id(), w = wave_id();
-  const int wm = w / 2, wn = w % 2, rr = lane & 15, kq = lane >> 4;
+  const int wm = w / WN, wn = w % WN, rr = lane & 15, kq = lane >> 4;
 #pragma unroll 4
   for (int kk = 0; kk < T64; kk += 4) {
     const int k = kk + kq;
-    double av[2], bv[2];
+    double av[FM], bv[FN];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const int m = wm * 32 + f * 16 + rr;
+    for (int f = 0; f < FM; ++f) {
+      const int m = wm * Tile::TM + f * 16 + rr;
       av[f] = sa * As[XA ? xs64(k, m) : k * T64 + m];
     }
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const int n = wn * 32 + f * 16 + rr;
+    for (int f = 0; f < FN; ++f) {
+      const int n = wn * Tile::TN + f * 16 + rr;
       bv[f] = Bs[XB ? xs64(k, n) : k * T64 + n];
     }
 #pragma unroll
-    for (int fi = 0; fi < 2; ++fi)
+    for (int fi = 0; fi < FM; ++fi)
 #pragma unroll
-      for (int fj = 0; fj < 2; ++fj) acc.acc[fi][fj] = mfma_f64(av[fi], bv[fj], acc.acc[fi][fj]);
+      for (int fj = 0; fj < FN; ++fj) acc.acc[fi][fj] = mfma_f64(av[fi], bv[fj], acc.acc[fi][fj]);
   }
 }
 
@@ -908,8 +915,12 @@ __device__ __forceinline__ void mma64_lds(TileF64<T64, T64, 2, 2>& acc, const do
 // folded products, tiles and inverses read once published); a variant of its
 // own so that it needs no more registers than two waves per SIMD allow and
 // shares the compute units with the factorization's workgroups.
-template <bool CONC>
-__global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBatch b) {
+// NW: waves per workgroup (4, or 8 to halve each wave's share of a product
+// on the chain).
+template <bool CONC, int NW>
+__global__ __launch_bounds__(64 * NW, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBatch b) {
+  constexpr int NT = 64 * NW, PER = T64 * T64 / NT, WM = NW / 2;
+  using Acc = TileF64<T64, T64, WM, 2>;
   __shared__ double As[T64 * T64];
   __shared__ double Bs[T64 * T64];
   __shared__ int sh[8];
@@ -955,17 +966,17 @@ __global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBat
     const bool bwd = !CONC && b.backward;
     const int i = bwd ? a.T - 1 - step : step;
     const int64_t i0 = (int64_t)i * T64, r0 = (int64_t)rt * T64;
-    TileF64<T64, T64, 2, 2> acc;
+    Acc acc;
     tile_to_acc(a.In, a.ldIn, i0, r0, acc, a.R - r0);    // acc = In[i block, rt]
     // the diagonal block's inverse is static: it travels while the task waits
     // forward: As[k][row] = Linv[row][k]; backward: As[k][row] = Linv[k][row]
-    TileRegs linv;
+    double linv[PER];
     if (!CONC) {
       const gdouble* Lb = gp(a.Linv + (int64_t)i * T64 * T64);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
-        linv.v[u] = bwd ? Lb[q + p * T64] : Lb[idx];
+      for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + NT * u, p = idx % T64, q = idx / T64;
+        linv[u] = bwd ? Lb[q + p * T64] : Lb[idx];
       }
     }
     if (threadIdx.x == 0) sh[4] = 0;                  // leading final tiles of row i (with a.cstate)
@@ -985,14 +996,14 @@ __global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBat
         if (!row_ready(a.cstate + (int64_t)i * a.cT, i, j, &sh[4], a.info, b.err, &sh[2])) { ok = false; break; }
         const gdouble* lt = gp(a.Lt + lt_off(i, j));   // final tile, column-major
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;
+        for (int u = 0; u < PER; ++u) {
+          const int idx = threadIdx.x + NT * u, p = idx % T64, q = idx / T64;
           As[xs64(q, p)] = lt[idx];                     // A[p][q] = L[i0+p][j0+q]
         }
       } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int idx = threadIdx.x + 256 * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
+        for (int u = 0; u < PER; ++u) {
+          const int idx = threadIdx.x + NT * u, p = idx % T64, q = idx / T64;   // p runs along a column of G
           if (!bwd) As[xs64(q, p)] = gp(a.G)[(i0 + p) + (j0 + q) * a.ld];   // A[p][q] = L[i0+p][j0+q]
           else As[xs64(p, q)] = gp(a.G)[(j0 + p) + (i0 + q) * a.ld];              // A[q][p] = L[j0+p][i0+q]
         }
@@ -1001,21 +1012,21 @@ __global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBat
       {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          double v[8];
+          double v[PER / 2];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;  // p: row in block j, q: rhs
+          for (int u = 0; u < PER / 2; ++u) {
+            const int idx = threadIdx.x + NT * (PER / 2 * h + u), p = idx % T64, q = idx / T64;  // p: row in block j, q: rhs
             v[u] = (r0 + q < a.R) ? ld_c(&a.Out[(j0 + p) + (r0 + q) * a.ldOut]) : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
+          for (int u = 0; u < PER / 2; ++u) {
+            const int idx = threadIdx.x + NT * (PER / 2 * h + u), p = idx % T64, q = idx / T64;
             Bs[xs64(p, q)] = v[u];
           }
         }
       }
       __syncthreads();
-      mma64_lds<true, true>(acc, As, Bs, -1.0);       // acc -= Lop * Out_j
+      mma64_lds<true, true, WM, 2>(acc, As, Bs, -1.0);   // acc -= Lop * Out_j
       __syncthreads();
     }
     if (!ok) continue;
@@ -1024,16 +1035,16 @@ __global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBat
       if (!wait_ge(&a.cstate[(int64_t)i * a.cT + i], i + 1, a.info, b.err, &sh[2])) continue;
       const double* Lb = a.Linv + (int64_t)i * T64 * T64;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) linv.v[u] = ld_c(&Lb[threadIdx.x + 256 * u]);
+      for (int u = 0; u < PER; ++u) linv[u] = ld_c(&Lb[threadIdx.x + NT * u]);
     }
     // Out_i = Linv_i (or its transpose) * acc
     acc.for_each([&](int r, int c, double v) { Bs[r * T64 + c] = v; });
 #pragma unroll
-    for (int u = 0; u < 16; ++u) As[threadIdx.x + 256 * u] = linv.v[u];
+    for (int u = 0; u < PER; ++u) As[threadIdx.x + NT * u] = linv[u];
     __syncthreads();
-    TileF64<T64, T64, 2, 2> res;
+    Acc res;
     res.zero();
-    res.template mma<T64, T64, T64>(As, Bs);
+    mma64_lds<false, false, WM, 2>(res, As, Bs, 1.0);
     __syncthreads();
     // res -= M_i Out_j for the block row j two steps back, then the previous
     // one (As[k][row] = -M[row][k])
@@ -1044,30 +1055,30 @@ __global__ __launch_bounds__(256, CONC ? 2 : 1) void solve_dag_kernel_t(SolveBat
       const int64_t j0 = (int64_t)j * T64;
       const gdouble* Mi = gp((d == 2 ? Mfold2 : Mfold) + (int64_t)i * T64 * T64);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) As[threadIdx.x + 256 * u] = -Mi[threadIdx.x + 256 * u];
+      for (int u = 0; u < PER; ++u) As[threadIdx.x + NT * u] = -Mi[threadIdx.x + NT * u];
       if (!wait_ge(&a.flags[j * a.nrt + rt], 1, a.info, b.err, &sh[2])) { fok = false; break; }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        double v[8];
+        double v[PER / 2];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
+        for (int u = 0; u < PER / 2; ++u) {
+          const int idx = threadIdx.x + NT * (PER / 2 * h + u), p = idx % T64, q = idx / T64;
           v[u] = (r0 + q < a.R) ? ld_c(&a.Out[(j0 + p) + (r0 + q) * a.ldOut]) : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int idx = threadIdx.x + 256 * (8 * h + u), p = idx % T64, q = idx / T64;
+        for (int u = 0; u < PER / 2; ++u) {
+          const int idx = threadIdx.x + NT * (PER / 2 * h + u), p = idx % T64, q = idx / T64;
           Bs[xs64(p, q)] = v[u];
         }
       }
       __syncthreads();
-      mma64_lds<false, true>(res, As, Bs, 1.0);
+      mma64_lds<false, true, WM, 2>(res, As, Bs, 1.0);
       __syncthreads();
     }
     if (!fok) continue;
     acc_to_lds_sw(res, As);
     __syncthreads();
-    lds_sw_to_global(As, nullptr, a.Out, a.ldOut, i0, r0, a.R - r0, false);
+    lds_sw_to_global<NT>(As, nullptr, a.Out, a.ldOut, i0, r0, a.R - r0, false);
     publish(&a.flags[i * a.nrt + rt], 1);
     __syncthreads();
   }
@@ -1132,11 +1143,11 @@ int check_chol_task_order(int T, int G) {
 // Workgroups that fit on the device at once for `kernel` (at least one per
 // CU), optionally capped at `want` per CU.
 template <typename K>
-static int persistent_grid(K kernel, int want = 0) {
+static int persistent_grid(K kernel, int want = 0, int block = 256) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   if (want > 0 && want < per_cu) per_cu = want;
   return (cus > 0 ? cus : 256) * per_cu;
@@ -1208,8 +1219,8 @@ static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
     const int64_t nflags = (int64_t)Ts * Ts + 1;
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)), dim3(256), 0, s,
                        v.flags, nflags);
-    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3((unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), sb.ntasks)),
-                       dim3(256), 0, s, sb);
+    hipLaunchKernelGGL((solve_dag_kernel_t<false, kSolveWaves>), dim3((unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false, kSolveWaves>, 0, 64 * kSolveWaves), sb.ntasks)),
+                       dim3(64 * kSolveWaves), 0, s, sb);
     // 3. panel: L_panel = G_panel X^T (from a copy of G_panel)
     double* panel = in.G + (k0 + nb) + k0 * ld;
     hipError_t e = launch_copy_panel(panel, ld, in.blk_P, m, m, nb, s);
@@ -1326,8 +1337,8 @@ hipError_t launch_chol_solve_fwd_concurrent(const Inst& in, int64_t R, hipStream
   const int64_t nflags = (int64_t)T * in.nrt_max + 2;       // flags, head, err
   hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)), dim3(256), 0,
                      s, b.one.flags, nflags);
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<true>, 1), b.ntasks);
-  hipLaunchKernelGGL(solve_dag_kernel_t<true>, dim3(g), dim3(256), 0, s, b);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<true, 4>, 1), b.ntasks);
+  hipLaunchKernelGGL((solve_dag_kernel_t<true, 4>), dim3(g), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
@@ -1353,7 +1364,7 @@ hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, 
   // the error flag, the flags and the head are reset before each pass (after
   // a blocked factorization nothing else clears the error flag)
   const int64_t nflags = (int64_t)T * in.nrt_max + 2;
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), b.ntasks);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false, kSolveWaves>, 0, 64 * kSolveWaves), b.ntasks);
   for (int pass = first_pass; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)),
                        dim3(256), 0, s, b.err, nflags);
@@ -1361,7 +1372,7 @@ hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, 
     if (pass == 1) {
       b.one.In = Wk; b.one.ldIn = ldW; b.one.Out = Y; b.one.ldOut = ldY;
     }
-    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3(g), dim3(256), 0, s, b);
+    hipLaunchKernelGGL((solve_dag_kernel_t<false, kSolveWaves>), dim3(g), dim3(64 * kSolveWaves), 0, s, b);
   }
   return hipGetLastError();
 }
@@ -1511,13 +1522,13 @@ hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s)
   sb.inst = b->solve[refine ? 1 : 0]; sb.segs = b->solve_segs; sb.nsegs = b->solve_nsegs;
   sb.ntasks = b->solve_total; sb.head = b->ctr + 2; sb.err = b->ctr + 1; sb.swap_io = 1;
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(b->rst_max[1], 256), 256));
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), b->solve_total);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false, kSolveWaves>, 0, 64 * kSolveWaves), b->solve_total);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3(1), dim3(64), 0, s, b->ctr + 2, (int64_t)1);
     hipLaunchKernelGGL(batch_reset_kernel, dim3(gx, (unsigned)b->count), dim3(256), 0, s, b->rst_ptr + b->count,
                        b->rst_cnt + b->count);
     sb.backward = pass;
-    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3(g), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL((solve_dag_kernel_t<false, kSolveWaves>), dim3(g), dim3(64 * kSolveWaves), 0, s, sb);
   }
   return hipGetLastError();
 }
@@ -1563,14 +1574,14 @@ hipError_t launch_member_block_inverse(const double* Gs, int64_t ld, int64_t o, 
   v.flags = a.head + 1; v.info = info; v.skip = nullptr;
   sb.ntasks = (int64_t)Tb * Tb; sb.head = v.flags + (int64_t)Tb * Tb; sb.err = ctr;
   const int64_t nflags = (int64_t)Tb * Tb + 1;
-  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false>), sb.ntasks);
+  const unsigned g = (unsigned)std::min<int64_t>(persistent_grid(solve_dag_kernel_t<false, kSolveWaves>, 0, 64 * kSolveWaves), sb.ntasks);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 64)), dim3(256), 0, s,
                        v.flags, nflags);
     sb.backward = pass;
     if (pass == 0) { v.In = I; v.ldIn = Mp; v.Out = Wk; v.ldOut = Mp; }
     else { v.In = Wk; v.ldIn = Mp; v.Out = Dinv; v.ldOut = Mp; }
-    hipLaunchKernelGGL(solve_dag_kernel_t<false>, dim3(g), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL((solve_dag_kernel_t<false, kSolveWaves>), dim3(g), dim3(64 * kSolveWaves), 0, s, sb);
   }
   return hipGetLastError();
 }
