@@ -204,9 +204,9 @@ pc_status pc_gram_export(const pc_plan *plan, int32_t instance, double *G, int64
 pc_status pc_autotune(pc_plan *plan, const char *cache_path, int32_t use_cached, void *stream);
 
 /* pc_set_tuning — set the launch shapes of instance `instance` by hand
- * (values as pc_query_tuning reports them; 0 = heuristic): gram_split 1, 2
- * or 4 contraction parts of the FP64 Gram, ztx_split 1 or 2, chol_per_cu 1
- * or 2 persistent workgroups per compute unit.  chol_per_cu
+ * (values as pc_query_tuning reports them; 0 = heuristic): gram_split 1 to
+ * 4 contraction parts of the FP64 Gram, ztx_split 1 or 2, chol_per_cu 1 or
+ * 2 persistent workgroups per compute unit.  chol_per_cu
  * applies to every instance of a plan with several instances.  chol_block
  * selects the factorization: 0 keeps the current one, -1 the tile DAG over
  * the whole Gram, a multiple of 64 that is >= 128 the blocked outer

@@ -80,18 +80,20 @@ hipError_t launch_column_grams(const Inst& in, hipStream_t s) {
 }
 
 // -------------------------------------------------------------- FP64 Gram
-// Tile: 128 pairs p x 128 mode pairs q (8 values of m x 16 values of m').
-// Per chunk of 16 grid columns j the workgroup stages the S rows of its
-// 128 pairs and the 24 columns of W its mode pairs use; the T operand
-// W[j,m] W[j,m'] is formed when the MFMA fragment is read from LDS.
-// Four waves own 64 x 64 quadrants (4 x 4 fragments of 16 x 16).
+// Tile: 128 pairs p x 128 mode pairs q, the latter two 8 x 8 blocks of
+// (m, m') (origins from the tile table; column c of block h is
+// m = m0_h + c / 8, m' = m0'_h + c % 8).  Per chunk of 16 grid columns j the
+// workgroup stages the S rows of its 128 pairs and the 32 columns of W its
+// mode pairs use; the T operand W[j,m] W[j,m'] is formed when the MFMA
+// fragment is read from LDS.  Four waves own 64 x 64 quadrants (4 x 4
+// fragments of 16 x 16); wave column h covers block h.
 // When the tiles are too few to fill the device the j range is split in two
-// or four parts written to G and G2 and summed afterwards in a fixed order
-// (results are reproducible); four when two would leave the last round of
-// workgroups mostly empty.  Workgroups are mapped so that each XCD (the hardware
+// to four parts written to G and G2 and summed afterwards in a fixed order
+// (results are reproducible), as many as keep the rounds of workgroups full.  Workgroups are mapped so that each XCD (the hardware
 // places workgroup b on XCD b mod 8) works on a contiguous range of tiles,
 // which then share S rows in its L2.
-constexpr int GB = 128, GKC = 16, GWC = 24;
+constexpr int GB = 128, GKC = 16, GWC = 32;
+constexpr int GWS = 36;                           // W row stride in LDS: the four row groups of a read on distinct banks
 constexpr int GSR = GKC / 4;                      // S rows staged per thread and chunk (two pairs each)
 constexpr int GWH = (GKC * GWC + 255) / 256;      // W values staged per thread and chunk
 
@@ -107,7 +109,7 @@ struct GramArgs {
 
 __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
   __shared__ double As[2][GKC * GB];
-  __shared__ double Ws[2][GKC * GWC];
+  __shared__ double Ws[2][GKC * GWS];
   const int64_t units = (int64_t)a.ntiles * a.split;
   const int64_t per = (units + 7) / 8;
   const int64_t b = blockIdx.x;
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
   const int part = (int)(u / a.ntiles), tile = (int)(u % a.ntiles);
   const int pt = tile / a.nq, qi = tile % a.nq;
   const int64_t p0 = (int64_t)pt * GB;
-  const int m0 = a.qtiles[2 * qi], mp0 = a.qtiles[2 * qi + 1];
+  const int* qt = a.qtiles + 4 * qi;                     // (m0, m0') of block 0, then of block 1
   const int64_t jbeg = (int64_t)part * a.jlen;
   const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
   const int nchunks = (int)((jend - jbeg + GKC - 1) / GKC);
@@ -132,7 +134,9 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
     const int idx = t + 256 * h;
     wcol[h] = idx / GKC;
     wrow[h] = idx % GKC;
-    wm_idx[h] = (wcol[h] < 8) ? (int64_t)m0 + wcol[h] : (int64_t)mp0 + wcol[h] - 8;
+    // W columns: 0..7 m of block 0, 8..15 m' of block 0, 16..23 m of block 1, 24..31 m' of block 1
+    const int wc = wcol[h] < GWC ? wcol[h] : 0;
+    wm_idx[h] = (int64_t)qt[2 * (wc / 16) + ((wc % 16) >= 8 ? 1 : 0)] + (wc % 8);
   }
   double sv[2 * GSR], wv[GWH];
   auto load = [&](int chunk) {
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
     }
 #pragma unroll
     for (int h = 0; h < GWH; ++h)
-      if (wcol[h] < GWC) Ws[buf][wrow[h] * GWC + wcol[h]] = wv[h];
+      if (wcol[h] < GWC) Ws[buf][wrow[h] * GWS + wcol[h]] = wv[h];
   };
 
   d4 acc[4][4];
@@ -184,9 +188,9 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
         double av[4], bv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) av[i] = Ab[krow * GB + wm * 64 + i * 16 + r];
-        const double wmp = Wb[krow * GWC + 8 + r];            // W[j, m0' + r]
+        const double wmp = Wb[krow * GWS + 16 * wn + 8 + (r & 7)];               // W[j, m']
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = Wb[krow * GWC + wn * 4 + j] * wmp;   // W[j, m] W[j, m']
+        for (int j = 0; j < 4; ++j) bv[j] = Wb[krow * GWS + 16 * wn + 2 * j + (r >> 3)] * wmp;   // W[j, m] W[j, m']
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -204,10 +208,10 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = wm * 64 + i * 16 + kq + 4 * v;   // pair
-        const int col = wn * 64 + j * 16 + r;            // mode pair
+        const int c = j * 16 + r;                        // mode pair c of block wn
         const int64_t p = p0 + row;
         if (p >= a.P) continue;
-        const int64_t m = m0 + (col >> 4), mp = mp0 + (col & 15);
+        const int64_t m = qt[2 * wn] + (c >> 3), mp = qt[2 * wn + 1] + (c & 7);
         if (mp >= a.M || m > mp) continue;
         const int64_t k = a.pairs[2 * p], kp = a.pairs[2 * p + 1];
         const double val = acc[i][j][v];
@@ -217,8 +221,9 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
 }
 
 // Contraction parts for the untuned FP64 Gram: one when the tiles fill the
-// device twice over, else two or four, whichever leaves the last round of
-// workgroups (two per compute unit) fuller.
+// device twice over, else the count from 2..4 that gives the fewest rounds
+// of workgroups (two per compute unit) per part, i.e. the shortest time when
+// every workgroup takes as long.
 int gram_split_for(const Inst& in) {
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
@@ -227,18 +232,18 @@ int gram_split_for(const Inst& in) {
   const int64_t tiles = ceil_div(in.P, GB) * (int64_t)in.nq;
   const int64_t slots = 2 * (int64_t)cus;
   if (tiles >= slots || in.n_h < 4 * GKC) return 1;
-  auto fill = [&](int parts) {
-    const int64_t units = tiles * parts;
-    return (double)units / (double)(ceil_div(units, slots) * slots);
-  };
-  return (in.n_h >= 8 * GKC && fill(4) > fill(2) + 0.05) ? 4 : 2;
+  int best = 2;
+  for (int parts = 3; parts <= 4; ++parts)
+    if (in.n_h >= 2 * parts * GKC &&
+        ceil_div(tiles * parts, slots) * best < ceil_div(tiles * best, slots) * parts)
+      best = parts;
+  return best;
 }
 
 int gram_parts_used(const Inst& in) {
-  int want = in.tune_gram_split > 0 ? in.tune_gram_split : gram_split_for(in);
+  const int want = in.tune_gram_split > 0 ? in.tune_gram_split : gram_split_for(in);
   if (!in.G2) return 1;
-  while (want > 1 && want - 1 > in.g2_parts) want /= 2;
-  return want;
+  return want - 1 <= in.g2_parts ? want : 1 + in.g2_parts;
 }
 
 hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {

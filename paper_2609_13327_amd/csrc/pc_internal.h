@@ -71,7 +71,7 @@ struct Inst {
   int* cgm_ctr = nullptr;       // DAG and solve counters of one block
   int64_t* cgm_offs = nullptr; int64_t cgm_ntasks = 0;
   // launch-shape choices of the autotuner (0: built-in heuristic)
-  int tune_gram_split = 0;   // FP64 Gram: 1, 2 or 4 contraction parts
+  int tune_gram_split = 0;   // FP64 Gram: 1 to 4 contraction parts
   int tune_ztx_split = 0;    // Z^T x: 1 or 2 contraction parts
   int tune_chol_per_cu = 0;  // Cholesky DAG: persistent workgroups per compute unit (1 or 2)
   // blocked outer factorization (large Grams): block columns of blk_NO (0: tile DAG only)
@@ -152,7 +152,7 @@ hipError_t set_batch_rhs(const DagBatch* b, const int64_t* R, hipStream_t s);   
 // G^{-1} on the plan buffers of every instance: Y (refine = 0) or D (refine = 1, skipping
 // converged instances), with B as the work buffer
 hipError_t launch_chol_solve_batch(const DagBatch* b, int refine, hipStream_t s);
-int gram_split_for(const Inst& in);      // contraction parts the FP64 Gram would use untuned (1, 2 or 4)
+int gram_split_for(const Inst& in);      // contraction parts the FP64 Gram would use untuned (1 to 4)
 int gram_parts_used(const Inst& in);     // contraction parts of the next FP64 Gram launch
 int check_chol_task_order(int T, int G = 0);
 

@@ -113,13 +113,26 @@ void free_plan(pc_plan* p) {
   delete p;
 }
 
-// mode-pair tiles of the FP64 Gram: 8 values of m (from m0) x 16 values of m'
-// (from m0'), kept when some m <= m' inside the tile
+// Mode-pair tiles of the FP64 Gram: each is two 8 x 8 blocks of (m, m')
+// (block origins m0, m0'), four ints per tile.  The blocks of the triangle
+// m <= m' (8-aligned) are paired along m' within a block row where they can
+// be; the diagonal blocks (36 of 64 pairs valid) and the unpaired ones are
+// paired with each other; an odd last block is paired with an empty one
+// (origin M: every pair skipped).
 std::vector<int> make_qtiles(int64_t M) {
-  std::vector<int> q;
-  for (int64_t d = 0; d * 16 < M; ++d)
-    for (int64_t c = 0; c * 8 < M; ++c)
-      if (8 * c <= 16 * d + 15) { q.push_back((int)(8 * c)); q.push_back((int)(16 * d)); }
+  const int nb = (int)((M + 7) / 8);
+  std::vector<int> q, rest;
+  auto tile = [&](int a0, int b0, int a1, int b1) { q.push_back(a0); q.push_back(b0); q.push_back(a1); q.push_back(b1); };
+  for (int a = 0; a < nb; ++a) {
+    rest.push_back(a); rest.push_back(a);               // the diagonal block
+    int b = a + 1;
+    for (; b + 1 < nb; b += 2) tile(8 * a, 8 * b, 8 * a, 8 * b + 8);
+    if (b < nb) { rest.push_back(a); rest.push_back(b); }
+  }
+  for (size_t u = 0; u < rest.size(); u += 4) {
+    if (u + 2 < rest.size()) tile(8 * rest[u], 8 * rest[u + 1], 8 * rest[u + 2], 8 * rest[u + 3]);
+    else tile(8 * rest[u], 8 * rest[u + 1], (int)M, (int)M);
+  }
   return q;
 }
 
@@ -194,7 +207,7 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   chk(dalloc(&in.S, in.n_h * in.ldS));
   chk(dalloc(&in.pairs, 2 * in.P));
   std::vector<int> qt = make_qtiles(in.M);
-  in.nq = (int)(qt.size() / 2);
+  in.nq = (int)(qt.size() / 4);
   chk(dalloc(&in.qtiles, (int64_t)qt.size()));
   chk(dalloc(&in.B, KMp * R));
   chk(dalloc(&in.Y, KMp * R));
@@ -1108,7 +1121,7 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
       continue;
     }
     any_measured = true;
-    // FP64 Gram: one, two or four contraction parts (the others need G2)
+    // FP64 Gram: one to four contraction parts (the others need G2)
     in.tune_gram_split = 1;
     if (prec == PC_PREC_FP64) {
       // four parts only where the tiles are few (the large Grams fill the device)
@@ -1116,7 +1129,7 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
       if (ensure_gram_parts(in, most) != hipSuccess) (void)ensure_gram_parts(in, 2);
       float best = 0.f;
       int choice = 1;
-      for (int c = 1; c <= most; c *= 2) {
+      for (int c = 1; c <= most; ++c) {
         if (c - 1 > in.g2_parts) break;
         in.tune_gram_split = c;
         float ms = 0.f;
@@ -1222,8 +1235,7 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
 pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_t ztx_split, int32_t chol_per_cu,
                         int32_t chol_block) {
   if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
-  if (gram_split < 0 || gram_split > 4 || gram_split == 3 || ztx_split < 0 || ztx_split > 2 || chol_per_cu < 0 ||
-      chol_per_cu > 2)
+  if (gram_split < 0 || gram_split > 4 || ztx_split < 0 || ztx_split > 2 || chol_per_cu < 0 || chol_per_cu > 2)
     return PC_ERR_INVALID_ARG;
   if (chol_block < -1 || (chol_block > 0 && (chol_block < 128 || chol_block % pc::NB != 0)))
     return PC_ERR_INVALID_ARG;

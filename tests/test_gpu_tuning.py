@@ -17,7 +17,7 @@ def _rel(got, ref):
     return (np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)).max()
 
 
-@pytest.mark.parametrize("gram,ztx,chol", list(itertools.product([1, 2, 4], [1, 2], [1, 2])))
+@pytest.mark.parametrize("gram,ztx,chol", list(itertools.product([1, 2, 3, 4], [1, 2], [1, 2])))
 def test_every_launch_shape_matches_oracle(gram, ztx, chol):
     inst = wl.make_instance(12, 24, 5, 24, 70, 0.2, 0.5, 21)
     plan = pc.Plan([inst_dict(inst)])
@@ -38,7 +38,7 @@ def test_autotune_cache_round_trip(tmp_path):
     pc.pc_autotune(plan.handle, cache, use_cached=True)
     chosen = [pc.pc_query_tuning(plan.handle, k) for k in range(len(insts))]
     for g, z, c in chosen:
-        assert g in (1, 2, 4) and z in (1, 2) and c in (1, 2)
+        assert g in (1, 2, 3, 4) and z in (1, 2) and c in (1, 2)
     assert len({c for _, _, c in chosen}) == 1            # one grid for the batched factorization
     plan.factor()
     Ys = [empty(i.KM, i.R) for i in insts]
@@ -58,7 +58,7 @@ def test_autotune_cache_round_trip(tmp_path):
 def test_set_tuning_rejects_bad_values():
     inst = wl.make_instance(6, 12, 2, 8, 4, 0.2, 0.5, 22)
     plan = pc.Plan([inst_dict(inst)])
-    for bad in ((3, 1, 1), (5, 1, 1), (1, 3, 1), (1, 1, 3)):
+    for bad in ((5, 1, 1), (-1, 1, 1), (1, 3, 1), (1, 1, 3)):
         with pytest.raises(pc.PcError) as e:
             pc.pc_set_tuning(plan.handle, 0, *bad)
         assert e.value.status == pc.PC_ERR_INVALID_ARG
@@ -66,13 +66,13 @@ def test_set_tuning_rejects_bad_values():
 
 
 def test_gram_parts_agree():
-    """The FP64 Gram in one, two and four contraction parts: the same Gram up
-    to the rounding of the partial sums (each a sum over a quarter of the
-    grid columns), and every part count reused after a smaller one."""
+    """The FP64 Gram in one to four contraction parts: the same Gram up to
+    the rounding of the partial sums, and every part count reused after
+    another."""
     inst = wl.make_instance(16, 32, 4, 20, 8, 0.2, 0.5, 23)
     plan = pc.Plan([inst_dict(inst)])
     grams = {}
-    for parts in (4, 1, 2, 4):
+    for parts in (4, 1, 3, 2, 4):
         pc.pc_set_tuning(plan.handle, 0, parts, 0, 0)
         pc.pc_gram_assemble(plan.handle)
         G = dev(np.zeros((inst.KM, inst.KM)))
