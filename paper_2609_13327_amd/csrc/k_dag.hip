@@ -26,7 +26,11 @@
 // Order (look-ahead of one step): DIAG(0); then for every k: DIAG(k+1),
 // TRSM(i,k) for i >= k+2, then the non-final update tasks ending at column k:
 // GEMM(i,j,k) for all j >= k+2 when k closes a group ((k + 1) % G == 0),
-// else only for j = k + 2 (a tile whose last non-final update is k).
+// else only for j = k + 2 (a tile whose last non-final update is k).  A
+// closing group's tasks beyond its first three columns are spread over the
+// next G - 1 iterations (interleaved columns, ahead of those iterations' own
+// tasks), so that the next diagonal steps are not queued behind a whole
+// triangle of updates; each still comes before any task that needs it.
 // Every task appears after the tasks it needs, which makes the waits
 // deadlock-free: a waiting workgroup only waits for a task that another
 // running workgroup has already taken.
@@ -111,12 +115,44 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info,
 struct TaskDesc { int type, i, j, k; };   // type 0 DIAG(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
 
 constexpr int kGemmGroup = 4;   // columns of updates per GEMM task
+constexpr int kNearCols = 3;    // columns of a closing group's tasks emitted in its own iteration
 
 // Whether iteration k closes a group of updates, and its GEMM task count.
 __host__ __device__ inline bool gemm_group_end(int k, int G) { return (k + 1) % G == 0; }
 __host__ __device__ inline int64_t gemm_task_count(int T, int k, int G) {
   const int64_t m2 = T - k - 2;
   return gemm_group_end(k, G) ? m2 * (m2 + 1) / 2 : m2;
+}
+
+// The tasks of a closing group (k0) in columns j >= k0 + 2 + kNearCols are
+// spread over the next G - 1 iterations: iteration k0 + d takes columns
+// k0 + 1 + kNearCols + d, then every G - 1.  The last group end before
+// iteration k whose tasks it carries, or -1.
+__host__ __device__ inline int deferred_group(int k, int G) {
+  if (G < 2) return -1;
+  const int d = 1 + k % G;
+  return (d <= G - 1 && k - d >= 0) ? k - d : -1;
+}
+__host__ __device__ inline int deferred_col0(int k0, int k) { return k0 + 1 + kNearCols + (k - k0); }
+// Tasks in the columns j0, j0 + B, ... below T (column j holds T - j tiles).
+__host__ __device__ inline int64_t strided_cols_tasks(int T, int j0, int B, int64_t* ncols = nullptr) {
+  const int64_t n = j0 < T ? (T - 1 - j0) / B + 1 : 0;
+  if (ncols) *ncols = n;
+  return n * (int64_t)(T - j0) - (int64_t)B * n * (n - 1) / 2;
+}
+// GEMM tasks of iteration k in the order below: the deferred ones first, then
+// its own (a closing group's near columns, else the single column k + 2).
+__host__ __device__ inline int64_t gemm_section_count(int T, int k, int G) {
+  int64_t c = 0;
+  const int k0 = deferred_group(k, G);
+  if (k0 >= 0) c += strided_cols_tasks(T, deferred_col0(k0, k), G - 1);
+  if (gemm_group_end(k, G)) {
+    const int jend = G >= 2 ? (k + 2 + kNearCols < T ? k + 2 + kNearCols : T) : T;
+    for (int j = k + 2; j < jend; ++j) c += T - j;
+  } else if (k + 2 < T) {
+    c += T - k - 2;
+  }
+  return c;
 }
 
 // t -> task in the order described above; offs[k] is the first index of
@@ -137,17 +173,37 @@ __host__ __device__ TaskDesc decode_task(int64_t t, int T, const int64_t* offs, 
     else { d.type = 1; d.i = k + 1 + (int)u; d.j = d.k = k; }
     return d;
   }
-  const int64_t w = u - m1;
-  if (!gemm_group_end(k, G)) {             // column j = k + 2 only
-    d.type = 2; d.i = k + 2 + (int)w; d.j = k + 2; d.k = k;
+  int64_t w = u - m1;
+  d.type = 2;
+  const int k0 = deferred_group(k, G);
+  if (k0 >= 0) {
+    const int j0 = deferred_col0(k0, k), B = G - 1;
+    int64_t n;
+    const int64_t nd = strided_cols_tasks(T, j0, B, &n);
+    if (w < nd) {
+      // column s of the run: the largest s with C(s) = s A - B s (s - 1) / 2 <= w
+      const double A = (double)(T - j0), h = A + 0.5 * B;
+      int64_t sc = (int64_t)((h - sqrt(fmax(h * h - 2.0 * B * (double)w, 0.0))) / B);
+      auto C = [&](int64_t x) { return x * (int64_t)(T - j0) - (int64_t)B * x * (x - 1) / 2; };
+      if (sc > n - 1) sc = n - 1;
+      if (sc < 0) sc = 0;
+      while (sc + 1 < n && C(sc + 1) <= w) ++sc;
+      while (sc > 0 && C(sc) > w) --sc;
+      d.j = j0 + (int)sc * B;
+      d.i = d.j + (int)(w - C(sc));
+      d.k = k0;
+      return d;
+    }
+    w -= nd;
+  }
+  d.k = k;
+  if (!gemm_group_end(k, G)) {             // column k + 2 only
+    d.i = k + 2 + (int)w; d.j = k + 2;
     return d;
   }
-  // lower triangle (a >= b) of size T-k-2
-  int64_t a = (int64_t)((sqrt(8.0 * (double)w + 1.0) - 1.0) * 0.5);
-  while ((a + 1) * (a + 2) / 2 <= w) ++a;
-  while (a * (a + 1) / 2 > w) --a;
-  const int64_t b = w - a * (a + 1) / 2;
-  d.type = 2; d.i = k + 2 + (int)a; d.j = k + 2 + (int)b; d.k = k;
+  int j = k + 2;                           // near columns (all of them when G = 1)
+  while (w >= T - j) { w -= T - j; ++j; }
+  d.j = j; d.i = j + (int)w;
   return d;
 }
 
@@ -1159,7 +1215,7 @@ int64_t chol_task_offsets(int T, std::vector<int64_t>& offs, int G) {
   int64_t t = 1;                                  // DIAG(0)
   for (int k = 0; k + 1 < T; ++k) {
     offs[k] = t;
-    t += (T - k - 1) + gemm_task_count(T, k, G);
+    t += (T - k - 1) + gemm_section_count(T, k, G);
   }
   if (T >= 1) offs[T - 1] = t;
   return t;
@@ -1466,7 +1522,7 @@ DagBatch* make_dag_batch(const std::vector<Inst>& insts) {
     for (int i : order)
       if (r + 1 < Ts[i]) add(cs, i, offs[i][r], Ts[i] - r - 1);              // DIAG(r+1), TRSM(., r)
     for (int i : order)
-      if (r + 1 < Ts[i]) add(cs, i, offs[i][r] + Ts[i] - r - 1, gemm_task_count(Ts[i], r, kGemmGroup));   // GEMM(., ., r)
+      if (r + 1 < Ts[i]) add(cs, i, offs[i][r] + Ts[i] - r - 1, gemm_section_count(Ts[i], r, kGemmGroup));   // GEMM(., ., r)
   }
   b->chol_total = g;
   b->chol_nsegs = (int)cs.size();
