@@ -114,7 +114,7 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int v, const int* info,
 
 struct TaskDesc { int type, i, j, k; };   // type 0 DIAG(k), 1 TRSM(i,k), 2 GEMM(i,j,k)
 
-constexpr int kGemmGroup = 4;   // columns of updates per GEMM task
+constexpr int kGemmGroup = 6;   // columns of updates per GEMM task
 constexpr int kNearCols = 3;    // columns of a closing group's tasks emitted in its own iteration
 
 // Whether iteration k closes a group of updates, and its GEMM task count.
