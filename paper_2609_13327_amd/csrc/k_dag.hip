@@ -370,48 +370,29 @@ __device__ __forceinline__ double bcast16(double v, int l) {
 #undef PC_BC
 }
 
-// Inverse of the 16 x 16 diagonal block b of the factor in A, by one wave,
-// into X + 256 b (row-major), by forward substitution: lane r holds row r
-// (every row of 16 lanes a copy), and row j of the inverse is final at
-// step j (X_jq = x_j[q] / L_jj).
-__device__ __forceinline__ void inv_diag_block(const double* A, double* X, int b) {
-  const int lane = lane_id(), r = lane & 15, c = 16 * b;
-  double row[16], x[16];
+// Blocks of the inverse Y of the 64 x 64 factor in A, by one wave each:
+// Y_pp = X_pp (from the panel sweeps) and, for p > q,
+//     Y_pq = -X_pp S_pq,   S_pq = L_pq X_qq + sum_{q<m<p} L_pm Y_mq.
+// Y blocks (p > q) are kept transposed in the upper triangle of A (rows
+// 16q.., columns 16p..), which the factor never touches.  inv_sum adds the
+// terms m0 <= m < m1 of S_pq (m = q is L_pq X_qq) to s4; inv_finish forms
+// Y_pq from S_pq through the wave's 16 x 16 scratch Sw.
+__device__ __forceinline__ d4 inv_sum(const double* A, const double* X, int p, int q, int m0, int m1, d4 s4) {
+  if (m0 == q) {
+    // B[k][n] = X_qq[k][n]
 #pragma unroll
-  for (int q = 0; q < 16; ++q) row[q] = (q <= r) ? A[(c + r) * LDP + c + q] : 0.0;
-  const double rdiag = 1.0 / A[(c + r) * LDP + c + r];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) x[q] = (q == r) ? 1.0 : 0.0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    // -L_rj / L_jj for rows below j (row[j] is 0 above the diagonal).  The
-    // broadcast runs on all lanes: a DPP move reading a lane that is
-    // switched off does not return that lane's value.
-    const double dj = bcast16(rdiag, j);
-    const double f = (r == j) ? 0.0 : -row[j] * dj;
-#pragma unroll
-    for (int q = 0; q <= j; ++q) x[q] = fma(f, bcast16(x[q], j), x[q]);
+    for (int kk = 0; kk < 16; kk += 4)
+      s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * q, kk), fr_b(X + q * 256, 16, 0, 0, kk), s4);
+    ++m0;
   }
-  if (lane < 16) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) X[b * 256 + r * 16 + q] = (q <= r) ? x[q] * rdiag : 0.0;
-  }
-}
-
-// Off-diagonal block (p, q), p > q, of the inverse, by one wave:
-// Y_pq = -X_pp (L_pq X_qq + sum_{q<m<p} L_pm Y_mq).  Y blocks are kept
-// transposed in the upper triangle of A (rows 16q.., columns 16p..), which
-// the factor never touches.  Sw: 16 x 16 scratch of this wave.
-__device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, double* Sw, int p, int q) {
-  d4 s4 = {0.0, 0.0, 0.0, 0.0};
   // B[k][n] = Y_mq[k][n] = A[16q + n][16m + k]
-#pragma unroll
-  for (int kk = 0; kk < 16; kk += 4)
-    s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * q, kk), fr_b(X + q * 256, 16, 0, 0, kk), s4);
-  for (int m = q + 1; m < p; ++m)
+  for (int m = m0; m < m1; ++m)
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4)
       s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * m, kk), fr_a(A, LDP, 16 * q, 16 * m, kk), s4);
+  return s4;
+}
+__device__ __forceinline__ void inv_finish(double* A, const double* X, double* Sw, int p, int q, const d4& s4) {
   fr_store(Sw, 16, 0, 0, s4);
   d4 y4 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -421,6 +402,9 @@ __device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, do
 #pragma unroll
   for (int v = 0; v < 4; ++v) A[(16 * q + (l & 15)) * LDP + 16 * p + (l >> 4) + 4 * v] = y4[v];
 }
+__device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, double* Sw, int p, int q) {
+  inv_finish(A, X, Sw, p, q, inv_sum(A, X, p, q, q, p, d4{0.0, 0.0, 0.0, 0.0}));
+}
 
 // Diagonal tile, blocked by 16.  For each 16-column panel one wave factors
 // the whole column panel (rows c..63) right-looking, column by column: every
@@ -428,11 +412,13 @@ __device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, do
 // and up to 16 rows of the panel below it, so the broadcasts of L_qj that
 // the updates need stay inside a row (DPP) and the panel is solved in the
 // same sweep.  The trailing lower part is then updated with MFMA.
-// The inverse of the tile is assembled block by block, Y_pp = X_pp (the
-// inverse of the diagonal block) and Y_pq = -X_pp sum_{q<=m<p} L_pm Y_mq,
-// by the waves that the sweeps leave idle: X_pp while the next panel is
-// swept, Y_10 with the last panel, then X_33, Y_21 and Y_20, and last the
-// three blocks of block row 3.
+// The lanes of the sweep that hold no panel row (always the last row of 16
+// lanes) sweep rows of the identity instead, which gives rows of
+// L_pp^{-T}: the inverse X_pp of the diagonal block comes out of the same
+// instructions.  The off-diagonal blocks of the inverse are formed by the
+// waves that the sweeps leave idle: Y_10 with panel 2; Y_21, Y_20 and the
+// parts of S_32, S_31, S_30 that do not need them with panel 3; after it
+// only the last terms and the products with X_33.
 // LDS: A (64 x 65), X (4 x 16 x 16), sweep scratch (64 x 16) and pivot
 // thresholds (64), then the inverse's scratch (4 x 256).
 // Factor the 64 x 64 lower triangle held in A (LDS, row-major, stride LDP)
@@ -449,6 +435,7 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
   // pivot thresholds of the 64 columns, read once
   if (t < T64) Sc[1024 + t] = gp(a.diag0)[k0 + t] * thr_scale;
   __syncthreads();
+  d4 sacc = {0.0, 0.0, 0.0, 0.0};          // this wave's part of S_3q, q = 3 - w
   for (int p = 0; p < 4; ++p) {
     const int c = 16 * p;
     if (w == 0) {
@@ -458,12 +445,15 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
       const int r = lane & 15, s = lane >> 4;
       const int prow = c + 16 + 16 * s + r;
       const bool has = prow < T64;
-      const int lrow = has ? prow : c + r;      // rows past the tile compute on a copy, never stored
+      const int lrow = has ? prow : c + r;      // rows past the tile sweep a row of the identity
       double dg[16], pr[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) dg[q] = A[(c + r) * LDP + c + q];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) pr[q] = A[lrow * LDP + c + q];
+      for (int q = 0; q < 16; ++q) {
+        const double v = A[lrow * LDP + c + q];
+        pr[q] = has ? v : (q == r ? 1.0 : 0.0);
+      }
       int fail = 16;                      // first failing pivot of this panel
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -488,19 +478,29 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
 #pragma unroll
         for (int q = j; q < 16; ++q) asm volatile("" : "+v"(pr[q]));
       }
-      // Stores are unconditional (lanes without a panel row write to the
-      // sweep scratch), so no part of the sweep is sunk into a branch.
-      // Every row of 16 lanes writes the same diagonal block.
-      double* pdst = has ? A + prow * LDP + c : Sc + lane * 16;
+      // Stores are unconditional (lanes without a panel row write row r of
+      // L_pp^{-T} to column r of X_pp from the last row of lanes, and to the
+      // sweep scratch from the others), so no part of the sweep is sunk into
+      // a branch.  Every row of 16 lanes writes the same diagonal block.
+      double* pdst = has ? A + prow * LDP + c : (s == 3 ? X + p * 256 + r : Sc + lane * 16);
+      const int pst = (!has && s == 3) ? 16 : 1;
 #pragma unroll
       for (int q = 0; q < 16; ++q) A[(c + r) * LDP + c + q] = (q <= r) ? dg[q] : 0.0;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) pdst[q] = pr[q];
+      for (int q = 0; q < 16; ++q) pdst[q * pst] = pr[q];
       if (fail < 16 && lane == 0) sh[1] = (int)(a.col_off + k0 + c + fail);
-    } else if (w == 1 && p >= 1) {
-      inv_diag_block(A, X, p - 1);        // L_{p-1,p-1} is final since the last sweep
-    } else if (w == 2 && p == 3) {
-      inv_offdiag_block(A, X, Sy + 2 * 256, 1, 0);
+    } else if (p == 2) {
+      if (w == 2) inv_offdiag_block(A, X, Sy + 2 * 256, 1, 0);
+    } else if (p == 3) {
+      if (w == 1) {
+        sacc = inv_sum(A, X, 3, 2, 2, 3, sacc);                  // S_32 = L_32 X_22
+      } else if (w == 2) {
+        inv_offdiag_block(A, X, Sy + 2 * 256, 2, 1);             // Y_21
+        sacc = inv_sum(A, X, 3, 1, 1, 2, sacc);                  // L_31 X_11
+      } else {
+        inv_offdiag_block(A, X, Sy + 3 * 256, 2, 0);             // Y_20
+        sacc = inv_sum(A, X, 3, 0, 0, 2, sacc);                  // L_30 X_00 + L_31 Y_10
+      }
     }
     __syncthreads();
     if (sh[1] >= 0) {
@@ -524,12 +524,12 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
     if (p < 3) __syncthreads();           // the last panel has no trailing part
     if (p == 0 && pend_flag && t == 0) st_release(pend_flag, pend_val);
   }
-  // the rest of the inverse: X_33, Y_21, Y_20, then block row 3
-  if (w == 1) inv_diag_block(A, X, 3);
-  else if (w == 2) inv_offdiag_block(A, X, Sy + 2 * 256, 2, 1);
-  else if (w == 3) inv_offdiag_block(A, X, Sy + 3 * 256, 2, 0);
-  __syncthreads();
-  if (w >= 1) inv_offdiag_block(A, X, Sy + w * 256, 3, 3 - w);
+  // the rest of block row 3 of the inverse: the terms with Y_21 and Y_20,
+  // then the products with X_33 (from the last sweep)
+  if (w >= 1) {
+    if (w >= 2) sacc = inv_sum(A, X, 3, 3 - w, 2, 3, sacc);     // + L_32 Y_21, + L_32 Y_20
+    inv_finish(A, X, Sy + w * 256, 3, 3 - w, sacc);
+  }
   __syncthreads();
   // the inverse first (the next panel's solves wait for it), then the flag,
   // then the factor tile itself (read only by later kernels)
