@@ -406,6 +406,13 @@ __device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, do
   inv_finish(A, X, Sw, p, q, inv_sum(A, X, p, q, q, p, d4{0.0, 0.0, 0.0, 0.0}));
 }
 
+// Pivot threshold of column 64 k + t (t < 64) of the tile, from the
+// diagonal of G before the factorization (see the pivot test above).
+__device__ __forceinline__ double pivot_threshold(const CholArgs& a, int k) {
+  const int t = threadIdx.x;
+  return t < T64 ? gp(a.diag0)[(int64_t)k * T64 + t] * (64.0 * (double)a.KM * 1.1102230246251565e-16) : 0.0;
+}
+
 // Diagonal tile, blocked by 16.  For each 16-column panel one wave factors
 // the whole column panel (rows c..63) right-looking, column by column: every
 // row of 16 lanes holds a copy of the 16 x 16 diagonal block (lane r: row r)
@@ -426,14 +433,13 @@ __device__ __forceinline__ void inv_offdiag_block(double* A, const double* X, do
 // (k,k).  If pend_flag is set, the flag is published after the first panel
 // (the caller's coherent stores have completed by then).
 __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, double* X, double* Sc, int* sh,
-                                         int* pend_flag, int pend_val) {
+                                         int* pend_flag, int pend_val, double thr_t) {
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int64_t k0 = (int64_t)k * T64;
   double* Sy = Sc + 1024 + T64;          // inverse scratch, 256 per wave
   if (t == 0) sh[1] = -1;
-  const double thr_scale = 64.0 * (double)a.KM * 1.1102230246251565e-16;
-  // pivot thresholds of the 64 columns, read once
-  if (t < T64) Sc[1024 + t] = gp(a.diag0)[k0 + t] * thr_scale;
+  // pivot thresholds of the 64 columns (fetched by the caller)
+  if (t < T64) Sc[1024 + t] = thr_t;
   __syncthreads();
   d4 sacc = {0.0, 0.0, 0.0, 0.0};          // this wave's part of S_3q, q = 3 - w
   for (int p = 0; p < 4; ++p) {
@@ -555,6 +561,7 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
 // DIAG(0): the first diagonal tile as it is.
 __device__ __noinline__ void diag0_task(const CholArgs& a, double* A, double* X, double* Sc, int* sh) {
   const int t = threadIdx.x;
+  const double thr = pivot_threshold(a, 0);
   double v[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -566,7 +573,7 @@ __device__ __noinline__ void diag0_task(const CholArgs& a, double* A, double* X,
     const int idx = t + 256 * q, r = idx % T64, c = idx / T64;
     A[r * LDP + c] = v[q];
   }
-  potrf_factor(a, 0, A, X, Sc, sh, nullptr, 0);
+  potrf_factor(a, 0, A, X, Sc, sh, nullptr, 0, thr);
 }
 
 // DIAG(k), k >= 1 (see the top of the file).  Returns false if the DAG was
@@ -578,6 +585,7 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
   const int T = a.T;
   const int64_t k0 = (int64_t)k * T64, p0 = k0 - T64;     // tile rows k and k-1
   int* st = a.state;
+  const double thr = pivot_threshold(a, k);
   // operands that are ready before the previous diagonal step ends
   if (k >= 3 && !wait_ge(&st[k * T + k - 1], k - 2, a.info, a.err, &sh[2])) return false;
   if (k >= 2) {
@@ -671,7 +679,7 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
     const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
     A[r * LDP + c] = (r >= c) ? A[r * LDP + c] + td.v[q] : 0.0;
   }
-  potrf_factor(a, k, A, buf + T64 * LDP, buf + T64 * LDP + 1024, sh, &st[k * T + k - 1], k);
+  potrf_factor(a, k, A, buf + T64 * LDP, buf + T64 * LDP + 1024, sh, &st[k * T + k - 1], k, thr);
   return true;
 }
 
