@@ -649,22 +649,38 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
   {
     // L_{k,k-1} L_{k,k-1}^T on the ten lower 16 x 16 fragments, three or two
     // per wave: w0 (0,0) (3,0) (3,1), w1 (1,0) (1,1) (3,2), w2 (2,0) (2,1),
-    // w3 (2,2) (3,3)
+    // w3 (2,2) (3,3).  w2 and w3 repeat their first fragment as the third
+    // (not stored), so the loop has no branch and the operands of the next
+    // step are read from LDS while the products of this one run.
     const int l = lane_id(), w = __builtin_amdgcn_readfirstlane(wave_id());
     const int nf = w < 2 ? 3 : 2;
     int fi[3], fj[3];
     fi[0] = w < 2 ? w : 2;  fj[0] = w == 3 ? 2 : (w == 1 ? 0 : 0);
     fi[1] = w == 0 ? 3 : (w == 1 ? 1 : (w == 2 ? 2 : 3));  fj[1] = w == 0 ? 0 : (w == 1 ? 1 : (w == 2 ? 1 : 3));
-    fi[2] = 3;  fj[2] = w == 0 ? 1 : 2;
+    fi[2] = w < 2 ? 3 : fi[0];  fj[2] = w == 0 ? 1 : (w == 1 ? 2 : fj[0]);
     d4 sy[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) sy[u] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < T64; kk += 4) {
+    double ca[3], cb[3];
+    auto operands = [&](int kk, double* oa, double* ob) {
       const double* col = As + (kk + (l >> 4)) * T64 + (l & 15);
 #pragma unroll
-      for (int u = 0; u < 3; ++u)
-        if (u < nf) sy[u] = mfma_f64(col[16 * fi[u]], col[16 * fj[u]], sy[u]);
+      for (int u = 0; u < 3; ++u) {
+        oa[u] = col[16 * fi[u]];
+        ob[u] = col[16 * fj[u]];
+      }
+    };
+    operands(0, ca, cb);
+#pragma unroll
+    for (int kk = 0; kk < T64; kk += 4) {
+      double na[3], nb[3];
+      if (kk + 4 < T64) operands(kk + 4, na, nb);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) sy[u] = mfma_f64(ca[u], cb[u], sy[u]);
+      if (kk + 4 < T64) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) { ca[u] = na[u]; cb[u] = nb[u]; }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -674,10 +690,19 @@ __device__ __noinline__ bool diag_task(const CholArgs& a, int k, double* buf, in
         for (int v = 0; v < 4; ++v) A[(16 * fi[u] + (l >> 4) + 4 * v) * LDP + 16 * fj[u] + (l & 15)] = -sy[u][v];
   }
   __syncthreads();
+  {
+    // all sixteen reads first, then the writes (no LDS round trip per element)
+    double cur[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
-    A[r * LDP + c] = (r >= c) ? A[r * LDP + c] + td.v[q] : 0.0;
+    for (int q = 0; q < 16; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+      cur[q] = A[r * LDP + c];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx % T64, c = idx / T64;
+      A[r * LDP + c] = (r >= c) ? cur[q] + td.v[q] : 0.0;
+    }
   }
   potrf_factor(a, k, A, buf + T64 * LDP, buf + T64 * LDP + 1024, sh, &st[k * T + k - 1], k, thr);
   return true;
