@@ -378,26 +378,45 @@ __device__ __forceinline__ double bcast16(double v, int l) {
 // terms m0 <= m < m1 of S_pq (m = q is L_pq X_qq) to s4; inv_finish forms
 // Y_pq from S_pq through the wave's 16 x 16 scratch Sw.
 __device__ __forceinline__ d4 inv_sum(const double* A, const double* X, int p, int q, int m0, int m1, d4 s4) {
+  // each block's eight operands are read before its four products
+  double av[4], bv[4];
   if (m0 == q) {
     // B[k][n] = X_qq[k][n]
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4)
-      s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * q, kk), fr_b(X + q * 256, 16, 0, 0, kk), s4);
+    for (int u = 0; u < 4; ++u) {
+      av[u] = fr_a(A, LDP, 16 * p, 16 * q, 4 * u);
+      bv[u] = fr_b(X + q * 256, 16, 0, 0, 4 * u);
+    }
+    __builtin_amdgcn_sched_barrier(0);    // keep the reads ahead of the products
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s4 = mfma_f64(av[u], bv[u], s4);
     ++m0;
   }
   // B[k][n] = Y_mq[k][n] = A[16q + n][16m + k]
-  for (int m = m0; m < m1; ++m)
+  for (int m = m0; m < m1; ++m) {
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4)
-      s4 = mfma_f64(fr_a(A, LDP, 16 * p, 16 * m, kk), fr_a(A, LDP, 16 * q, 16 * m, kk), s4);
+    for (int u = 0; u < 4; ++u) {
+      av[u] = fr_a(A, LDP, 16 * p, 16 * m, 4 * u);
+      bv[u] = fr_a(A, LDP, 16 * q, 16 * m, 4 * u);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s4 = mfma_f64(av[u], bv[u], s4);
+  }
   return s4;
 }
 __device__ __forceinline__ void inv_finish(double* A, const double* X, double* Sw, int p, int q, const d4& s4) {
   fr_store(Sw, 16, 0, 0, s4);
+  double av[4], bv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    av[u] = -fr_a(X + p * 256, 16, 0, 0, 4 * u);
+    bv[u] = fr_b(Sw, 16, 0, 0, 4 * u);
+  }
+  __builtin_amdgcn_sched_barrier(0);
   d4 y4 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int kk = 0; kk < 16; kk += 4)
-    y4 = mfma_f64(-fr_a(X + p * 256, 16, 0, 0, kk), fr_b(Sw, 16, 0, 0, kk), y4);
+  for (int u = 0; u < 4; ++u) y4 = mfma_f64(av[u], bv[u], y4);
   const int l = lane_id();
 #pragma unroll
   for (int v = 0; v < 4; ++v) A[(16 * q + (l & 15)) * LDP + 16 * p + (l >> 4) + 4 * v] = y4[v];
@@ -456,10 +475,11 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
 #pragma unroll
       for (int q = 0; q < 16; ++q) dg[q] = A[(c + r) * LDP + c + q];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const double v = A[lrow * LDP + c + q];
-        pr[q] = has ? v : (q == r ? 1.0 : 0.0);
-      }
+      for (int q = 0; q < 16; ++q) pr[q] = A[lrow * LDP + c + q];
+      // identity rows: 0 * v keeps the loads above unconditional (a select
+      // that dropped v would have them issued one by one under a branch)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pr[q] = has ? pr[q] : fma(0.0, pr[q], q == r ? 1.0 : 0.0);
       int fail = 16;                      // first failing pivot of this panel
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
