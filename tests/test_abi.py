@@ -41,9 +41,9 @@ def test_cholesky_task_order_is_topological():
     """The persistent Cholesky kernel takes tasks in a fixed order; the host
     replay checks every task appears once and after everything it waits for."""
     import paper_2609_13327_amd as pc
-    for T in (1, 2, 3, 5, 8, 33, 64, 256, 512):
+    for T in (1, 2, 3, 5, 7, 8, 13, 33, 64, 97, 256, 512):
         assert pc.pc_selftest_task_order(T) == 0, T
-        for G in (1, 2, 3, 4):
+        for G in (1, 2, 3, 4, 5, 6, 7, 8):
             if G <= T:
                 assert pc.pc_selftest_task_order(T, G) == 0, (T, G)
     assert pc.pc_selftest_task_order(0) == -1
