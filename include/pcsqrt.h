@@ -58,7 +58,8 @@ typedef enum {
   PC_ERR_NO_CONVERGENCE = 6, /* refinement budget spent before the tolerance was met */
   PC_ERR_OOM = 7,            /* device allocation failed */
   PC_ERR_DEVICE = 8,         /* a HIP runtime call failed */
-  PC_ERR_TOO_MANY_RHS = 9    /* R larger than the max_rhs given at build time */
+  PC_ERR_TOO_MANY_RHS = 9,   /* R larger than the max_rhs given at build time */
+  PC_ERR_WORKSPACE = 10      /* the problem does not fit the fixed workspace of pc_factor_apply_noalloc */
 } pc_status;
 
 typedef enum {
@@ -347,6 +348,38 @@ pc_status pc_mlp_warm_start(pc_mlp *mlp, const double *B, int64_t ldB, int64_t R
 pc_status pc_learned_apply(pc_plan *plan, int32_t instance, pc_mlp *mlp, const double *X,
                            int64_t ldX, int64_t R, double *Y, int64_t ldY, double tol,
                            int32_t maxiter, int32_t *iterations, int32_t *fallback, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free entry point.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of the fixed device workspace of pc_factor_apply_noalloc (one copy
+ * per device the library runs on, held until the process ends). */
+#define PC_NOALLOC_WORKSPACE_BYTES (64 * 1024 * 1024)
+
+/* pc_factor_apply_noalloc — for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): Y = Z^+ X for ONE instance in FP64, the same kernels and
+ * result as pc_sqrt_build + pc_factor_apply (precision FP64, no refinement),
+ * with every workspace buffer taken from a fixed, library-owned device array
+ * of PC_NOALLOC_WORKSPACE_BYTES instead of allocated.  No plan is involved
+ * and nothing is allocated or freed (no hipMalloc/hipFree, no pinned host
+ * memory, no internal streams or events).
+ * inst: host pointer to one instance (inst->max_rhs is ignored; R is used).
+ * X: device n x R (ldX >= n); Y: device K*M x R (ldY >= K*M).  R = 0 returns
+ * PC_OK at once.
+ * Synchronizes `stream` once, at the end (to read the pivot status).
+ * Statuses: PC_ERR_SHAPE / PC_ERR_INVALID_ARG as pc_sqrt_build;
+ * PC_ERR_WORKSPACE if the Gram, its factor and the right-hand-side buffers
+ * (about 12 (K*M)^2 + 8 n_h K^2/2 + 16 K*M R bytes) do not fit the workspace,
+ * or K*M > 8192; PC_ERR_NONFINITE for NaN/Inf in E or W; PC_ERR_NOT_SPD
+ * (Y undefined) for a rank-deficient Z; PC_ERR_DEVICE for a HIP failure.
+ * The workspace keeps the last call's contents and is shared by every call
+ * on the same device: calls that overlap on one device (concurrent host
+ * threads, or work still running on another stream) race and must be
+ * serialized by the caller. */
+pc_status pc_factor_apply_noalloc(const pc_instance *inst, const double *X, int64_t ldX, int64_t R,
+                                  double *Y, int64_t ldY, void *stream);
 
 #ifdef __cplusplus
 }

@@ -28,6 +28,7 @@ PC_ERR_NO_CONVERGENCE = 6
 PC_ERR_OOM = 7
 PC_ERR_DEVICE = 8
 PC_ERR_TOO_MANY_RHS = 9
+PC_ERR_WORKSPACE = 10
 
 PC_PREC_FP64 = 0
 PC_PREC_FP32_REFINE = 1
@@ -45,7 +46,7 @@ EXPORTED = [
     "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
-    "pc_set_tuning", "pc_factor_apply",
+    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout", "solve_alongside"]
@@ -131,6 +132,8 @@ def load_library(path: str = LIB_PATH):
                                     POINTER(c_int32)]
     lib.pc_learned_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                      c_double, c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p]
+    lib.pc_factor_apply_noalloc.argtypes = [POINTER(PcInstance), c_void_p, c_int64, c_int64, c_void_p, c_int64,
+                                            c_void_p]
     for name in EXPORTED:
         if name != "pc_status_string":
             getattr(lib, name).restype = c_int32
@@ -256,6 +259,25 @@ def pc_factor_apply(plan: int, X: Sequence, Y: Sequence, stream=None, raise_on_e
     if raise_on_error:
         _check(st, "pc_factor_apply", f"(instance {failed.value})")
     return st, failed.value
+
+
+def pc_factor_apply_noalloc(E, W, X, Y, n_w: int = 1, stream=None, raise_on_error: bool = True) -> int:
+    """Y <- Z^+ X for one instance in FP64 without any allocation (fixed
+    library workspace, no plan).  E, W, X, Y: column-major float64 device
+    tensors.  Returns the status."""
+    lib = load_library()
+    n_h = int(W.shape[0])
+    if E.shape[0] != n_h * int(n_w):
+        raise ValueError("E must have n_h * n_w rows")
+    if X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y must have the same number of columns")
+    inst = PcInstance(n_h, int(n_w), int(E.shape[1]), int(W.shape[1]), _ptr(E), _ld(E), _ptr(W), _ld(W),
+                      int(X.shape[1]))
+    st = lib.pc_factor_apply_noalloc(ctypes.byref(inst), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
+                                     c_void_p(_stream(stream)))
+    if raise_on_error:
+        _check(st, "pc_factor_apply_noalloc")
+    return st
 
 
 def pc_left_inverse_apply(plan: int, X: Sequence, Y: Sequence, stream=None,

@@ -86,6 +86,9 @@ struct Inst {
   double last_rel = 0.0;
 };
 
+// Mode-pair tiles of the FP64 Gram (four ints per tile: m0, m0', m1, m1').
+std::vector<int> make_qtiles(int64_t M);
+
 // ---- kernels (launchers return hipError_t of the launch) ----
 hipError_t launch_pairs_init(const Inst& in, hipStream_t s);
 hipError_t launch_column_grams(const Inst& in, hipStream_t s);

@@ -15,6 +15,32 @@
 #include "pc_internal.h"
 
 using pc::Inst;
+using pc::make_qtiles;
+
+namespace pc {
+// Mode-pair tiles of the FP64 Gram: each is two 8 x 8 blocks of (m, m')
+// (block origins m0, m0'), four ints per tile.  The blocks of the triangle
+// m <= m' (8-aligned) are paired along m' within a block row where they can
+// be; the diagonal blocks (36 of 64 pairs valid) and the unpaired ones are
+// paired with each other; an odd last block is paired with an empty one
+// (origin M: every pair skipped).
+std::vector<int> make_qtiles(int64_t M) {
+  const int nb = (int)((M + 7) / 8);
+  std::vector<int> q, rest;
+  auto tile = [&](int a0, int b0, int a1, int b1) { q.push_back(a0); q.push_back(b0); q.push_back(a1); q.push_back(b1); };
+  for (int a = 0; a < nb; ++a) {
+    rest.push_back(a); rest.push_back(a);               // the diagonal block
+    int b = a + 1;
+    for (; b + 1 < nb; b += 2) tile(8 * a, 8 * b, 8 * a, 8 * b + 8);
+    if (b < nb) { rest.push_back(a); rest.push_back(b); }
+  }
+  for (size_t u = 0; u < rest.size(); u += 4) {
+    if (u + 2 < rest.size()) tile(8 * rest[u], 8 * rest[u + 1], 8 * rest[u + 2], 8 * rest[u + 3]);
+    else tile(8 * rest[u], 8 * rest[u + 1], (int)M, (int)M);
+  }
+  return q;
+}
+}  // namespace pc
 
 // A refinement that stops shrinking is accepted as converged when its last
 // relative update is at most this (far below the 1e-8 accuracy target of the
@@ -113,28 +139,6 @@ void free_plan(pc_plan* p) {
   delete p;
 }
 
-// Mode-pair tiles of the FP64 Gram: each is two 8 x 8 blocks of (m, m')
-// (block origins m0, m0'), four ints per tile.  The blocks of the triangle
-// m <= m' (8-aligned) are paired along m' within a block row where they can
-// be; the diagonal blocks (36 of 64 pairs valid) and the unpaired ones are
-// paired with each other; an odd last block is paired with an empty one
-// (origin M: every pair skipped).
-std::vector<int> make_qtiles(int64_t M) {
-  const int nb = (int)((M + 7) / 8);
-  std::vector<int> q, rest;
-  auto tile = [&](int a0, int b0, int a1, int b1) { q.push_back(a0); q.push_back(b0); q.push_back(a1); q.push_back(b1); };
-  for (int a = 0; a < nb; ++a) {
-    rest.push_back(a); rest.push_back(a);               // the diagonal block
-    int b = a + 1;
-    for (; b + 1 < nb; b += 2) tile(8 * a, 8 * b, 8 * a, 8 * b + 8);
-    if (b < nb) { rest.push_back(a); rest.push_back(b); }
-  }
-  for (size_t u = 0; u < rest.size(); u += 4) {
-    if (u + 2 < rest.size()) tile(8 * rest[u], 8 * rest[u + 1], 8 * rest[u + 2], 8 * rest[u + 3]);
-    else tile(8 * rest[u], 8 * rest[u + 1], (int)M, (int)M);
-  }
-  return q;
-}
 
 // Room in G2 for the contraction parts 2..parts of a split FP64 Gram.
 hipError_t ensure_gram_parts(Inst& in, int parts) {
@@ -633,6 +637,7 @@ const char* pc_status_string(pc_status s) {
     case PC_ERR_OOM: return "device out of memory";
     case PC_ERR_DEVICE: return "HIP runtime error";
     case PC_ERR_TOO_MANY_RHS: return "more right-hand sides than max_rhs";
+    case PC_ERR_WORKSPACE: return "problem too large for the fixed workspace of the allocation-free entry point";
   }
   return "unknown status";
 }
