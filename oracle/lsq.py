@@ -16,6 +16,8 @@ range(Z) (and everywhere when Z is square).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import scipy.linalg
 import scipy.linalg.lapack as lapack
@@ -123,6 +125,182 @@ def lstsq_qr(Z: np.ndarray, X: np.ndarray, own: bool = False, check_rank: bool =
     Y = scipy.linalg.solve_triangular(R, C[:n], lower=False)
     info = {"residual_norm": np.linalg.norm(C[n:], axis=0), "rdiag": np.diag(R).copy()}
     return (Y[:, 0] if vec else Y), info
+
+
+def form_z_fortran(E: np.ndarray, W: np.ndarray, n_w: int) -> np.ndarray:
+    """`form_z` written column by column into one column-major array (no
+    intermediate copies: the largest workload's Z is 34 GB)."""
+    n, K = E.shape
+    n_h, M = W.shape
+    assert n == n_h * n_w
+    Z = np.empty((n, K * M), order="F")
+    for k in range(K):
+        for l in range(n_w):
+            Z[l * n_h:(l + 1) * n_h, k * M:(k + 1) * M] = E[l * n_h:(l + 1) * n_h, k:k + 1] * W
+    return Z
+
+
+def _larft(V: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    """Upper-triangular T of the compact WY form H_1 H_2 ... H_b = I - V T V^T
+    (Schreiber and Van Loan), built column by column:
+    T[j, j] = tau_j,  T[:j, j] = -tau_j T[:j, :j] (V[:, :j]^T v_j)."""
+    b = V.shape[1]
+    T = np.zeros((b, b))
+    VtV = V.T @ V
+    for j in range(b):
+        T[j, j] = tau[j]
+        if j:
+            T[:j, j] = -tau[j] * (T[:j, :j] @ VtV[:j, j])
+    return T
+
+
+def _blas_gemm():
+    """cblas_dgemm of the BLAS numpy itself links (located through
+    threadpoolctl), for products written in place into strided column-major
+    views; None if it cannot be found (numpy's matmul is used instead)."""
+    import ctypes
+    try:
+        from threadpoolctl import threadpool_info
+        for d in threadpool_info():
+            if d.get("internal_api") != "openblas" or "numpy" not in d.get("filepath", ""):
+                continue
+            lib = ctypes.CDLL(d["filepath"])
+            for name in ("scipy_cblas_dgemm64_", "cblas_dgemm64_", "cblas_dgemm"):
+                if hasattr(lib, name):
+                    f = getattr(lib, name)
+                    i64 = ctypes.c_int64 if "64" in name else ctypes.c_int32
+                    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i64, i64, i64, ctypes.c_double,
+                                  ctypes.c_void_p, i64, ctypes.c_void_p, i64, ctypes.c_double, ctypes.c_void_p, i64]
+                    f.restype = None
+                    return f
+    except Exception:
+        return None
+    return None
+
+
+def _col_major(a):
+    """(pointer, leading dimension) of a column-major (possibly strided) 2-D view."""
+    assert a.dtype == np.float64 and a.strides[0] == 8 and a.strides[1] % 8 == 0
+    return a.ctypes.data, max(a.strides[1] // 8, a.shape[0], 1)
+
+
+def lstsq_qr_inplace(Z: np.ndarray, X: np.ndarray, panel: int = 512, progress=None):
+    """Least squares by Householder QR, computed in place on a column-major Z.
+
+    The same factorization as `lstsq_qr` (LAPACK's reflector convention),
+    organized by panels so that a Z too large to copy can be factored and so
+    that progress can be reported: each panel of `panel` columns is factored
+    by LAPACK dgeqrf (numpy, mode "raw"), its reflectors are written back below
+    the diagonal, and its Q_p^T = I - V T^T V^T (compact WY form) is applied
+    to the trailing columns, C <- C - V (T^T (V^T C)), with the products
+    written in place by the BLAS, and to X.  Afterwards
+    y = R^{-1} (Q^T x)[:ncols] by block back substitution.
+    Z is overwritten (R on and above the diagonal).  Returns (Y, info) as
+    `lstsq_qr` does, info also holding "rdiag".
+    """
+    if not (Z.flags.f_contiguous and Z.dtype == np.float64):
+        raise ValueError("Z must be a column-major float64 array")
+    m, n = Z.shape
+    if n > m:
+        raise ValueError("Z must be tall (K*M <= n)")
+    gemm = _blas_gemm()
+    COL, NT, TR = 102, 111, 112
+    C = np.array(X, dtype=np.float64, order="F", copy=True)
+    if C.ndim == 1:
+        C = C[:, None]
+    for j0 in range(0, n, panel):
+        j1 = min(n, j0 + panel)
+        b = j1 - j0
+        h, tau = np.linalg.qr(np.asfortranarray(Z[j0:, j0:j1]), mode="raw")
+        A = h.T                                        # (m - j0) x b, R above, reflectors below
+        Z[j0:, j0:j1] = A
+        V = np.asfortranarray(np.tril(A, -1))
+        V[np.arange(b), np.arange(b)] = 1.0
+        Tt = np.asfortranarray(_larft(V, tau).T)
+        if j1 < n:
+            Cv = Z[j0:, j1:]                           # trailing columns, a strided view
+            if gemm is not None:
+                Wm = np.empty((b, n - j1), order="F")
+                pc_, ldc = _col_major(Cv)
+                gemm(COL, TR, NT, b, n - j1, m - j0, 1.0, V.ctypes.data, m - j0, pc_, ldc, 0.0,
+                     Wm.ctypes.data, b)                # W = V^T C
+                Wm = np.asfortranarray(Tt @ Wm)        # T^T W
+                gemm(COL, NT, NT, m - j0, n - j1, b, -1.0, V.ctypes.data, m - j0, Wm.ctypes.data, b, 1.0,
+                     pc_, ldc)                         # C <- C - V (T^T W)
+            else:
+                for c0 in range(j1, n, 2048):
+                    blk = Z[j0:, c0:min(n, c0 + 2048)]
+                    blk -= V @ (Tt @ (V.T @ blk))
+        C[j0:] -= V @ (Tt @ (V.T @ C[j0:]))
+        if progress is not None:
+            progress(j1, n)
+    rdiag = np.array([Z[i, i] for i in range(n)])
+    Y = C[:n].copy()
+    for i1 in range(n, 0, -panel):                     # back substitution by diagonal blocks
+        i0 = max(0, i1 - panel)
+        if i1 < n:
+            Y[i0:i1] -= Z[i0:i1, i1:n] @ Y[i1:n]
+        Y[i0:i1] = scipy.linalg.solve_triangular(np.triu(Z[i0:i1, i0:i1]), Y[i0:i1], lower=False)
+    info = {"residual_norm": np.linalg.norm(C[n:], axis=0), "rdiag": rdiag}
+    return Y, info
+
+
+def triu_cond_estimate(R: np.ndarray, iters: int = 60, seed: int = 0):
+    """2-norm condition number of an upper-triangular R (only its upper
+    triangle is read; R may be a view into a larger array) by power
+    iteration on R^T R for sigma_max and inverse iteration (two triangular
+    solves by diagonal blocks) for sigma_min.  Returns (kappa, sigma_max,
+    sigma_min); both iterations approach their singular value from the
+    inside, so kappa is a lower bound that tightens with `iters`."""
+    n = R.shape[0]
+    blk = 1024
+
+    def rmul(v):                                       # R v
+        out = np.empty_like(v)
+        for i0 in range(0, n, blk):
+            i1 = min(n, i0 + blk)
+            out[i0:i1] = np.triu(R[i0:i1, i0:i1]) @ v[i0:i1] + R[i0:i1, i1:n] @ v[i1:n]
+        return out
+
+    def rtmul(v):                                      # R^T v
+        out = np.empty_like(v)
+        for i0 in range(0, n, blk):
+            i1 = min(n, i0 + blk)
+            out[i0:i1] = np.triu(R[i0:i1, i0:i1]).T @ v[i0:i1] + R[:i0, i0:i1].T @ v[:i0]
+        return out
+
+    def rsolve(v):                                     # R^{-1} v
+        y = v.copy()
+        for i1 in range(n, 0, -blk):
+            i0 = max(0, i1 - blk)
+            if i1 < n:
+                y[i0:i1] -= R[i0:i1, i1:n] @ y[i1:n]
+            y[i0:i1] = scipy.linalg.solve_triangular(np.triu(R[i0:i1, i0:i1]), y[i0:i1], lower=False)
+        return y
+
+    def rtsolve(v):                                    # R^{-T} v
+        y = v.copy()
+        for i0 in range(0, n, blk):
+            i1 = min(n, i0 + blk)
+            if i0:
+                y[i0:i1] -= R[:i0, i0:i1].T @ y[:i0]
+            y[i0:i1] = scipy.linalg.solve_triangular(np.triu(R[i0:i1, i0:i1]), y[i0:i1], lower=False,
+                                                     trans="T")
+        return y
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(n)
+    w = rng.standard_normal(n)
+    smax = smin_inv = 0.0
+    for _ in range(iters):
+        v /= np.linalg.norm(v)
+        v = rtmul(rmul(v))
+        smax = math.sqrt(np.linalg.norm(v))
+        w /= np.linalg.norm(w)
+        w = rsolve(rtsolve(w))
+        smin_inv = math.sqrt(np.linalg.norm(w))
+    smin = 1.0 / smin_inv
+    return smax / smin, smax, smin
 
 
 def left_inverse_apply(E: np.ndarray, W: np.ndarray, n_w: int, X: np.ndarray,

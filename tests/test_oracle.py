@@ -347,3 +347,73 @@ def test_block_jacobi_tiles_inverts_its_blocks():
     assert np.abs(G @ full(b) - b).max() <= 1e-9 * np.abs(b).max()
     y, it = cg.pcg(G, b, precond=pre, tol=1e-13, maxiter=200)
     assert np.abs(G @ y - b).max() <= 1e-10 * np.abs(b).max()
+
+
+# ------------------------------------------------ large-problem QR and condition
+@pytest.mark.parametrize("m,n,panel", [(700, 300, 64), (500, 500, 128), (900, 130, 512), (257, 129, 32)])
+def test_inplace_panel_qr_matches_lapack(m, n, panel):
+    """The panel-by-panel in-place Householder QR (used for the stored values
+    of the largest workload) gives LAPACK's factorization: same |R_ii|, same
+    least-squares solution and residual norms, including ragged last panels
+    (the trailing products are written in place by the BLAS), on a matrix
+    with condition number 1e3."""
+    rng = np.random.Generator(np.random.PCG64(m + n))
+    Z = rng.standard_normal((m, n)) @ np.diag(np.logspace(0, 3, n))
+    X = rng.standard_normal((m, 3))
+    Y0, i0 = lsq.lstsq_qr(Z, X)
+    Zc = np.asfortranarray(Z.copy())
+    Y1, i1 = lsq.lstsq_qr_inplace(Zc, X, panel=panel)
+    assert np.abs(Y1 - Y0).max() <= 1e-12 * np.abs(Y0).max()
+    np.testing.assert_allclose(np.abs(i1["rdiag"]), np.abs(i0["rdiag"]), rtol=1e-12)
+    np.testing.assert_allclose(i1["residual_norm"], i0["residual_norm"], rtol=1e-10)
+    # Z now holds R on and above the diagonal: R^T R = Z^T Z
+    R = np.triu(Zc[:n, :n])
+    assert np.abs(R.T @ R - Z.T @ Z).max() <= 1e-12 * np.abs(Z.T @ Z).max()
+
+
+def test_inplace_panel_qr_without_blas_handle(monkeypatch):
+    """The same factorization when the BLAS cannot be reached directly
+    (numpy's matmul on column chunks instead)."""
+    monkeypatch.setattr(lsq, "_blas_gemm", lambda: None)
+    rng = np.random.Generator(np.random.PCG64(3))
+    Z = rng.standard_normal((600, 250)) @ np.diag(np.logspace(0, 3, 250))
+    X = rng.standard_normal((600, 2))
+    Y0, _ = lsq.lstsq_qr(Z, X)
+    Y1, _ = lsq.lstsq_qr_inplace(np.asfortranarray(Z.copy()), X, panel=96)
+    assert np.abs(Y1 - Y0).max() <= 1e-12 * np.abs(Y0).max()
+
+
+def test_triu_cond_estimate_against_svd_and_diagonal():
+    """Power / inverse iteration on R^T R: exact for a diagonal R (kappa =
+    max|d| / min|d|), and within 1e-6 of the SVD value for a dense R with
+    well-separated extreme singular values."""
+    d = np.array([3.0, -0.5, 7.0, 0.02, 1.0])
+    k, smax, smin = lsq.triu_cond_estimate(np.diag(d), iters=80)
+    assert abs(k - 350.0) <= 1e-9 * 350 and abs(smax - 7.0) <= 1e-12 and abs(smin - 0.02) <= 1e-14
+    rng = np.random.Generator(np.random.PCG64(5))
+    A = rng.standard_normal((400, 300)) @ np.diag(np.logspace(0, 4, 300))
+    R = np.linalg.qr(A, mode="r")
+    k, _, _ = lsq.triu_cond_estimate(np.asfortranarray(R), iters=200)
+    assert abs(k / np.linalg.cond(R) - 1) <= 1e-6
+
+
+def test_cond_closed_form_single_member():
+    """K = 1 with e = 1: Z = W, whose columns are orthogonal with squared norms
+    the localization eigenvalues, so kappa(Z) = sqrt(lambda_1 / lambda_M)."""
+    W, info = wl.localization_modes(6, 12, 9, 0.5)
+    E = np.ones((72, 1))
+    lam = info["eigvals"][:9]
+    assert abs(lsq.cond(E, W, 1) / math.sqrt(lam[0] / lam[8]) - 1) <= 1e-10
+
+
+def test_gram_lowprec_rounds_the_product_once():
+    """Hand case: e = w = 1 + 2^-8.  The product 1 + 2^-7 + 2^-16 rounds to
+    1 + 2^-7 in bfloat16 (8 significant bits), while rounding the factors
+    first (1 + 2^-8 is a tie, to even: 1) would give 1.  So the Gram of the
+    once-rounded Z is (1 + 2^-7)^2, not 1.  In float32 the product is exact."""
+    E = np.array([[1.0 + 2.0 ** -8]])
+    W = np.array([[1.0 + 2.0 ** -8]])
+    G = lsq.gram_lowprec(E, W, 1, "bf16")
+    assert G.shape == (1, 1) and G[0, 0] == (1.0 + 2.0 ** -7) ** 2
+    G32 = lsq.gram_lowprec(E, W, 1, "fp32")
+    assert G32[0, 0] == (1.0 + 2.0 ** -8) ** 4
