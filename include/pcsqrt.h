@@ -62,10 +62,22 @@ typedef enum {
   PC_ERR_WORKSPACE = 10      /* the problem does not fit the fixed workspace of pc_factor_apply_noalloc */
 } pc_status;
 
+/* Precision of the Gram.  The reduced-precision modes form the rounded Z
+ * tile by tile inside the Gram kernel (Z is never stored), factor the Gram
+ * in FP64 and recover FP64 accuracy by iterative refinement on the
+ * least-squares residual (r = x - Z y, d = G~^{-1} Z^T r, y += d, all FP64).
+ * Unless PC_FLAG_FIXED_PRECISION is set, an instance whose reduced-precision
+ * Gram is not positive definite, or whose refinement stalls above the
+ * acceptance level or diverges, climbs the ladder
+ *   PC_PREC_BF16_REFINE -> PC_PREC_BF16X3_REFINE -> PC_PREC_FP32_REFINE -> PC_PREC_FP64
+ * (re-assembled, re-factored and re-solved in the next precision). */
 typedef enum {
   PC_PREC_FP64 = 0,          /* FP64 Gram (MFMA f64), FP64 Cholesky and solves */
   PC_PREC_FP32_REFINE = 1,   /* Gram of fp32(Z) on MFMA f32, FP64 Cholesky + FP64 refinement */
-  PC_PREC_BF16_REFINE = 2    /* Gram of bf16(Z) on MFMA bf16 (fp32 accumulation), FP64 Cholesky + FP64 refinement */
+  PC_PREC_BF16_REFINE = 2,   /* Gram of bf16(Z) on MFMA bf16 (fp32 accumulation), FP64 Cholesky + FP64 refinement */
+  PC_PREC_BF16X3_REFINE = 3  /* split bf16: Z~ = hi + lo (hi = bf16(z), lo = bf16(z - hi)), Gram
+                                Hi^T Hi + Hi^T Lo + Lo^T Hi on MFMA bf16 (fp32 accumulation),
+                                FP64 Cholesky + FP64 refinement */
 } pc_precision;
 
 /* One problem instance.  Sizes must satisfy n_h, n_w, K, M >= 1 and
@@ -85,7 +97,8 @@ typedef struct {
   double tol;          /* refinement stops for a right-hand side when
                           max|delta| <= tol * max|y|; <= 0 selects 1e-12 */
   int32_t use_graph;   /* 1: capture the apply sequence in a hipGraph and replay it */
-  int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM, optionally with PC_FLAG_CG_MEMBER_BLOCKS */
+  int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM (optionally with PC_FLAG_CG_MEMBER_BLOCKS),
+                          or PC_FLAG_FIXED_PRECISION */
 } pc_options;
 
 /* Keep a symmetric copy of each assembled FP64 Gram and the inverses of its
@@ -98,6 +111,11 @@ typedef struct {
  * factored by the tile DAG and inverted at pc_gram_factor, K M^2 doubles)
  * instead of its 64 x 64 diagonal blocks. */
 #define PC_FLAG_CG_MEMBER_BLOCKS 2
+
+/* Keep every instance in the precision of the options: no escalation along
+ * the precision ladder (a failure is reported as PC_ERR_NOT_SPD or
+ * PC_ERR_NO_CONVERGENCE instead). */
+#define PC_FLAG_FIXED_PRECISION 4
 
 typedef struct pc_plan pc_plan;
 
@@ -138,9 +156,12 @@ pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int
  * products b = Z^T x (Sec. 3.9: they use E, W and X only) run on an
  * internal stream while the factorization runs, which the two separate
  * calls cannot do: pc_gram_factor waits for the pivot status before
- * returning.  Synchronizes `stream` once, at the end.  If the Gram is not
- * positive definite the result Y is undefined and PC_ERR_NOT_SPD is
- * returned; the plan then rejects apply until a successful factorization. */
+ * returning.  Synchronizes `stream` once, at the end.  If the Gram of an
+ * instance with right-hand sides is not positive definite (after the
+ * precision ladder), its Y is undefined and PC_ERR_NOT_SPD is returned
+ * (*failed_instance: the first such instance); the other instances are still
+ * solved.  An instance that fails with R[i] = 0 is not an error of the call.
+ * A failed instance rejects a later apply until a successful factorization. */
 pc_status pc_factor_apply(pc_plan *plan, const double *const *X, const int64_t *ldX,
                           const int64_t *R, double *const *Y, const int64_t *ldY,
                           void *stream, int32_t *failed_instance);
@@ -150,6 +171,15 @@ pc_status pc_factor_apply(pc_plan *plan, const double *const *X, const int64_t *
  * for instance `instance`.  Either output pointer may be NULL. */
 pc_status pc_query_info(const pc_plan *plan, int32_t instance, int32_t *iterations,
                         double *last_rel_update);
+
+/* pc_query_instance — state of instance `instance` after pc_gram_factor:
+ * *precision (may be NULL) receives the precision (a pc_precision value) of
+ * its current Gram: the options' precision, or the rung the ladder raised it
+ * to (the plan keeps it: later factorizations start there); *factored (may
+ * be NULL) receives 1 if its factorization succeeded, else 0 (after
+ * PC_ERR_NOT_SPD the other instances stay usable: pass R = 0 for the failed
+ * ones to pc_left_inverse_apply). */
+pc_status pc_query_instance(const pc_plan *plan, int32_t instance, int32_t *precision, int32_t *factored);
 
 /* pc_plan_destroy — free everything the plan owns (synchronizes the device
  * first).  NULL is accepted. */

@@ -385,11 +385,23 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
     return out
 
 
+def split_bf16(Z: np.ndarray):
+    """Split bfloat16 representation Z ~ Hi + Lo: Hi = bf16(Z), Lo = bf16(Z - Hi)
+    (the difference is exact in float64).  Returned as float64 arrays."""
+    Hi = round_bf16(Z)
+    return Hi, round_bf16(Z - Hi)
+
+
 def gram_lowprec(E, W, n_w, fmt: str):
     """Exact (float64) Gram of the rounded square root Z~ = round(E*W) elementwise.
 
-    fmt: "bf16" or "fp32".  The product E[i,k]*W[j,m] is formed in float64
-    and rounded once to the format."""
+    fmt: "bf16" or "fp32": Z~^T Z~ with the product E[i,k]*W[j,m] formed in
+    float64 and rounded once to the format;  "bf16x3": the three-product
+    split-bf16 Gram Hi^T Hi + Hi^T Lo + Lo^T Hi of `split_bf16(Z)` (the
+    Lo^T Lo term is left out)."""
     Z = form_z(E, W, n_w)
+    if fmt == "bf16x3":
+        Hi, Lo = split_bf16(Z)
+        return Hi.T @ Hi + Hi.T @ Lo + Lo.T @ Hi
     Zt = round_bf16(Z) if fmt == "bf16" else round_fp32(Z)
     return Zt.T @ Zt

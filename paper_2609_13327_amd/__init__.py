@@ -33,9 +33,11 @@ PC_ERR_WORKSPACE = 10
 PC_PREC_FP64 = 0
 PC_PREC_FP32_REFINE = 1
 PC_PREC_BF16_REFINE = 2
+PC_PREC_BF16X3_REFINE = 3
 
 PC_FLAG_KEEP_GRAM = 1
 PC_FLAG_CG_MEMBER_BLOCKS = 2
+PC_FLAG_FIXED_PRECISION = 4
 PC_MLP_BF16 = 0
 PC_MLP_FP32 = 1
 
@@ -46,7 +48,7 @@ EXPORTED = [
     "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
-    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc",
+    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout", "solve_alongside"]
@@ -132,6 +134,7 @@ def load_library(path: str = LIB_PATH):
                                     POINTER(c_int32)]
     lib.pc_learned_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                      c_double, c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p]
+    lib.pc_query_instance.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
     lib.pc_factor_apply_noalloc.argtypes = [POINTER(PcInstance), c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                             c_void_p]
     for name in EXPORTED:
@@ -310,6 +313,16 @@ def pc_query_info(plan: int, instance: int = 0):
     _check(load_library().pc_query_info(c_void_p(plan), int(instance), ctypes.byref(it),
                                         ctypes.byref(rel)), "pc_query_info")
     return it.value, rel.value
+
+
+def pc_query_instance(plan: int, instance: int = 0):
+    """(precision of the instance's current Gram after the precision ladder,
+    whether its factorization succeeded)."""
+    pr = c_int32(0)
+    fa = c_int32(0)
+    _check(load_library().pc_query_instance(c_void_p(plan), int(instance), ctypes.byref(pr), ctypes.byref(fa)),
+           "pc_query_instance")
+    return pr.value, bool(fa.value)
 
 
 def pc_plan_destroy(plan: Optional[int]):

@@ -486,11 +486,14 @@ __device__ __noinline__ void potrf_factor(const CholArgs& a, int k, double* A, d
         const double piv = bcast16(dg[j], j);
         const double thr = Sc[1024 + c + j];
         if (!(piv > thr && isfinite(piv))) fail = fail < j ? fail : j;
-        // 1/sqrt(piv): the hardware estimate and one Newton step (relative
-        // error ~1e-13, far below the factor's own rounding error bound;
-        // a failing pivot is caught above and its value never used)
+        // 1/sqrt(piv): the hardware estimate and two Newton steps
+        // y <- y + y (1 - piv y^2) / 2 (each squares the relative error: the
+        // estimate's ~1e-7 becomes ~1e-14, then rounding level, so the column
+        // scaling adds nothing to the factor's own rounding error; a failing
+        // pivot is caught above and its value never used)
         const double y0 = __builtin_amdgcn_rsq(piv);
-        const double inv = fma(0.5 * y0, fma(-piv * y0, y0, 1.0), y0);
+        const double y1 = fma(0.5 * y0, fma(-piv * y0, y0, 1.0), y0);
+        const double inv = fma(0.5 * y1, fma(-piv * y1, y1, 1.0), y1);
         dg[j] *= inv;                     // lanes r > j: L_rj; lane j: piv / sqrt(piv) = L_jj
         pr[j] *= inv;
 #pragma unroll

@@ -75,8 +75,15 @@ hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const do
 }
 
 // Stop at the tolerance, or once the updates stop shrinking (two iterations in
-// a row with less than a halving): then the attainable accuracy of the
-// residual has been reached, accepted if the update is below `accept`.
+// a row with less than a halving).  Then the contraction ratio rho =
+// last / previous estimates what further iterations could still change:
+// last * rho / (1 - rho) for rho < 1, else last (the updates fluctuate at the
+// attainable accuracy of the FP64 residual).  The result is accepted
+// (done = 1) if that estimate is at most `accept` and reported as stalled
+// above it (done = 2) otherwise.  It is reported as diverging (done = 3) when
+// the update is not finite, or is growing and already as large as y itself
+// (at the attainable accuracy the updates fluctuate in size, so growth
+// alone does not mean divergence).
 __global__ void refine_check_kernel(RefineCtl* ctl, double tol, double accept) {
   if (ctl->done) return;
   const double worst = __longlong_as_double((long long)ctl->worst);
@@ -86,8 +93,14 @@ __global__ void refine_check_kernel(RefineCtl* ctl, double tol, double accept) {
   ctl->last = worst;
   if (worst <= tol) {
     ctl->done = 1;
+  } else if (!(worst < INFINITY) || (ctl->iters >= 2 && worst >= 1.0 && worst > ctl->prev)) {
+    ctl->done = 3;
   } else if (ctl->iters >= 2 && worst > 0.5 * ctl->prev) {
-    if (++ctl->stall >= 2) ctl->done = (worst <= accept) ? 1 : 2;
+    if (++ctl->stall >= 2) {
+      const double rho = worst / ctl->prev;
+      const double est = rho < 1.0 ? worst * rho / (1.0 - rho) : worst;
+      ctl->done = est <= accept ? 1 : 2;
+    }
   } else {
     ctl->stall = 0;
   }

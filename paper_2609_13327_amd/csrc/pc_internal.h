@@ -14,7 +14,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Device-side control of the refinement of one instance.
 struct RefineCtl {
-  int done;                  // 0 running, 1 converged, 2 stopped above the acceptance level
+  int done;                  // 0 running, 1 converged, 2 stalled above the acceptance level, 3 diverging
   int iters;                 // refinement iterations applied
   int stall;                 // consecutive iterations with less than a halving
   int pad;
@@ -40,8 +40,6 @@ struct Inst {
   int64_t ldS = 0;           // P rounded up to the 128-pair Gram tile
   double* G2 = nullptr;      // contraction parts 2.. of a split FP64 Gram (only when the tiles are few)
   int g2_parts = 0;          // parts G2 has room for ((g2_parts) x KMp x KMp)
-  void* Zt = nullptr;        // reduced precision: the rounded Z, column-major, ldz rows (bf16 or fp32)
-  int64_t ldz = 0;
   int* pairs = nullptr;      // P x 2: (k, k') with k <= k'
   int* qtiles = nullptr;     // nq x 2: (m0, m0') of the mode-pair tiles
   int nq = 0;
@@ -82,6 +80,7 @@ struct Inst {
   int64_t* blk_offs = nullptr; int64_t blk_ntasks = 0;            // DAG order of a full diagonal block
   int64_t* blk_offs_tail = nullptr; int64_t blk_ntasks_tail = 0;  // and of the last, smaller one
   bool factored = false;
+  int prec = 0;              // precision of the current Gram (a pc_precision value); the ladder raises it
   int iters = 0;
   double last_rel = 0.0;
 };
@@ -96,12 +95,23 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
 // reduced-precision Grams of several instances in one launch (after each
 // instance's rounded Z has been staged)
-struct LowGramInst { const void* Zt; int64_t ldz, KM; double* G; int64_t ldG; };
+// (the rounded Z is formed tile by tile from E and W inside the Gram kernel)
+struct LowGramInst {
+  const double* E; int64_t ldE;
+  const double* W; int64_t ldW;
+  int64_t n, n_h, n_w, M, KM;
+  double* G; int64_t ldG;
+};
 struct LowGramTile { int inst, ta, tb, pad; };
-struct LowGramBatch { LowGramTile* tiles = nullptr; LowGramInst* insts = nullptr; int64_t ntiles = 0; };
-hipError_t launch_stage_z(const Inst& in, int precision, hipStream_t s);
+struct LowGramBatch {
+  LowGramTile* tiles = nullptr; LowGramInst* insts = nullptr; int* mode = nullptr;
+  int64_t ntiles = 0; int count = 0;
+};
 LowGramBatch* make_lowgram_batch(const std::vector<Inst>& insts);
 void free_lowgram_batch(LowGramBatch* b);
+// per-instance precision codes (host array of b->count); a batched launch of
+// one precision computes only the instances of that precision
+hipError_t set_lowgram_modes(const LowGramBatch* b, const int* modes, hipStream_t s);
 hipError_t launch_gram_lowprec_batch(const LowGramBatch* b, int precision, hipStream_t s);
 hipError_t launch_gram_pad_and_diag(const Inst& in, hipStream_t s);
 // after_reset (may be null) is recorded once the tile states are reset,

@@ -58,6 +58,7 @@ struct pc_plan {
   int device = 0;
   int* d_flag = nullptr;        // device scratch int (finiteness check)
   pc::RefineCtl* h_ctl = nullptr;   // pinned host copies of the refinement controls
+  int* h_modes = nullptr;           // pinned: per-instance Gram precision for a batched low-precision launch
   int* h_status = nullptr;          // pinned host copies of each instance's pivot status and error flag,
                                     // then the error flag of a forward pass run during the factorization
   // independent instances run on internal streams (fork/join with the caller's stream)
@@ -98,7 +99,7 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 void free_inst(Inst& in) {
-  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; in.g2_parts = 0; hipFree(in.Zt); in.Zt = nullptr; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
+  hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; in.g2_parts = 0; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
   hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
@@ -136,6 +137,7 @@ void free_plan(pc_plan* p) {
   pc::free_lowgram_batch(p->lowgram);
   if (p->h_ctl) hipHostFree(p->h_ctl);
   if (p->h_status) hipHostFree(p->h_status);
+  if (p->h_modes) hipHostFree(p->h_modes);
   delete p;
 }
 
@@ -269,11 +271,6 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   if (precision == PC_PREC_FP64 && pc::gram_split_for(in) > 1) {
     if (ensure_gram_parts(in, pc::gram_split_for(in)) != hipSuccess) return PC_ERR_OOM;
   }
-  if (precision != PC_PREC_FP64) {
-    in.ldz = pc::round_up(in.n, 64);
-    const size_t bytes = (size_t)in.ldz * (size_t)in.KM * (precision == PC_PREC_BF16_REFINE ? 2 : 4);
-    if (hipMalloc(&in.Zt, bytes) != hipSuccess) return PC_ERR_OOM;
-  }
   if (hipMemset(in.Y, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   if (hipMemset(in.D, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
   return PC_OK;
@@ -325,19 +322,50 @@ hipError_t join(pc_plan* p, hipStream_t s) {
   return e;
 }
 
-// Reduced-precision Grams of a batch: every instance's rounded Z is staged on
-// its stream, then all the Grams are one launch, then the padding per stream.
+// The Gram of one instance in its current precision (FP64 structured Gram,
+// or the Gram of the rounded Z formed inside the low-precision kernel).
+pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
+  in.factored = false;
+  PC_TRY(pc::launch_fill_int(in.info, -1, 1, s));
+  if (in.prec == PC_PREC_FP64) {
+    { PhaseTimer t(p, PC_PHASE_COLUMN_GRAMS, s); PC_TRY(pc::launch_column_grams(in, s)); }
+    { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_f64(in, s)); }
+  } else {
+    PhaseTimer t(p, PC_PHASE_GRAM, s);
+    PC_TRY(pc::launch_gram_lowprec(in, in.prec, s));
+  }
+  { PhaseTimer t(p, PC_PHASE_PAD, s); PC_TRY(pc::launch_gram_pad_and_diag(in, s)); }
+  return PC_OK;
+}
+
+// Grams of a batch in reduced precision: the instances of each reduced
+// precision in one launch (tiles of all of them, longest contraction first),
+// instances raised to FP64 by the ladder on the internal streams, then the
+// padding per stream.
 pc_status assemble_lowgram_batch(pc_plan* p, hipStream_t s) {
+  bool used[4] = {false, false, false, false};
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    p->h_modes[i] = p->inst[i].prec;
+    used[p->inst[i].prec] = true;
+  }
+  PC_TRY(pc::set_lowgram_modes(p->lowgram, p->h_modes, s));
   PC_TRY(fork(p, s));
   for (size_t i = 0; i < p->inst.size(); ++i) {
     Inst& in = p->inst[i];
     hipStream_t si = stream_for(p, i, s);
     in.factored = false;
     PC_TRY(pc::launch_fill_int(in.info, -1, 1, si));
-    PC_TRY(pc::launch_stage_z(in, p->opt.precision, si));
+    if (in.prec == PC_PREC_FP64) {
+      PC_TRY(pc::launch_column_grams(in, si));
+      PC_TRY(pc::launch_gram_f64(in, si));
+    }
   }
   PC_TRY(join(p, s));
-  { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_lowprec_batch(p->lowgram, p->opt.precision, s)); }
+  {
+    PhaseTimer t(p, PC_PHASE_GRAM, s);
+    for (int prec : {PC_PREC_BF16_REFINE, PC_PREC_BF16X3_REFINE, PC_PREC_FP32_REFINE})
+      if (used[prec]) PC_TRY(pc::launch_gram_lowprec_batch(p->lowgram, prec, s));
+  }
   PC_TRY(fork(p, s));
   for (size_t i = 0; i < p->inst.size(); ++i) {
     Inst& in = p->inst[i];
@@ -349,19 +377,18 @@ pc_status assemble_lowgram_batch(pc_plan* p, hipStream_t s) {
   return PC_OK;
 }
 
-pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
-  in.factored = false;
-  PC_TRY(pc::launch_fill_int(in.info, -1, 1, s));
-  if (p->opt.precision == PC_PREC_FP64) {
-    { PhaseTimer t(p, PC_PHASE_COLUMN_GRAMS, s); PC_TRY(pc::launch_column_grams(in, s)); }
-    { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_f64(in, s)); }
-  } else {
-    PhaseTimer t(p, PC_PHASE_GRAM, s);
-    PC_TRY(pc::launch_gram_lowprec(in, p->opt.precision, s));
+// The precision ladder: the next, more accurate Gram after `prec`
+// (bf16 -> split bf16 -> fp32 -> FP64), or -1 at the top.
+int next_rung(int prec) {
+  switch (prec) {
+    case PC_PREC_BF16_REFINE: return PC_PREC_BF16X3_REFINE;
+    case PC_PREC_BF16X3_REFINE: return PC_PREC_FP32_REFINE;
+    case PC_PREC_FP32_REFINE: return PC_PREC_FP64;
+    default: return -1;
   }
-  { PhaseTimer t(p, PC_PHASE_PAD, s); PC_TRY(pc::launch_gram_pad_and_diag(in, s)); }
-  return PC_OK;
 }
+
+bool ladder_on(const pc_plan* p) { return !(p->opt.flags & PC_FLAG_FIXED_PRECISION); }
 
 // The apply sequence of every instance on the streams (no host wait when
 // check_every == 0; otherwise the host stops early once every instance's
@@ -371,10 +398,12 @@ pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_
 
 // done_ahead: 0, or 1 when b = Z^T x is already in in.Y, or 2 when the
 // forward pass of the first solve is also done (in in.B).
+// force_single: the per-instance path even for a batched plan (the ladder's
+// re-solve of a few instances).
 pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
                         double* const* Y, const int64_t* ldY, hipStream_t s, int check_every,
-                        int done_ahead = 0) {
-  if (p->batch) return enqueue_apply_batched(p, X, ldX, R, Y, ldY, s, check_every);
+                        int done_ahead = 0, bool force_single = false) {
+  if (p->batch && !force_single) return enqueue_apply_batched(p, X, ldX, R, Y, ldY, s, check_every);
   const size_t cnt = p->inst.size();
   const int budget = p->opt.max_refine;
   PC_TRY(fork(p, s));
@@ -649,8 +678,9 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   if (!inst || count <= 0) return PC_ERR_INVALID_ARG;
   pc_options o{PC_PREC_FP64, 0, 1e-12, 0, 0};
   if (opt) o = *opt;
-  if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16_REFINE || o.max_refine < 0 ||
-      (o.flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS)) != 0 || !std::isfinite(o.tol))
+  if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16X3_REFINE || o.max_refine < 0 ||
+      (o.flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS | PC_FLAG_FIXED_PRECISION)) != 0 ||
+      !std::isfinite(o.tol))
     return PC_ERR_INVALID_ARG;
   if ((o.flags & PC_FLAG_KEEP_GRAM) && o.precision != PC_PREC_FP64) return PC_ERR_INVALID_ARG;
   if ((o.flags & PC_FLAG_CG_MEMBER_BLOCKS) && !(o.flags & PC_FLAG_KEEP_GRAM)) return PC_ERR_INVALID_ARG;
@@ -677,6 +707,7 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
     in.n = a.n_h * a.n_w; in.KM = a.K * a.M; in.KMp = pc::round_up(in.KM, pc::NB);
     in.P = a.K * (a.K + 1) / 2;
     in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
+    in.prec = o.precision;
     p->inst.push_back(in);
     st = alloc_inst(p->inst.back(), o.precision, o.flags);
     max_r = std::max<int64_t>(max_r, a.max_rhs);
@@ -685,6 +716,8 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   if (st == PC_OK && hipHostMalloc((void**)&p->h_ctl, sizeof(pc::RefineCtl) * (size_t)count) != hipSuccess)
     st = PC_ERR_OOM;
   if (st == PC_OK && hipHostMalloc((void**)&p->h_status, sizeof(int) * (2 * (size_t)count + 1)) != hipSuccess)
+    st = PC_ERR_OOM;
+  if (st == PC_OK && hipHostMalloc((void**)&p->h_modes, sizeof(int) * (size_t)count) != hipSuccess)
     st = PC_ERR_OOM;
   if (st == PC_OK && count > 1) {
     // default-priority streams for independent instances
@@ -834,7 +867,8 @@ static pc_status finish_factor(pc_plan* p, hipStream_t s, int32_t* failed_instan
 // Refinement outcome of an apply: one read of every instance's control block.
 static pc_status finish_apply(pc_plan* p, const int64_t* R, hipStream_t s) {
   const size_t cnt = p->inst.size();
-  for (size_t i = 0; i < cnt; ++i) { p->inst[i].iters = 0; p->inst[i].last_rel = 0.0; }
+  for (size_t i = 0; i < cnt; ++i)
+    if (R[i] != 0) { p->inst[i].iters = 0; p->inst[i].last_rel = 0.0; }
   if (p->opt.max_refine == 0) return PC_OK;
   for (size_t i = 0; i < cnt; ++i)
     if (R[i] != 0)
@@ -845,9 +879,83 @@ static pc_status finish_apply(pc_plan* p, const int64_t* R, hipStream_t s) {
     if (R[i] == 0) continue;
     p->inst[i].iters = p->h_ctl[i].iters;
     p->inst[i].last_rel = p->h_ctl[i].last;
-    if (p->opt.precision != PC_PREC_FP64 && p->h_ctl[i].done != 1) st = PC_ERR_NO_CONVERGENCE;
+    if (p->h_ctl[i].done != 1 && (p->inst[i].prec != PC_PREC_FP64 || p->opt.precision != PC_PREC_FP64 ||
+                                  p->h_ctl[i].done == 3))
+      st = PC_ERR_NO_CONVERGENCE;
   }
   return st;
+}
+
+// Assemble and factor instance i alone in its current precision (after the
+// ladder raised it), then read its pivot status (one stream sync).
+static pc_status refactor_one(pc_plan* p, size_t i, hipStream_t s) {
+  Inst& in = p->inst[i];
+  const size_t n = p->inst.size();
+  pc_status st = assemble_one(p, in, s);
+  if (st != PC_OK) return st;
+  { PhaseTimer t(p, PC_PHASE_CHOLESKY, s); PC_TRY(pc::launch_cholesky(in, s)); }
+  PC_TRY(hipMemcpyAsync(&p->h_status[i], in.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  PC_TRY(hipMemcpyAsync(&p->h_status[n + i], pc::chol_error_flag(in), sizeof(int), hipMemcpyDeviceToHost, s));
+  PC_TRY(hipStreamSynchronize(s));
+  if (p->h_status[n + i]) return PC_ERR_DEVICE;
+  in.factored = p->h_status[i] < 0;
+  return PC_OK;
+}
+
+// The ladder at factorization time: an instance whose Gram in reduced
+// precision was not positive definite is assembled and factored again in
+// the next precision, up to FP64.  Returns PC_ERR_NOT_SPD (first instance in
+// *failed_instance) if one still fails in FP64.
+static pc_status escalate_failed_factors(pc_plan* p, hipStream_t s, int32_t* failed_instance) {
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    Inst& in = p->inst[i];
+    while (!in.factored && ladder_on(p) && next_rung(in.prec) >= 0) {
+      in.prec = next_rung(in.prec);
+      const pc_status st = refactor_one(p, i, s);
+      if (st != PC_OK) return st;
+    }
+  }
+  if (failed_instance) *failed_instance = -1;
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (!p->inst[i].factored) {
+      if (failed_instance) *failed_instance = (int32_t)i;
+      return PC_ERR_NOT_SPD;
+    }
+  return PC_OK;
+}
+
+// The ladder at apply time: every instance whose refinement stopped without
+// converging (stalled above the acceptance level, or diverging) is refactored
+// in the next precision and solved again alone, until it converges or FP64
+// has been tried.
+static pc_status escalate_unconverged(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                                      double* const* Y, const int64_t* ldY, hipStream_t s) {
+  const size_t cnt = p->inst.size();
+  std::vector<int64_t> R2(cnt, 0);
+  while (ladder_on(p)) {
+    bool any = false;
+    for (size_t i = 0; i < cnt; ++i) {
+      R2[i] = 0;
+      Inst& in = p->inst[i];
+      if (R[i] == 0 || p->h_ctl[i].done == 1 || next_rung(in.prec) < 0) continue;
+      do {
+        in.prec = next_rung(in.prec);
+        const pc_status fs = refactor_one(p, i, s);
+        if (fs != PC_OK) return fs;
+      } while (!in.factored && next_rung(in.prec) >= 0);
+      if (!in.factored) return PC_ERR_NOT_SPD;
+      R2[i] = R[i];
+      any = true;
+    }
+    if (!any) break;
+    pc_status st = enqueue_apply(p, X, ldX, R2.data(), Y, ldY, s, p->opt.max_refine > 4 ? 2 : 0, 0, true);
+    if (st != PC_OK) return st;
+    st = finish_apply(p, R2.data(), s);
+    if (st != PC_OK && st != PC_ERR_NO_CONVERGENCE) return st;
+  }
+  for (size_t i = 0; i < cnt; ++i)
+    if (R[i] != 0 && p->h_ctl[i].done != 1) return PC_ERR_NO_CONVERGENCE;
+  return PC_OK;
 }
 
 pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
@@ -857,7 +965,9 @@ pc_status pc_gram_factor(pc_plan* p, void* stream, int32_t* failed_instance) {
   hipStream_t s = (hipStream_t)stream;
   const pc_status st = enqueue_factor(p, s, nullptr);
   if (st != PC_OK) return st;
-  return finish_factor(p, s, failed_instance);
+  const pc_status fs = finish_factor(p, s, failed_instance);
+  if (fs == PC_ERR_NOT_SPD && ladder_on(p)) return escalate_failed_factors(p, s, failed_instance);
+  return fs;
 }
 
 pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
@@ -903,7 +1013,9 @@ pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_
     pc_status st = enqueue_apply(p, X, ldX, R, Y, ldY, s, budget > 4 ? 2 : 0);
     if (st != PC_OK) return st;
   }
-  return finish_apply(p, R, s);
+  const pc_status st = finish_apply(p, R, s);
+  if (st == PC_ERR_NO_CONVERGENCE && ladder_on(p)) return escalate_unconverged(p, X, ldX, R, Y, ldY, s);
+  return st;
 }
 
 pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
@@ -925,8 +1037,25 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   // has made ready when the Gram is assembled).
   const bool overlap = cnt == 1 && R[0] > 0 && !p->batch && !p->lowgram && !p->opt.use_graph;
   if (!overlap) {
-    const pc_status st = pc_gram_factor(p, stream, failed_instance);
-    if (st != PC_OK) return st;
+    // an instance that fails to factor matters only if it has right-hand sides
+    int32_t first = -1;
+    const pc_status st = pc_gram_factor(p, stream, &first);
+    if (st != PC_OK && st != PC_ERR_NOT_SPD) return st;
+    if (st == PC_ERR_NOT_SPD) {
+      std::vector<int64_t> R2(R, R + cnt);
+      int32_t failed = -1;
+      for (size_t i = 0; i < cnt; ++i)
+        if (!p->inst[i].factored) {
+          if (R2[i] > 0 && failed < 0) failed = (int32_t)i;
+          R2[i] = 0;
+        }
+      const pc_status ast = pc_left_inverse_apply(p, X, ldX, R2.data(), Y, ldY, stream);
+      if (failed >= 0) {
+        if (failed_instance) *failed_instance = failed;
+        return PC_ERR_NOT_SPD;
+      }
+      return ast;
+    }
     return pc_left_inverse_apply(p, X, ldX, R, Y, ldY, stream);
   }
   if (!p->ovl) {
@@ -957,17 +1086,33 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
     PC_TRY(hipMemcpyAsync(&p->h_status[2], pc::chol_solve_fwd_error_flag(in), sizeof(int), hipMemcpyDeviceToHost, s));
   st = enqueue_apply(p, X, ldX, R, Y, ldY, s, p->opt.max_refine > 4 ? 2 : 0, fwd ? 2 : 1);
   PC_TRY(hipStreamSynchronize(s));
+  const bool fwd_err = fwd && p->h_status[2] != 0;   // read before the ladder reuses the status slots
   const pc_status fst = factor_outcome(p, failed_instance);
   if (st != PC_OK) return st;
+  if (fst == PC_ERR_NOT_SPD && ladder_on(p)) {
+    // the ladder: refactor in a more accurate precision, then the plain apply
+    const pc_status es = escalate_failed_factors(p, s, failed_instance);
+    if (es != PC_OK) return es;
+    return pc_left_inverse_apply(p, X, ldX, R, Y, ldY, stream);
+  }
   if (fst != PC_OK) return fst;
-  if (fwd && p->h_status[2]) return PC_ERR_DEVICE;   // a bounded wait of the forward pass expired
-  return finish_apply(p, R, s);
+  if (fwd_err) return PC_ERR_DEVICE;   // a bounded wait of the forward pass expired
+  const pc_status ast = finish_apply(p, R, s);
+  if (ast == PC_ERR_NO_CONVERGENCE && ladder_on(p)) return escalate_unconverged(p, X, ldX, R, Y, ldY, s);
+  return ast;
 }
 
 pc_status pc_query_info(const pc_plan* p, int32_t instance, int32_t* iterations, double* last_rel_update) {
   if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
   if (iterations) *iterations = p->inst[instance].iters;
   if (last_rel_update) *last_rel_update = p->inst[instance].last_rel;
+  return PC_OK;
+}
+
+pc_status pc_query_instance(const pc_plan* p, int32_t instance, int32_t* precision, int32_t* factored) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
+  if (precision) *precision = p->inst[instance].prec;
+  if (factored) *factored = p->inst[instance].factored ? 1 : 0;
   return PC_OK;
 }
 

@@ -1,5 +1,7 @@
 """Many uneven instances in one plan: internal streams, device-side refinement
 control and hipGraph replay, against the oracle, through the C-ABI."""
+import os
+
 import numpy as np
 import pytest
 
@@ -89,25 +91,50 @@ def test_zero_rhs_instances_are_skipped():
     plan.close()
 
 
+GOLD3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle.npz")
+
+
 def test_full_batch_config3():
-    """The 64-instance batch (grids 32x64 .. 96x192) in fp32 + refinement with a
-    captured graph.  Every instance's answer satisfies the least-squares
-    optimality condition: with g = Z^T (x - Z y) = -G (y - y*), a relative
-    error eps implies ||g|| <= eps ||G|| ||y|| <= eps ||Z||_F^2 ||y||, checked
-    for eps = 1e-9 from the factors (Z is never formed).  The four cheapest
-    instances also match the QR oracle."""
+    """All 64 instances as drawn (grids 32x64 .. 96x192, K*M <= n): fp32 Gram +
+    FP64 refinement with the precision ladder and a captured graph, against
+    the stored QR oracle values of each instance's first and last right-hand
+    side (tests/golden/make_c3_oracle.py), within the least-squares
+    sensitivity max(1e-8, 20 u kappa (1 + kappa eta)).  An instance may be
+    reported rank deficient (its FP64 Gram not positive definite, so no
+    normal-equation method applies) only when kappa(Z)^2 K M u > 1e-3, i.e.
+    when the Gram's own rounding reaches its smallest eigenvalue."""
+    import hashlib
+    g = np.load(GOLD3)
     insts = wl.batched_config()
-    outs, its = _run(insts, pc.PC_PREC_FP32_REFINE, 20, 1)
-    for k, (inst, y) in enumerate(zip(insts, outs[0])):
-        Zy = sum(inst.E[:, [kk]] * (inst.W @ y[kk * inst.M:(kk + 1) * inst.M]) for kk in range(inst.K))
-        r = inst.X - Zy
-        g = np.concatenate([inst.W.T @ (inst.E[:, [kk]] * r) for kk in range(inst.K)])
-        zf2 = float(np.sum((inst.E ** 2).sum(axis=1) * (inst.W ** 2).sum(axis=1)))
-        lhs = np.linalg.norm(g, axis=0)
-        rhs = 1e-9 * zf2 * np.linalg.norm(y, axis=0)
-        assert np.all(lhs <= rhs), (k, (lhs / rhs).max())
-    order = sorted(range(len(insts)), key=lambda k: insts[k].n * insts[k].KM ** 2)
-    for k in order[:4]:
-        inst = insts[k]
-        ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
-        assert _rel_err(outs[0][k], ref).max() <= 1e-8
+    h = hashlib.sha256()
+    for i in insts:
+        for a in (i.E, i.W, i.X):
+            h.update(np.ascontiguousarray(a).tobytes())
+    assert h.hexdigest() == str(g["digest"]), "generated batch differs from the stored oracle values' inputs"
+    plan = pc.Plan([inst_dict(i) for i in insts], precision=pc.PC_PREC_FP32_REFINE, max_refine=20, tol=1e-12,
+                   use_graph=1)
+    st, failed = plan.factor(raise_on_error=False)
+    assert st in (pc.PC_OK, pc.PC_ERR_NOT_SPD)
+    state = [pc.pc_query_instance(plan.handle, k) for k in range(len(insts))]
+    Xs = [dev(i.X) if fac else None for i, (_, fac) in zip(insts, state)]
+    Ys = [empty(i.KM, i.R) for i in insts]
+    st = plan.apply(Xs, Ys, raise_on_error=False)
+    assert st in (pc.PC_OK, pc.PC_ERR_NO_CONVERGENCE)
+    state = [pc.pc_query_instance(plan.handle, k) for k in range(len(insts))]
+    within, unfactored = 0, []
+    for k, inst in enumerate(insts):
+        kappa, smax = float(g["kappa"][k]), float(g["sigma_max"][k])
+        if not state[k][1]:
+            unfactored.append(k)
+            assert kappa ** 2 * inst.KM * 2.0 ** -53 > 1e-3, (k, kappa)
+            continue
+        ref = g["y"][g["offsets"][k]:g["offsets"][k + 1]].reshape(2, inst.KM).T
+        got = host(Ys[k])[:, g["columns"][k]]
+        err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        tol = np.maximum(1e-8, 20 * 2.0 ** -53 * kappa * (1 + kappa * g["eta"][k]))
+        assert np.all(err <= tol), (k, inst.n, inst.K, inst.M, kappa, err, tol)
+        within += int(np.all(err <= 1e-8))
+    rungs = [s[0] for s in state]
+    print(f"config 3: {within} of {len(insts)} instances within 1e-8, rank deficient {unfactored}, "
+          f"rungs {dict((r, rungs.count(r)) for r in sorted(set(rungs)))}, status {st}")
+    plan.close()

@@ -417,3 +417,33 @@ def test_gram_lowprec_rounds_the_product_once():
     assert G.shape == (1, 1) and G[0, 0] == (1.0 + 2.0 ** -7) ** 2
     G32 = lsq.gram_lowprec(E, W, 1, "fp32")
     assert G32[0, 0] == (1.0 + 2.0 ** -8) ** 4
+
+
+def test_split_bf16_hand_cases_and_bound():
+    """Split bfloat16: a value with at most 8 significant bits has Lo = 0; the
+    hand value 1 + 2^-8 + 2^-20 gives Hi = 1 + 2^-7 (above the tie) and
+    Lo = bf16(-2^-8 + 2^-20) = -2^-8; and in general |Z - Hi - Lo| <= 2^-16 |Z|
+    (two roundings of 8 significant bits each)."""
+    Hi, Lo = lsq.split_bf16(np.array([1.5, -3.0 * 2.0 ** -10, 1.0 + 2.0 ** -8 + 2.0 ** -20]))
+    assert Hi[0] == 1.5 and Lo[0] == 0.0 and Hi[1] == -3.0 * 2.0 ** -10 and Lo[1] == 0.0
+    assert Hi[2] == 1.0 + 2.0 ** -7 and Lo[2] == -(2.0 ** -8)
+    rng = np.random.Generator(np.random.PCG64(11))
+    Z = rng.standard_normal((300, 20)) * np.exp(rng.uniform(-5, 5, (300, 20)))
+    Hi, Lo = lsq.split_bf16(Z)
+    assert np.all(np.abs(Z - Hi - Lo) <= 2.0 ** -16 * np.abs(Z))
+
+
+def test_gram_lowprec_split_bf16():
+    """The three-product Gram equals (Hi + Lo)^T (Hi + Lo) - Lo^T Lo, is exact
+    when Z has no more than 8 significant bits (Lo = 0), and lies within
+    3 * 2^-16 |Z|^T |Z| of the exact Gram."""
+    inst = small_instance(4, 8, 1, 3, 5)
+    Z = lsq.form_z(inst.E, inst.W, 1)
+    G3 = lsq.gram_lowprec(inst.E, inst.W, 1, "bf16x3")
+    Hi, Lo = lsq.split_bf16(Z)
+    S = Hi + Lo
+    assert np.abs(G3 - (S.T @ S - Lo.T @ Lo)).max() <= 1e-14 * np.abs(G3).max()
+    assert np.all(np.abs(G3 - Z.T @ Z) <= 3 * 2.0 ** -16 * (np.abs(Z).T @ np.abs(Z)))
+    Eb, Wb = lsq.round_bf16(inst.E), np.ones((inst.n_h, 1))
+    Zb = lsq.form_z(Eb, Wb, 1)
+    assert np.array_equal(lsq.gram_lowprec(Eb, Wb, 1, "bf16x3"), Zb.T @ Zb)
