@@ -65,9 +65,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None, help="default: 2 (256x512 instance), 3 otherwise")
     ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--train", type=int, default=20000, help="config 5: training pairs")
-    ap.add_argument("--epochs", type=int, default=3, help="config 5: passes over the training pairs")
-    ap.add_argument("--heldout", type=int, default=256, help="config 5: held-out right-hand sides")
-    ap.add_argument("--cg-maxiter", type=int, default=400, help="config 5: CG iteration cap")
+    ap.add_argument("--epochs", type=int, default=4, help="config 5: passes over the training pairs (at most)")
+    ap.add_argument("--cg-maxiter", type=int, default=200, help="config 5: CG iteration cap")
+    ap.add_argument("--cg-precision", default="bf16", choices=["bf16", "bf16x3", "fp32"],
+                    help="config 5: precision of the Gram whose factor preconditions CG")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16", "bf16x3"],
                     help="default: fp32 for config 3, fp64 otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -198,11 +199,13 @@ def main():
         if not args.no_tune:   # launch shapes, measured on this plan before timing (like an FFT plan)
             pc.pc_autotune(plan.handle, args.tune_cache, True)
             tuning = sorted({pc.pc_query_tuning(plan.handle, k) for k in range(len(insts))})
+            log(f"  {prec_name}: tuned {tuning}")
         # instances whose Gram is not positive definite even in FP64 (after the
         # precision ladder) are left out: no right-hand sides, not counted
         st, _ = plan.factor(raise_on_error=False)
         ok = [pc.pc_query_instance(plan.handle, k)[1] for k in range(len(insts))]
         Xs = [x if good else None for x, good in zip(dX, ok)]
+        log(f"  {prec_name}: factored, precisions {sorted(set(pc.pc_query_instance(plan.handle, k)[0] for k in range(len(insts))))}")
         for _ in range(warmup):
             plan.factor_apply(Xs, dY, raise_on_error=False)
         torch.cuda.synchronize()
@@ -211,8 +214,10 @@ def main():
             pc.pc_profile_enable(plan.handle, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):   # one step: factor and apply (the fused call overlaps Z^T x with the factor)
+        for k in range(steps):   # one step: factor and apply (the fused call overlaps Z^T x with the factor)
             plan.factor_apply(Xs, dY, raise_on_error=False)
+            if args.config == 4:
+                log(f"  {prec_name}: step {k + 1}")   # progress (a step takes seconds here)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         phases = pc.pc_profile_read(plan.handle)
@@ -411,102 +416,101 @@ def main():
 
 
 def learned(args, torch, pc, wl, dev):
-    """The learned warm start on the 131072 x 32768 instance: train the
-    network on pairs (b = Z^T x, Z^+ x) from the direct solve, then solve
-    held-out right-hand sides by CG from zero and from the network's
-    prediction (direct solve as fallback and as the reference)."""
-    inst = wl.config(5, R=args.heldout)
-    KM = inst.KM
+    """The learned warm start on the 131072 x 32768 instance.  Training pairs
+    (b = Z^T x, Z^+ x) come from the plain FP64 direct solve; the network is
+    trained on the GPU by the library's kernels (early stopping on held-out
+    pairs); CG on the kept FP64 Gram, preconditioned by the FP64 Cholesky
+    factor of the reduced-precision Gram, solves the 1024 right-hand sides of
+    the instance's X from zero and from the network's prediction.  The FP64
+    direct solve and the stored oracle values judge the results."""
+    from paper_2609_13327_amd import learned as lrn
+    inst = wl.config(5)
+    KM, R = inst.KM, inst.R
+    gold = np.load(GOLDEN[4])
+    for k, a in (("E", inst.E), ("W", inst.W), ("X", inst.X)):
+        if hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest() != str(gold["digest_" + k]):
+            raise RuntimeError("generated inputs differ from those of the stored oracle values")
 
     def to_dev(a):
         return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to(dev).t()
 
-    E, W = to_dev(inst.E), to_dev(inst.W)
-    chunk = 1024
-    plan = pc.Plan([{"E": E, "W": W, "n_w": 1, "max_rhs": chunk}],
-                   flags=pc.PC_FLAG_KEEP_GRAM | pc.PC_FLAG_CG_MEMBER_BLOCKS)
+    E, W, X = to_dev(inst.E), to_dev(inst.W), to_dev(inst.X)
+    direct = pc.Plan([{"E": E, "W": W, "n_w": 1, "max_rhs": 1024}])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.factor()
+    direct.factor()
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
-    log(f"factor (FP64 Gram and Cholesky, kept Gram, member-block inverses) {t_factor:.2f} s")
-    # training pairs from the direct solve
-    g = torch.Generator(device=dev)
-    g.manual_seed(5000)
-    N = args.train
-    Xin = torch.empty((N, KM), dtype=torch.float32, device=dev)
-    Tin = torch.empty_like(Xin)
-    Bc = torch.empty((chunk, KM), dtype=torch.float64, device=dev).t()
-    Yc = torch.empty((chunk, KM), dtype=torch.float64, device=dev).t()
+    log(f"direct FP64 factor {t_factor:.2f} s")
+    prec_code = PRECS[args.cg_precision][0]
+    cgplan = pc.Plan([{"E": E, "W": W, "n_w": 1, "max_rhs": R}], precision=prec_code, max_refine=30, tol=1e-12,
+                     flags=pc.PC_FLAG_KEEP_GRAM)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for c0 in range(0, N, chunk):
-        c1 = min(N, c0 + chunk)
-        Xc = torch.randn((c1 - c0, inst.n), generator=g, dtype=torch.float64, device=dev).t()
-        pc.pc_sqrt_transpose_apply(plan.handle, 0, Xc, Bc[:, :c1 - c0])
-        plan.apply([Xc], [Yc[:, :c1 - c0]])
-        pc.pc_mlp_training_pairs(Bc[:, :c1 - c0], Yc[:, :c1 - c0], Xin[c0:c1], Tin[c0:c1])
+    cgplan.factor()
+    torch.cuda.synchronize()
+    t_cg_factor = time.perf_counter() - t0
+    rung = pc.pc_query_instance(cgplan.handle, 0)[0]
+    log(f"CG plan ({args.cg_precision} Gram factor as preconditioner, kept FP64 Gram) {t_cg_factor:.2f} s, rung {rung}")
+    t0 = time.perf_counter()
+    Xin, Tin = lrn.make_pairs(direct, inst.n, KM, args.train, 5000)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
-    log(f"{N} training pairs {t_pairs:.2f} s")
-    h, batch, lr = 1024, 256, 1e-3
-    W1, b1, W2, b2 = wl.mlp_init(KM, h, 5001)
-    net = pc.Mlp(KM, h, max(batch, args.heldout), pc.PC_MLP_BF16)
-    f32 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
-    pc.pc_mlp_set_params(net.handle, f32(W1), f32(b1), f32(W2), f32(b2))
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
-    losses = []
-    steps = args.epochs * (N // batch)
-    torch.cuda.synchronize()
+    log(f"{args.train} training pairs from the direct solve {t_pairs:.2f} s")
+    h, batch = 1024, 256
+    net = lrn.new_network(KM, h, max(batch, R), 5001, pc.PC_MLP_BF16)
+    n_val = max(256, args.train // 10)
+    steps = args.epochs * ((args.train - n_val) // batch)
     t0 = time.perf_counter()
-    for st in range(steps):
-        r0 = (st * batch) % (N - batch + 1)
-        pc.pc_mlp_train_step(net.handle, Xin[r0:r0 + batch], Tin[r0:r0 + batch], lr, loss)
-        if st % max(1, steps // 10) == 0 or st == steps - 1:
-            losses.append(round(float(loss.item()), 5))
+    best_val, hist = lrn.train(net, Xin, Tin, n_val, batch=batch, lr=1e-3, max_steps=steps, eval_every=50, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     train_flops = 6.0 * 2 * batch * KM * h * steps
-    log(f"training {steps} steps {t_train:.2f} s, losses {losses}")
     del Xin, Tin
-    # held-out right-hand sides
-    R = inst.R
-    X = to_dev(inst.X)
+    # reference: the direct FP64 solve of the same right-hand sides
     Yd = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.apply([X], [Yd])
+    direct.apply([X], [Yd])
     torch.cuda.synchronize()
     t_direct = time.perf_counter() - t0
     ref = Yd.cpu().numpy()
+    cols = list(gold["columns"])
     res = {}
     for name, m in (("cold", None), ("warm", net.handle)):
         Y = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        it, fb = pc.pc_learned_apply(plan.handle, 0, m, X, Y, 1e-11, args.cg_maxiter)
+        it, fb = pc.pc_learned_apply(cgplan.handle, 0, m, X, Y, 1e-11, args.cg_maxiter)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        e = np.linalg.norm(Y.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        y = Y.cpu().numpy()
+        e = np.linalg.norm(y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        eo = np.linalg.norm(y[:, cols] - gold["Y"], axis=0) / np.linalg.norm(gold["Y"], axis=0)
         res[name] = {"seconds": t, "rhs_per_s": R / t, "cg_iterations": it, "fallback_to_direct": bool(fb),
-                     "rel_err_vs_direct_max": float(e.max())}
-        log(f"CG {name}: {it} iterations, fallback {fb}, {t:.2f} s, max rel err vs direct {e.max():.2e}")
+                     "rel_err_vs_direct_max": float(e.max()), "rel_err_vs_oracle_max": float(eo.max())}
+        log(f"CG {name}: {it} iterations, fallback {fb}, {t:.2f} s, max rel err vs direct {e.max():.2e}, "
+            f"vs oracle {eo.max():.2e}")
     B = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
-    pc.pc_sqrt_transpose_apply(plan.handle, 0, X, B)
+    pc.pc_sqrt_transpose_apply(cgplan.handle, 0, X, B)
     Y0 = torch.empty((R, KM), dtype=torch.float64, device=dev).t()
     pc.pc_mlp_warm_start(net.handle, B, Y0)
     e0 = np.linalg.norm(Y0.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)
     net.close()
-    plan.close()
-    out = {"metric": "learned warm start + CG: RHS/s at rel.err<=1e-8 vs the direct solve", "unit": "RHS/s",
-           "value": res["warm"]["rhs_per_s"], "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-           "dtype": "bf16 network, f64 CG",
-           "config": {"workload": wl.CONFIG_NAMES[5], "n": inst.n, "KM": KM, "heldout_rhs": R, "train_pairs": N,
-                      "hidden": h, "batch": batch, "epochs": args.epochs},
-           "factor_s": t_factor, "pairs_s": t_pairs, "train_s": t_train,
-           "train_tflops": train_flops / t_train / 1e12, "losses": losses,
-           "warm_start_rel_err_median": float(np.median(e0)),
-           "direct_apply_rhs_per_s": R / t_direct, "cg": res}
+    cgplan.close()
+    direct.close()
+    ok = all(not r["fallback_to_direct"] and r["rel_err_vs_oracle_max"] <= ACCEPT for r in res.values())
+    out = {"metric": "learned warm start + CG: RHS/s at rel.err<=1e-8 vs the FP64 oracle", "unit": "RHS/s",
+           "value": res["warm"]["rhs_per_s"] if ok else 0.0, "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "bf16 network, f64 CG",
+           "config": {"workload": wl.CONFIG_NAMES[5], "n": inst.n, "KM": KM, "heldout_rhs": R, "train_pairs": args.train,
+                      "validation_pairs": n_val, "hidden": h, "batch": batch, "max_steps": steps,
+                      "cg_preconditioner": f"FP64 Cholesky factor of the {args.cg_precision} Gram (rung {rung})"},
+           "factor_s": t_factor, "cg_factor_s": t_cg_factor, "pairs_s": t_pairs, "train_s": t_train,
+           "train_tflops": train_flops / t_train / 1e12, "validation_loss_best": best_val, "history": hist[-12:],
+           "warm_start_rel_err_median": float(np.median(e0)), "warm_start_rel_err_max": float(e0.max()),
+           "direct_apply_rhs_per_s": R / t_direct, "cg": res,
+           "iterations_saved": res["cold"]["cg_iterations"] - res["warm"]["cg_iterations"]}
     print(json.dumps(out))
     return 0
 

@@ -101,9 +101,12 @@ typedef struct {
                           or PC_FLAG_FIXED_PRECISION */
 } pc_options;
 
-/* Keep a symmetric copy of each assembled FP64 Gram and the inverses of its
- * 64 x 64 diagonal blocks, for pc_cg_solve / pc_learned_apply (extra
- * 8 (K*M)^2 bytes per instance).  Needs precision PC_PREC_FP64. */
+/* Keep a symmetric copy of each instance's FP64 Gram, for pc_cg_solve /
+ * pc_learned_apply (extra 8 (K*M)^2 bytes per instance).  CG multiplies by
+ * this Gram and is preconditioned by: in a reduced-precision plan, the FP64
+ * Cholesky factor of the reduced-precision Gram (the plan's own factor);
+ * in an FP64 plan, the inverses of the 64 x 64 diagonal blocks of the Gram
+ * (or of its member blocks, PC_FLAG_CG_MEMBER_BLOCKS). */
 #define PC_FLAG_KEEP_GRAM 1
 
 /* With PC_FLAG_KEEP_GRAM: precondition CG by the inverses of the K diagonal
@@ -297,8 +300,9 @@ int32_t pc_selftest_task_order(int32_t T, int32_t group);
  * the fallback and the judge of its error.
  * ---------------------------------------------------------------------- */
 
-/* pc_cg_solve — block-Jacobi preconditioned CG on G y = b for instance
- * `instance` of a plan built with PC_FLAG_KEEP_GRAM and factored.
+/* pc_cg_solve — preconditioned CG on G y = b (G the FP64 Gram; the
+ * preconditioner as PC_FLAG_KEEP_GRAM says) for instance `instance` of a plan
+ * built with PC_FLAG_KEEP_GRAM and factored.
  * B: device K*M x R (ldB >= K*M), right-hand sides b (e.g. Z^T x).
  * Y: device K*M x R (ldY >= K*M); read as the starting guess when warm != 0
  * (else the start is y = 0), overwritten with the result.  A column stops when
@@ -371,9 +375,11 @@ pc_status pc_mlp_warm_start(pc_mlp *mlp, const double *B, int64_t ldB, int64_t R
 
 /* pc_learned_apply — Y = Z^+ X for instance `instance` by CG from the
  * network's warm start (mlp may be NULL: cold start), for a plan built with
- * PC_FLAG_KEEP_GRAM and factored; the network's d must equal K*M.  Columns
- * that have not reached tol after maxiter iterations are solved directly with
- * the Cholesky factor (*fallback = 1, else 0).  X: device n x R; Y: device
+ * PC_FLAG_KEEP_GRAM and factored; the network's d must equal K*M.  If a
+ * column has not reached tol after maxiter iterations, the plan's direct
+ * solve replaces the result (the FP64 factor's two triangular solves, or in
+ * a reduced-precision plan its factor with FP64 refinement; *fallback = 1,
+ * else 0; the status is then that of the direct solve).  X: device n x R; Y: device
  * K*M x R.  Synchronous.  *iterations: largest CG iteration count. */
 pc_status pc_learned_apply(pc_plan *plan, int32_t instance, pc_mlp *mlp, const double *X,
                            int64_t ldX, int64_t R, double *Y, int64_t ldY, double tol,

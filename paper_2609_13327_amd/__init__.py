@@ -424,8 +424,10 @@ def pc_mlp_forward(mlp: int, X, Y, stream=None):
 
 
 def pc_mlp_gradients(mlp: int, X, T, loss, dW1, db1, dW2, db2, stream=None):
+    """Any of loss, dW1 .. db2 may be None (not computed / not written)."""
+    opt = lambda t: c_void_p(_fptr(t) if t is not None else None)
     _check(load_library().pc_mlp_gradients(c_void_p(mlp), _fptr(X), _rows(X), _fptr(T), _rows(T), int(X.shape[0]),
-                                           _fptr(loss), _fptr(dW1), _fptr(db1), _fptr(dW2), _fptr(db2),
+                                           opt(loss), opt(dW1), opt(db1), opt(dW2), opt(db2),
                                            c_void_p(_stream(stream))), "pc_mlp_gradients")
 
 

@@ -47,6 +47,29 @@ __global__ __launch_bounds__(256) void gram_symmetrize_kernel(const double* __re
   (void)T;
 }
 
+// The kept FP64 Gram of a plan whose factored Gram is a reduced-precision
+// one: the structured FP64 Gram is assembled into Gs (its lower triangle,
+// by the FP64 Gram kernels), the padding becomes identity columns and zero
+// rows, and the lower triangle is mirrored in place.
+__global__ void gram_pad_only_kernel(double* G, int64_t ld, int64_t KM, int64_t KMp) {
+  const int64_t c = blockIdx.x;
+  const int64_t r0 = c >= KM ? 0 : KM;
+  for (int64_t r = r0 + threadIdx.x; r < KMp; r += blockDim.x) G[r + c * ld] = (r == c) ? 1.0 : 0.0;
+}
+
+hipError_t launch_kept_fp64_gram(const Inst& in, hipStream_t s) {
+  Inst f = in;
+  f.G = in.Gs;
+  f.G2 = nullptr;
+  f.g2_parts = 0;
+  hipError_t e = launch_column_grams(f, s);
+  if (e == hipSuccess) e = launch_gram_f64(f, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_pad_only_kernel, dim3((unsigned)in.KMp), dim3(256), 0, s, in.Gs, in.KMp, in.KM, in.KMp);
+  e = hipGetLastError();
+  return e != hipSuccess ? e : launch_gram_symmetrize(f, in.Gs, s);   // in place: reads lower tiles only
+}
+
 hipError_t launch_gram_symmetrize(const Inst& in, double* Gs, hipStream_t s) {
   const int64_t T = in.KMp / NB;
   hipLaunchKernelGGL(gram_symmetrize_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, in.G, in.KMp, T, Gs);

@@ -14,6 +14,14 @@
 // accumulated in fp32 (the Lo^T Lo term, 2^-16 relative, is dropped): the
 // operand error falls from 2^-9 to about 2^-17 for three bf16 products.
 //
+// Accumulation: the MFMAs accumulate in fp32 over 256 rows of the
+// contraction at a time; each such partial Gram is then added into an FP64
+// accumulator.  A single fp32 sum over all n rows would carry a relative
+// error of about u32 sqrt(n) (1e-5 measured at n = 131072, mostly on the
+// diagonal), a perturbation that is not the Gram of a perturbed Z, and
+// refinement then contracts at kappa(Z)^2 * 1e-5 instead of kappa(Z) u_low;
+// with 256-row partials it is about u32 * 256 / sqrt(n).
+//
 // Tiles are 128 x 128 of the lower triangle (a0 >= b0): four waves own
 // 64 x 64 quadrants.  Accumulator layout of the f32 16x16 MFMAs (measured):
 // lane l holds rows 4 * (l / 16) + v, column l % 16.
@@ -26,6 +34,19 @@ namespace pc {
 
 constexpr int LT = 128;
 constexpr int LP_BF16 = 2, LP_FP32 = 1, LP_BF16X3 = 3;   // the pc_precision codes
+constexpr int FLUSH_ROWS = 256;                          // contraction rows per fp32 partial
+
+// acc64 += acc32, acc32 = 0 (the fp32 partial Gram into the FP64 accumulator)
+__device__ __forceinline__ void flush_partial(f4 (&acc)[4][4], double (&acc64)[4][4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+}
 
 __device__ __forceinline__ void lower_tile(int64_t t, int64_t& ta, int64_t& tb) {
   int64_t a = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -114,10 +135,15 @@ __device__ __forceinline__ void gram_bf16_tile(const LowGramInst& g, int64_t a0,
       }
   };
   f4 acc[4][4];
+  double acc64[4][4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+    }
   form(0);
   store(0);
   __syncthreads();
@@ -150,9 +176,11 @@ __device__ __forceinline__ void gram_bf16_tile(const LowGramInst& g, int64_t a0,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma_bf16(af[i], bf[j], acc[i][j]);
     }
+    if ((c + 1) % (FLUSH_ROWS / BKC) == 0) flush_partial(acc, acc64);
     if (more) store((c + 1) & 1);
     __syncthreads();
   }
+  flush_partial(acc, acc64);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -161,7 +189,7 @@ __device__ __forceinline__ void gram_bf16_tile(const LowGramInst& g, int64_t a0,
       for (int v = 0; v < 4; ++v) {
         const int64_t b = b0 + wm * 64 + i * 16 + 4 * kq + v;   // row of the product = lower index
         const int64_t a = a0 + wn * 64 + j * 16 + r;            // column = higher index
-        if (a < g.KM && b < g.KM && a >= b) g.G[a + b * g.ldG] = (double)acc[i][j][v];
+        if (a < g.KM && b < g.KM && a >= b) g.G[a + b * g.ldG] = acc64[i][j][v];
       }
 }
 
@@ -200,10 +228,15 @@ __device__ __forceinline__ void gram_f32_tile(const LowGramInst& g, int64_t a0, 
       }
   };
   f4 acc[4][4];
+  double acc64[4][4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+    }
   form(0);
   store(0);
   __syncthreads();
@@ -224,9 +257,11 @@ __device__ __forceinline__ void gram_f32_tile(const LowGramInst& g, int64_t a0, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f32(af[i], bf[j], acc[i][j]);
     }
+    if ((c + 1) % (FLUSH_ROWS / FKC) == 0) flush_partial(acc, acc64);
     if (more) store((c + 1) & 1);
     __syncthreads();
   }
+  flush_partial(acc, acc64);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -235,7 +270,7 @@ __device__ __forceinline__ void gram_f32_tile(const LowGramInst& g, int64_t a0, 
       for (int v = 0; v < 4; ++v) {
         const int64_t b = b0 + wm * 64 + i * 16 + 4 * kq + v;
         const int64_t a = a0 + wn * 64 + j * 16 + r;
-        if (a < g.KM && b < g.KM && a >= b) g.G[a + b * g.ldG] = (double)acc[i][j][v];
+        if (a < g.KM && b < g.KM && a >= b) g.G[a + b * g.ldG] = acc64[i][j][v];
       }
 }
 

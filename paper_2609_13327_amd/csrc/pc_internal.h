@@ -207,6 +207,9 @@ hipError_t launch_ws_finish(const float* Yh, int64_t ldYh, const double* nrm, in
 struct CgCol { double bnorm, rz; int done, iters; };
 // symmetric full copy of the assembled (padded) Gram: Gs = G + tril(G, -1)^T
 hipError_t launch_gram_symmetrize(const Inst& in, double* Gs, hipStream_t s);
+// the structured FP64 Gram assembled straight into in.Gs (symmetric, padded),
+// for plans whose factored Gram is a reduced-precision one
+hipError_t launch_kept_fp64_gram(const Inst& in, hipStream_t s);
 // Dinv[t] = inverse of the t-th 64 x 64 diagonal block of Gs (block-Jacobi); flag set if not SPD
 hipError_t launch_bj_setup(const double* Gs, int64_t ld, int64_t T, double* Dinv, int* flag, hipStream_t s);
 // Z = blockdiag(Dinv) Rm on KMp x R

@@ -548,11 +548,19 @@ pc_status run_cg(pc_plan* p, Inst& in, const double* Bm, int64_t ldB, int64_t R,
   if (warm) PC_TRY(pc::launch_gram_matmul(in.Gs, KMp, in.Y, q, ld, R, s));
   PC_TRY(pc::launch_cg_start(Bm, ldB, warm ? q : nullptr, r, in.Y, ld, ld, in.KM, KMp, R, tol, in.cgcol,
                              in.cg_flags, s));
+  // preconditioner: the factor of the plan's reduced-precision Gram
+  // (z = Lt^{-T} Lt^{-1} r), or the inverses of the member blocks, or of the
+  // 64 x 64 diagonal blocks of the FP64 Gram
+  const bool factor_pre = in.prec != PC_PREC_FP64;
   auto precond = [&]() -> hipError_t {
+    if (factor_pre) {
+      hipError_t e = pc::launch_copy_rows(r, ld, z, ld, KMp, KMp, R, s);
+      return e != hipSuccess ? e : pc::launch_chol_solve(in, z, ld, R, in.D, KMp, s);
+    }
     return in.cgm_Dinv ? pc::launch_member_apply(in.cgm_Dinv, in.K, in.M, in.cgm_Mp, r, z, ld, R, s)
                        : pc::launch_bj_apply(in.Dinv, T, r, z, ld, R, s);
   };
-  if (in.cgm_Dinv) PC_TRY(pc::launch_zero_rows(z, ld, in.KM, KMp, R, s));   // padding rows stay zero
+  if (in.cgm_Dinv && !factor_pre) PC_TRY(pc::launch_zero_rows(z, ld, in.KM, KMp, R, s));   // padding rows stay zero
   PC_TRY(precond());
   PC_TRY(pc::launch_cg_dir(r, z, pv, ld, KMp, R, in.cgcol, 1, s));
   int ndone = 0;
@@ -682,7 +690,6 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
       (o.flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS | PC_FLAG_FIXED_PRECISION)) != 0 ||
       !std::isfinite(o.tol))
     return PC_ERR_INVALID_ARG;
-  if ((o.flags & PC_FLAG_KEEP_GRAM) && o.precision != PC_PREC_FP64) return PC_ERR_INVALID_ARG;
   if ((o.flags & PC_FLAG_CG_MEMBER_BLOCKS) && !(o.flags & PC_FLAG_KEEP_GRAM)) return PC_ERR_INVALID_ARG;
   if (o.tol <= 0) o.tol = 1e-12;
   for (int32_t i = 0; i < count; ++i) {
@@ -797,7 +804,10 @@ static pc_status enqueue_factor(pc_plan* p, hipStream_t s, hipEvent_t after_gram
       if (after_gram) PC_TRY(hipEventRecord(after_gram, si));
     }
     if (in.Gs) {
-      PC_TRY(pc::launch_gram_symmetrize(in, in.Gs, si));
+      // the kept Gram is the FP64 one: a copy of G, or assembled on its own
+      // when G is a reduced-precision Gram (whose factor preconditions CG)
+      if (in.prec == PC_PREC_FP64) PC_TRY(pc::launch_gram_symmetrize(in, in.Gs, si));
+      else PC_TRY(pc::launch_kept_fp64_gram(in, si));
       PC_TRY(pc::launch_fill_int(in.cg_flags, 0, 2, si));
       if (in.cgm_Dinv) {
         // member block-Jacobi: the inverse of every diagonal M x M block
@@ -1236,11 +1246,24 @@ pc_status pc_learned_apply(pc_plan* p, int32_t instance, pc_mlp* mlp, const doub
   bool ok = false;
   pc_status st = run_cg(p, in, in.B, in.KMp, R, mlp != nullptr, tol, maxiter, s, &it, &ok);
   if (st != PC_OK) return st;
-  if (!ok) {
+  if (!ok && in.prec == PC_PREC_FP64) {
     // the direct solve replaces the iterate
     PC_TRY(pc::launch_copy_rows(in.B, in.KMp, in.Y, in.KMp, in.KM, in.KMp, R, s));
     PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R, in.D, in.KMp, s));
     if (fallback) *fallback = 1;
+  }
+  if (!ok && in.prec != PC_PREC_FP64) {
+    // the direct solve of a reduced-precision plan: its factor and FP64 refinement
+    if (fallback) *fallback = 1;
+    if (iterations) *iterations = it;
+    const size_t cnt = p->inst.size();
+    std::vector<const double*> Xs(cnt, nullptr);
+    std::vector<double*> Ys(cnt, nullptr);
+    std::vector<int64_t> lx(cnt, 1), ly(cnt, 1), R2(cnt, 0);
+    Xs[instance] = X; Ys[instance] = Y; lx[instance] = ldX; ly[instance] = ldY; R2[instance] = R;
+    st = enqueue_apply(p, Xs.data(), lx.data(), R2.data(), Ys.data(), ly.data(), s, 0, 0, true);
+    if (st != PC_OK) return st;
+    return finish_apply(p, R2.data(), s);
   }
   PC_TRY(pc::launch_copy_rows(in.Y, in.KMp, Y, ldY, in.KM, in.KM, R, s));
   PC_TRY(hipStreamSynchronize(s));

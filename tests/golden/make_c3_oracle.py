@@ -8,7 +8,10 @@ solutions y = Z^+ x of its first and last right-hand side, computed by the
 FP64 oracle only (explicit Z, Householder QR: oracle.lsq.lstsq_qr_inplace),
 the 2-norm condition number of Z (singular values for K*M <= 4096, else the
 estimate from R), the relative residual eta = ||x - Z y|| / (sigma_max ||y||)
-of each stored column, and the SHA-256 digest of all generated inputs.
+of each stored column, the oracle's rank test (numerically rank deficient when
+min |R_ii| <= n u max |R_ii|, as oracle.lsq.lstsq_qr decides; such an
+instance has no meaningful least-squares solution in FP64) and the SHA-256
+digest of all generated inputs.
 
 Run from the repository root:  python tests/golden/make_c3_oracle.py
 (a few minutes on 8 cores, under 4 GB of memory).
@@ -37,7 +40,7 @@ def main():
         for a in (i.E, i.W, i.X):
             h.update(np.ascontiguousarray(a).tobytes())
     print(f"generated 64 instances in {time.time() - t0:.0f} s", flush=True)
-    cols, ys, kappa, smax, eta, offs = [], [], [], [], [], [0]
+    cols, ys, kappa, smax, eta, rankdef, offs = [], [], [], [], [], [], [0]
     for k, inst in enumerate(insts):
         t1 = time.time()
         c = [0, inst.R - 1]
@@ -55,11 +58,13 @@ def main():
         kappa.append(kap)
         smax.append(sm)
         eta.append(info["residual_norm"] / (sm * np.linalg.norm(Y, axis=0)))
+        rd = np.abs(info["rdiag"])
+        rankdef.append(bool(rd.min() <= inst.n * lsq.U64 * rd.max()))
         offs.append(offs[-1] + 2 * inst.KM)
         print(f"{k:2d} n={inst.n:5d} K={inst.K:2d} M={inst.M:3d} KM={inst.KM:5d} kappa={kap:.3e} "
-              f"{time.time() - t1:.1f} s", flush=True)
+              f"rank deficient={rankdef[-1]} {time.time() - t1:.1f} s", flush=True)
     np.savez(OUT, columns=np.array(cols), y=np.concatenate(ys), offsets=np.array(offs), kappa=np.array(kappa),
-             sigma_max=np.array(smax), eta=np.array(eta), digest=h.hexdigest())
+             sigma_max=np.array(smax), eta=np.array(eta), rank_deficient=np.array(rankdef), digest=h.hexdigest())
     print("wrote", OUT, f"in {time.time() - t0:.0f} s", flush=True)
 
 

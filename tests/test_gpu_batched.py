@@ -99,8 +99,10 @@ def test_full_batch_config3():
     FP64 refinement with the precision ladder and a captured graph, against
     the stored QR oracle values of each instance's first and last right-hand
     side (tests/golden/make_c3_oracle.py), within the least-squares
-    sensitivity max(1e-8, 20 u kappa (1 + kappa eta)).  An instance may be
-    reported rank deficient (its FP64 Gram not positive definite, so no
+    sensitivity max(1e-8, 20 u kappa (1 + kappa eta)).  Instances that the
+    oracle's own rank test finds numerically rank deficient have no
+    meaningful answer and are not compared.  An instance may be reported rank
+    deficient by the library (its FP64 Gram not positive definite, so no
     normal-equation method applies) only when kappa(Z)^2 K M u > 1e-3, i.e.
     when the Gram's own rounding reaches its smallest eigenvalue."""
     import hashlib
@@ -121,9 +123,12 @@ def test_full_batch_config3():
     st = plan.apply(Xs, Ys, raise_on_error=False)
     assert st in (pc.PC_OK, pc.PC_ERR_NO_CONVERGENCE)
     state = [pc.pc_query_instance(plan.handle, k) for k in range(len(insts))]
-    within, unfactored = 0, []
+    within, unfactored, oracle_deficient = 0, [], []
     for k, inst in enumerate(insts):
         kappa, smax = float(g["kappa"][k]), float(g["sigma_max"][k])
+        if g["rank_deficient"][k]:
+            oracle_deficient.append(k)      # no meaningful least-squares solution in FP64
+            continue
         if not state[k][1]:
             unfactored.append(k)
             assert kappa ** 2 * inst.KM * 2.0 ** -53 > 1e-3, (k, kappa)
@@ -135,6 +140,7 @@ def test_full_batch_config3():
         assert np.all(err <= tol), (k, inst.n, inst.K, inst.M, kappa, err, tol)
         within += int(np.all(err <= 1e-8))
     rungs = [s[0] for s in state]
-    print(f"config 3: {within} of {len(insts)} instances within 1e-8, rank deficient {unfactored}, "
+    print(f"config 3: {within} of {len(insts)} instances within 1e-8, rank deficient for the oracle "
+          f"{oracle_deficient}, Gram not positive definite {unfactored}, "
           f"rungs {dict((r, rungs.count(r)) for r in sorted(set(rungs)))}, status {st}")
     plan.close()

@@ -160,9 +160,6 @@ def test_cg_and_learned_apply_argument_checks():
     st, _ = pc.pc_cg_solve(plain.handle, 0, B, B, 1e-10, 10, raise_on_error=False)
     assert st == pc.PC_ERR_INVALID_ARG
     plain.close()
-    with pytest.raises(pc.PcError) as e:
-        pc.Plan([inst_dict(inst)], precision=pc.PC_PREC_FP32_REFINE, max_refine=5, flags=pc.PC_FLAG_KEEP_GRAM)
-    assert e.value.status == pc.PC_ERR_INVALID_ARG
     keep = pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_KEEP_GRAM)
     st, _ = pc.pc_cg_solve(keep.handle, 0, B, B, 1e-10, 10, raise_on_error=False)
     assert st == pc.PC_ERR_NOT_FACTORED
@@ -173,6 +170,32 @@ def test_cg_and_learned_apply_argument_checks():
     assert e.value.status == pc.PC_ERR_INVALID_ARG
     net.close()
     keep.close()
+
+
+@pytest.mark.parametrize("precision", [pc.PC_PREC_BF16_REFINE, pc.PC_PREC_FP32_REFINE])
+def test_cg_preconditioned_by_reduced_precision_factor(precision):
+    """A reduced-precision plan that keeps the Gram: CG multiplies by the kept
+    FP64 Gram and is preconditioned by the plan's factor of the rounded Z's
+    Gram; it converges in a few iterations to the oracle's answer, and with
+    too few iterations the plan's own solve (factor + FP64 refinement) is the
+    fallback, also at the oracle's answer."""
+    inst = _cg_instance(16)
+    plan = pc.Plan([inst_dict(inst)], precision=precision, max_refine=30, tol=1e-13, flags=pc.PC_FLAG_KEEP_GRAM)
+    plan.factor()
+    B = empty(inst.KM, inst.R)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, dev(inst.X), B)
+    Y = empty(inst.KM, inst.R)
+    st, it = pc.pc_cg_solve(plan.handle, 0, B, Y, tol=1e-13, maxiter=100)
+    assert st == pc.PC_OK and it <= 30, it
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    err = np.linalg.norm(host(Y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-9, err.max()
+    Y2 = empty(inst.KM, inst.R)
+    it2, fb = pc.pc_learned_apply(plan.handle, 0, None, dev(inst.X), Y2, 1e-14, 1)
+    assert fb == 1 and it2 == 1
+    err = np.linalg.norm(host(Y2) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-8, err.max()
+    plan.close()
 
 
 def test_warm_start_and_training_pairs_match_oracle():
@@ -313,3 +336,62 @@ def test_member_blocks_need_kept_gram():
     with pytest.raises(pc.PcError) as e:
         pc.Plan([inst_dict(inst)], flags=pc.PC_FLAG_CG_MEMBER_BLOCKS)
     assert e.value.status == pc.PC_ERR_INVALID_ARG
+
+
+def test_learned_warm_start_at_full_size():
+    """The largest workload's shapes (131072 x 32768, network 32768 -> 1024 ->
+    32768): CG on the kept FP64 Gram, preconditioned by the FP64 factor of the
+    bf16 Gram, converges on held-out right-hand sides (the 8 with stored
+    oracle values) with no fallback, from zero and from the warm start of a
+    network trained on 4096 pairs from the FP64 direct solve with early
+    stopping on 512 more; both answers are within 1e-8 of the oracle and of
+    the direct solve.  The kept network is never worse than the zero start on
+    the held-out pairs (validation loss <= 1, the zero start's), and CG from
+    its prediction takes no more iterations.  (At this size the network does
+    not generalize: every validation loss it reaches is above the zero
+    start's, so early stopping keeps the zero-output network; the gain where
+    it can represent the map is shown at 16 x 32 above.)"""
+    import hashlib
+    import os
+    from paper_2609_13327_amd import learned as lrn
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_oracle.npz"))
+    inst = wl.config(4)
+    for name, a in (("E", inst.E), ("W", inst.W), ("X", inst.X)):
+        assert hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest() == str(g["digest_" + name])
+    d = inst_dict(inst, max_rhs=1024)
+    direct = pc.Plan([d])
+    direct.factor()
+    cgplan = pc.Plan([d], precision=pc.PC_PREC_BF16_REFINE, max_refine=30, tol=1e-12, flags=pc.PC_FLAG_KEEP_GRAM)
+    cgplan.factor()
+    Xin, Tin = lrn.make_pairs(direct, inst.n, inst.KM, 4096 + 512, 5000)
+    net = lrn.new_network(inst.KM, 1024, 256, 5001, pc.PC_MLP_BF16)
+    best_val, hist = lrn.train(net, Xin, Tin, 512, batch=256, lr=1e-3, max_steps=200, eval_every=25)
+    del Xin, Tin
+    cols = list(g["columns"])
+    X = dev(inst.X[:, cols])
+    Yd = empty(inst.KM, len(cols))
+    direct.apply([X], [Yd])
+    yd = host(Yd)
+    its = {}
+    for name, m in (("cold", None), ("warm", net.handle)):
+        Y = empty(inst.KM, len(cols))
+        it, fb = pc.pc_learned_apply(cgplan.handle, 0, m, X, Y, 1e-11, 200)
+        y = host(Y)
+        e_or = np.linalg.norm(y - g["Y"], axis=0) / np.linalg.norm(g["Y"], axis=0)
+        e_d = np.linalg.norm(y - yd, axis=0) / np.linalg.norm(yd, axis=0)
+        print(f"{name}: {it} CG iterations, fallback {fb}, max rel err vs oracle {e_or.max():.2e}, "
+              f"vs direct {e_d.max():.2e}")
+        assert fb == 0
+        assert e_or.max() <= 1e-8 and e_d.max() <= 1e-8
+        its[name] = it
+    B = empty(inst.KM, len(cols))
+    pc.pc_sqrt_transpose_apply(cgplan.handle, 0, X, B)
+    Y0 = empty(inst.KM, len(cols))
+    pc.pc_mlp_warm_start(net.handle, B, Y0)
+    e0 = np.linalg.norm(host(Y0) - yd, axis=0) / np.linalg.norm(yd, axis=0)
+    print("validation loss", best_val, "history", hist, "warm-start rel err", np.round(e0, 4), "iterations", its)
+    assert best_val <= 1.0 and np.all(e0 <= 1.0 + 1e-6)
+    assert its["warm"] <= its["cold"]
+    net.close()
+    cgplan.close()
+    direct.close()
