@@ -2,7 +2,7 @@
 //
 // A "problem" type P supplies the tile geometry and how operand chunks are
 // formed; the loop double-buffers the chunks in LDS (one barrier per chunk):
-//   P::BM, P::BN  workgroup tile (rows x cols), P::WM x P::WN waves
+//   P::BM, P::BN  workgroup tile (rows x cols), P::WM x P::WN waves (64 P::WM P::WN threads)
 //   P::KC         contraction rows per chunk (multiple of 4)
 //   P::LDA/LDB    LDS row strides (>= BM / BN)
 //   struct Ctx    per-tile state; P::ctx(tile_index) builds it (valid=false skips)
@@ -45,8 +45,9 @@ __device__ __forceinline__ void gemm_tile_f64(const P& prob, const typename P::C
   }
 }
 
+// P::WM * P::WN waves per workgroup (64 * WM * WN threads)
 template <class P>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(P prob) {
+__global__ __launch_bounds__(64 * P::WM * P::WN) void gemm_f64_kernel(P prob) {
   __shared__ double As[2 * P::KC * P::LDA];
   __shared__ double Bs[2 * P::KC * P::LDB];
   const typename P::Ctx ctx = prob.ctx(blockIdx.x);

@@ -3,9 +3,12 @@
 //   C(i, j) = alpha sum_k A(i, k) B(j, k)            (overwrite), or
 //   C(i, j) = C(i, j) + alpha sum_k A(i, k) B(j, k)  (accumulate),
 // optionally on the lower triangle only (tiles with i >= j; inside a
-// diagonal tile only i >= j is written).  128 x 128 workgroup tiles, four
-// waves of 64 x 64, contraction staged through LDS 16 columns at a time;
-// both operands are read along their columns (coalesced).
+// diagonal tile only i >= j is written).  Waves own 64 x 64 sub-tiles; the
+// contraction is staged through LDS 16 columns at a time; both operands are
+// read along their columns (coalesced).  Large products use 256 x 128
+// workgroup tiles (8 waves, two per SIMD): a third less operand traffic per
+// flop than 128 x 128 (four waves), and the second wave on each SIMD hides
+// the latency of the staged loads.
 #include "pc_common.h"
 #include "pc_internal.h"
 #include "gemm_core.h"
@@ -14,10 +17,15 @@
 
 namespace pc {
 
+template <int BM_, int BN_, int WM_, int WN_>
 struct NtGemmProb {
-  static constexpr int BM = 128, BN = 128, WM = 2, WN = 2, KC = 16;
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = 16;
+  static constexpr int NT = 64 * WM * WN;          // threads
   static constexpr int LDA = BM + 8, LDB = BN + 8;
-  static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
+  static constexpr int NA = BM * KC / NT, NB_ = BN * KC / NT;
+  static constexpr int RT = BM / BN;              // column tiles per row tile (lower-triangle mode)
+  static_assert(NA >= 1 && NB_ >= 1 && BM * KC % NT == 0 && BN * KC % NT == 0, "tile / thread mismatch");
+  static_assert(BM % BN == 0, "row tiles must cover whole column tiles");
   const double* A; int64_t lda;
   const double* B; int64_t ldb;
   double* C; int64_t ldc;
@@ -37,10 +45,12 @@ struct NtGemmProb {
     c.valid = u < ntiles;
     int64_t ti, tj;
     if (lower) {
-      ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
-      while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
-      while (ti * (ti + 1) / 2 > u) --ti;
-      tj = u - ti * (ti + 1) / 2;
+      // tile row ti holds the RT (ti + 1) column tiles that reach the lower
+      // triangle (RT = BM / BN); rows before it hold RT ti (ti + 1) / 2
+      ti = (int64_t)((sqrt(8.0 * (double)u / RT + 1.0) - 1.0) * 0.5);
+      while (RT * (ti + 1) * (ti + 2) / 2 <= u) ++ti;
+      while (RT * ti * (ti + 1) / 2 > u) --ti;
+      tj = u - RT * ti * (ti + 1) / 2;
     } else {
       ti = u % tm;
       tj = u / tm;
@@ -53,7 +63,7 @@ struct NtGemmProb {
   __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + 256 * q, row = e % BM, kk = e / BM;
+      const int e = threadIdx.x + NT * q, row = e % BM, kk = e / BM;
       const int64_t i = c.i0 + row, k = (int64_t)chunk * KC + kk;
       r.v[q] = (i < M && k < K) ? A[i + k * lda] : 0.0;
     }
@@ -61,14 +71,14 @@ struct NtGemmProb {
   __device__ void storeA(const ARegs& r, double* As) const {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + 256 * q;
+      const int e = threadIdx.x + NT * q;
       As[(e / BM) * LDA + e % BM] = r.v[q];
     }
   }
   __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
 #pragma unroll
     for (int q = 0; q < NB_; ++q) {
-      const int e = threadIdx.x + 256 * q, col = e % BN, kk = e / BN;
+      const int e = threadIdx.x + NT * q, col = e % BN, kk = e / BN;
       const int64_t j = c.j0 + col, k = (int64_t)chunk * KC + kk;
       r.v[q] = (j < N && k < K) ? B[j + k * ldb] : 0.0;
     }
@@ -76,7 +86,7 @@ struct NtGemmProb {
   __device__ void storeB(const BRegs& r, double* Bs) const {
 #pragma unroll
     for (int q = 0; q < NB_; ++q) {
-      const int e = threadIdx.x + 256 * q;
+      const int e = threadIdx.x + NT * q;
       Bs[(e / BN) * LDB + e % BN] = r.v[q];
     }
   }
@@ -90,18 +100,32 @@ struct NtGemmProb {
   }
 };
 
+using NtGemm128 = NtGemmProb<128, 128, 2, 2>;
+using NtGemm256 = NtGemmProb<256, 128, 4, 2>;
+
+template <class P>
+static hipError_t run_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                              int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower,
+                              hipStream_t s) {
+  P g;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower;
+  g.tm = ceil_div(M, P::BM);
+  g.tn = ceil_div(N, P::BN);
+  g.ntiles = lower ? P::RT * g.tm * (g.tm + 1) / 2 : g.tm * g.tn;
+  const int64_t grid = 8 * ((g.ntiles + 7) / 8);
+  hipLaunchKernelGGL(gemm_f64_kernel<P>, dim3((unsigned)grid), dim3(P::NT), 0, s, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                           int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  NtGemmProb g;
-  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
-  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower;
-  g.tm = ceil_div(M, NtGemmProb::BM);
-  g.tn = ceil_div(N, NtGemmProb::BN);
-  g.ntiles = lower ? g.tm * (g.tm + 1) / 2 : g.tm * g.tn;
-  const int64_t grid = 8 * ((g.ntiles + 7) / 8);
-  hipLaunchKernelGGL(gemm_f64_kernel<NtGemmProb>, dim3((unsigned)grid), dim3(256), 0, s, g);
-  return hipGetLastError();
+  // 256 x 128 tiles once there are enough of them to fill the device twice
+  const int64_t t256 = lower ? ceil_div(M, 256) * (ceil_div(M, 256) + 1) : ceil_div(M, 256) * ceil_div(N, 128);
+  if (t256 >= 512)
+    return run_nt_gemm<NtGemm256>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
+  return run_nt_gemm<NtGemm128>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
 }
 
 // dst (rows x cols, ld ldd) = src (ld lds)
