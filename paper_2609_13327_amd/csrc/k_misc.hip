@@ -79,8 +79,8 @@ hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const do
 // last / previous estimates what further iterations could still change:
 // last * rho / (1 - rho) for rho < 1, else last (the updates fluctuate at the
 // attainable accuracy of the FP64 residual).  The result is accepted
-// (done = 1) if that estimate is at most `accept` and reported as stalled
-// above it (done = 2) otherwise.  It is reported as diverging (done = 3) when
+// (done = 1) if that estimate is at most `accept` and rho < 0.9, and
+// reported as stalled (done = 2) otherwise.  It is reported as diverging (done = 3) when
 // the update is not finite, or is growing and already as large as y itself
 // (at the attainable accuracy the updates fluctuate in size, so growth
 // alone does not mean divergence).
@@ -99,7 +99,10 @@ __global__ void refine_check_kernel(RefineCtl* ctl, double tol, double accept) {
     if (++ctl->stall >= 2) {
       const double rho = worst / ctl->prev;
       const double est = rho < 1.0 ? worst * rho / (1.0 - rho) : worst;
-      ctl->done = est <= accept ? 1 : 2;
+      // a ratio near 1 (a preconditioner far from the Gram, as for a
+      // rounded Z that is much better conditioned than Z itself) cannot
+      // bound the remaining change: not accepted however small the update
+      ctl->done = (est <= accept && rho < 0.9) ? 1 : 2;
     }
   } else {
     ctl->stall = 0;

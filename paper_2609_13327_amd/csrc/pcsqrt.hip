@@ -49,8 +49,11 @@ static constexpr double kStallAccept = 1e-9;
 
 // Grams of order above this are factored by block columns of 1024, each block
 // by the tile DAG (the DAG alone has one diagonal step per 64 rows on its
-// critical path).
+// critical path).  In a plan of several instances the factorizations of all
+// of them form one persistent tile-DAG launch, whose chains overlap, up to
+// the larger order kBatchDagUpTo.
 static constexpr int64_t kBlockedAbove = 8192;
+static constexpr int64_t kBatchDagUpTo = 16384;
 
 struct pc_plan {
   std::vector<Inst> inst;
@@ -201,7 +204,7 @@ pc_status alloc_blocked(Inst& in, int64_t NO) {
   return PC_OK;
 }
 
-pc_status alloc_inst(Inst& in, int precision, int flags) {
+pc_status alloc_inst(Inst& in, int precision, int flags, bool batched) {
   const int64_t KMp = in.KMp, nblk = KMp / pc::NB, R = std::max<int64_t>(in.max_rhs, 1);
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
@@ -230,7 +233,7 @@ pc_status alloc_inst(Inst& in, int precision, int flags) {
   std::vector<int64_t> offs;
   in.chol_ntasks = pc::chol_task_offsets((int)T, offs);
   chk(dalloc(&in.chol_offs, (int64_t)offs.size()));
-  if (KMp > kBlockedAbove && e == hipSuccess) {
+  if (KMp > (batched ? kBatchDagUpTo : kBlockedAbove) && e == hipSuccess) {
     const pc_status bs = alloc_blocked(in, 1024);
     if (bs != PC_OK) return bs;
   } else {
@@ -716,7 +719,7 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
     in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
     in.prec = o.precision;
     p->inst.push_back(in);
-    st = alloc_inst(p->inst.back(), o.precision, o.flags);
+    st = alloc_inst(p->inst.back(), o.precision, o.flags, count > 1);
     max_r = std::max<int64_t>(max_r, a.max_rhs);
   }
   (void)max_r;
