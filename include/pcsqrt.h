@@ -386,6 +386,48 @@ pc_status pc_learned_apply(pc_plan *plan, int32_t instance, pc_mlp *mlp, const d
                            int32_t maxiter, int32_t *iterations, int32_t *fallback, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's own left inverse for the square case n_w = K.
+ * ---------------------------------------------------------------------- */
+
+/* With as many levels (or variable kinds) per grid column as members,
+ * n_w = K, the per-column blocks A_m of the member matrix are square and the
+ * paper's left inverse (Sec. 3.9, eq. InverseSquareRootSwift; steps V1-V5 of
+ * Sec. 3.10) applies:
+ *   V1   w^(m) = A_m^{-1} x^(m) for every grid column m, where
+ *        A_m[l, k] = E[l*n_h + m, k] (K x K) and x^(m)[l] = x[l*n_h + m];
+ *   V2-3 w_k = (w^(0)_k, ..., w^(n_h-1)_k) for every member k;
+ *   V4   x~_k = Delta_b^{-1/2} V_b^T w_k;
+ *   V5   x~ = (x~_0; ...; x~_{K-1}): row k*L + l of the output.
+ * It is a left inverse of Z = [diag(z_k) V_b Delta_b^{1/2}] (Z is n x K*L,
+ * n = n_h*K): it equals the Moore-Penrose Z^+ on range(Z), and everywhere
+ * when L = n_h (Z square).  The paper factors A_m by SVD; here A_m is
+ * inverted once, at build time, by Gauss-Jordan elimination with partial
+ * pivoting (the same A_m^{-1} up to rounding). */
+typedef struct pc_swift pc_swift;
+
+/* pc_swift_build — validate, allocate the workspace (n_h*K^2 + n_h*K*max_rhs
+ * + L doubles) and invert every A_m (one stream sync).
+ * E: device, n_h*K x K column-major (ldE >= n_h*K), the scaled members in
+ * segment order (row l*n_h + m: level l of grid column m); borrowed, kept
+ * alive by the caller.  Vb: device, n_h x L column-major (ldV >= n_h), the
+ * orthonormal eigenvectors of the localization block; borrowed.  delta:
+ * device, L positive eigenvalues (read at build time).  Needs K <= 64 and
+ * L <= n_h (PC_ERR_SHAPE otherwise).  Returns PC_ERR_NOT_SPD if some A_m is
+ * singular to working precision (a pivot |p| <= K u max|A_m|: A, and Z,
+ * have no inverse), PC_ERR_INVALID_ARG for a non-positive eigenvalue. */
+pc_status pc_swift_build(int64_t n_h, int64_t K, int64_t L, const double *E, int64_t ldE, const double *Vb,
+                         int64_t ldV, const double *delta, int64_t max_rhs, void *stream, pc_swift **out);
+
+/* pc_swift_apply — Y = (paper's left inverse) X for R <= max_rhs columns.
+ * X: device n_h*K x R (ldX >= n_h*K); Y: device K*L x R (ldY >= K*L).
+ * Asynchronous. */
+pc_status pc_swift_apply(pc_swift *s, const double *X, int64_t ldX, int64_t R, double *Y, int64_t ldY,
+                         void *stream);
+
+/* pc_swift_destroy — free the workspace (synchronizes the device).  NULL is accepted. */
+pc_status pc_swift_destroy(pc_swift *s);
+
+/* ------------------------------------------------------------------------
  * Allocation-free entry point.
  * ---------------------------------------------------------------------- */
 

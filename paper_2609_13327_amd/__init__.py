@@ -49,6 +49,7 @@ EXPORTED = [
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
     "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance",
+    "pc_swift_build", "pc_swift_apply", "pc_swift_destroy",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout", "solve_alongside"]
@@ -134,6 +135,10 @@ def load_library(path: str = LIB_PATH):
                                     POINTER(c_int32)]
     lib.pc_learned_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                      c_double, c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p]
+    lib.pc_swift_build.argtypes = [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                   c_int64, c_void_p, POINTER(c_void_p)]
+    lib.pc_swift_apply.argtypes = [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p]
+    lib.pc_swift_destroy.argtypes = [c_void_p]
     lib.pc_query_instance.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
     lib.pc_factor_apply_noalloc.argtypes = [POINTER(PcInstance), c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                             c_void_p]
@@ -471,6 +476,54 @@ def pc_query_tuning(plan: int, instance: int = 0, with_block: bool = False):
 
 
 # -------------------------------------------------------------- convenience
+def pc_swift_build(E, Vb, delta, max_rhs: int, stream=None) -> int:
+    """The paper's left inverse for n_w = K.  E: column-major float64 device
+    tensor (n_h*K, K); Vb: (n_h, L); delta: float64 device vector (L,)."""
+    import torch
+    n_h, L = int(Vb.shape[0]), int(Vb.shape[1])
+    K = int(E.shape[1])
+    if E.shape[0] != n_h * K:
+        raise ValueError("E must have n_h * K rows (n_w = K)")
+    if delta.dtype != torch.float64 or not delta.is_cuda or delta.numel() != L or not delta.is_contiguous():
+        raise ValueError("delta: contiguous float64 device vector of L eigenvalues")
+    h = c_void_p()
+    _check(load_library().pc_swift_build(n_h, K, L, _ptr(E), _ld(E), _ptr(Vb), _ld(Vb), delta.data_ptr(),
+                                         int(max_rhs), c_void_p(_stream(stream)), ctypes.byref(h)), "pc_swift_build")
+    return h.value
+
+
+def pc_swift_apply(handle: int, X, Y, stream=None):
+    _check(load_library().pc_swift_apply(c_void_p(handle), _ptr(X), _ld(X), int(X.shape[1]), _ptr(Y), _ld(Y),
+                                         c_void_p(_stream(stream))), "pc_swift_apply")
+
+
+def pc_swift_destroy(handle: Optional[int]):
+    _check(load_library().pc_swift_destroy(c_void_p(handle)), "pc_swift_destroy")
+
+
+class Swift:
+    """Owns a pc_swift handle and keeps its borrowed V_b tensor alive (E is
+    only read at build time, V_b at every apply)."""
+
+    def __init__(self, E, Vb, delta, max_rhs: int, stream=None):
+        self._keep = (E, Vb, delta)
+        self.handle = pc_swift_build(E, Vb, delta, max_rhs, stream)
+
+    def apply(self, X, Y, stream=None):
+        pc_swift_apply(self.handle, X, Y, stream)
+
+    def close(self):
+        if self.handle:
+            pc_swift_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """Owns a plan and keeps its borrowed E/W tensors alive."""
 
