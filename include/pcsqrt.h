@@ -94,8 +94,10 @@ typedef struct {
   int32_t precision;   /* a pc_precision value */
   int32_t max_refine;  /* refinement iterations allowed; in PC_PREC_FP64 these are
                           corrected semi-normal steps (0 = plain normal equations) */
-  double tol;          /* refinement stops for a right-hand side when
-                          max|delta| <= tol * max|y|; <= 0 selects 1e-12 */
+  double tol;          /* each right-hand side stops refining on its own once
+                          max|delta| <= tol * max|y| over its column (later
+                          iterations leave its column of Y unchanged); <= 0
+                          selects 1e-12 */
   int32_t use_graph;   /* 1: capture the apply sequence in a hipGraph and replay it */
   int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM (optionally with PC_FLAG_CG_MEMBER_BLOCKS),
                           or PC_FLAG_FIXED_PRECISION */
@@ -146,8 +148,18 @@ pc_status pc_gram_factor(pc_plan *plan, void *stream, int32_t *failed_instance);
  * R[i] = 0 skips instance i.  Asynchronous in FP64 mode without refinement;
  * with refinement the convergence test runs on the device and the host
  * reads its flags every two iterations (without a graph) or once at the
- * end.  Returns PC_ERR_NO_CONVERGENCE (Y holds the last iterate) if the
- * budget ends before the tolerance is met. */
+ * end.  Every right-hand side follows its own stop rule: it converges at
+ * tol; when its updates stop shrinking (two iterations in a row with less
+ * than a halving), it is accepted if the geometric estimate of what further
+ * iterations could change, last * rho / (1 - rho) with rho the last ratio of
+ * successive updates, is at most 1e-8 * max|y| and rho < 0.9, and counted
+ * as stalled otherwise; it diverges when an update is not finite or grows
+ * while at least max|y|.  An instance is done when none of its right-hand
+ * sides still runs.  Returns PC_ERR_NO_CONVERGENCE (Y holds the last
+ * iterates) if a right-hand side ran out of budget, diverged, or stalled in
+ * a reduced-precision plan (an FP64 plan accepts a stall: the updates then
+ * fluctuate at the attainable accuracy of the FP64 residual);
+ * pc_query_rhs_info tells which. */
 pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int64_t *ldX,
                                 const int64_t *R, double *const *Y, const int64_t *ldY,
                                 void *stream);
@@ -170,10 +182,26 @@ pc_status pc_factor_apply(pc_plan *plan, const double *const *X, const int64_t *
                           void *stream, int32_t *failed_instance);
 
 /* pc_query_info — after an apply and a stream sync: iterations used by the
- * last apply (max over its right-hand sides) and its final max|delta|/max|y|,
- * for instance `instance`.  Either output pointer may be NULL. */
+ * last apply (max over its right-hand sides) and its final max|delta|/max|y|
+ * (max over the right-hand sides still running at the last iteration), for
+ * instance `instance`.  Either output pointer may be NULL. */
 pc_status pc_query_info(const pc_plan *plan, int32_t instance, int32_t *iterations,
                         double *last_rel_update);
+
+/* Refinement outcome of one right-hand side. */
+typedef struct {
+  int32_t iterations;      /* refinement updates applied to this column of Y */
+  int32_t state;           /* 0 budget spent while running, 1 converged or accepted,
+                              2 stalled above the acceptance level, 3 diverging */
+  double last_rel_update;  /* max|delta| / max|y| of its last update (0 if none) */
+} pc_rhs_info;
+
+/* pc_query_rhs_info — per-right-hand-side outcome of the last apply of
+ * instance `instance` (pc_left_inverse_apply or pc_factor_apply, after it
+ * returned): out[r] for r < R, out a HOST array of R entries.  R may not
+ * exceed that apply's R[instance] (PC_ERR_INVALID_ARG).  Without refinement
+ * (max_refine = 0) every entry is {0, 1, 0}. */
+pc_status pc_query_rhs_info(const pc_plan *plan, int32_t instance, int64_t R, pc_rhs_info *out);
 
 /* pc_query_instance — state of instance `instance` after pc_gram_factor:
  * *precision (may be NULL) receives the precision (a pc_precision value) of
@@ -202,7 +230,7 @@ pc_status pc_sqrt_transpose_apply(pc_plan *plan, int32_t instance, const double 
                                   int64_t R, double *B, int64_t ldB, void *stream);
 
 /* pc_sqrt_apply — X = Z Y, the back-transform to model variables
- * (x = (P^c)^{1/2} x~, Sec. 2.3).  Y: device K*M x R; X: device n x R. */
+ * (x = (P^c)^{1/2} x~, Sec. 2.2).  Y: device K*M x R; X: device n x R. */
 pc_status pc_sqrt_apply(pc_plan *plan, int32_t instance, const double *Y, int64_t ldY,
                         int64_t R, double *X, int64_t ldX, void *stream);
 
@@ -225,7 +253,8 @@ pc_status pc_gram_export(const pc_plan *plan, int32_t instance, double *G, int64
 
 /* pc_autotune — for every instance, time the candidate launch shapes on the
  * plan's own data and keep the fastest: the FP64 Gram's contraction split
- * (1 or 2 parts), the Z^T x contraction split (1 or 2) and the persistent
+ * (1 to 2 parts, 1 to 4 where the Gram has few tiles), the Z^T x
+ * contraction split (1 or 2) and the persistent
  * Cholesky grid (1 or 2 workgroups per compute unit; one choice for a plan
  * with several instances, whose factorization is one launch).  Choices are
  * kept in the plan.  cache_path (host string, may be NULL) names a text file

@@ -48,7 +48,7 @@ EXPORTED = [
     "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
-    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance",
+    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance", "pc_query_rhs_info",
     "pc_swift_build", "pc_swift_apply", "pc_swift_destroy",
 ]
 
@@ -59,6 +59,10 @@ class PcInstance(ctypes.Structure):
     _fields_ = [("n_h", c_int64), ("n_w", c_int64), ("K", c_int64), ("M", c_int64),
                 ("E", c_void_p), ("ldE", c_int64), ("W", c_void_p), ("ldW", c_int64),
                 ("max_rhs", c_int64)]
+
+
+class PcRhsInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("state", c_int32), ("last_rel_update", c_double)]
 
 
 class PcOptions(ctypes.Structure):
@@ -140,6 +144,7 @@ def load_library(path: str = LIB_PATH):
     lib.pc_swift_apply.argtypes = [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p]
     lib.pc_swift_destroy.argtypes = [c_void_p]
     lib.pc_query_instance.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
+    lib.pc_query_rhs_info.argtypes = [c_void_p, c_int32, c_int64, POINTER(PcRhsInfo)]
     lib.pc_factor_apply_noalloc.argtypes = [POINTER(PcInstance), c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                             c_void_p]
     for name in EXPORTED:
@@ -328,6 +333,15 @@ def pc_query_instance(plan: int, instance: int = 0):
     _check(load_library().pc_query_instance(c_void_p(plan), int(instance), ctypes.byref(pr), ctypes.byref(fa)),
            "pc_query_instance")
     return pr.value, bool(fa.value)
+
+
+def pc_query_rhs_info(plan: int, instance: int, R: int):
+    """Per-right-hand-side refinement outcome of the instance's last apply:
+    a list of R (iterations, state, last relative update), state 0 budget
+    spent, 1 converged, 2 stalled, 3 diverging."""
+    out = (PcRhsInfo * max(int(R), 1))()
+    _check(load_library().pc_query_rhs_info(c_void_p(plan), int(instance), int(R), out), "pc_query_rhs_info")
+    return [(out[r].iterations, out[r].state, out[r].last_rel_update) for r in range(int(R))]
 
 
 def pc_plan_destroy(plan: Optional[int]):

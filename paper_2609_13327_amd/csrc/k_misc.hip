@@ -23,29 +23,68 @@ hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t
   return hipGetLastError();
 }
 
-__global__ void refine_init_kernel(RefineCtl* ctl, int budget) {
-  ctl->done = budget > 0 ? 0 : 1;
-  ctl->iters = 0;
-  ctl->stall = 0;
-  ctl->worst = 0ULL;
-  ctl->last = 0.0;
-  ctl->prev = 0.0;
+__global__ void refine_init_kernel(RefineCtl* ctl, RhsCtl* rhs, int64_t R, int budget) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl->done = budget > 0 ? 0 : 1;
+    ctl->iters = 0;
+    ctl->running = 0;
+    ctl->stops = 0;
+    ctl->worst = 0ULL;
+    ctl->last = 0.0;
+    ctl->prev = 0.0;
+  }
+  if (i < R) rhs[i] = RhsCtl{budget > 0 ? 0 : 1, 0, 0, 0, 0.0, 0.0};
 }
 
-hipError_t launch_refine_init(RefineCtl* ctl, int budget, hipStream_t s) {
-  hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(1), 0, s, ctl, budget);
+hipError_t launch_refine_init(RefineCtl* ctl, RhsCtl* rhs, int64_t R, int budget, hipStream_t s) {
+  const int64_t n = std::max<int64_t>(R, 1);
+  hipLaunchKernelGGL(refine_init_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, ctl, rhs, R, budget);
   return hipGetLastError();
 }
 
-// Y[:, r] += D[:, r] over the first KM rows, and max over r of
-// max|D[:, r]| / max|Y_new[:, r]| into ctl->worst (the bit patterns of
-// non-negative doubles order like the values).  One workgroup per rhs.
+// The stop rule of one right-hand side after an update of relative size rel
+// = max|delta| / max|y|.  Stop at the tolerance, or once the updates stop
+// shrinking (two iterations in a row with less than a halving): then the
+// contraction ratio rho = last / previous estimates what further iterations
+// could still change, last * rho / (1 - rho) for rho < 1, else last (the
+// updates fluctuate at the attainable accuracy of the FP64 residual).  The
+// result is accepted (1) if that estimate is at most `accept` and rho < 0.9
+// (a ratio near 1, from a preconditioner far from the Gram, as for a rounded
+// Z much better conditioned than Z, cannot bound the remaining change), and
+// reported as stalled (2) otherwise.  It is diverging (3) when the update is
+// not finite, or is growing and already as large as y (at the attainable
+// accuracy the updates fluctuate in size, so growth alone does not mean
+// divergence).
+__device__ __forceinline__ void rhs_stop_rule(RhsCtl& c, double rel, double tol, double accept) {
+  c.iters += 1;
+  c.prev = c.last;
+  c.last = rel;
+  if (rel <= tol) {
+    c.state = 1;
+  } else if (!(rel < INFINITY) || (c.iters >= 2 && rel >= 1.0 && rel > c.prev)) {
+    c.state = 3;
+  } else if (c.iters >= 2 && rel > 0.5 * c.prev) {
+    if (++c.stall >= 2) {
+      const double rho = rel / c.prev;
+      const double est = rho < 1.0 ? rel * rho / (1.0 - rho) : rel;
+      c.state = (est <= accept && rho < 0.9) ? 1 : 2;
+    }
+  } else {
+    c.stall = 0;
+  }
+}
+
+// Y[:, r] += D[:, r] over the first KM rows for every right-hand side still
+// running, then its stop rule.  One workgroup per right-hand side.
 __global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__ Y, int64_t ldY,
                                                             const double* __restrict__ D, int64_t ldD,
-                                                            int64_t KM, RefineCtl* ctl) {
+                                                            int64_t KM, RefineCtl* ctl, RhsCtl* rhs, double tol,
+                                                            double accept) {
   __shared__ double red[2][4];
   if (ctl->done) return;
   const int64_t r = blockIdx.x;
+  if (rhs[r].state != 0) return;
   double md = 0.0, my = 0.0;
   for (int64_t i = threadIdx.x; i < KM; i += 256) {
     const double d = D[i + r * ldD];
@@ -63,54 +102,39 @@ __global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__
     for (int w = 1; w < 4; ++w) { a = fmax(a, red[0][w]); b = fmax(b, red[1][w]); }
     double rel = b > 0.0 ? a / b : (a > 0.0 ? INFINITY : 0.0);
     if (!(rel >= 0.0)) rel = INFINITY;   // NaN
+    RhsCtl c = rhs[r];
+    rhs_stop_rule(c, rel, tol, accept);
+    rhs[r] = c;
     atomicMax(&ctl->worst, (unsigned long long)__double_as_longlong(rel));
+    if (c.state == 0) atomicAdd(&ctl->running, 1);
+    else if (c.state == 2) atomicOr(&ctl->stops, 1);
+    else if (c.state == 3) atomicOr(&ctl->stops, 2);
   }
 }
 
 hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const double* Dl, int64_t ldD,
-                                int64_t R, RefineCtl* ctl, hipStream_t s) {
+                                int64_t R, RefineCtl* ctl, double tol, double accept, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(refine_update_kernel, dim3((unsigned)R), dim3(256), 0, s, Y, ldY, Dl, ldD, in.KM, ctl);
+  hipLaunchKernelGGL(refine_update_kernel, dim3((unsigned)R), dim3(256), 0, s, Y, ldY, Dl, ldD, in.KM, ctl, in.rhs,
+                     tol, accept);
   return hipGetLastError();
 }
 
-// Stop at the tolerance, or once the updates stop shrinking (two iterations in
-// a row with less than a halving).  Then the contraction ratio rho =
-// last / previous estimates what further iterations could still change:
-// last * rho / (1 - rho) for rho < 1, else last (the updates fluctuate at the
-// attainable accuracy of the FP64 residual).  The result is accepted
-// (done = 1) if that estimate is at most `accept` and rho < 0.9, and
-// reported as stalled (done = 2) otherwise.  It is reported as diverging (done = 3) when
-// the update is not finite, or is growing and already as large as y itself
-// (at the attainable accuracy the updates fluctuate in size, so growth
-// alone does not mean divergence).
-__global__ void refine_check_kernel(RefineCtl* ctl, double tol, double accept) {
+// One thread, after an update: the instance is done when no right-hand side
+// is still running; its outcome is the worst of theirs.
+__global__ void refine_check_kernel(RefineCtl* ctl) {
   if (ctl->done) return;
   const double worst = __longlong_as_double((long long)ctl->worst);
   ctl->worst = 0ULL;
   ctl->iters += 1;
   ctl->prev = ctl->last;
   ctl->last = worst;
-  if (worst <= tol) {
-    ctl->done = 1;
-  } else if (!(worst < INFINITY) || (ctl->iters >= 2 && worst >= 1.0 && worst > ctl->prev)) {
-    ctl->done = 3;
-  } else if (ctl->iters >= 2 && worst > 0.5 * ctl->prev) {
-    if (++ctl->stall >= 2) {
-      const double rho = worst / ctl->prev;
-      const double est = rho < 1.0 ? worst * rho / (1.0 - rho) : worst;
-      // a ratio near 1 (a preconditioner far from the Gram, as for a
-      // rounded Z that is much better conditioned than Z itself) cannot
-      // bound the remaining change: not accepted however small the update
-      ctl->done = (est <= accept && rho < 0.9) ? 1 : 2;
-    }
-  } else {
-    ctl->stall = 0;
-  }
+  if (ctl->running == 0) ctl->done = (ctl->stops & 2) ? 3 : (ctl->stops & 1) ? 2 : 1;
+  ctl->running = 0;
 }
 
-hipError_t launch_refine_check(RefineCtl* ctl, double tol, double accept, hipStream_t s) {
-  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(1), 0, s, ctl, tol, accept);
+hipError_t launch_refine_check(RefineCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(1), 0, s, ctl);
   return hipGetLastError();
 }
 

@@ -12,14 +12,22 @@ constexpr int NB = 64;  // Cholesky / triangular-solve block size
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Device-side control of the refinement of one instance.
+// Device-side control of the refinement of one instance.  Every right-hand
+// side stops on its own (RhsCtl): once stopped, its iterate is no longer
+// updated; the instance is done when none is running.
 struct RefineCtl {
-  int done;                  // 0 running, 1 converged, 2 stalled above the acceptance level, 3 diverging
-  int iters;                 // refinement iterations applied
-  int stall;                 // consecutive iterations with less than a halving
-  int pad;
-  unsigned long long worst;  // bits of max over rhs of max|delta| / max|y| (non-negative double)
-  double last, prev;         // relative update of the last and the previous iteration
+  int done;                  // 0 running, 1 all converged, 2 some stalled above the acceptance level, 3 some diverging
+  int iters;                 // refinement iterations applied (to the slowest right-hand side)
+  int running;               // right-hand sides still running after the last update (counted by it)
+  int stops;                 // bit 1: a right-hand side stalled, bit 2: one diverged
+  unsigned long long worst;  // bits of max over running rhs of max|delta| / max|y| (non-negative double)
+  double last, prev;         // worst relative update of the last and the previous iteration
+};
+
+// One right-hand side's refinement (state as RefineCtl::done).
+struct RhsCtl {
+  int state, iters, stall, pad;
+  double last, prev;         // relative update max|delta| / max|y| of the last and the previous iteration
 };
 
 // Everything the kernels need to know about one instance.
@@ -53,6 +61,9 @@ struct Inst {
   int64_t* chol_offs = nullptr;  // first task index of each Cholesky look-ahead iteration
   int64_t chol_ntasks = 0;
   RefineCtl* ctl = nullptr;  // device refinement control
+  RhsCtl* rhs = nullptr;     // max_rhs per-right-hand-side controls
+  std::vector<RhsCtl> rhs_host;   // per-right-hand-side outcome of the last apply
+  int64_t last_R = 0;        // right-hand sides of the last apply of this instance
   // CG on the stored Gram (plans built with PC_FLAG_KEEP_GRAM)
   double* Gs = nullptr;      // KMp x KMp symmetric copy of the assembled Gram
   double* Dinv = nullptr;    // (KMp/NB) blocks NB x NB: inverses of the diagonal blocks of Gs
@@ -135,12 +146,13 @@ hipError_t launch_chol_solve_fwd_concurrent(const Inst& in, int64_t R, hipStream
 int* chol_solve_fwd_error_flag(const Inst& in);   // device int set when one of its bounded waits expired
 hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                             int64_t rows_zero_to, int64_t R, hipStream_t s);
-hipError_t launch_refine_init(RefineCtl* ctl, int budget, hipStream_t s);
+hipError_t launch_refine_init(RefineCtl* ctl, RhsCtl* rhs, int64_t R, int budget, hipStream_t s);
 // Y[:, r] += D[:, r]; the worst relative update goes to ctl->worst.
+// (per right-hand side: stop rule of refine_check_kernel on its own updates)
 hipError_t launch_refine_update(const Inst& in, double* Y, int64_t ldY, const double* Dl,
-                                int64_t ldD, int64_t R, RefineCtl* ctl, hipStream_t s);
-// one thread: decide converged / stalled from ctl->worst, then clear it
-hipError_t launch_refine_check(RefineCtl* ctl, double tol, double accept, hipStream_t s);
+                                int64_t ldD, int64_t R, RefineCtl* ctl, double tol, double accept, hipStream_t s);
+// one thread: the instance is done once no right-hand side is running
+hipError_t launch_refine_check(RefineCtl* ctl, hipStream_t s);
 hipError_t launch_nonfinite_check(const double* A, int64_t ld, int64_t rows, int64_t cols,
                                   int* flag, hipStream_t s);
 hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int64_t ldd,

@@ -104,7 +104,7 @@ hipError_t dalloc(T** p, int64_t count) {
 void free_inst(Inst& in) {
   hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; in.g2_parts = 0; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
-  hipFree(in.info); hipFree(in.ctl); hipFree(in.dag); hipFree(in.chol_offs);
+  hipFree(in.info); hipFree(in.ctl); hipFree(in.rhs); hipFree(in.dag); hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
   hipFree(in.blk_P); hipFree(in.blk_X); hipFree(in.blk_I); hipFree(in.blk_offs); hipFree(in.blk_offs_tail);
   hipFree(in.cgm_Dinv); hipFree(in.cgm_work); hipFree(in.cgm_I); hipFree(in.cgm_d0); hipFree(in.cgm_Linv);
@@ -113,7 +113,7 @@ void free_inst(Inst& in) {
   in.cgm_ctr = nullptr; in.cgm_offs = nullptr;
   in.blk_P = in.blk_X = in.blk_I = nullptr; in.blk_offs = in.blk_offs_tail = nullptr;
   in.Gs = in.Dinv = in.cg = nullptr; in.cgcol = nullptr; in.cg_flags = nullptr;
-  in.dag = nullptr; in.chol_offs = nullptr; in.ctl = nullptr;
+  in.dag = nullptr; in.chol_offs = nullptr; in.ctl = nullptr; in.rhs = nullptr;
   in.G = in.diag0 = in.Linv = in.S = in.B = in.Y = in.D = in.Rres = nullptr;
   in.pairs = in.qtiles = in.info = nullptr;
 }
@@ -224,6 +224,8 @@ pc_status alloc_inst(Inst& in, int precision, int flags, bool batched) {
   chk(dalloc(&in.Rres, in.n * R));
   chk(dalloc(&in.info, 1));
   chk(dalloc(&in.ctl, 1));
+  chk(dalloc(&in.rhs, R));
+  in.rhs_host.assign((size_t)R, pc::RhsCtl{});
   const int64_t T = KMp / pc::NB;
   in.nrt_max = (int)pc::ceil_div(R, pc::NB);
   // counters: Cholesky states, head, error, solve flags, solve head, and the
@@ -422,7 +424,7 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
       PhaseTimer t(p, PC_PHASE_SOLVE, si);
       PC_TRY(pc::launch_chol_solve(in, in.Y, in.KMp, R[i], in.B, in.KMp, si, nullptr, done_ahead >= 2 ? 1 : 0));
     }
-    PC_TRY(pc::launch_refine_init(in.ctl, budget, si));
+    PC_TRY(pc::launch_refine_init(in.ctl, in.rhs, R[i], budget, si));
   }
   // refinement on the least-squares residual: r = x - Z y, d = G^{-1} Z^T r, y += d;
   // converged instances skip the remaining iterations on the GPU
@@ -437,8 +439,8 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
       PC_TRY(pc::launch_zy(in, in.Y, in.KMp, R[i], X[i], ldX[i], in.Rres, in.n, si, skip));
       PC_TRY(pc::launch_ztx(in, in.Rres, in.n, R[i], in.D, in.KMp, si, skip));
       PC_TRY(pc::launch_chol_solve(in, in.D, in.KMp, R[i], in.B, in.KMp, si, skip));
-      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.ctl, si));
-      PC_TRY(pc::launch_refine_check(in.ctl, p->opt.tol, kStallAccept, si));
+      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.ctl, p->opt.tol, kStallAccept, si));
+      PC_TRY(pc::launch_refine_check(in.ctl, si));
     }
     if (check_every > 0 && it % check_every == 0 && it < budget) {
       bool all = true;
@@ -487,7 +489,7 @@ pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_
   { PhaseTimer t(p, PC_PHASE_SOLVE, s); PC_TRY(pc::launch_chol_solve_batch(p->batch, 0, s)); }
   PC_TRY(fork(p, s));
   for (size_t i = 0; i < cnt; ++i)
-    if (R[i] != 0) PC_TRY(pc::launch_refine_init(p->inst[i].ctl, budget, stream_for(p, i, s)));
+    if (R[i] != 0) PC_TRY(pc::launch_refine_init(p->inst[i].ctl, p->inst[i].rhs, R[i], budget, stream_for(p, i, s)));
   std::unique_ptr<PhaseTimer> refine_timer;
   if (budget > 0) refine_timer.reset(new PhaseTimer(p, PC_PHASE_REFINE, s));
   for (int it = 1; it <= budget; ++it) {
@@ -506,8 +508,8 @@ pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_
       Inst& in = p->inst[i];
       if (R[i] == 0) continue;
       hipStream_t si = stream_for(p, i, s);
-      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.ctl, si));
-      PC_TRY(pc::launch_refine_check(in.ctl, p->opt.tol, kStallAccept, si));
+      PC_TRY(pc::launch_refine_update(in, in.Y, in.KMp, in.D, in.KMp, R[i], in.ctl, p->opt.tol, kStallAccept, si));
+      PC_TRY(pc::launch_refine_check(in.ctl, si));
     }
     if (check_every > 0 && it % check_every == 0 && it < budget) {
       for (size_t i = 0; i < cnt; ++i)
@@ -881,11 +883,18 @@ static pc_status finish_factor(pc_plan* p, hipStream_t s, int32_t* failed_instan
 static pc_status finish_apply(pc_plan* p, const int64_t* R, hipStream_t s) {
   const size_t cnt = p->inst.size();
   for (size_t i = 0; i < cnt; ++i)
-    if (R[i] != 0) { p->inst[i].iters = 0; p->inst[i].last_rel = 0.0; }
+    if (R[i] != 0) {
+      Inst& in = p->inst[i];
+      in.iters = 0; in.last_rel = 0.0; in.last_R = R[i];
+      std::fill(in.rhs_host.begin(), in.rhs_host.begin() + R[i], pc::RhsCtl{1, 0, 0, 0, 0.0, 0.0});
+    }
   if (p->opt.max_refine == 0) return PC_OK;
   for (size_t i = 0; i < cnt; ++i)
-    if (R[i] != 0)
+    if (R[i] != 0) {
       PC_TRY(hipMemcpyAsync(&p->h_ctl[i], p->inst[i].ctl, sizeof(pc::RefineCtl), hipMemcpyDeviceToHost, s));
+      PC_TRY(hipMemcpyAsync(p->inst[i].rhs_host.data(), p->inst[i].rhs, sizeof(pc::RhsCtl) * (size_t)R[i],
+                            hipMemcpyDeviceToHost, s));
+    }
   PC_TRY(hipStreamSynchronize(s));
   pc_status st = PC_OK;
   for (size_t i = 0; i < cnt; ++i) {
@@ -1119,6 +1128,19 @@ pc_status pc_query_info(const pc_plan* p, int32_t instance, int32_t* iterations,
   if (!p || instance < 0 || (size_t)instance >= p->inst.size()) return PC_ERR_INVALID_ARG;
   if (iterations) *iterations = p->inst[instance].iters;
   if (last_rel_update) *last_rel_update = p->inst[instance].last_rel;
+  return PC_OK;
+}
+
+pc_status pc_query_rhs_info(const pc_plan* p, int32_t instance, int64_t R, pc_rhs_info* out) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || R < 0 || (R > 0 && !out)) return PC_ERR_INVALID_ARG;
+  const Inst& in = p->inst[instance];
+  if (R > in.last_R) return PC_ERR_INVALID_ARG;
+  for (int64_t r = 0; r < R; ++r) {
+    const pc::RhsCtl& c = in.rhs_host[(size_t)r];
+    out[r].iterations = c.iters;
+    out[r].state = c.state;
+    out[r].last_rel_update = c.last;
+  }
   return PC_OK;
 }
 
