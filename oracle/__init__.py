@@ -15,9 +15,11 @@ Modules
           SVDs, eq. InverseSquareRootSwift and steps V1-V5)
   mlp     two-layer GELU network: forward, backward, relative-MSE loss, Adam
   cg      (block-Jacobi preconditioned) conjugate gradients on the normal equations
+  hybrid  the Hybrid covariance model in standardized variables (Sec. 2.2), both
+          of the paper's forms as explicit matrices
 
 Parity status: every function here is pinned by tests in tests/test_oracle.py
 against library routines, closed forms, invariants or brute force, except the
 items marked "parity unpinned" in their docstrings.
 """
-from . import lsq, swift, mlp, cg  # noqa: F401
+from . import lsq, swift, mlp, cg, hybrid  # noqa: F401

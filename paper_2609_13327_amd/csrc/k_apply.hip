@@ -8,7 +8,8 @@
 //    shape of its member step V4).  GEMM rows = (k, r), cols = m, depth = j;
 //    the u operand is formed while it is staged in LDS.
 //
-//  Z y  (the back-transform, and the residual x - Z y of refinement):
+//  Z y  (the back-transform, the residual x - Z y of refinement, and the
+//  Hybrid product (1 - beta) v + beta Z (Z^T v)): out = alpha xs + beta (Z y),
 //      (Z y)[i, r] = sum_{k,m} E[i, k] * W[j(i), m] * Y[k*M + m, r],
 //    GEMM rows = r, cols = i, depth = (k, m); the Z operand E[i,k] W[j,m] is
 //    formed while it is staged in LDS.
@@ -291,7 +292,8 @@ struct ZyProb {
   const double* E; int64_t ldE;
   const double* W; int64_t ldW;
   const double* Y; int64_t ldY;
-  const double* Xs; int64_t ldXs;   // optional: out = Xs - Z Y
+  const double* Xs; int64_t ldXs;   // optional: out = alpha Xs + beta Z Y (else beta Z Y)
+  double alpha, beta;
   double* Out; int64_t ldO;
   int64_t n_h, n, K, M, KM, R;
   int ntr, ntc;   // tiles along rows (r) and cols (i)
@@ -355,16 +357,18 @@ struct ZyProb {
     acc.for_each([&](int row, int col, double v) {
       const int64_t rr = c.r0 + row, ii = c.i0 + col;
       if (rr >= R || ii >= n) return;
-      Out[ii + rr * ldO] = Xs ? Xs[ii + rr * ldXs] - v : v;
+      Out[ii + rr * ldO] = Xs ? fma(beta, v, alpha * Xs[ii + rr * ldXs]) : beta * v;
     });
   }
 };
 
 template <class P>
 static hipError_t run_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs,
-                         int64_t ldXs, double* out, int64_t ldOut, hipStream_t s, const int* skip) {
+                         int64_t ldXs, double alpha, double beta, double* out, int64_t ldOut, hipStream_t s,
+                         const int* skip) {
   P pr;
   pr.skip = skip;
+  pr.alpha = alpha; pr.beta = beta;
   pr.E = in.E; pr.ldE = in.ldE; pr.W = in.W; pr.ldW = in.ldW;
   pr.Y = Y; pr.ldY = ldY; pr.Xs = Xs; pr.ldXs = ldXs; pr.Out = out; pr.ldO = ldOut;
   pr.n_h = in.n_h; pr.n = in.n; pr.K = in.K; pr.M = in.M; pr.KM = in.KM; pr.R = R;
@@ -375,7 +379,7 @@ static hipError_t run_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R
   return hipGetLastError();
 }
 
-// Single level (n_w = 1): out[j, r] = (Xs[j, r] -) sum_{k,m} E[j,k] W[j,m] Y[k*M+m, r].
+// Single level (n_w = 1): out[j, r] = (alpha Xs[j, r] +) beta sum_{k,m} E[j,k] W[j,m] Y[k*M+m, r].
 // Product rows = right-hand sides, columns = grid columns j (coalesced output);
 // the contraction runs over (k, m) in chunks of 16 modes of one member when
 // M is a multiple of 16 (else element by element); the Z operand is formed
@@ -387,6 +391,7 @@ struct Zy1Args {
   const double* W; int64_t ldW;
   const double* Y; int64_t ldY;
   const double* Xs; int64_t ldXs;
+  double alpha, beta;
   double* Out; int64_t ldO;
   int64_t n_h, K, M, KM, R;
   int ntr, ntj;
@@ -476,16 +481,18 @@ __global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
         const int64_t jj = j0 + wn * 32 + j * 16 + rr;
         if (r >= a.R || jj >= a.n_h) continue;
         const double val = acc[i][j][v];
-        a.Out[jj + r * a.ldO] = a.Xs ? a.Xs[jj + r * a.ldXs] - val : val;
+        a.Out[jj + r * a.ldO] = a.Xs ? fma(a.beta, val, a.alpha * a.Xs[jj + r * a.ldXs]) : a.beta * val;
       }
 }
 
-hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs, int64_t ldXs,
-                     double* out, int64_t ldOut, hipStream_t s, const int* skip) {
+hipError_t launch_zy_axpby(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs,
+                           int64_t ldXs, double alpha, double beta, double* out, int64_t ldOut, hipStream_t s,
+                           const int* skip) {
   if (R <= 0) return hipSuccess;
   if (in.n_w == 1) {
     Zy1Args a;
     a.skip = skip;
+    a.alpha = alpha; a.beta = beta;
     a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.Y = Y; a.ldY = ldY; a.Xs = Xs; a.ldXs = ldXs;
     a.Out = out; a.ldO = ldOut; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.KM = in.KM; a.R = R;
     a.ntr = (int)ceil_div(R, YT); a.ntj = (int)ceil_div(in.n_h, YT);
@@ -493,9 +500,15 @@ hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, co
     hipLaunchKernelGGL(zy1_kernel, dim3((unsigned)(8 * ((ntiles + 7) / 8))), dim3(256), 0, s, a);
     return hipGetLastError();
   }
-  if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s, skip);
-  if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s, skip);
-  return run_zy<ZyProb<64, 64, 2, 2>>(in, Y, ldY, R, Xs, ldXs, out, ldOut, s, skip);
+  if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+  if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+  return run_zy<ZyProb<64, 64, 2, 2>>(in, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+}
+
+hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs, int64_t ldXs,
+                     double* out, int64_t ldOut, hipStream_t s, const int* skip) {
+  // x - Z y exactly as a subtraction (fma(-1, v, 1 * x) rounds once), else Z y
+  return launch_zy_axpby(in, Y, ldY, R, Xs, ldXs, 1.0, Xs ? -1.0 : 1.0, out, ldOut, s, skip);
 }
 
 }  // namespace pc
