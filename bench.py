@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--tune-cache", default=None, help="tuning cache file (read and updated)")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the Hybrid product and swift left inverse timings (256x512 instance)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -190,8 +192,8 @@ def main():
 
     def measure(prec_name, steps, warmup, profile=True):
         code, refine = PRECS[prec_name]
-        if args.config == 3 and refine:
-            refine = 20
+        if args.config == 3:
+            refine = 20   # FP64 too: corrected semi-normal steps for the ill-conditioned members
         plan = pc.Plan([{"E": e, "W": w, "n_w": 1, "max_rhs": i.R} for e, w, i in zip(dE, dW, insts)],
                        precision=code, max_refine=refine, tol=1e-10 if refine else 0.0,
                        use_graph=use_graph)
@@ -214,14 +216,20 @@ def main():
             pc.pc_profile_enable(plan.handle, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        statuses = set()
         for k in range(steps):   # one step: factor and apply (the fused call overlaps Z^T x with the factor)
-            plan.factor_apply(Xs, dY, raise_on_error=False)
+            statuses.add(plan.factor_apply(Xs, dY, raise_on_error=False)[0])
             if args.config == 4:
                 log(f"  {prec_name}: step {k + 1}")   # progress (a step takes seconds here)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         phases = pc.pc_profile_read(plan.handle)
         pc.pc_profile_enable(plan.handle, False)
+        # instances left without a factor by the precision ladder during the
+        # steps (a reduced-precision Gram that factored but whose refinement
+        # diverged, and whose FP64 Gram is not positive definite) have no answer
+        ok = [good and pc.pc_query_instance(plan.handle, k)[1] for k, good in enumerate(ok)]
+        Xs = [x if good else None for x, good in zip(dX, ok)]
         # apply only (factor reused)
         plan.apply(Xs, dY, raise_on_error=False)
         torch.cuda.synchronize()
@@ -261,6 +269,7 @@ def main():
                 "apply_only_rhs_per_s": total_rhs / ((tb - ta) / napply),
                 "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
                 "kernels": kernels, "tuning": tuning, "factored": ok, "rungs": rungs,
+                "statuses": sorted(pc.pc_status_string(st) for st in statuses),
                 "refine_iters_max": max(it for it, _ in info), "Y": Y}
 
     log(f"timing {prec_main}: {warmup} warmup + {steps} steps")
@@ -357,6 +366,8 @@ def main():
                                   "speedup_vs_fp64": None,
                                   "refine_iters_max": v["refine_iters_max"],
                                   "rel_err_max": e_max, "rungs": sorted(set(v["rungs"])),
+                                  "instances_not_factored": [k for k, g in enumerate(v["factored"]) if not g],
+                                  "statuses": v["statuses"],
                                   "phases_ms_per_step": v["phases_ms_per_step"]}
             except Exception as ex:  # a variant that is not available is reported as such
                 variants[name] = {"error": str(ex)}
@@ -408,13 +419,96 @@ def main():
         "apply_only_rhs_per_s": main_res["apply_only_rhs_per_s"],
         "refine_iters_max": main_res["refine_iters_max"],
         "instances_not_factored": [k for k, ok in enumerate(main_res["factored"]) if not ok],
+        "statuses": main_res["statuses"],
         "tuning": {"shapes (gram_split, ztx_split, chol_wgs_per_cu)": main_res["tuning"]},
         "kernels": kern,
         "phases_ms_per_step": main_res["phases_ms_per_step"],
         "variants": variants,
     }
+    if args.config == 4 and not args.no_next:
+        out["next"] = next_rows(torch, pc, wl, dE[0], dW[0], dX[0], insts[0])
     print(json.dumps(out))
     return 0
+
+
+def _event_ms(torch, fn, reps):
+    """Average time of fn() over reps calls, with HIP events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def next_rows(torch, pc, wl, E, W, X, inst):
+    """The products either side of the path, timed on their own:
+    the Hybrid covariance product in standardized variables (two products
+    with Z~ = [e~_k o w~_m]) with the 256x512 instance's E and W as its
+    factors and its 1024 right-hand sides as the vectors; the paper's own
+    left inverse for n_w = K (per-column inverses, then the projection on
+    the localization modes) on a 64x128 grid with 64 levels, K = 64 members,
+    L = 512 modes, 64 right-hand sides in range(Z), with its accuracy on them."""
+    res = {}
+    n, n_h, K, M, R = inst.n, inst.n_h, inst.K, inst.M, inst.R
+    Out = torch.empty((R, n), dtype=torch.float64, device=X.device).t()
+    work = torch.empty((R, K * M), dtype=torch.float64, device=X.device).t()
+    beta = 0.5
+    log("hybrid product on the 256x512 instance's factors")
+    ms = _event_ms(torch, lambda: pc.pc_hybrid_apply(E, W, beta, X, Out, work), 3)
+    flops = 2.0 * n_h * M * K * R + float(n) * K * R + 2.0 * n * K * M * R
+    # properties at full size: symmetry u^T (P v) = v^T (P u), and v^T P v >= (1 - beta) |v|^2
+    Xt = X[:, :2]
+    O2 = torch.empty((2, n), dtype=torch.float64, device=X.device).t()
+    pc.pc_hybrid_apply(E, W, beta, Xt, O2, work[:, :2])
+    u, v, Pu, Pv = Xt[:, 0], Xt[:, 1], O2[:, 0], O2[:, 1]
+    sym = float(abs(torch.dot(u, Pv) - torch.dot(v, Pu)) / (torch.norm(u) * torch.norm(Pv)))
+    margin = float(torch.dot(v, Pv) / ((1 - beta) * torch.dot(v, v)))
+    res["hybrid"] = {"workload": f"factors n={n}, K={K}, M={M}; {R} vectors; beta_e={beta}",
+                     "ms": ms, "vectors_per_s": R / (ms * 1e-3), "flops": flops,
+                     "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": 78.6,
+                                  "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / 78.6},
+                     "symmetry_rel": sym, "pd_margin_ratio": margin}
+    del Out, work
+    log("swift left inverse (n_w = K) on a 64x128 grid, 64 levels")
+    sw = wl.make_instance(64, 128, 64, 512, 64, 0.05, 0.2, 4100, n_w=64, centring="discard")
+    delta = np.sum(sw.W * sw.W, axis=0)
+    Vb = sw.W / np.sqrt(delta)[None, :]
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to(X.device).t()
+    dEs, dWs, dVb = to_dev(sw.E), to_dev(sw.W), to_dev(Vb)
+    dd = torch.tensor(delta, dtype=torch.float64, device=X.device)
+    Rs = 64
+    xt = torch.randn((Rs, sw.KM), generator=torch.Generator(device=X.device).manual_seed(4101),
+                     dtype=torch.float64, device=X.device).t()
+    xs = torch.empty((Rs, sw.n), dtype=torch.float64, device=X.device).t()
+    plan = pc.Plan([{"E": dEs, "W": dWs, "n_w": 64, "max_rhs": Rs}])
+    pc.pc_sqrt_apply(plan.handle, 0, xt, xs)             # x = Z x~ (range(Z))
+    torch.cuda.synchronize()
+    plan.close()
+    holder = {}
+
+    def build():
+        if "s" in holder:
+            holder["s"].close()
+        holder["s"] = pc.Swift(dEs, dVb, dd, Rs)
+    build_ms = _event_ms(torch, build, 2)
+    ys = torch.empty((Rs, sw.KM), dtype=torch.float64, device=X.device).t()
+    apply_ms = _event_ms(torch, lambda: holder["s"].apply(xs, ys), 5)
+    err = torch.linalg.vector_norm(ys - xt, dim=0) / torch.linalg.vector_norm(xt, dim=0)
+    holder["s"].close()
+    n_hs, Ks, Ls = sw.n_h, sw.K, sw.M
+    fl = 2.0 * n_hs * Ks * Ks * Rs + 2.0 * Ls * n_hs * Ks * Rs
+    res["swift"] = {"workload": f"n_h={n_hs}, n_w=K={Ks}, L={Ls}; {Rs} right-hand sides in range(Z)",
+                    "build_ms": build_ms, "apply_ms": apply_ms, "rhs_per_s_apply": Rs / (apply_ms * 1e-3),
+                    "rhs_per_s_build_and_apply": Rs / ((build_ms + apply_ms) * 1e-3),
+                    "apply_flops": fl,
+                    "roofline_apply": {"bound": "mfma", "achieved": fl / (apply_ms * 1e-3) / 1e12, "peak": 78.6,
+                                       "unit": "TFLOP/s", "frac": fl / (apply_ms * 1e-3) / 1e12 / 78.6},
+                    "rel_err_max_on_range": float(err.max())}
+    return res
 
 
 def learned(args, torch, pc, wl, dev):

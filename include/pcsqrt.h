@@ -55,7 +55,7 @@ typedef enum {
   PC_ERR_NONFINITE = 3,      /* NaN or Inf in E or W (checked by pc_sqrt_build) */
   PC_ERR_NOT_SPD = 4,        /* a Cholesky pivot <= 0: Z is (numerically) rank deficient */
   PC_ERR_NOT_FACTORED = 5,   /* apply before a successful pc_gram_factor */
-  PC_ERR_NO_CONVERGENCE = 6, /* refinement budget spent before the tolerance was met */
+  PC_ERR_NO_CONVERGENCE = 6, /* an iteration did not meet its tolerance (refinement, CG: see each call) */
   PC_ERR_OOM = 7,            /* device allocation failed */
   PC_ERR_DEVICE = 8,         /* a HIP runtime call failed */
   PC_ERR_TOO_MANY_RHS = 9,   /* R larger than the max_rhs given at build time */
@@ -74,8 +74,10 @@ typedef enum {
 typedef enum {
   PC_PREC_FP64 = 0,          /* FP64 Gram (MFMA f64), FP64 Cholesky and solves */
   PC_PREC_FP32_REFINE = 1,   /* Gram of fp32(Z) on MFMA f32, FP64 Cholesky + FP64 refinement */
-  PC_PREC_BF16_REFINE = 2,   /* Gram of bf16(Z) on MFMA bf16 (fp32 accumulation), FP64 Cholesky + FP64 refinement */
-  PC_PREC_BF16X3_REFINE = 3  /* split bf16: Z~ = hi + lo (hi = bf16(z), lo = bf16(z - hi)), Gram
+  PC_PREC_BF16_REFINE = 2,   /* Gram of bf16(z32) on MFMA bf16 (fp32 accumulation), FP64 Cholesky + FP64
+                                refinement; z32 = fl32(fp32(e) * fp32(w)), the fp32 product of fp32 copies
+                                of E and W that the plan keeps */
+  PC_PREC_BF16X3_REFINE = 3  /* split bf16: z32 = hi + lo (hi = bf16(z32), lo = bf16(z32 - hi)), Gram
                                 Hi^T Hi + Hi^T Lo + Lo^T Hi on MFMA bf16 (fp32 accumulation),
                                 FP64 Cholesky + FP64 refinement */
 } pc_precision;
@@ -156,10 +158,13 @@ pc_status pc_gram_factor(pc_plan *plan, void *stream, int32_t *failed_instance);
  * as stalled otherwise; it diverges when an update is not finite or grows
  * while at least max|y|.  An instance is done when none of its right-hand
  * sides still runs.  Returns PC_ERR_NO_CONVERGENCE (Y holds the last
- * iterates) if a right-hand side ran out of budget, diverged, or stalled in
- * a reduced-precision plan (an FP64 plan accepts a stall: the updates then
- * fluctuate at the attainable accuracy of the FP64 residual);
- * pc_query_rhs_info tells which. */
+ * iterates) if a right-hand side diverged, or, in an instance whose Gram is
+ * in reduced precision, stalled or ran out of budget (after the ladder).  An
+ * instance in FP64 (the plan's precision, or the ladder's last rung) takes
+ * corrected semi-normal steps and accepts a stall or a spent budget: the
+ * updates then fluctuate at the attainable accuracy of the FP64 residual, or
+ * the caller asked for a fixed number of steps.  pc_query_rhs_info tells
+ * which right-hand side ended how. */
 pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int64_t *ldX,
                                 const int64_t *R, double *const *Y, const int64_t *ldY,
                                 void *stream);
@@ -246,6 +251,38 @@ pc_status pc_gram_assemble(pc_plan *plan, void *stream);
  * Entries of G above the diagonal are not written.  Asynchronous. */
 pc_status pc_gram_export(const pc_plan *plan, int32_t instance, double *G, int64_t ldG,
                          void *stream);
+
+/* ------------------------------------------------------------------------
+ * Hybrid covariance product in standardized variables (Sec. 2.2, eq.
+ * svCBKHybrid): P~h v = (1 - beta_e) v + beta_e (C~ o P~e) v.
+ * ---------------------------------------------------------------------- */
+
+/* pc_hybrid_apply — Out = (1 - beta_e) V + beta_e (C~ o P~e) V for R vectors
+ * of the standardized space (n~ = n_h * n_w entries each).  The two factors
+ * come as an instance (sizes as in pc_instance, except that K*M <= n~ is not
+ * required and max_rhs is ignored):
+ *   E: n~ x K, the standardized ensemble perturbations e~_k (the forecast
+ *      members mapped by the left inverse of the square root, Sec. 2.1 eq.
+ *      svTransform, e.g. with pc_left_inverse_apply), scaled so that
+ *      P~e = E E^T;
+ *   W: n_h x M, the modes of the localization, C~ = (1 1^T) (x) (W W^T)
+ *      over the n_w levels (index l * n_h + j, as for Z).
+ * By the Schur product identity C~ o (E E^T) = Z~ Z~^T with Z~ the columns
+ * e~_k o w~_m (Sec. 3.7), so Out = (1 - beta_e) V + beta_e Z~ (Z~^T V): two
+ * structured products, forming neither Z~ nor an n~ x n~ matrix.  The
+ * paper obtains this form from its unsimplified one assuming every
+ * diagonal entry of C~ is 1 (rows of W with unit norm); the product
+ * computed is this form whatever W is.  For 0 < beta_e < 1 it is positive
+ * definite (C~ is positive semi-definite by construction).
+ * V, Out: device n~ x R (ldV, ldOut >= n~; Out may be V itself, with the
+ * same leading dimension).  work: device K*M x R scratch (ldwork >= K*M),
+ * caller-owned and overwritten.  Allocates nothing; asynchronous on stream.
+ * Errors: PC_ERR_SHAPE (a size below 1, R < 0), PC_ERR_INVALID_ARG (null
+ * pointer, short leading dimension, beta_e outside [0, 1] or not finite),
+ * PC_ERR_DEVICE (a launch failed). */
+pc_status pc_hybrid_apply(const pc_instance *hybrid, double beta_e, const double *V, int64_t ldV,
+                          int64_t R, double *Out, int64_t ldOut, double *work, int64_t ldwork,
+                          void *stream);
 
 /* ------------------------------------------------------------------------
  * Autotuning of launch shapes.

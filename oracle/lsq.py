@@ -392,16 +392,37 @@ def split_bf16(Z: np.ndarray):
     return Hi, round_bf16(Z - Hi)
 
 
-def gram_lowprec(E, W, n_w, fmt: str):
-    """Exact (float64) Gram of the rounded square root Z~ = round(E*W) elementwise.
+def form_z32(E: np.ndarray, W: np.ndarray, n_w: int) -> np.ndarray:
+    """Z32[l*n_h + j, k*M + m] = fl32(fp32(E[l*n_h + j, k]) * fp32(W[j, m])): Z formed
+    in float32 arithmetic from float32 copies of E and W (each value rounded to
+    nearest even once, the product rounded once), returned as float64."""
+    E32 = np.asarray(E, dtype=np.float64).astype(np.float32)
+    C32 = np.tile(np.asarray(W, dtype=np.float64).astype(np.float32), (n_w, 1))
+    return np.concatenate([E32[:, k:k + 1] * C32 for k in range(E32.shape[1])], axis=1).astype(np.float64)
 
-    fmt: "bf16" or "fp32": Z~^T Z~ with the product E[i,k]*W[j,m] formed in
-    float64 and rounded once to the format;  "bf16x3": the three-product
-    split-bf16 Gram Hi^T Hi + Hi^T Lo + Lo^T Hi of `split_bf16(Z)` (the
-    Lo^T Lo term is left out)."""
-    Z = form_z(E, W, n_w)
+
+def lowprec_operands(E, W, n_w, fmt: str):
+    """The rounded square root whose Gram the reduced-precision modes form:
+    "fp32": [fp32(Z)], each FP64 product E[i,k]*W[j,m] rounded once to float32;
+    "bf16": [bf16(Z32)];  "bf16x3": [Hi, Lo] = split_bf16(Z32),
+    with Z32 the float32 product of float32 copies of E and W (form_z32)."""
+    if fmt == "fp32":
+        return [round_fp32(form_z(E, W, n_w))]
+    Z32 = form_z32(E, W, n_w)
+    if fmt == "bf16":
+        return [round_bf16(Z32)]
     if fmt == "bf16x3":
-        Hi, Lo = split_bf16(Z)
+        return list(split_bf16(Z32))
+    raise ValueError(fmt)
+
+
+def gram_lowprec(E, W, n_w, fmt: str):
+    """Exact (float64) Gram of the rounded square root of `lowprec_operands`:
+    Zt^T Zt for "bf16" and "fp32"; for "bf16x3" the three-product split-bf16
+    Gram Hi^T Hi + Hi^T Lo + Lo^T Hi (the Lo^T Lo term is left out)."""
+    ops = lowprec_operands(E, W, n_w, fmt)
+    if fmt == "bf16x3":
+        Hi, Lo = ops
         return Hi.T @ Hi + Hi.T @ Lo + Lo.T @ Hi
-    Zt = round_bf16(Z) if fmt == "bf16" else round_fp32(Z)
+    Zt = ops[0]
     return Zt.T @ Zt

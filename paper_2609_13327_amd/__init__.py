@@ -48,7 +48,7 @@ EXPORTED = [
     "pc_selftest_task_order", "pc_cg_solve", "pc_mlp_create", "pc_mlp_destroy", "pc_mlp_set_params",
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
-    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance", "pc_query_rhs_info",
+    "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance", "pc_query_rhs_info", "pc_hybrid_apply",
     "pc_swift_build", "pc_swift_apply", "pc_swift_destroy",
 ]
 
@@ -145,6 +145,8 @@ def load_library(path: str = LIB_PATH):
     lib.pc_swift_destroy.argtypes = [c_void_p]
     lib.pc_query_instance.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
     lib.pc_query_rhs_info.argtypes = [c_void_p, c_int32, c_int64, POINTER(PcRhsInfo)]
+    lib.pc_hybrid_apply.argtypes = [POINTER(PcInstance), c_double, c_void_p, c_int64, c_int64, c_void_p,
+                                    c_int64, c_void_p, c_int64, c_void_p]
     lib.pc_factor_apply_noalloc.argtypes = [POINTER(PcInstance), c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                             c_void_p]
     for name in EXPORTED:
@@ -291,6 +293,23 @@ def pc_factor_apply_noalloc(E, W, X, Y, n_w: int = 1, stream=None, raise_on_erro
     if raise_on_error:
         _check(st, "pc_factor_apply_noalloc")
     return st
+
+
+def pc_hybrid_apply(E, W, beta_e: float, V, Out, work, n_w: int = 1, stream=None) -> None:
+    """Out <- (1 - beta_e) V + beta_e (C~ o P~e) V with P~e = E E^T and the
+    localization C~ given by its modes W (n_h x M).  E (n~ x K), W, V, Out
+    (n~ x R) and work (K*M x R, overwritten): column-major float64 device
+    tensors; Out may be V."""
+    lib = load_library()
+    n_h = int(W.shape[0])
+    if E.shape[0] != n_h * int(n_w) or V.shape[0] != E.shape[0] or Out.shape[0] != E.shape[0]:
+        raise ValueError("E, V and Out must have n_h * n_w rows")
+    R = int(V.shape[1])
+    if Out.shape[1] != R or work.shape[1] < R or work.shape[0] < E.shape[1] * W.shape[1]:
+        raise ValueError("Out must be n~ x R and work at least K*M x R")
+    inst = PcInstance(n_h, int(n_w), int(E.shape[1]), int(W.shape[1]), _ptr(E), _ld(E), _ptr(W), _ld(W), 0)
+    _check(lib.pc_hybrid_apply(ctypes.byref(inst), float(beta_e), _ptr(V), _ld(V), R, _ptr(Out), _ld(Out),
+                               _ptr(work), _ld(work), c_void_p(_stream(stream))), "pc_hybrid_apply")
 
 
 def pc_left_inverse_apply(plan: int, X: Sequence, Y: Sequence, stream=None,

@@ -60,6 +60,12 @@ struct Inst {
   int nrt_max = 1;           // 64-column tiles of max_rhs
   int64_t* chol_offs = nullptr;  // first task index of each Cholesky look-ahead iteration
   int64_t chol_ntasks = 0;
+  // fp32 copies of E and W for the bf16 Grams: E32 has ldE32 = n rounded up
+  // to 32 rows (zero beyond n) and K + 1 columns (column K zero); W32 has
+  // ldW32 = n_h rounded up to 32 rows (zero beyond n_h)
+  float* E32 = nullptr; int64_t ldE32 = 0;
+  float* W32 = nullptr; int64_t ldW32 = 0;
+  int* lp_tiles = nullptr; int64_t lp_ntiles = 0;   // reduced-precision Gram tiles (ta, tb), in launch order
   RefineCtl* ctl = nullptr;  // device refinement control
   RhsCtl* rhs = nullptr;     // max_rhs per-right-hand-side controls
   std::vector<RhsCtl> rhs_host;   // per-right-hand-side outcome of the last apply
@@ -104,13 +110,20 @@ hipError_t launch_pairs_init(const Inst& in, hipStream_t s);
 hipError_t launch_column_grams(const Inst& in, hipStream_t s);
 hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
+// fp32 copies E32, W32 of E and W (the bf16 forms' operands), before their Gram
+hipError_t launch_stage_f32(const Inst& in, hipStream_t s);
+// launch order of the lower-triangle 128 x 128 tiles of a reduced-precision
+// Gram: (ta, tb) pairs, grouped by the pair of 128-mode blocks they read
+std::vector<int> lowgram_tile_order(int64_t KM, int64_t M);
 // reduced-precision Grams of several instances in one launch (after each
 // instance's rounded Z has been staged)
 // (the rounded Z is formed tile by tile from E and W inside the Gram kernel)
 struct LowGramInst {
   const double* E; int64_t ldE;
   const double* W; int64_t ldW;
-  int64_t n, n_h, n_w, M, KM;
+  const float* E32; int64_t ldE32;   // fp32 copies (bf16 forms only)
+  const float* W32; int64_t ldW32;
+  int64_t n, n_h, n_w, K, M, KM;
   double* G; int64_t ldG;
 };
 struct LowGramTile { int inst, ta, tb, pad; };
@@ -137,6 +150,10 @@ hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, d
 // out = Xsub - Z Y  (Xsub may be null: out = Z Y)
 hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xsub,
                      int64_t ldXs, double* out, int64_t ldOut, hipStream_t s, const int* skip = nullptr);
+// out = alpha Xs + beta (Z Y) (Xs may be null: beta (Z Y)); out may alias Xs
+hipError_t launch_zy_axpby(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs,
+                           int64_t ldXs, double alpha, double beta, double* out, int64_t ldOut, hipStream_t s,
+                           const int* skip = nullptr);
 // in-place Y <- L^{-T} L^{-1} Y on the KMp x R block (ld = ldY), using work buffer Wk
 // (first_pass = 1: Wk already holds L^{-1} Y, only the backward pass runs)
 hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk,

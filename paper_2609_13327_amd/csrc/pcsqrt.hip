@@ -104,7 +104,9 @@ hipError_t dalloc(T** p, int64_t count) {
 void free_inst(Inst& in) {
   hipFree(in.G); hipFree(in.G2); in.G2 = nullptr; in.g2_parts = 0; hipFree(in.diag0); hipFree(in.Linv); hipFree(in.Lt); in.Lt = nullptr; in.lt_tiles = 0; hipFree(in.Msol); in.Msol = nullptr; hipFree(in.S); hipFree(in.pairs);
   hipFree(in.qtiles); hipFree(in.B); hipFree(in.Y); hipFree(in.D); hipFree(in.Rres);
-  hipFree(in.info); hipFree(in.ctl); hipFree(in.rhs); hipFree(in.dag); hipFree(in.chol_offs);
+  hipFree(in.info); hipFree(in.ctl); hipFree(in.rhs); hipFree(in.dag);
+  hipFree(in.E32); hipFree(in.W32); in.E32 = nullptr; in.W32 = nullptr;
+  hipFree(in.lp_tiles); in.lp_tiles = nullptr; in.lp_ntiles = 0; hipFree(in.chol_offs);
   hipFree(in.Gs); hipFree(in.Dinv); hipFree(in.cg); hipFree(in.cgcol); hipFree(in.cg_flags);
   hipFree(in.blk_P); hipFree(in.blk_X); hipFree(in.blk_I); hipFree(in.blk_offs); hipFree(in.blk_offs_tail);
   hipFree(in.cgm_Dinv); hipFree(in.cgm_work); hipFree(in.cgm_I); hipFree(in.cgm_d0); hipFree(in.cgm_Linv);
@@ -225,6 +227,20 @@ pc_status alloc_inst(Inst& in, int precision, int flags, bool batched) {
   chk(dalloc(&in.info, 1));
   chk(dalloc(&in.ctl, 1));
   chk(dalloc(&in.rhs, R));
+  if (precision != PC_PREC_FP64) {
+    const std::vector<int> order = pc::lowgram_tile_order(in.KM, in.M);
+    in.lp_ntiles = (int64_t)(order.size() / 2);
+    chk(dalloc(&in.lp_tiles, (int64_t)order.size()));
+    if (e == hipSuccess) chk(hipMemcpy(in.lp_tiles, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  }
+  if (precision == PC_PREC_BF16_REFINE || precision == PC_PREC_BF16X3_REFINE) {
+    in.ldE32 = pc::round_up(in.n, 32);
+    in.ldW32 = pc::round_up(in.n_h, 32);
+    chk(dalloc(&in.E32, in.ldE32 * (in.K + 1)));
+    chk(dalloc(&in.W32, in.ldW32 * in.M));
+    if (e == hipSuccess) chk(hipMemset(in.E32, 0, sizeof(float) * in.ldE32 * (in.K + 1)));
+    if (e == hipSuccess) chk(hipMemset(in.W32, 0, sizeof(float) * in.ldW32 * in.M));
+  }
   in.rhs_host.assign((size_t)R, pc::RhsCtl{});
   const int64_t T = KMp / pc::NB;
   in.nrt_max = (int)pc::ceil_div(R, pc::NB);
@@ -337,6 +353,7 @@ pc_status assemble_one(pc_plan* p, Inst& in, hipStream_t s) {
     { PhaseTimer t(p, PC_PHASE_GRAM, s); PC_TRY(pc::launch_gram_f64(in, s)); }
   } else {
     PhaseTimer t(p, PC_PHASE_GRAM, s);
+    if (in.prec != PC_PREC_FP32_REFINE) PC_TRY(pc::launch_stage_f32(in, s));
     PC_TRY(pc::launch_gram_lowprec(in, in.prec, s));
   }
   { PhaseTimer t(p, PC_PHASE_PAD, s); PC_TRY(pc::launch_gram_pad_and_diag(in, s)); }
@@ -363,6 +380,8 @@ pc_status assemble_lowgram_batch(pc_plan* p, hipStream_t s) {
     if (in.prec == PC_PREC_FP64) {
       PC_TRY(pc::launch_column_grams(in, si));
       PC_TRY(pc::launch_gram_f64(in, si));
+    } else if (in.prec != PC_PREC_FP32_REFINE) {
+      PC_TRY(pc::launch_stage_f32(in, si));
     }
   }
   PC_TRY(join(p, s));
@@ -879,6 +898,17 @@ static pc_status finish_factor(pc_plan* p, hipStream_t s, int32_t* failed_instan
   return factor_outcome(p, failed_instance);
 }
 
+// Whether instance i's refinement failed: any right-hand side diverging,
+// or, for a Gram in reduced precision, one stalled above the acceptance
+// level or out of budget.  In FP64 (the plan's precision or the ladder's
+// last rung) the refinement steps are corrected semi-normal steps: a stall
+// (the updates fluctuate at the attainable accuracy of the FP64 residual)
+// or a spent budget is the result.
+static bool refinement_failed(const pc_plan* p, size_t i) {
+  const int done = p->h_ctl[i].done;
+  return done == 3 || (done != 1 && p->inst[i].prec != PC_PREC_FP64);
+}
+
 // Refinement outcome of an apply: one read of every instance's control block.
 static pc_status finish_apply(pc_plan* p, const int64_t* R, hipStream_t s) {
   const size_t cnt = p->inst.size();
@@ -901,9 +931,7 @@ static pc_status finish_apply(pc_plan* p, const int64_t* R, hipStream_t s) {
     if (R[i] == 0) continue;
     p->inst[i].iters = p->h_ctl[i].iters;
     p->inst[i].last_rel = p->h_ctl[i].last;
-    if (p->h_ctl[i].done != 1 && (p->inst[i].prec != PC_PREC_FP64 || p->opt.precision != PC_PREC_FP64 ||
-                                  p->h_ctl[i].done == 3))
-      st = PC_ERR_NO_CONVERGENCE;
+    if (refinement_failed(p, i)) st = PC_ERR_NO_CONVERGENCE;
   }
   return st;
 }
@@ -959,7 +987,7 @@ static pc_status escalate_unconverged(pc_plan* p, const double* const* X, const 
     for (size_t i = 0; i < cnt; ++i) {
       R2[i] = 0;
       Inst& in = p->inst[i];
-      if (R[i] == 0 || p->h_ctl[i].done == 1 || next_rung(in.prec) < 0) continue;
+      if (R[i] == 0 || !refinement_failed(p, i) || next_rung(in.prec) < 0) continue;
       do {
         in.prec = next_rung(in.prec);
         const pc_status fs = refactor_one(p, i, s);
@@ -976,7 +1004,7 @@ static pc_status escalate_unconverged(pc_plan* p, const double* const* X, const 
     if (st != PC_OK && st != PC_ERR_NO_CONVERGENCE) return st;
   }
   for (size_t i = 0; i < cnt; ++i)
-    if (R[i] != 0 && p->h_ctl[i].done != 1) return PC_ERR_NO_CONVERGENCE;
+    if (R[i] != 0 && refinement_failed(p, i)) return PC_ERR_NO_CONVERGENCE;
   return PC_OK;
 }
 

@@ -121,7 +121,7 @@ def test_full_batch_config3():
     Xs = [dev(i.X) if fac else None for i, (_, fac) in zip(insts, state)]
     Ys = [empty(i.KM, i.R) for i in insts]
     st = plan.apply(Xs, Ys, raise_on_error=False)
-    assert st in (pc.PC_OK, pc.PC_ERR_NO_CONVERGENCE)
+    assert st == pc.PC_OK, pc.pc_status_string(st)   # instances on the FP64 rung accept their CSNE result
     state = [pc.pc_query_instance(plan.handle, k) for k in range(len(insts))]
     within, unfactored, oracle_deficient = 0, [], []
     for k, inst in enumerate(insts):

@@ -30,24 +30,26 @@ def _inst(shape, seed=31):
 @pytest.mark.parametrize("prec", sorted(PRECS))
 @pytest.mark.parametrize("shape", SHAPES)
 def test_lowprec_gram_is_gram_of_rounded_z(prec, shape):
-    """The assembled Gram equals the exact Gram of round(Z) (oracle, float64)
-    up to fp32 accumulation: |G - Gt| <= 2 n u32 (|Zt|^T |Zt|); for split
-    bf16, of its three products, with 3n terms per entry."""
+    """The assembled Gram equals the exact Gram of the oracle's rounded Z
+    (bf16 of the fp32 product of fp32 copies of E and W, or fp32 of the FP64
+    product; float64 Gram) up to the fp32 accumulation of the MFMAs:
+    |G - Gt| <= 2 n u32 (|Zt|^T |Zt|); for split bf16, of its three
+    products, with 3n terms per entry."""
     inst = _inst(shape)
     plan = pc.Plan([inst_dict(inst)], precision=PRECS[prec], max_refine=1, flags=pc.PC_FLAG_FIXED_PRECISION)
     pc.pc_gram_assemble(plan.handle)
     G = dev(np.zeros((inst.KM, inst.KM)))
     pc.pc_gram_export(plan.handle, 0, G)
     got = np.tril(host(G))
-    Z = lsq.form_z(inst.E, inst.W, inst.n_w)
+    ops = lsq.lowprec_operands(inst.E, inst.W, inst.n_w, prec)
     u32 = 2.0 ** -24
     if prec == "bf16x3":
-        Hi, Lo = lsq.split_bf16(Z)
+        Hi, Lo = ops
         ref = np.tril(Hi.T @ Hi + Hi.T @ Lo + Lo.T @ Hi)
         absum = np.abs(Hi).T @ np.abs(Hi) + np.abs(Hi).T @ np.abs(Lo) + np.abs(Lo).T @ np.abs(Hi)
         bound = np.tril(2 * 3 * inst.n * u32 * absum) + 1e-300
     else:
-        Zt = lsq.round_bf16(Z) if prec == "bf16" else lsq.round_fp32(Z)
+        Zt = ops[0]
         ref = np.tril(Zt.T @ Zt)
         bound = np.tril(2 * inst.n * u32 * (np.abs(Zt).T @ np.abs(Zt))) + 1e-300
     assert np.array_equal(np.tril(lsq.gram_lowprec(inst.E, inst.W, inst.n_w, prec)), ref)

@@ -419,6 +419,29 @@ def test_gram_lowprec_rounds_the_product_once():
     assert G32[0, 0] == (1.0 + 2.0 ** -8) ** 4
 
 
+def test_bf16_forms_round_the_fp32_product():
+    """The bf16 forms round the float32 product of float32 copies of E and W:
+    e = 1 + 2^-8 + 2^-30 has the float32 copy 1 + 2^-8 (2^-30 is below its 24
+    bits), an exact tie for bfloat16 that rounds to even, 1; the float64
+    product rounded once would have given 1 + 2^-7.  Split bf16 then has
+    Hi = 1 and Lo = 2^-8 (the float32 value is recovered exactly).  The fp32
+    form keeps the float64 product: fp32(1 + 2^-8 + 2^-30) = 1 + 2^-8."""
+    E = np.array([[1.0 + 2.0 ** -8 + 2.0 ** -30]])
+    W = np.array([[1.0]])
+    assert lsq.form_z32(E, W, 1)[0, 0] == 1.0 + 2.0 ** -8
+    assert lsq.gram_lowprec(E, W, 1, "bf16")[0, 0] == 1.0
+    Hi, Lo = lsq.lowprec_operands(E, W, 1, "bf16x3")
+    assert Hi[0, 0] == 1.0 and Lo[0, 0] == 2.0 ** -8
+    assert lsq.lowprec_operands(E, W, 1, "fp32")[0][0, 0] == 1.0 + 2.0 ** -8
+    # the float32 product is rounded to nearest even: (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24 is a tie
+    # (half an ulp of 2^-23), to even: 1 + 2^-11; (1 + 2^-12 + 2^-23)(1 + 2^-12) =
+    # 1 + 2^-11 + 2^-23 + 2^-24 + 2^-35 lies above the next tie and rounds up to 1 + 2^-11 + 2^-22
+    a = np.array([[1.0 + 2.0 ** -12], [1.0 + 2.0 ** -12 + 2.0 ** -23]])
+    z = lsq.form_z32(a, np.array([[1.0 + 2.0 ** -12], [1.0 + 2.0 ** -12]]), 1)
+    assert z[0, 0] == 1.0 + 2.0 ** -11
+    assert z[1, 0] == 1.0 + 2.0 ** -11 + 2.0 ** -22
+
+
 def test_split_bf16_hand_cases_and_bound():
     """Split bfloat16: a value with at most 8 significant bits has Lo = 0; the
     hand value 1 + 2^-8 + 2^-20 gives Hi = 1 + 2^-7 (above the tie) and
@@ -440,7 +463,7 @@ def test_gram_lowprec_split_bf16():
     inst = small_instance(4, 8, 1, 3, 5)
     Z = lsq.form_z(inst.E, inst.W, 1)
     G3 = lsq.gram_lowprec(inst.E, inst.W, 1, "bf16x3")
-    Hi, Lo = lsq.split_bf16(Z)
+    Hi, Lo = lsq.split_bf16(lsq.form_z32(inst.E, inst.W, 1))
     S = Hi + Lo
     assert np.abs(G3 - (S.T @ S - Lo.T @ Lo)).max() <= 1e-14 * np.abs(G3).max()
     assert np.all(np.abs(G3 - Z.T @ Z) <= 3 * 2.0 ** -16 * (np.abs(Z).T @ np.abs(Z)))
