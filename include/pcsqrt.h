@@ -135,6 +135,34 @@ typedef struct pc_plan pc_plan;
 pc_status pc_sqrt_build(const pc_instance *inst, int32_t count, const pc_options *opt,
                         void *stream, pc_plan **out);
 
+/* An instance whose localization modes are separable on an n_lat x n_lon
+ * latitude-longitude grid (grid column j = a * n_lon + i, a the latitude
+ * row, i the longitude): mode m is the product of a latitude factor and a
+ * longitude factor,
+ *   W[a * n_lon + i, m] = U[a, m] * Phi[i, m]   (FP64 product, rounded once),
+ * as for Fourier modes in longitude times latitude eigenvectors of an
+ * isotropic localization on such a grid.  The plan never forms W: every
+ * kernel that reads a mode value generates it from U and Phi where it is
+ * used (the paper points out that analytically defined modes need not be
+ * stored, Sec. 3.11).  Results equal those of a plan built with the dense W
+ * formed by that product, bit for bit.  n_h = n_lat * n_lon; other fields as
+ * in pc_instance. */
+typedef struct {
+  int64_t n_lat, n_lon, n_w, K, M;
+  const double *E; int64_t ldE;     /* device, n x K (n = n_lat n_lon n_w), segment order */
+  const double *U; int64_t ldU;     /* device, n_lat x M, ldU >= n_lat */
+  const double *Phi; int64_t ldPhi; /* device, n_lon x M, ldPhi >= n_lon */
+  int64_t max_rhs;
+} pc_instance_separable;
+
+/* pc_sqrt_build_separable — pc_sqrt_build for instances with separable
+ * modes: same options, ownership (E, U, Phi borrowed until destroy), checks
+ * (NaN/Inf in E, U and Phi) and statuses; every other call takes the plan as
+ * it comes.  Reduced-precision plans still keep their fp32 copy of the modes
+ * (formed from U and Phi). */
+pc_status pc_sqrt_build_separable(const pc_instance_separable *inst, int32_t count, const pc_options *opt,
+                                  void *stream, pc_plan **out);
+
 /* pc_gram_factor — for every instance form G = Z^T Z (or the Gram of the
  * rounded Z in reduced precision) from the per-column Grams and W, then
  * factor G = L L^T in FP64.  Synchronizes `stream` once to read the pivot

@@ -38,6 +38,16 @@ def form_z(E: np.ndarray, W: np.ndarray, n_w: int) -> np.ndarray:
     return np.concatenate([E[:, k:k + 1] * C_half for k in range(K)], axis=1)
 
 
+def separable_modes(U: np.ndarray, Phi: np.ndarray) -> np.ndarray:
+    """Dense modes from separable factors on an n_lat x n_lon grid (grid column
+    j = a*n_lon + i): W[a*n_lon + i, m] = U[a, m] * Phi[i, m], each product
+    formed once in float64 (modes defined analytically need not be stored,
+    Sec. 3.11; this is their value at each grid column)."""
+    n_lat, M = U.shape
+    n_lon = Phi.shape[0]
+    return (U[:, None, :] * Phi[None, :, :]).reshape(n_lat * n_lon, M)
+
+
 def localized_covariance(E: np.ndarray, W: np.ndarray, n_w: int) -> np.ndarray:
     """P^c = C o P^s (eq. HLocalizedPc) with P^s = E E^T and C = 1 (x) (W W^T) blocks."""
     Ps = E @ E.T                                       # eq. PsAndItsSquareRoot

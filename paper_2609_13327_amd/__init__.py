@@ -49,6 +49,7 @@ EXPORTED = [
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
     "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance", "pc_query_rhs_info", "pc_hybrid_apply",
+    "pc_sqrt_build_separable",
     "pc_swift_build", "pc_swift_apply", "pc_swift_destroy",
 ]
 
@@ -59,6 +60,12 @@ class PcInstance(ctypes.Structure):
     _fields_ = [("n_h", c_int64), ("n_w", c_int64), ("K", c_int64), ("M", c_int64),
                 ("E", c_void_p), ("ldE", c_int64), ("W", c_void_p), ("ldW", c_int64),
                 ("max_rhs", c_int64)]
+
+
+class PcInstanceSeparable(ctypes.Structure):
+    _fields_ = [("n_lat", c_int64), ("n_lon", c_int64), ("n_w", c_int64), ("K", c_int64), ("M", c_int64),
+                ("E", c_void_p), ("ldE", c_int64), ("U", c_void_p), ("ldU", c_int64),
+                ("Phi", c_void_p), ("ldPhi", c_int64), ("max_rhs", c_int64)]
 
 
 class PcRhsInfo(ctypes.Structure):
@@ -100,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     lib.pc_sqrt_build.argtypes = [POINTER(PcInstance), c_int32, POINTER(PcOptions), c_void_p,
                                   POINTER(c_void_p)]
+    lib.pc_sqrt_build_separable.argtypes = [POINTER(PcInstanceSeparable), c_int32, POINTER(PcOptions), c_void_p,
+                                            POINTER(c_void_p)]
     lib.pc_gram_factor.argtypes = [c_void_p, c_void_p, POINTER(c_int32)]
     lib.pc_left_inverse_apply.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
                                           POINTER(c_int64), POINTER(c_void_p), POINTER(c_int64),
@@ -213,8 +222,25 @@ def _stream(stream) -> int:
 def pc_sqrt_build(instances: Sequence[dict], precision: int = PC_PREC_FP64, max_refine: int = 0,
                   tol: float = 0.0, use_graph: int = 0, stream=None, flags: int = 0) -> int:
     """instances: dicts with E (n x K), W (n_h x M) column-major float64 device
-    tensors, n_w and max_rhs.  Returns the plan handle."""
+    tensors, n_w and max_rhs -- or, for separable modes, U (n_lat x M) and
+    Phi (n_lon x M) in place of W (pc_sqrt_build_separable).  Returns the plan
+    handle."""
     lib = load_library()
+    opt = PcOptions(int(precision), int(max_refine), float(tol), int(use_graph), int(flags))
+    if instances and "U" in instances[0]:
+        sep = (PcInstanceSeparable * len(instances))()
+        for i, d in enumerate(instances):
+            E, U, Phi = d["E"], d["U"], d["Phi"]
+            n_w = int(d.get("n_w", 1))
+            n_lat, n_lon = int(U.shape[0]), int(Phi.shape[0])
+            if E.shape[0] != n_lat * n_lon * n_w or U.shape[1] != Phi.shape[1]:
+                raise ValueError("E must have n_lat * n_lon * n_w rows; U and Phi the same mode count")
+            sep[i] = PcInstanceSeparable(n_lat, n_lon, n_w, int(E.shape[1]), int(U.shape[1]), _ptr(E), _ld(E),
+                                         _ptr(U), _ld(U), _ptr(Phi), _ld(Phi), int(d.get("max_rhs", 1)))
+        plan = c_void_p()
+        _check(lib.pc_sqrt_build_separable(sep, len(instances), ctypes.byref(opt), c_void_p(_stream(stream)),
+                                           ctypes.byref(plan)), "pc_sqrt_build_separable")
+        return plan.value
     arr = (PcInstance * len(instances))()
     for i, d in enumerate(instances):
         E, W = d["E"], d["W"]
@@ -224,7 +250,6 @@ def pc_sqrt_build(instances: Sequence[dict], precision: int = PC_PREC_FP64, max_
                             _ld(W), int(d.get("max_rhs", 1)))
         if E.shape[0] != n_h * n_w:
             raise ValueError("E must have n_h * n_w rows")
-    opt = PcOptions(int(precision), int(max_refine), float(tol), int(use_graph), int(flags))
     plan = c_void_p()
     _check(lib.pc_sqrt_build(arr, len(instances), ctypes.byref(opt), c_void_p(_stream(stream)),
                              ctypes.byref(plan)), "pc_sqrt_build")
@@ -562,7 +587,7 @@ class Plan:
 
     def __init__(self, instances: Sequence[dict], precision: int = PC_PREC_FP64, max_refine: int = 0,
                  tol: float = 0.0, use_graph: int = 0, stream=None, flags: int = 0):
-        self._keep = [(d["E"], d["W"]) for d in instances]
+        self._keep = [tuple(d[k] for k in ("E", "W", "U", "Phi") if k in d) for d in instances]
         self.instances = list(instances)
         self.handle = pc_sqrt_build(instances, precision, max_refine, tol, use_graph, stream, flags)
 

@@ -21,14 +21,14 @@
 namespace pc {
 
 // ------------------------------------------------------------------ Z^T X
-template <int BM_, int BN_, int WM_, int WN_>
+template <int BM_, int BN_, int WM_, int WN_, class WS>
 struct ZtxProb {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = 16;
   static constexpr int LDA = BM + 1, LDB = BN + 1;
   static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
   static_assert(NA >= 1 && NB_ >= 1, "tile too small for 256 threads");
   const double* E; int64_t ldE;
-  const double* W; int64_t ldW;
+  WS w;
   const double* X; int64_t ldX;
   double* Bout; int64_t ldB;
   int64_t n_h, n_w, K, M, R, KR;
@@ -81,7 +81,7 @@ struct ZtxProb {
       const int e = t + 256 * i;
       const int jj = e % KC, col = e / KC;
       const int64_t j = (int64_t)chunk * KC + jj, m = c.m0 + col;
-      r.v[i] = (j < n_h && m < M) ? W[j + m * ldW] : 0.0;
+      r.v[i] = (j < n_h && m < M) ? w(j, m) : 0.0;
     }
   }
   __device__ void storeB(const BRegs& r, double* Bs) const {
@@ -102,12 +102,12 @@ struct ZtxProb {
   }
 };
 
-template <class P>
-static hipError_t run_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
+template <class P, class WS>
+static hipError_t run_ztx(const Inst& in, WS w, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
                           hipStream_t s, const int* skip) {
   P pr;
   pr.skip = skip;
-  pr.E = in.E; pr.ldE = in.ldE; pr.W = in.W; pr.ldW = in.ldW;
+  pr.E = in.E; pr.ldE = in.ldE; pr.w = w;
   pr.X = X; pr.ldX = ldX; pr.Bout = B; pr.ldB = ldB;
   pr.n_h = in.n_h; pr.n_w = in.n_w; pr.K = in.K; pr.M = in.M; pr.R = R; pr.KR = in.K * R;
   pr.ntr = (int)ceil_div(pr.KR, P::BM);
@@ -126,9 +126,10 @@ static hipError_t run_ztx(const Inst& in, const double* X, int64_t ldX, int64_t 
 constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1, ZKB = 2;
 constexpr int ZNQ = ZKC * ZT / 256;     // X and W values staged per thread and chunk
 
+template <class WS>
 struct Ztx1Args {
   const double* E; int64_t ldE;
-  const double* W; int64_t ldW;
+  WS w;
   const double* X; int64_t ldX;
   double* B; int64_t ldB;
   int64_t n_h, K, M, R;
@@ -137,7 +138,8 @@ struct Ztx1Args {
   const int* skip;
 };
 
-__global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
+template <class WS>
+__global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args<WS> a) {
   if (a.skip && *a.skip) return;
   __shared__ double Xs[2][ZKC * ZLD];
   __shared__ double Ws[2][ZKC * ZLD];
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args a) {
       const int e = t + 256 * q, jj = e % ZKC, col = e / ZKC;
       const int64_t j = j0 + jj;
       xv[q] = (j < jend && r0 + col < a.R) ? a.X[j + (r0 + col) * a.ldX] : 0.0;
-      wv[q] = (j < jend && m0 + col < a.M) ? a.W[j + (m0 + col) * a.ldW] : 0.0;
+      wv[q] = (j < jend && m0 + col < a.M) ? a.w(j, m0 + col) : 0.0;
     }
     if (estage) ev = (evalid && j0 + ej < jend) ? Ek[j0 + ej] : 0.0;
   };
@@ -250,11 +252,12 @@ __global__ void zero_block_kernel(double* B, int64_t ld, int64_t rows, int64_t c
     B[i + c * ld] = 0.0;
 }
 
-static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
+template <class WS>
+static hipError_t run_ztx1(const Inst& in, WS w, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
                            hipStream_t s, const int* skip) {
-  Ztx1Args a;
+  Ztx1Args<WS> a;
   a.skip = skip;
-  a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
+  a.E = in.E; a.ldE = in.ldE; a.w = w; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
   a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
   a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT); a.ntk = (int)ceil_div(in.K, ZKB);
   int dev = 0, cus = 0;
@@ -270,27 +273,34 @@ static hipError_t run_ztx1(const Inst& in, const double* X, int64_t ldX, int64_t
     hipLaunchKernelGGL(zero_block_kernel, dim3(gx, (unsigned)R), dim3(256), 0, s, B, ldB, in.KM, R, skip);
   }
   const int64_t units = ntiles * a.split;
-  hipLaunchKernelGGL(ztx1_kernel, dim3((unsigned)(8 * ((units + 7) / 8))), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(ztx1_kernel<WS>, dim3((unsigned)(8 * ((units + 7) / 8))), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+template <class WS>
+static hipError_t ztx_for(const Inst& in, WS w, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
+                          hipStream_t s, const int* skip) {
+  if (in.n_w == 1) return run_ztx1(in, w, X, ldX, R, B, ldB, s, skip);
+  if (in.M <= 32) return run_ztx<ZtxProb<128, 32, 4, 1, WS>>(in, w, X, ldX, R, B, ldB, s, skip);
+  return run_ztx<ZtxProb<64, 64, 2, 2, WS>>(in, w, X, ldX, R, B, ldB, s, skip);
 }
 
 hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
                       hipStream_t s, const int* skip) {
   if (R <= 0) return hipSuccess;
-  if (in.n_w == 1) return run_ztx1(in, X, ldX, R, B, ldB, s, skip);
-  if (in.M <= 32) return run_ztx<ZtxProb<128, 32, 4, 1>>(in, X, ldX, R, B, ldB, s, skip);
-  return run_ztx<ZtxProb<64, 64, 2, 2>>(in, X, ldX, R, B, ldB, s, skip);
+  return in.W ? ztx_for(in, wdense(in), X, ldX, R, B, ldB, s, skip)
+              : ztx_for(in, wsep(in), X, ldX, R, B, ldB, s, skip);
 }
 
 // ------------------------------------------------------------------- Z Y
-template <int BM_, int BN_, int WM_, int WN_>
+template <int BM_, int BN_, int WM_, int WN_, class WS>
 struct ZyProb {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = 16;
   static constexpr int LDA = BM + 1, LDB = BN;
   static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
   static_assert(NA >= 1 && NB_ >= 1, "tile too small for 256 threads");
   const double* E; int64_t ldE;
-  const double* W; int64_t ldW;
+  WS w;
   const double* Y; int64_t ldY;
   const double* Xs; int64_t ldXs;   // optional: out = alpha Xs + beta Z Y (else beta Z Y)
   double alpha, beta;
@@ -340,7 +350,7 @@ struct ZyProb {
       double z = 0.0;
       if (q < KM && ii < n) {
         const int64_t k = q / M, m = q % M, j = ii % n_h;
-        z = E[ii + k * ldE] * W[j + m * ldW];
+        z = E[ii + k * ldE] * w(j, m);
       }
       r.v[i] = z;
     }
@@ -362,14 +372,14 @@ struct ZyProb {
   }
 };
 
-template <class P>
-static hipError_t run_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs,
+template <class P, class WS>
+static hipError_t run_zy(const Inst& in, WS w, const double* Y, int64_t ldY, int64_t R, const double* Xs,
                          int64_t ldXs, double alpha, double beta, double* out, int64_t ldOut, hipStream_t s,
                          const int* skip) {
   P pr;
   pr.skip = skip;
   pr.alpha = alpha; pr.beta = beta;
-  pr.E = in.E; pr.ldE = in.ldE; pr.W = in.W; pr.ldW = in.ldW;
+  pr.E = in.E; pr.ldE = in.ldE; pr.w = w;
   pr.Y = Y; pr.ldY = ldY; pr.Xs = Xs; pr.ldXs = ldXs; pr.Out = out; pr.ldO = ldOut;
   pr.n_h = in.n_h; pr.n = in.n; pr.K = in.K; pr.M = in.M; pr.KM = in.KM; pr.R = R;
   pr.ntr = (int)ceil_div(R, P::BM);
@@ -386,9 +396,10 @@ static hipError_t run_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R
 // at fragment time from staged W rows and the member's E values.
 constexpr int YT = 64, YKC = 16, YLD = YT + 1;
 
+template <class WS>
 struct Zy1Args {
   const double* E; int64_t ldE;
-  const double* W; int64_t ldW;
+  WS w;
   const double* Y; int64_t ldY;
   const double* Xs; int64_t ldXs;
   double alpha, beta;
@@ -398,7 +409,8 @@ struct Zy1Args {
   const int* skip;
 };
 
-__global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
+template <class WS>
+__global__ __launch_bounds__(256) void zy1_kernel(Zy1Args<WS> a) {
   if (a.skip && *a.skip) return;
   __shared__ double Ys[2][YKC * YLD];    // Ys[q][r]
   __shared__ double Zs[2][YKC * YLD];    // Zs[q][j] = E[j,k(q)] W[j,m(q)]
@@ -428,7 +440,7 @@ __global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
         double z = 0.0;
         if (q < a.KM && j < a.n_h) {
           const int64_t k = q / a.M, m = q - k * a.M;
-          z = a.E[j + k * a.ldE] * a.W[j + m * a.ldW];
+          z = a.E[j + k * a.ldE] * a.w(j, m);
         }
         zv[h] = z;
       }
@@ -485,24 +497,32 @@ __global__ __launch_bounds__(256) void zy1_kernel(Zy1Args a) {
       }
 }
 
+template <class WS>
+static hipError_t zy_for(const Inst& in, WS w, const double* Y, int64_t ldY, int64_t R, const double* Xs,
+                         int64_t ldXs, double alpha, double beta, double* out, int64_t ldOut, hipStream_t s,
+                         const int* skip) {
+  if (in.n_w == 1) {
+    Zy1Args<WS> a;
+    a.skip = skip;
+    a.alpha = alpha; a.beta = beta;
+    a.E = in.E; a.ldE = in.ldE; a.w = w; a.Y = Y; a.ldY = ldY; a.Xs = Xs; a.ldXs = ldXs;
+    a.Out = out; a.ldO = ldOut; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.KM = in.KM; a.R = R;
+    a.ntr = (int)ceil_div(R, YT); a.ntj = (int)ceil_div(in.n_h, YT);
+    const int64_t ntiles = (int64_t)a.ntr * a.ntj;
+    hipLaunchKernelGGL(zy1_kernel<WS>, dim3((unsigned)(8 * ((ntiles + 7) / 8))), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4, WS>>(in, w, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+  if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4, WS>>(in, w, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+  return run_zy<ZyProb<64, 64, 2, 2, WS>>(in, w, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+}
+
 hipError_t launch_zy_axpby(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs,
                            int64_t ldXs, double alpha, double beta, double* out, int64_t ldOut, hipStream_t s,
                            const int* skip) {
   if (R <= 0) return hipSuccess;
-  if (in.n_w == 1) {
-    Zy1Args a;
-    a.skip = skip;
-    a.alpha = alpha; a.beta = beta;
-    a.E = in.E; a.ldE = in.ldE; a.W = in.W; a.ldW = in.ldW; a.Y = Y; a.ldY = ldY; a.Xs = Xs; a.ldXs = ldXs;
-    a.Out = out; a.ldO = ldOut; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.KM = in.KM; a.R = R;
-    a.ntr = (int)ceil_div(R, YT); a.ntj = (int)ceil_div(in.n_h, YT);
-    const int64_t ntiles = (int64_t)a.ntr * a.ntj;
-    hipLaunchKernelGGL(zy1_kernel, dim3((unsigned)(8 * ((ntiles + 7) / 8))), dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-  if (R <= 16) return run_zy<ZyProb<16, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
-  if (R <= 32) return run_zy<ZyProb<32, 128, 1, 4>>(in, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
-  return run_zy<ZyProb<64, 64, 2, 2>>(in, Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
+  return in.W ? zy_for(in, wdense(in), Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip)
+              : zy_for(in, wsep(in), Y, ldY, R, Xs, ldXs, alpha, beta, out, ldOut, s, skip);
 }
 
 hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xs, int64_t ldXs,

@@ -97,9 +97,10 @@ constexpr int GWS = 36;                           // W row stride in LDS: the fo
 constexpr int GSR = GKC / 4;                      // S rows staged per thread and chunk (two pairs each)
 constexpr int GWH = (GKC * GWC + 255) / 256;      // W values staged per thread and chunk
 
+template <class WS>
 struct GramArgs {
   const double* S; int64_t ldS;
-  const double* W; int64_t ldW;
+  WS w;
   int64_t n_h, M, P;
   const int* pairs; const int* qtiles;
   int npt, nq, ntiles, split;
@@ -107,7 +108,8 @@ struct GramArgs {
   double* G; double* G2; int64_t ldG;     // part q >= 1 goes to G2 + (q - 1) ldG^2
 };
 
-__global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
+template <class WS>
+__global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
   __shared__ double As[2][GKC * GB];
   __shared__ double Ws[2][GKC * GWS];
   const int64_t units = (int64_t)a.ntiles * a.split;
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs a) {
 #pragma unroll
     for (int h = 0; h < GWH; ++h) {
       const int64_t j = j0 + wrow[h];
-      wv[h] = (wcol[h] < GWC && j < jend && wm_idx[h] < a.M) ? a.W[j + wm_idx[h] * a.ldW] : 0.0;
+      wv[h] = (wcol[h] < GWC && j < jend && wm_idx[h] < a.M) ? a.w(j, wm_idx[h]) : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -246,9 +248,10 @@ int gram_parts_used(const Inst& in) {
   return want - 1 <= in.g2_parts ? want : 1 + in.g2_parts;
 }
 
-hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
-  GramArgs a;
-  a.S = in.S; a.ldS = in.ldS; a.W = in.W; a.ldW = in.ldW;
+template <class WS>
+static hipError_t run_gram_f64(const Inst& in, WS w, hipStream_t s) {
+  GramArgs<WS> a;
+  a.S = in.S; a.ldS = in.ldS; a.w = w;
   a.n_h = in.n_h; a.M = in.M; a.P = in.P;
   a.pairs = in.pairs; a.qtiles = in.qtiles;
   a.npt = (int)ceil_div(in.P, GB); a.nq = in.nq; a.ntiles = a.npt * a.nq;
@@ -257,8 +260,12 @@ hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
   a.G = in.G; a.G2 = a.split > 1 ? in.G2 : nullptr; a.ldG = in.KMp;
   const int64_t units = (int64_t)a.ntiles * a.split;
   const int64_t grid = 8 * ((units + 7) / 8);
-  hipLaunchKernelGGL(gram_f64_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(gram_f64_kernel<WS>, dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_gram_f64(const Inst& in, hipStream_t s) {
+  return in.W ? run_gram_f64(in, wdense(in), s) : run_gram_f64(in, wsep(in), s);
 }
 
 // ------------------------------------ padding of the Gram and its diagonal

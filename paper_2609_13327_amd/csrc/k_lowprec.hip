@@ -310,14 +310,14 @@ struct Raw4 { double e[4], w[4]; };
 // c + 1 are issued before the MFMAs of chunk c and converted after them.
 // ONE: n_w = 1 and every chunk but a ragged last one is read as contiguous
 // rows without checks; otherwise each row is checked and j = i mod n_h.
-template <bool ONE>
-__device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, int64_t a0, int64_t b0,
+template <bool ONE, class WS>
+__device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, WS ws, int64_t a0, int64_t b0,
                                                 float (&As)[2][LT * FST], float (&Bs)[2][LT * FST]) {
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 2, wn = w & 3, r = lane & 15, kq = lane >> 4;
   const int seg = t & 3, col = t >> 2;
   const double* pe[2];
-  const double* pw[2];
+  int64_t mc[2];
   bool valid[2];
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -326,7 +326,7 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, int64_t a0
     int64_t k = 0, m = 0;
     if (valid[side]) { k = c / g.M; m = c - k * g.M; }
     pe[side] = g.E + k * g.ldE;
-    pw[side] = g.W + m * g.ldW;
+    mc[side] = m;
   }
   const int64_t nchunks = (g.n + FKC - 1) / FKC;
   const int64_t nfull = ONE ? g.n / FKC : 0;     // chunks read without row checks
@@ -340,7 +340,7 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, int64_t a0
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           raw[side].e[q] = pe[side][i0 + q];
-          raw[side].w[q] = pw[side][i0 + q];
+          raw[side].w[q] = ws(i0 + q, mc[side]);
         }
       return;
     }
@@ -351,7 +351,7 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, int64_t a0
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         raw[side].e[q] = in ? pe[side][i0 + q] : 0.0;
-        raw[side].w[q] = in ? pw[side][j] : 0.0;
+        raw[side].w[q] = in ? ws(j, mc[side]) : 0.0;
       }
       if (++j == g.n_h) j = 0;
     }
@@ -409,8 +409,15 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, int64_t a0
 __device__ __forceinline__ void gram_f32_tile(const LowGramInst& g, int64_t a0, int64_t b0) {
   __shared__ float As[2][LT * FST];
   __shared__ float Bs[2][LT * FST];
-  if (g.n_w == 1) gram_f32_tile_w<true>(g, a0, b0, As, Bs);
-  else gram_f32_tile_w<false>(g, a0, b0, As, Bs);
+  if (g.W) {
+    const WDense ws{g.W, g.ldW};
+    if (g.n_w == 1) gram_f32_tile_w<true>(g, ws, a0, b0, As, Bs);
+    else gram_f32_tile_w<false>(g, ws, a0, b0, As, Bs);
+  } else {
+    const WSep ws{g.U, g.ldU, g.Phi, g.ldPhi, g.n_lon, g.inv_lon};
+    if (g.n_w == 1) gram_f32_tile_w<true>(g, ws, a0, b0, As, Bs);
+    else gram_f32_tile_w<false>(g, ws, a0, b0, As, Bs);
+  }
 }
 
 template <int MODE>
@@ -474,8 +481,9 @@ std::vector<int> lowgram_tile_order(int64_t KM, int64_t M) {
 }
 
 static LowGramInst lowgram_args(const Inst& in) {
-  return LowGramInst{in.E, in.ldE, in.W, in.ldW, in.E32, in.ldE32, in.W32, in.ldW32,
-                     in.n, in.n_h, in.n_w, in.K, in.M, in.KM, in.G, in.KMp};
+  const WSep sep = wsep(in);
+  return LowGramInst{in.E, in.ldE, in.W, in.ldW, in.U, in.ldU, in.Phi, in.ldPhi, in.n_lon, sep.inv,
+                     in.E32, in.ldE32, in.W32, in.ldW32, in.n, in.n_h, in.n_w, in.K, in.M, in.KM, in.G, in.KMp};
 }
 
 // fp32 copies of E and W for the bf16 forms (round to nearest even); the
@@ -489,12 +497,28 @@ __global__ __launch_bounds__(256) void stage_f32_kernel(const double* __restrict
   }
 }
 
+// The fp32 copy of the modes, from either source (the FP64 value rounded once).
+template <class WS>
+__global__ __launch_bounds__(256) void stage_w32_kernel(WS w, int64_t n_h, int64_t M, float* __restrict__ B,
+                                                        int64_t ldB) {
+  const int64_t total = n_h * M;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t m = e / n_h, j = e - m * n_h;
+    B[j + m * ldB] = (float)w(j, m);
+  }
+}
+
 hipError_t launch_stage_f32(const Inst& in, hipStream_t s) {
   if (!in.E32 || !in.W32) return hipErrorInvalidValue;
   const unsigned ge = (unsigned)std::min<int64_t>(ceil_div(in.n * in.K, 256), 8192);
   hipLaunchKernelGGL(stage_f32_kernel, dim3(ge), dim3(256), 0, s, in.E, in.ldE, in.n, in.K, in.E32, in.ldE32);
   const unsigned gw = (unsigned)std::min<int64_t>(ceil_div(in.n_h * in.M, 256), 8192);
-  hipLaunchKernelGGL(stage_f32_kernel, dim3(gw), dim3(256), 0, s, in.W, in.ldW, in.n_h, in.M, in.W32, in.ldW32);
+  if (in.W)
+    hipLaunchKernelGGL(stage_w32_kernel<WDense>, dim3(gw), dim3(256), 0, s, wdense(in), in.n_h, in.M, in.W32,
+                       in.ldW32);
+  else
+    hipLaunchKernelGGL(stage_w32_kernel<WSep>, dim3(gw), dim3(256), 0, s, wsep(in), in.n_h, in.M, in.W32,
+                       in.ldW32);
   return hipGetLastError();
 }
 

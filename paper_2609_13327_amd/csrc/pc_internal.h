@@ -7,6 +7,29 @@
 
 namespace pc {
 
+// The localization modes read by the kernels: a dense n_h x M matrix, or
+// separable modes generated where they are read,
+//   W[a n_lon + i, m] = U[a, m] * Phi[i, m]   (a: latitude row, i: longitude),
+// so that no n_h x M array exists (the paper notes that analytic modes can be
+// computed when needed instead of stored, Sec. 3.11).  Both return the same
+// FP64 value for the same (j, m): fl(U Phi) is the definition of W then.
+struct WDense {
+  const double* W; int64_t ld;
+  __device__ __forceinline__ double operator()(int64_t j, int64_t m) const { return W[j + m * ld]; }
+};
+struct WSep {
+  const double* U; int64_t ldU;
+  const double* Phi; int64_t ldPhi;
+  int64_t n_lon; double inv;   // inv = 1 / n_lon (row split by a rounded quotient, corrected once)
+  __device__ __forceinline__ double operator()(int64_t j, int64_t m) const {
+    int64_t a = (int64_t)((double)j * inv);
+    int64_t i = j - a * n_lon;
+    if (i < 0) { --a; i += n_lon; } else if (i >= n_lon) { ++a; i -= n_lon; }
+    return U[a + m * ldU] * Phi[i + m * ldPhi];
+  }
+};
+
+
 constexpr int NB = 64;  // Cholesky / triangular-solve block size
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -35,7 +58,10 @@ struct Inst {
   int64_t n_h, n_w, K, M;
   int64_t n, KM, KMp, P;   // n = n_h*n_w, KMp = KM rounded up to NB, P = K(K+1)/2
   const double* E; int64_t ldE;
-  const double* W; int64_t ldW;
+  const double* W; int64_t ldW;          // dense modes (null for separable modes)
+  const double* U = nullptr; int64_t ldU = 0;      // separable modes: n_lat x M latitude factors
+  const double* Phi = nullptr; int64_t ldPhi = 0;  // and n_lon x M longitude factors
+  int64_t n_lon = 0;
   int64_t max_rhs;
   // plan-owned device buffers
   double* G = nullptr;       // KMp x KMp, ld = KMp; Gram then its Cholesky factor (lower)
@@ -102,6 +128,11 @@ struct Inst {
   double last_rel = 0.0;
 };
 
+inline WDense wdense(const Inst& in) { return WDense{in.W, in.ldW}; }
+inline WSep wsep(const Inst& in) {
+  return WSep{in.U, in.ldU, in.Phi, in.ldPhi, in.n_lon, 1.0 / (double)(in.n_lon > 0 ? in.n_lon : 1)};
+}
+
 // Mode-pair tiles of the FP64 Gram (four ints per tile: m0, m0', m1, m1').
 std::vector<int> make_qtiles(int64_t M);
 
@@ -120,7 +151,10 @@ std::vector<int> lowgram_tile_order(int64_t KM, int64_t M);
 // (the rounded Z is formed tile by tile from E and W inside the Gram kernel)
 struct LowGramInst {
   const double* E; int64_t ldE;
-  const double* W; int64_t ldW;
+  const double* W; int64_t ldW;       // dense modes, or null: separable (U, Phi)
+  const double* U; int64_t ldU;
+  const double* Phi; int64_t ldPhi;
+  int64_t n_lon; double inv_lon;
   const float* E32; int64_t ldE32;   // fp32 copies (bf16 forms only)
   const float* W32; int64_t ldW32;
   int64_t n, n_h, n_w, K, M, KM;

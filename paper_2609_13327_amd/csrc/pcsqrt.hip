@@ -703,47 +703,38 @@ const char* pc_status_string(pc_status s) {
   return "unknown status";
 }
 
-pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options* opt, void* stream,
-                        pc_plan** out) {
-  if (!out) return PC_ERR_INVALID_ARG;
-  *out = nullptr;
-  if (!inst || count <= 0) return PC_ERR_INVALID_ARG;
-  pc_options o{PC_PREC_FP64, 0, 1e-12, 0, 0};
-  if (opt) o = *opt;
-  if (o.precision < PC_PREC_FP64 || o.precision > PC_PREC_BF16X3_REFINE || o.max_refine < 0 ||
-      (o.flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS | PC_FLAG_FIXED_PRECISION)) != 0 ||
-      !std::isfinite(o.tol))
+// Options as given (NULL: FP64 defaults), validated.
+static pc_status checked_options(const pc_options* opt, pc_options* o) {
+  *o = pc_options{PC_PREC_FP64, 0, 1e-12, 0, 0};
+  if (opt) *o = *opt;
+  if (o->precision < PC_PREC_FP64 || o->precision > PC_PREC_BF16X3_REFINE || o->max_refine < 0 ||
+      (o->flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS | PC_FLAG_FIXED_PRECISION)) != 0 ||
+      !std::isfinite(o->tol))
     return PC_ERR_INVALID_ARG;
-  if ((o.flags & PC_FLAG_CG_MEMBER_BLOCKS) && !(o.flags & PC_FLAG_KEEP_GRAM)) return PC_ERR_INVALID_ARG;
-  if (o.tol <= 0) o.tol = 1e-12;
-  for (int32_t i = 0; i < count; ++i) {
-    const pc_instance& a = inst[i];
-    if (a.n_h < 1 || a.n_w < 1 || a.K < 1 || a.M < 1) return PC_ERR_SHAPE;
-    if (a.K * a.M > a.n_h * a.n_w) return PC_ERR_SHAPE;
-    if (!ok_ptr(a.E) || !ok_ptr(a.W)) return PC_ERR_INVALID_ARG;
-    if (a.ldE < a.n_h * a.n_w || a.ldW < a.n_h || a.max_rhs < 0) return PC_ERR_INVALID_ARG;
-  }
+  if ((o->flags & PC_FLAG_CG_MEMBER_BLOCKS) && !(o->flags & PC_FLAG_KEEP_GRAM)) return PC_ERR_INVALID_ARG;
+  if (o->tol <= 0) o->tol = 1e-12;
+  return PC_OK;
+}
+
+// A plan over instances whose sizes, E and modes (dense W, or separable U and
+// Phi) are set and validated: allocation, streams, batches, finiteness of
+// the inputs, pair tables.
+static pc_status build_plan(const std::vector<Inst>& descs, const pc_options& o, hipStream_t s, pc_plan** out) {
+  const int32_t count = (int32_t)descs.size();
   pc_plan* p = new (std::nothrow) pc_plan();
   if (!p) return PC_ERR_OOM;
   p->opt = o;
   hipGetDevice(&p->device);
-  hipStream_t s = (hipStream_t)stream;
   pc_status st = PC_OK;
   if (hipMalloc((void**)&p->d_flag, sizeof(int)) != hipSuccess) st = PC_ERR_OOM;
-  int64_t max_r = 1;
   for (int32_t i = 0; i < count && st == PC_OK; ++i) {
-    const pc_instance& a = inst[i];
-    Inst in;
-    in.n_h = a.n_h; in.n_w = a.n_w; in.K = a.K; in.M = a.M;
-    in.n = a.n_h * a.n_w; in.KM = a.K * a.M; in.KMp = pc::round_up(in.KM, pc::NB);
-    in.P = a.K * (a.K + 1) / 2;
-    in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
+    Inst in = descs[i];
+    in.n = in.n_h * in.n_w; in.KM = in.K * in.M; in.KMp = pc::round_up(in.KM, pc::NB);
+    in.P = in.K * (in.K + 1) / 2;
     in.prec = o.precision;
     p->inst.push_back(in);
     st = alloc_inst(p->inst.back(), o.precision, o.flags, count > 1);
-    max_r = std::max<int64_t>(max_r, a.max_rhs);
   }
-  (void)max_r;
   if (st == PC_OK && hipHostMalloc((void**)&p->h_ctl, sizeof(pc::RefineCtl) * (size_t)count) != hipSuccess)
     st = PC_ERR_OOM;
   if (st == PC_OK && hipHostMalloc((void**)&p->h_status, sizeof(int) * (2 * (size_t)count + 1)) != hipSuccess)
@@ -772,15 +763,20 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
       !(p->lowgram = pc::make_lowgram_batch(p->inst)))
     st = PC_ERR_OOM;
   if (st == PC_OK) {
-    // finiteness of E and W, then the pair tables
+    // finiteness of E and of the modes (W, or its factors U and Phi), then the pair tables
     int bad = 0;
     if (hipMemsetAsync(p->d_flag, 0, sizeof(int), s) != hipSuccess) st = PC_ERR_DEVICE;
     for (auto& in : p->inst) {
       if (st != PC_OK) break;
-      if (pc::launch_nonfinite_check(in.E, in.ldE, in.n, in.K, p->d_flag, s) != hipSuccess ||
-          pc::launch_nonfinite_check(in.W, in.ldW, in.n_h, in.M, p->d_flag, s) != hipSuccess ||
-          pc::launch_pairs_init(in, s) != hipSuccess)
-        st = PC_ERR_DEVICE;
+      hipError_t e = pc::launch_nonfinite_check(in.E, in.ldE, in.n, in.K, p->d_flag, s);
+      if (in.W) {
+        if (e == hipSuccess) e = pc::launch_nonfinite_check(in.W, in.ldW, in.n_h, in.M, p->d_flag, s);
+      } else {
+        if (e == hipSuccess) e = pc::launch_nonfinite_check(in.U, in.ldU, in.n_h / in.n_lon, in.M, p->d_flag, s);
+        if (e == hipSuccess) e = pc::launch_nonfinite_check(in.Phi, in.ldPhi, in.n_lon, in.M, p->d_flag, s);
+      }
+      if (e == hipSuccess) e = pc::launch_pairs_init(in, s);
+      if (e != hipSuccess) st = PC_ERR_DEVICE;
     }
     if (st == PC_OK && (hipMemcpyAsync(&bad, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess))
@@ -793,6 +789,54 @@ pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options
   }
   *out = p;
   return PC_OK;
+}
+
+pc_status pc_sqrt_build(const pc_instance* inst, int32_t count, const pc_options* opt, void* stream,
+                        pc_plan** out) {
+  if (!out) return PC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!inst || count <= 0) return PC_ERR_INVALID_ARG;
+  pc_options o;
+  const pc_status os = checked_options(opt, &o);
+  if (os != PC_OK) return os;
+  std::vector<Inst> descs;
+  for (int32_t i = 0; i < count; ++i) {
+    const pc_instance& a = inst[i];
+    if (a.n_h < 1 || a.n_w < 1 || a.K < 1 || a.M < 1) return PC_ERR_SHAPE;
+    if (a.K * a.M > a.n_h * a.n_w) return PC_ERR_SHAPE;
+    if (!ok_ptr(a.E) || !ok_ptr(a.W)) return PC_ERR_INVALID_ARG;
+    if (a.ldE < a.n_h * a.n_w || a.ldW < a.n_h || a.max_rhs < 0) return PC_ERR_INVALID_ARG;
+    Inst in;
+    in.n_h = a.n_h; in.n_w = a.n_w; in.K = a.K; in.M = a.M;
+    in.E = a.E; in.ldE = a.ldE; in.W = a.W; in.ldW = a.ldW; in.max_rhs = a.max_rhs;
+    descs.push_back(in);
+  }
+  return build_plan(descs, o, (hipStream_t)stream, out);
+}
+
+pc_status pc_sqrt_build_separable(const pc_instance_separable* inst, int32_t count, const pc_options* opt,
+                                  void* stream, pc_plan** out) {
+  if (!out) return PC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!inst || count <= 0) return PC_ERR_INVALID_ARG;
+  pc_options o;
+  const pc_status os = checked_options(opt, &o);
+  if (os != PC_OK) return os;
+  std::vector<Inst> descs;
+  for (int32_t i = 0; i < count; ++i) {
+    const pc_instance_separable& a = inst[i];
+    if (a.n_lat < 1 || a.n_lon < 1 || a.n_w < 1 || a.K < 1 || a.M < 1) return PC_ERR_SHAPE;
+    const int64_t n_h = a.n_lat * a.n_lon;
+    if (a.K * a.M > n_h * a.n_w || n_h * a.n_w >= ((int64_t)1 << 40)) return PC_ERR_SHAPE;
+    if (!ok_ptr(a.E) || !ok_ptr(a.U) || !ok_ptr(a.Phi)) return PC_ERR_INVALID_ARG;
+    if (a.ldE < n_h * a.n_w || a.ldU < a.n_lat || a.ldPhi < a.n_lon || a.max_rhs < 0) return PC_ERR_INVALID_ARG;
+    Inst in;
+    in.n_h = n_h; in.n_w = a.n_w; in.K = a.K; in.M = a.M;
+    in.E = a.E; in.ldE = a.ldE; in.W = nullptr; in.ldW = 0; in.max_rhs = a.max_rhs;
+    in.U = a.U; in.ldU = a.ldU; in.Phi = a.Phi; in.ldPhi = a.ldPhi; in.n_lon = a.n_lon;
+    descs.push_back(in);
+  }
+  return build_plan(descs, o, (hipStream_t)stream, out);
 }
 
 pc_status pc_gram_assemble(pc_plan* p, void* stream) {

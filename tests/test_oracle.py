@@ -470,3 +470,24 @@ def test_gram_lowprec_split_bf16():
     Eb, Wb = lsq.round_bf16(inst.E), np.ones((inst.n_h, 1))
     Zb = lsq.form_z(Eb, Wb, 1)
     assert np.array_equal(lsq.gram_lowprec(Eb, Wb, 1, "bf16x3"), Zb.T @ Zb)
+
+
+def test_separable_modes_match_the_generator():
+    """The separable form of the generator's modes: the oracle's product
+    U[a, m] Phi[i, m] at grid column a n_lon + i equals localization_modes'
+    W to rounding (same modes, products in another order), and its columns
+    are orthogonal with squared norms the eigenvalues (unit Fourier columns
+    times orthonormal latitude vectors)."""
+    for n_lat, n_lon, M, ell in ((6, 12, 20, 0.5), (8, 16, 37, 0.3)):
+        U, Phi, info = wl.localization_factors(n_lat, n_lon, M, ell)
+        W, info2 = wl.localization_modes(n_lat, n_lon, M, ell)
+        Ws = lsq.separable_modes(U, Phi)
+        assert np.abs(Ws - W).max() <= 8 * 2.0 ** -53 * np.abs(W).max()
+        assert np.array_equal(info["eigvals"], info2["eigvals"])
+        Gm = Ws.T @ Ws
+        lam = info["eigvals"][:M]
+        assert np.abs(np.diag(Gm) - lam).max() <= 1e-13 * lam.max()
+        assert np.abs(Gm - np.diag(np.diag(Gm))).max() <= 1e-13 * lam.max()
+        # lat-major: row a n_lon + i of W is U[a] * Phi[i]
+        a, i, m = n_lat - 2, 3, M - 1
+        assert Ws[a * n_lon + i, m] == U[a, m] * Phi[i, m]

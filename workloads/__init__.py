@@ -119,6 +119,35 @@ def grf_draws(n_lat: int, n_lon: int, count: int, length: float,
 
 
 @_one_thread
+def localization_factors(n_lat: int, n_lon: int, M: int, length: float):
+    """The M leading localization modes of `localization_modes` in separable
+    form: mode m is sqrt(lambda_m) u_m (a latitude eigenvector, n_lat values)
+    times a real Fourier mode in longitude (n_lon values), same order.
+    Returns (U, Phi, info): U (n_lat x M) = sqrt(lambda_m) u_m, Phi (n_lon x M)
+    the unit-norm cos/sin columns; the mode at grid column j = a n_lon + i is
+    U[a, m] Phi[i, m]."""
+    spec = circulant_spectrum(n_lat, n_lon, length)
+    cands = []
+    for q, lam, u in spec:
+        for kind_idx, (kind, _) in enumerate(_mode_columns(q, n_lon)):
+            for r in range(lam.shape[0]):
+                cands.append((-lam[r], q, kind_idx, r))
+    cands.sort()
+    if M > len(cands):
+        raise ValueError("M exceeds the number of grid columns")
+    by_q = {q: (lam, u) for q, lam, u in spec}
+    U = np.empty((n_lat, M))
+    Phi = np.empty((n_lon, M))
+    for c in range(M):
+        _, q, kind_idx, r = cands[c]
+        lam, u = by_q[q]
+        U[:, c] = math.sqrt(max(lam[r], 0.0)) * u[:, r]
+        Phi[:, c] = _mode_columns(q, n_lon)[kind_idx][1]
+    lead = np.array([-c[0] for c in cands[:M + 1]])
+    gap = lead[M - 1] / lead[M] if M < len(cands) and lead[M] > 0 else float("inf")
+    return U, Phi, {"eigvals": lead, "gap": float(gap)}
+
+
 def localization_modes(n_lat: int, n_lon: int, M: int, length: float):
     """W = V_b Delta_b^{1/2} from the M leading eigenpairs of the localization block.
 
@@ -232,6 +261,12 @@ CONFIG_NAMES = {
     4: "c4_n131072_K64_M512_R1024",
     5: "c5_learned_n131072_K64_M512",
 }
+
+
+def config_params(c: int) -> dict:
+    """Generator parameters of single-problem configuration c (5 reuses 4's)."""
+    n_lat, n_lon, K, M, R, l_ens, l_loc, seed = _CONFIGS[4 if c == 5 else c]
+    return dict(n_lat=n_lat, n_lon=n_lon, K=K, M=M, R=R, l_ens=l_ens, l_loc=l_loc, seed=seed)
 
 
 def config(c: int, R: Optional[int] = None) -> Instance:
