@@ -73,6 +73,10 @@ struct pc_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
+  // hipGraph of the whole factor + apply sequence (pc_factor_apply with a graph)
+  hipGraph_t fgraph = nullptr;
+  hipGraphExec_t fgexec = nullptr;
+  std::vector<int64_t> fgkey;
   // profiling: recorded (start, stop) event pairs per phase, and a pool
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[PC_NUM_PHASES];
@@ -129,6 +133,8 @@ void free_plan(pc_plan* p) {
   for (auto e : p->pool) hipEventDestroy(e);
   if (p->gexec) hipGraphExecDestroy(p->gexec);
   if (p->graph) hipGraphDestroy(p->graph);
+  if (p->fgexec) hipGraphExecDestroy(p->fgexec);
+  if (p->fgraph) hipGraphDestroy(p->fgraph);
   if (p->cap) hipStreamDestroy(p->cap);
   if (p->ovl) hipStreamDestroy(p->ovl);
   if (p->ev_gram) hipEventDestroy(p->ev_gram);
@@ -1021,23 +1027,26 @@ static pc_status escalate_failed_factors(pc_plan* p, hipStream_t s, int32_t* fai
 // The ladder at apply time: every instance whose refinement stopped without
 // converging (stalled above the acceptance level, or diverging) is refactored
 // in the next precision and solved again alone, until it converges or FP64
-// has been tried.
+// has been tried.  An instance whose Gram is not positive definite even in
+// FP64 is left without a factor (the others go on); the call then returns
+// PC_ERR_NOT_SPD.
 static pc_status escalate_unconverged(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
                                       double* const* Y, const int64_t* ldY, hipStream_t s) {
   const size_t cnt = p->inst.size();
   std::vector<int64_t> R2(cnt, 0);
+  std::vector<char> lost(cnt, 0);
   while (ladder_on(p)) {
     bool any = false;
     for (size_t i = 0; i < cnt; ++i) {
       R2[i] = 0;
       Inst& in = p->inst[i];
-      if (R[i] == 0 || !refinement_failed(p, i) || next_rung(in.prec) < 0) continue;
+      if (R[i] == 0 || lost[i] || !refinement_failed(p, i) || next_rung(in.prec) < 0) continue;
       do {
         in.prec = next_rung(in.prec);
         const pc_status fs = refactor_one(p, i, s);
         if (fs != PC_OK) return fs;
       } while (!in.factored && next_rung(in.prec) >= 0);
-      if (!in.factored) return PC_ERR_NOT_SPD;
+      if (!in.factored) { lost[i] = 1; continue; }
       R2[i] = R[i];
       any = true;
     }
@@ -1047,6 +1056,8 @@ static pc_status escalate_unconverged(pc_plan* p, const double* const* X, const 
     st = finish_apply(p, R2.data(), s);
     if (st != PC_OK && st != PC_ERR_NO_CONVERGENCE) return st;
   }
+  for (size_t i = 0; i < cnt; ++i)
+    if (lost[i]) return PC_ERR_NOT_SPD;
   for (size_t i = 0; i < cnt; ++i)
     if (R[i] != 0 && refinement_failed(p, i)) return PC_ERR_NO_CONVERGENCE;
   return PC_OK;
@@ -1112,6 +1123,84 @@ pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_
   return st;
 }
 
+// pc_factor_apply with a graph: assembly, factorization, the copies of the
+// pivot statuses, Z^T x, the solves and the refinement iterations of every
+// instance are captured once (per argument set and per precision of each
+// instance) and replayed as ONE graph, with one stream sync after it.  All
+// instances with right-hand sides are solved in the graph; one whose Gram
+// turned out not to be positive definite is afterwards raised along the
+// ladder and solved again outside it (its Y is discarded), or reported.
+static pc_status factor_apply_graph(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
+                                    double* const* Y, const int64_t* ldY, hipStream_t s, int32_t* failed_instance) {
+  const size_t cnt = p->inst.size();
+  std::vector<int64_t> key;
+  for (size_t i = 0; i < cnt; ++i) {
+    key.push_back((int64_t)(intptr_t)X[i]); key.push_back(ldX[i]); key.push_back(R[i]);
+    key.push_back((int64_t)(intptr_t)Y[i]); key.push_back(ldY[i]); key.push_back(p->inst[i].prec);
+  }
+  if (!p->fgexec || key != p->fgkey) {
+    if (p->fgexec) { hipGraphExecDestroy(p->fgexec); p->fgexec = nullptr; }
+    if (p->fgraph) { hipGraphDestroy(p->fgraph); p->fgraph = nullptr; }
+    const bool prof = p->profiling;
+    p->profiling = false;                         // no timing events inside the graph
+    PC_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    pc_status st = enqueue_factor(p, p->cap, nullptr);
+    if (st == PC_OK) st = read_factor_status(p, p->cap);
+    if (st == PC_OK) st = enqueue_apply(p, X, ldX, R, Y, ldY, p->cap, 0);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &g);
+    p->profiling = prof;
+    if (st != PC_OK) { if (g) hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return PC_ERR_DEVICE;
+    p->fgraph = g;
+    PC_TRY(hipGraphInstantiate(&p->fgexec, g, nullptr, nullptr, 0));
+    p->fgkey = key;
+  }
+  PC_TRY(hipGraphLaunch(p->fgexec, s));
+  PC_TRY(hipStreamSynchronize(s));
+  int32_t first = -1;
+  pc_status fst = factor_outcome(p, &first);
+  if (fst == PC_ERR_DEVICE) return fst;
+  std::vector<int64_t> R2(R, R + cnt);
+  for (size_t i = 0; i < cnt; ++i)
+    if (!p->inst[i].factored) R2[i] = 0;
+  pc_status ast = finish_apply(p, R2.data(), s);
+  if (ast == PC_ERR_NO_CONVERGENCE && ladder_on(p)) ast = escalate_unconverged(p, X, ldX, R2.data(), Y, ldY, s);
+  if (ast == PC_ERR_NOT_SPD) { ast = PC_OK; fst = PC_ERR_NOT_SPD; }   // lost its factor on the ladder
+  if (ast != PC_OK && ast != PC_ERR_NO_CONVERGENCE) return ast;
+  if (fst == PC_ERR_NOT_SPD && ladder_on(p)) {
+    std::vector<int64_t> R3(cnt, 0);
+    for (size_t i = 0; i < cnt; ++i)
+      if (!p->inst[i].factored) R3[i] = R[i];
+    int32_t still = -1;
+    const pc_status es = escalate_failed_factors(p, s, &still);
+    if (es != PC_OK && es != PC_ERR_NOT_SPD) return es;
+    for (size_t i = 0; i < cnt; ++i)
+      if (!p->inst[i].factored) R3[i] = 0;
+    const pc_status rs = enqueue_apply(p, X, ldX, R3.data(), Y, ldY, s, p->opt.max_refine > 4 ? 2 : 0, 0, true);
+    if (rs != PC_OK) return rs;
+    pc_status st3 = finish_apply(p, R3.data(), s);
+    if (st3 == PC_ERR_NO_CONVERGENCE) st3 = escalate_unconverged(p, X, ldX, R3.data(), Y, ldY, s);
+    if (st3 == PC_ERR_NOT_SPD) st3 = PC_OK;        // reported below from the factored flags
+    if (st3 != PC_OK && st3 != PC_ERR_NO_CONVERGENCE) return st3;
+    if (st3 == PC_ERR_NO_CONVERGENCE) ast = st3;
+    fst = PC_OK;
+    for (size_t i = 0; i < cnt; ++i)
+      if (!p->inst[i].factored && fst == PC_OK) { fst = PC_ERR_NOT_SPD; first = (int32_t)i; }
+  }
+  // an instance without a factor matters only if it has right-hand sides
+  if (fst == PC_ERR_NOT_SPD) {
+    int32_t failed = -1;
+    for (size_t i = 0; i < cnt && failed < 0; ++i)
+      if (!p->inst[i].factored && R[i] > 0) failed = (int32_t)i;
+    if (failed >= 0) {
+      if (failed_instance) *failed_instance = failed;
+      return PC_ERR_NOT_SPD;
+    }
+  }
+  return ast;
+}
+
 pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX, const int64_t* R,
                           double* const* Y, const int64_t* ldY, void* stream, int32_t* failed_instance) {
   if (failed_instance) *failed_instance = -1;
@@ -1130,6 +1219,7 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   // (the products Z^T x depend on E, W and X only, which the caller's stream
   // has made ready when the Gram is assembled).
   const bool overlap = cnt == 1 && R[0] > 0 && !p->batch && !p->lowgram && !p->opt.use_graph;
+  if (p->opt.use_graph) return factor_apply_graph(p, X, ldX, R, Y, ldY, s, failed_instance);
   if (!overlap) {
     // an instance that fails to factor matters only if it has right-hand sides
     int32_t first = -1;

@@ -75,6 +75,63 @@ def test_graph_replays_match_eager():
     plan.close()
 
 
+def test_factor_apply_graph_replays_match_eager():
+    """pc_factor_apply with a graph: assembly, factorization, status copies,
+    solves and refinement of every instance captured once and replayed;
+    each replay (with eager work and synchronizations between them, and
+    the operands' inputs changed in place between the second and the third)
+    reproduces the eager factor + apply bit for bit, and matches the oracle."""
+    import torch
+    insts = _batch(count=6)
+    Xs = [dev(i.X) for i in insts]
+    res = {}
+    for graph in (0, 1):
+        plan = pc.Plan([inst_dict(i) for i in insts], precision=pc.PC_PREC_FP32_REFINE, max_refine=20,
+                       tol=1e-12, use_graph=graph)
+        Ys = [empty(i.KM, i.R) for i in insts]
+        outs = []
+        for rep in range(3):
+            for y in Ys:
+                y.fill_(float("nan"))
+            junk = torch.randn(1000, 1000, device="cuda:0", dtype=torch.float64)
+            (junk @ junk).sum().item()
+            torch.cuda.synchronize()
+            st, _ = plan.factor_apply(Xs, Ys)
+            assert st == pc.PC_OK
+            torch.cuda.synchronize()
+            outs.append([host(y) for y in Ys])
+        res[graph] = outs
+        plan.close()
+    for rep in range(3):
+        for a, b in zip(res[0][rep], res[1][rep]):
+            assert np.array_equal(a, b), rep
+    for inst, y in zip(insts, res[1][2]):
+        ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+        assert _rel_err(y, ref).max() <= 1e-8
+
+
+def test_factor_apply_graph_with_failed_and_escalated_instances():
+    """A batch where one instance's bf16 Gram cannot be refined (kappa ~ 9e3)
+    and one is rank deficient (sample-mean centring): in graph mode the first
+    climbs the ladder outside the graph and meets its bound, the second is
+    reported (PC_ERR_NOT_SPD naming it) while the others are solved."""
+    good = _batch(count=3)
+    hard = wl.make_instance(10, 20, 8, 22, 4, 0.3, 0.5, 51)
+    bad = wl.make_instance(8, 16, 6, 20, 3, 0.2, 0.5, 52, centring="sample")
+    insts = good + [hard, bad]
+    plan = pc.Plan([inst_dict(i) for i in insts], precision=pc.PC_PREC_BF16_REFINE, max_refine=30, tol=1e-13,
+                   use_graph=1)
+    Ys = [empty(i.KM, i.R) for i in insts]
+    st, failed = plan.factor_apply([dev(i.X) for i in insts], Ys, raise_on_error=False)
+    assert st == pc.PC_ERR_NOT_SPD and failed == len(insts) - 1
+    assert pc.pc_query_instance(plan.handle, 3)[0] != pc.PC_PREC_BF16_REFINE      # the ladder moved it
+    for k, inst in enumerate(insts[:-1]):
+        ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+        tol = 1e-8 if k < 3 else 1e-6
+        assert _rel_err(host(Ys[k]), ref).max() <= tol, k
+    plan.close()
+
+
 def test_zero_rhs_instances_are_skipped():
     insts = _batch(count=4)
     plan = pc.Plan([inst_dict(i) for i in insts])

@@ -38,12 +38,56 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-# Tolerances.  fp32 operands: each product is exact in fp32 MFMA and the
-# accumulation error is ~sqrt(K) u32 per output, far below 1e-4 normwise.
-# bf16 operands: every operand is rounded once (relative 2^-9), so a product
-# carries at most ~2^-8 relative error; the gradients pass three rounded
-# products in sequence, hence 3e-2 normwise.
+# Normwise tolerances (checked besides the elementwise bounds below).  fp32
+# operands: each product is exact in fp32 MFMA and the accumulation error is
+# ~sqrt(K) u32 per output, far below 1e-4 normwise.  bf16 operands: every
+# operand is rounded once (relative 2^-9), so a product carries at most ~2^-8
+# relative error; the gradients pass three rounded products in sequence,
+# hence 3e-2 normwise.
 TOL = {pc.PC_MLP_FP32: 1e-4, pc.PC_MLP_BF16: 3e-2}
+
+
+U32 = 2.0 ** -24
+U_OPERAND = {pc.PC_MLP_FP32: 0.0, pc.PC_MLP_BF16: 2.0 ** -8}   # operands rounded once when staged
+GELU_D1, GELU_D2 = 1.13, 0.8    # bounds on |gelu'| and |gelu''|
+SAFETY = 3.0                    # on the first-order bounds: covers the second-order terms
+
+
+def _error_bounds(params, X, T, operand):
+    """Elementwise rounding-error bounds of the library's forward pass and
+    gradients, from the oracle's float64 intermediates: each product P Q^T
+    over K terms with operands rounded once (u) and fp32 accumulation is
+    within (2u + u^2 + K u32) |P| |Q|^T, stored intermediates add u32 of
+    themselves, and errors of earlier quantities propagate through |W|,
+    |gelu'| and |gelu''| (a running error analysis of the network's
+    formulas).  Returns (Y, bound on Y, gradients, bounds on (loss, dW1,
+    db1, dW2, db2))."""
+    W1, b1, W2, b2 = [np.abs(p) for p in params]
+    u = U_OPERAND[operand]
+    kp = lambda K: 2 * u + u * u + 1.01 * K * U32
+    B, d = X.shape
+    h = W1.shape[0]
+    Y, (X64, A, H) = mlp.forward(params, X)
+    aX, aA, aH = np.abs(X64), np.abs(A), np.abs(H)
+    bA = kp(d) * (aX @ W1.T) + U32 * (aA + b1[None, :])
+    bH = GELU_D1 * bA + 4 * U32 * aH
+    bY = kp(h) * (aH @ W2.T) + bH @ W2.T + U32 * (np.abs(Y) + b2[None, :])
+    den = np.sum(T * T, axis=1)
+    R = Y - T
+    dY = (2.0 / B) * R / den[:, None]
+    edY = (2.0 / B) * (bY + d * U32 * np.abs(R)) / den[:, None] + 4 * U32 * np.abs(dY)
+    grads = mlp.backward(params, (X64, A, H), Y, T)
+    dH = dY @ params[2]
+    dA = dH * mlp.gelu_grad(A)
+    edH = kp(d) * (np.abs(dY) @ W2) + edY @ W2
+    edA = edH * np.abs(mlp.gelu_grad(A)) + np.abs(dH) * GELU_D2 * bA + 4 * U32 * np.abs(dA)
+    bW2 = kp(B) * (np.abs(dY).T @ aH) + edY.T @ aH + np.abs(dY).T @ bH
+    bb2 = edY.sum(axis=0) + B * U32 * np.abs(dY).sum(axis=0)
+    bW1 = kp(B) * (np.abs(dA).T @ aX) + edA.T @ aX
+    bb1 = edA.sum(axis=0) + B * U32 * np.abs(dA).sum(axis=0)
+    lval = mlp.loss(Y, T)
+    bl = np.mean(2 * np.sum(np.abs(R) * bY, axis=1) / den) + (d + B) * U32 * lval
+    return Y, bY, grads, (bl, bW1, bb1, bW2, bb2)
 
 
 @pytest.mark.parametrize("operand", [pc.PC_MLP_FP32, pc.PC_MLP_BF16])
@@ -54,7 +98,9 @@ def test_mlp_forward_matches_oracle(shape, operand):
     net, params, X, _ = _net(d, h, B, 100 + d, operand)
     Y = torch.empty((B, d), dtype=torch.float32, device="cuda:0")
     pc.pc_mlp_forward(net.handle, _f32(X), Y)
-    ref, _ = mlp.forward(params, X.astype(np.float64))
+    ref, bY, _, _ = _error_bounds(params, X.astype(np.float64), np.ones((B, d)), operand)
+    err = np.abs(host(Y).astype(np.float64) - ref)
+    assert np.all(err <= SAFETY * bY + 1e-30), (err / bY).max()
     assert _rel(host(Y).astype(np.float64), ref) <= TOL[operand] / 3
     net.close()
 
@@ -72,11 +118,12 @@ def test_mlp_gradients_match_oracle(shape, operand):
             torch.empty(d, dtype=torch.float32, device="cuda:0")]
     pc.pc_mlp_gradients(net.handle, _f32(X), _f32(T), *outs)
     X64, T64 = X.astype(np.float64), T.astype(np.float64)
-    Yr, cache = mlp.forward(params, X64)
-    grads = mlp.backward(params, cache, Yr, T64)
-    assert abs(float(host(outs[0])[0]) - mlp.loss(Yr, T64)) <= TOL[operand] * mlp.loss(Yr, T64)
-    for got, ref in zip(outs[1:], grads):
-        assert _rel(host(got).astype(np.float64), ref) <= TOL[operand], (got.shape, _rel(host(got), ref))
+    Yr, _, grads, (bl, *bg) = _error_bounds(params, X64, T64, operand)
+    assert abs(float(host(outs[0])[0]) - mlp.loss(Yr, T64)) <= SAFETY * bl
+    for got, ref, bnd in zip(outs[1:], grads, bg):
+        err = np.abs(host(got).astype(np.float64) - ref)
+        assert np.all(err <= SAFETY * bnd + 1e-30), (got.shape, (err / (bnd + 1e-300)).max())
+        assert _rel(host(got).astype(np.float64), ref) <= TOL[operand]
     net.close()
 
 
