@@ -200,7 +200,8 @@ def main():
         tuning = None
         if not args.no_tune:   # launch shapes, measured on this plan before timing (like an FFT plan)
             pc.pc_autotune(plan.handle, args.tune_cache, True)
-            tuning = sorted({pc.pc_query_tuning(plan.handle, k) for k in range(len(insts))})
+            tuning = sorted({pc.pc_query_tuning(plan.handle, k, with_block=True) + (pc.pc_query_tile_shape(plan.handle, k),)
+                             for k in range(len(insts))})
             log(f"  {prec_name}: tuned {tuning}")
         # instances whose Gram is not positive definite even in FP64 (after the
         # precision ladder) are left out: no right-hand sides, not counted
@@ -212,7 +213,9 @@ def main():
             plan.factor_apply(Xs, dY, raise_on_error=False)
         torch.cuda.synchronize()
         pc.pc_profile_read(plan.handle)  # drop anything recorded so far
-        if profile:
+        # a graph carries no timing events: with a graph the timed steps replay
+        # it, and the kernel durations come from as many eager steps after them
+        if profile and not use_graph:
             pc.pc_profile_enable(plan.handle, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -223,6 +226,11 @@ def main():
                 log(f"  {prec_name}: step {k + 1}")   # progress (a step takes seconds here)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if profile and use_graph:
+            pc.pc_profile_enable(plan.handle, True)
+            for _ in range(steps):
+                plan.factor_apply(Xs, dY, raise_on_error=False)
+            torch.cuda.synchronize()
         phases = pc.pc_profile_read(plan.handle)
         pc.pc_profile_enable(plan.handle, False)
         # instances left without a factor by the precision ladder during the
@@ -420,7 +428,7 @@ def main():
         "refine_iters_max": main_res["refine_iters_max"],
         "instances_not_factored": [k for k, ok in enumerate(main_res["factored"]) if not ok],
         "statuses": main_res["statuses"],
-        "tuning": {"shapes (gram_split, ztx_split, chol_wgs_per_cu)": main_res["tuning"]},
+        "tuning": {"shapes (gram_split, ztx_split, chol_wgs_per_cu, chol_block, product_tile)": main_res["tuning"]},
         "kernels": kern,
         "phases_ms_per_step": main_res["phases_ms_per_step"],
         "variants": variants,

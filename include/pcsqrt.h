@@ -100,7 +100,11 @@ typedef struct {
                           max|delta| <= tol * max|y| over its column (later
                           iterations leave its column of Y unchanged); <= 0
                           selects 1e-12 */
-  int32_t use_graph;   /* 1: capture the apply sequence in a hipGraph and replay it */
+  int32_t use_graph;   /* 1: hipGraphs: pc_left_inverse_apply captures its apply sequence, and
+                          pc_factor_apply the whole assemble + factor + apply sequence (with the
+                          pivot status copies), once per argument set and per precision of each
+                          instance, then replays it (both run eagerly while phase timing,
+                          pc_profile_enable, is on: a graph carries no timing events) */
   int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM (optionally with PC_FLAG_CG_MEMBER_BLOCKS),
                           or PC_FLAG_FIXED_PRECISION */
 } pc_options;
@@ -321,7 +325,9 @@ pc_status pc_hybrid_apply(const pc_instance *hybrid, double beta_e, const double
  * (1 to 2 parts, 1 to 4 where the Gram has few tiles), the Z^T x
  * contraction split (1 or 2) and the persistent
  * Cholesky grid (1 or 2 workgroups per compute unit; one choice for a plan
- * with several instances, whose factorization is one launch).  Choices are
+ * with several instances, whose factorization is one launch) and, for an
+ * instance factored by blocks, the block width (1024 or 2048) and the tile
+ * shape of its products (see pc_set_tile_shape).  Choices are
  * kept in the plan.  cache_path (host string, may be NULL) names a text file
  * of earlier results keyed by (n_h, n_w, K, M, max_rhs, precision): with
  * use_cached != 0 an instance found there is not measured; new results are
@@ -349,6 +355,16 @@ pc_status pc_set_tuning(pc_plan *plan, int32_t instance, int32_t gram_split, int
  * block-column width).  Output pointers may be NULL. */
 pc_status pc_query_tuning(const pc_plan *plan, int32_t instance, int32_t *gram_split,
                           int32_t *ztx_split, int32_t *chol_per_cu, int32_t *chol_block);
+
+/* pc_set_tile_shape / pc_query_tile_shape — the tile shape of the panel and
+ * trailing products of the blocked factorization of instance `instance`
+ * (used above order 8192): 1 = 128 x 128 tiles, 2 = 256 x 128 tiles (8
+ * waves), 0 = by size (256 x 128 once they fill the device twice).
+ * pc_autotune chooses it together with the block width (1024 or 2048) for
+ * blocked instances.  The plan must be factored again afterwards.
+ * PC_ERR_INVALID_ARG for another value or a bad instance. */
+pc_status pc_set_tile_shape(pc_plan *plan, int32_t instance, int32_t gemm_tile);
+pc_status pc_query_tile_shape(const pc_plan *plan, int32_t instance, int32_t *gemm_tile);
 
 /* ------------------------------------------------------------------------
  * Per-phase timing (HIP events recorded on the caller's stream).

@@ -49,7 +49,7 @@ EXPORTED = [
     "pc_mlp_get_params", "pc_mlp_forward", "pc_mlp_gradients", "pc_mlp_train_step", "pc_mlp_warm_start",
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
     "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance", "pc_query_rhs_info", "pc_hybrid_apply",
-    "pc_sqrt_build_separable",
+    "pc_sqrt_build_separable", "pc_set_tile_shape", "pc_query_tile_shape",
     "pc_swift_build", "pc_swift_apply", "pc_swift_destroy",
 ]
 
@@ -154,6 +154,8 @@ def load_library(path: str = LIB_PATH):
     lib.pc_swift_destroy.argtypes = [c_void_p]
     lib.pc_query_instance.argtypes = [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]
     lib.pc_query_rhs_info.argtypes = [c_void_p, c_int32, c_int64, POINTER(PcRhsInfo)]
+    lib.pc_set_tile_shape.argtypes = [c_void_p, c_int32, c_int32]
+    lib.pc_query_tile_shape.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     lib.pc_hybrid_apply.argtypes = [POINTER(PcInstance), c_double, c_void_p, c_int64, c_int64, c_void_p,
                                     c_int64, c_void_p, c_int64, c_void_p]
     lib.pc_factor_apply_noalloc.argtypes = [POINTER(PcInstance), c_void_p, c_int64, c_int64, c_void_p, c_int64,
@@ -386,6 +388,16 @@ def pc_query_rhs_info(plan: int, instance: int, R: int):
     out = (PcRhsInfo * max(int(R), 1))()
     _check(load_library().pc_query_rhs_info(c_void_p(plan), int(instance), int(R), out), "pc_query_rhs_info")
     return [(out[r].iterations, out[r].state, out[r].last_rel_update) for r in range(int(R))]
+
+
+def pc_set_tile_shape(plan: int, instance: int, gemm_tile: int):
+    _check(load_library().pc_set_tile_shape(c_void_p(plan), int(instance), int(gemm_tile)), "pc_set_tile_shape")
+
+
+def pc_query_tile_shape(plan: int, instance: int = 0) -> int:
+    t = c_int32(0)
+    _check(load_library().pc_query_tile_shape(c_void_p(plan), int(instance), ctypes.byref(t)), "pc_query_tile_shape")
+    return t.value
 
 
 def pc_plan_destroy(plan: Optional[int]):

@@ -119,11 +119,13 @@ static hipError_t run_nt_gemm(const double* A, int64_t lda, const double* B, int
 }
 
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                          int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s) {
+                          int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
+                          int tile) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  // 256 x 128 tiles once there are enough of them to fill the device twice
+  // tile 1: 128 x 128, tile 2: 256 x 128; 0: 256 x 128 once there are enough
+  // of them to fill the device twice
   const int64_t t256 = lower ? ceil_div(M, 256) * (ceil_div(M, 256) + 1) : ceil_div(M, 256) * ceil_div(N, 128);
-  if (t256 >= 512)
+  if (tile == 2 || (tile == 0 && t256 >= 512))
     return run_nt_gemm<NtGemm256>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
   return run_nt_gemm<NtGemm128>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
 }

@@ -1336,10 +1336,12 @@ static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
     // 3. panel: L_panel = G_panel X^T (from a copy of G_panel)
     double* panel = in.G + (k0 + nb) + k0 * ld;
     hipError_t e = launch_copy_panel(panel, ld, in.blk_P, m, m, nb, s);
-    if (e == hipSuccess) e = launch_nt_gemm(in.blk_P, m, in.blk_X, NO, panel, ld, m, nb, nb, 1.0, 0, 0, s);
+    if (e == hipSuccess)
+      e = launch_nt_gemm(in.blk_P, m, in.blk_X, NO, panel, ld, m, nb, nb, 1.0, 0, 0, s, in.tune_gemm_tile);
     // 4. trailing lower triangle: G_22 -= L_panel L_panel^T
     if (e == hipSuccess)
-      e = launch_nt_gemm(panel, ld, panel, ld, in.G + (k0 + nb) + (k0 + nb) * ld, ld, m, m, nb, -1.0, 1, 1, s);
+      e = launch_nt_gemm(panel, ld, panel, ld, in.G + (k0 + nb) + (k0 + nb) * ld, ld, m, m, nb, -1.0, 1, 1, s,
+                         in.tune_gemm_tile);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();

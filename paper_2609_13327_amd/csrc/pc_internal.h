@@ -114,6 +114,7 @@ struct Inst {
   // launch-shape choices of the autotuner (0: built-in heuristic)
   int tune_gram_split = 0;   // FP64 Gram: 1 to 4 contraction parts
   int tune_ztx_split = 0;    // Z^T x: 1 or 2 contraction parts
+  int tune_gemm_tile = 0;    // blocked factorization products: 0 by size, 1 128 x 128, 2 256 x 128 tiles
   int tune_chol_per_cu = 0;  // Cholesky DAG: persistent workgroups per compute unit (1 or 2)
   // blocked outer factorization (large Grams): block columns of blk_NO (0: tile DAG only)
   int64_t blk_NO = 0;
@@ -211,8 +212,10 @@ hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int6
 hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
 // C = alpha A B^T (or C += alpha A B^T when accumulate), column-major, FP64 MFMA;
 // lower != 0 writes only the lower triangle (i >= j) of a square C
+// tile: 0 by size, 1: 128 x 128 tiles, 2: 256 x 128 tiles
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                          int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s);
+                          int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
+                          int tile = 0);
 hipError_t launch_copy_panel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
                              hipStream_t s);
 hipError_t launch_identity(double* I, int64_t n, hipStream_t s);

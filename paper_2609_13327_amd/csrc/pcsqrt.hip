@@ -621,9 +621,9 @@ pc_status run_cg(pc_plan* p, Inst& in, const double* Bm, int64_t ldB, int64_t R,
 
 // ------------------------------------------------------------- autotuning
 // Tuning cache: a text file with one line per instance shape,
-//   n_h n_w K M max_rhs precision  gram_split ztx_split chol_per_cu
+//   n_h n_w K M max_rhs precision  gram_split ztx_split chol_per_cu chol_block gemm_tile
 // after a first line naming the format.
-const char* kTuneHeader = "pcsqrt-tune-v1";
+const char* kTuneHeader = "pcsqrt-tune-v2";
 
 struct TuneKey {
   int64_t n_h, n_w, K, M, rhs;
@@ -632,7 +632,7 @@ struct TuneKey {
     return n_h == o.n_h && n_w == o.n_w && K == o.K && M == o.M && rhs == o.rhs && prec == o.prec;
   }
 };
-struct TuneEntry { TuneKey key; int gram_split, ztx_split, chol_per_cu; };
+struct TuneEntry { TuneKey key; int gram_split, ztx_split, chol_per_cu, chol_block, gemm_tile; };
 
 std::vector<TuneEntry> read_tune_cache(const char* path) {
   std::vector<TuneEntry> v;
@@ -643,10 +643,11 @@ std::vector<TuneEntry> read_tune_cache(const char* path) {
   if (std::fscanf(f, "%63s", head) == 1 && std::string(head) == kTuneHeader) {
     TuneEntry e;
     long long a, b, c, d, r;
-    int pr, g, z, ch;
-    while (std::fscanf(f, "%lld %lld %lld %lld %lld %d %d %d %d", &a, &b, &c, &d, &r, &pr, &g, &z, &ch) == 9) {
+    int pr, g, z, ch, cb, gt;
+    while (std::fscanf(f, "%lld %lld %lld %lld %lld %d %d %d %d %d %d", &a, &b, &c, &d, &r, &pr, &g, &z, &ch, &cb,
+                       &gt) == 11) {
       e.key = TuneKey{a, b, c, d, r, pr};
-      e.gram_split = g; e.ztx_split = z; e.chol_per_cu = ch;
+      e.gram_split = g; e.ztx_split = z; e.chol_per_cu = ch; e.chol_block = cb; e.gemm_tile = gt;
       v.push_back(e);
     }
   }
@@ -660,9 +661,9 @@ bool write_tune_cache(const char* path, const std::vector<TuneEntry>& v) {
   if (!f) return false;
   std::fprintf(f, "%s\n", kTuneHeader);
   for (const auto& e : v)
-    std::fprintf(f, "%lld %lld %lld %lld %lld %d %d %d %d\n", (long long)e.key.n_h, (long long)e.key.n_w,
+    std::fprintf(f, "%lld %lld %lld %lld %lld %d %d %d %d %d %d\n", (long long)e.key.n_h, (long long)e.key.n_w,
                  (long long)e.key.K, (long long)e.key.M, (long long)e.key.rhs, e.key.prec, e.gram_split, e.ztx_split,
-                 e.chol_per_cu);
+                 e.chol_per_cu, e.chol_block, e.gemm_tile);
   const bool ok = std::fclose(f) == 0;
   return ok && std::rename(tmp.c_str(), path) == 0;
 }
@@ -1090,8 +1091,9 @@ pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_
     if (!X[i] || !Y[i] || ldX[i] < in.n || ldY[i] < in.KM) return PC_ERR_INVALID_ARG;
   }
   const int budget = p->opt.max_refine;
-  if (p->opt.use_graph) {
+  if (p->opt.use_graph && !p->profiling) {
     // capture once per argument set on the internal stream, then replay on `s`
+    // (with phase timing on, the sequence runs eagerly: timing events are not captured)
     std::vector<int64_t> key;
     for (size_t i = 0; i < cnt; ++i) {
       key.push_back((int64_t)(intptr_t)X[i]); key.push_back(ldX[i]); key.push_back(R[i]);
@@ -1100,13 +1102,10 @@ pc_status pc_left_inverse_apply(pc_plan* p, const double* const* X, const int64_
     if (!p->gexec || key != p->gkey) {
       if (p->gexec) { hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
       if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
-      const bool prof = p->profiling;
-      p->profiling = false;                       // no timing events inside the graph
       PC_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
       pc_status st = enqueue_apply(p, X, ldX, R, Y, ldY, p->cap, 0);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(p->cap, &g);
-      p->profiling = prof;
       if (st != PC_OK) { if (g) hipGraphDestroy(g); return st; }
       if (e != hipSuccess) return PC_ERR_DEVICE;
       p->graph = g;
@@ -1141,15 +1140,12 @@ static pc_status factor_apply_graph(pc_plan* p, const double* const* X, const in
   if (!p->fgexec || key != p->fgkey) {
     if (p->fgexec) { hipGraphExecDestroy(p->fgexec); p->fgexec = nullptr; }
     if (p->fgraph) { hipGraphDestroy(p->fgraph); p->fgraph = nullptr; }
-    const bool prof = p->profiling;
-    p->profiling = false;                         // no timing events inside the graph
     PC_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     pc_status st = enqueue_factor(p, p->cap, nullptr);
     if (st == PC_OK) st = read_factor_status(p, p->cap);
     if (st == PC_OK) st = enqueue_apply(p, X, ldX, R, Y, ldY, p->cap, 0);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(p->cap, &g);
-    p->profiling = prof;
     if (st != PC_OK) { if (g) hipGraphDestroy(g); return st; }
     if (e != hipSuccess) return PC_ERR_DEVICE;
     p->fgraph = g;
@@ -1219,7 +1215,8 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   // (the products Z^T x depend on E, W and X only, which the caller's stream
   // has made ready when the Gram is assembled).
   const bool overlap = cnt == 1 && R[0] > 0 && !p->batch && !p->lowgram && !p->opt.use_graph;
-  if (p->opt.use_graph) return factor_apply_graph(p, X, ldX, R, Y, ldY, s, failed_instance);
+  // (with phase timing on, the sequence runs eagerly: timing events are not captured)
+  if (p->opt.use_graph && !p->profiling) return factor_apply_graph(p, X, ldX, R, Y, ldY, s, failed_instance);
   if (!overlap) {
     // an instance that fails to factor matters only if it has right-hand sides
     int32_t first = -1;
@@ -1478,6 +1475,11 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
       in.tune_gram_split = hit->gram_split;
       in.tune_ztx_split = hit->ztx_split;
       in.tune_chol_per_cu = hit->chol_per_cu;
+      in.tune_gemm_tile = hit->gemm_tile;
+      if (in.blk_NO > 0 && hit->chol_block > 0 && hit->chol_block != in.blk_NO) {
+        const pc_status bs = alloc_blocked(in, hit->chol_block);
+        if (bs != PC_OK) return bs;
+      }
       continue;
     }
     any_measured = true;
@@ -1541,6 +1543,52 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
         if (c == 2 || tot < best) { best = tot; choice = c; }
       }
       in.tune_chol_per_cu = choice;
+      // blocked factorization (large Grams): block width and the tile shape
+      // of its panel and trailing products, timed on one assembled Gram kept
+      // in a copy (restored before each run)
+      if (in.blk_NO > 0) {
+        pc_status st = assemble_one(p, in, s);
+        if (st != PC_OK) return st;
+        double* keep = nullptr;
+        const size_t bytes = sizeof(double) * (size_t)(in.KMp * in.KMp);
+        const bool copy = hipMalloc((void**)&keep, bytes) == hipSuccess;
+        if (copy) PC_TRY(hipMemcpyAsync(keep, in.G, bytes, hipMemcpyDeviceToDevice, s));
+        float bestb = 0.f;
+        int64_t bw = in.blk_NO;
+        int bt = 0;
+        bool first = true;
+        for (int64_t w : {(int64_t)1024, (int64_t)2048}) {
+          if (w >= in.KMp) continue;
+          st = alloc_blocked(in, w);
+          if (st != PC_OK) break;
+          for (int tile : {1, 2}) {
+            in.tune_gemm_tile = tile;
+            float tot = 0.f;
+            for (int r = 0; r < 2 && st == PC_OK; ++r) {
+              if (copy) {
+                if (hipMemcpyAsync(in.G, keep, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) st = PC_ERR_DEVICE;
+              } else {
+                st = assemble_one(p, in, s);
+              }
+              float ms = 0.f;
+              if (st == PC_OK)
+                st = time_ms(s, 1, [&]() -> pc_status { PC_TRY(pc::launch_cholesky(in, s)); return PC_OK; }, &ms,
+                             false);
+              tot += ms;
+            }
+            if (st != PC_OK) break;
+            if (first || tot < bestb) { bestb = tot; bw = w; bt = tile; first = false; }
+          }
+          if (st != PC_OK) break;
+        }
+        if (copy) { (void)hipStreamSynchronize(s); (void)hipFree(keep); }
+        if (st != PC_OK) return st;
+        if (in.blk_NO != bw) {
+          st = alloc_blocked(in, bw);
+          if (st != PC_OK) return st;
+        }
+        in.tune_gemm_tile = bt;
+      }
     }
   }
   if (p->batch && any_measured) {
@@ -1581,7 +1629,7 @@ pc_status pc_autotune(pc_plan* p, const char* cache_path, int32_t use_cached, vo
   if (cache_path && any_measured) {
     for (const auto& in : p->inst) {
       const TuneKey key{in.n_h, in.n_w, in.K, in.M, in.max_rhs, prec};
-      TuneEntry e{key, in.tune_gram_split, in.tune_ztx_split, in.tune_chol_per_cu};
+      TuneEntry e{key, in.tune_gram_split, in.tune_ztx_split, in.tune_chol_per_cu, (int)in.blk_NO, in.tune_gemm_tile};
       bool found = false;
       for (auto& c : cache)
         if (c.key == key) { c = e; found = true; }
@@ -1614,6 +1662,20 @@ pc_status pc_set_tuning(pc_plan* p, int32_t instance, int32_t gram_split, int32_
   if (p->batch)
     for (auto& o : p->inst) o.tune_chol_per_cu = chol_per_cu;
   in.factored = false;
+  return PC_OK;
+}
+
+pc_status pc_set_tile_shape(pc_plan* p, int32_t instance, int32_t gemm_tile) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || gemm_tile < 0 || gemm_tile > 2)
+    return PC_ERR_INVALID_ARG;
+  p->inst[instance].tune_gemm_tile = gemm_tile;
+  p->inst[instance].factored = false;
+  return PC_OK;
+}
+
+pc_status pc_query_tile_shape(const pc_plan* p, int32_t instance, int32_t* gemm_tile) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || !gemm_tile) return PC_ERR_INVALID_ARG;
+  *gemm_tile = p->inst[instance].tune_gemm_tile;
   return PC_OK;
 }
 

@@ -47,8 +47,10 @@ def test_autotune_cache_round_trip(tmp_path):
         assert _rel(host(y), lsq.left_inverse_apply(i.E, i.W, 1, i.X)) <= 1e-10
     plan.close()
     lines = open(cache).read().split("\n")
-    assert lines[0] == "pcsqrt-tune-v1"
-    assert len([ln for ln in lines[1:] if ln.strip()]) == len({(i.n_h, i.K, i.M, i.R) for i in insts})
+    assert lines[0] == "pcsqrt-tune-v2"
+    rows = [ln.split() for ln in lines[1:] if ln.strip()]
+    assert len(rows) == len({(i.n_h, i.K, i.M, i.R) for i in insts})
+    assert all(len(r) == 11 for r in rows)   # shape key, then gram, ztx, grid, block width, product tile
     plan2 = pc.Plan([inst_dict(i) for i in insts])
     pc.pc_autotune(plan2.handle, cache, use_cached=True)
     assert [pc.pc_query_tuning(plan2.handle, k) for k in range(len(insts))] == chosen
@@ -100,6 +102,26 @@ def test_blocked_factorization_matches_oracle(block):
     plan.apply([dev(inst.X)], [Y])
     ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
     assert _rel(host(Y), ref) <= 1e-10
+    plan.close()
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_blocked_factorization_tile_shapes(tile):
+    """Both tile shapes of the blocked factorization's products give the same
+    answer as the oracle (block columns of 128 over K*M = 420: panel and
+    trailing products with ragged edges)."""
+    inst = wl.make_instance(20, 40, 6, 70, 33, 0.15, 0.4, 23)
+    plan = pc.Plan([inst_dict(inst)])
+    pc.pc_set_tuning(plan.handle, 0, 0, 0, 0, 128)
+    pc.pc_set_tile_shape(plan.handle, 0, tile)
+    assert pc.pc_query_tile_shape(plan.handle, 0) == tile
+    plan.factor()
+    Y = empty(inst.KM, inst.R)
+    plan.apply([dev(inst.X)], [Y])
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    assert _rel(host(Y), ref) <= 1e-10
+    with pytest.raises(pc.PcError):
+        pc.pc_set_tile_shape(plan.handle, 0, 3)
     plan.close()
 
 
