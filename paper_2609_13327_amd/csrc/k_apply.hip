@@ -389,12 +389,15 @@ static hipError_t run_zy(const Inst& in, WS w, const double* Y, int64_t ldY, int
   return hipGetLastError();
 }
 
-// Single level (n_w = 1): out[j, r] = (alpha Xs[j, r] +) beta sum_{k,m} E[j,k] W[j,m] Y[k*M+m, r].
-// Product rows = right-hand sides, columns = grid columns j (coalesced output);
-// the contraction runs over (k, m) in chunks of 16 modes of one member when
-// M is a multiple of 16 (else element by element); the Z operand is formed
-// at fragment time from staged W rows and the member's E values.
-constexpr int YT = 64, YKC = 16, YLD = YT + 1;
+// Single level (n_w = 1): out[j, r] = (alpha Xs[j, r] +) beta sum_k E[j,k] sum_m W[j,m] Y[k*M+m, r].
+// Tile: 64 right-hand sides x 256 grid columns, four waves of 64 x 64.  The
+// contraction runs mode chunk by mode chunk (16 modes) on the outside and
+// member by member inside: a chunk of W rows is staged once and serves all
+// K members (each member's column of E scales it when the MFMA fragment is
+// read), so W is read once per tile instead of once per member; per member
+// only 16 rows of Y and 256 values of E are staged (double-buffered).
+constexpr int YR = 64, YJ = 256, YKC = 16;
+constexpr int YLD = YR + 16, WLD = YJ + 16;   // row strides: the four row groups of a fragment read on distinct banks
 
 template <class WS>
 struct Zy1Args {
@@ -410,87 +413,92 @@ struct Zy1Args {
 };
 
 template <class WS>
-__global__ __launch_bounds__(256) void zy1_kernel(Zy1Args<WS> a) {
+__global__ __launch_bounds__(256, 2) void zy1_kernel(Zy1Args<WS> a) {
   if (a.skip && *a.skip) return;
-  __shared__ double Ys[2][YKC * YLD];    // Ys[q][r]
-  __shared__ double Zs[2][YKC * YLD];    // Zs[q][j] = E[j,k(q)] W[j,m(q)]
+  __shared__ double Ws[YKC * WLD];         // Ws[m][j]: W rows of the current mode chunk
+  __shared__ double Ys[2][YKC * YLD];      // Ys[m][r]: Y rows of one member in that chunk
+  __shared__ double Es[2][YJ];             // the member's E values on the tile's grid columns
   const int64_t ntiles = (int64_t)a.ntr * a.ntj;
   const int64_t per = (ntiles + 7) / 8;
-  const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t u = (blockIdx.x % 8) * per + blockIdx.x / 8;   // contiguous ranges per XCD
   if (u >= ntiles) return;
   const int tr = (int)(u % a.ntr), tj = (int)(u / a.ntr);
-  const int64_t r0 = (int64_t)tr * YT, j0 = (int64_t)tj * YT;
-  const int nchunks = (int)((a.KM + YKC - 1) / YKC);
+  const int64_t r0 = (int64_t)tr * YR, j0 = (int64_t)tj * YJ;
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
-  const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
-  double yv[4], zv[4];
-  auto load = [&](int chunk) {
-    const int64_t q0 = (int64_t)chunk * YKC;
+  const int rr = lane & 15, kq = lane >> 4;
+  const int64_t mchunks = (a.M + YKC - 1) / YKC;
+  const int64_t jt = j0 + t;                     // this thread's grid column for W and E staging
+  const bool jin = jt < a.n_h;
+  double yv[4], ev = 0.0;
+  auto load_member = [&](int64_t mc, int64_t k) {
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int e = t + 256 * h;
-      {   // Y: q fastest (contiguous in a column of Y)
-        const int qq = e % YKC, col = e / YKC;
-        const int64_t q = q0 + qq, r = r0 + col;
-        yv[h] = (q < a.KM && r < a.R) ? a.Y[q + r * a.ldY] : 0.0;
-      }
-      {   // Z: j fastest (contiguous in a column of W and of E)
-        const int jj = e % YT, qq = e / YT;
-        const int64_t q = q0 + qq, j = j0 + jj;
-        double z = 0.0;
-        if (q < a.KM && j < a.n_h) {
-          const int64_t k = q / a.M, m = q - k * a.M;
-          z = a.E[j + k * a.ldE] * a.w(j, m);
-        }
-        zv[h] = z;
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, mm = e % YKC, col = e / YKC;
+      const int64_t m = mc * YKC + mm, r = r0 + col;
+      yv[q] = (m < a.M && r < a.R) ? a.Y[k * a.M + m + r * a.ldY] : 0.0;
+    }
+    ev = jin ? a.E[jt + k * a.ldE] : 0.0;
+  };
+  auto store_member = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      Ys[buf][(e % YKC) * YLD + e / YKC] = yv[q];
+    }
+    Es[buf][t] = ev;
+  };
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t steps = mchunks * a.K;           // (mode chunk, member) pairs, member fastest
+  load_member(0, 0);
+  for (int64_t st = 0; st < steps; ++st) {
+    const int64_t mc = st / a.K, k = st - mc * a.K;
+    const int buf = (int)(st & 1);
+    if (k == 0) {
+      // a new mode chunk: every wave is past the last fragment reads of Ws
+      __syncthreads();
+#pragma unroll
+      for (int mm = 0; mm < YKC; ++mm) {
+        const int64_t m = mc * YKC + mm;
+        Ws[mm * WLD + t] = (jin && m < a.M) ? a.w(jt, m) : 0.0;
       }
     }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int e = t + 256 * h;
-      Ys[buf][(e % YKC) * YLD + e / YKC] = yv[h];
-      Zs[buf][(e / YT) * YLD + e % YT] = zv[h];
+    store_member(buf);
+    __syncthreads();
+    if (st + 1 < steps) {
+      const int64_t st1 = st + 1, mc1 = st1 / a.K;
+      load_member(mc1, st1 - mc1 * a.K);
     }
-  };
-  d4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
-    const bool more = c + 1 < nchunks;
-    if (more) load(c + 1);
-    const double* Yb = Ys[c & 1];
-    const double* Zb = Zs[c & 1];
+    const double* Yb = Ys[buf];
+    const double* Eb = Es[buf];
 #pragma unroll
     for (int kk = 0; kk < YKC; kk += 4) {
-      const int krow = kk + kq;
-      double av[2], bv[2];
+      const int mrow = kk + kq;
+      double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = Yb[krow * YLD + wm * 32 + i * 16 + rr];
+      for (int i = 0; i < 4; ++i) av[i] = Yb[mrow * YLD + i * 16 + rr];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Zb[krow * YLD + wn * 32 + j * 16 + rr];
+      for (int j = 0; j < 4; ++j) {
+        const int jc = w * 64 + j * 16 + rr;
+        bv[j] = Ws[mrow * WLD + jc] * Eb[jc];    // z = E[j, k] W[j, m]
+      }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
     }
-    if (more) store((c + 1) & 1);
-    __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t r = r0 + wm * 32 + i * 16 + kq + 4 * v;
-        const int64_t jj = j0 + wn * 32 + j * 16 + rr;
+        const int64_t r = r0 + i * 16 + kq + 4 * v;
+        const int64_t jj = j0 + w * 64 + j * 16 + rr;
         if (r >= a.R || jj >= a.n_h) continue;
         const double val = acc[i][j][v];
         a.Out[jj + r * a.ldO] = a.Xs ? fma(a.beta, val, a.alpha * a.Xs[jj + r * a.ldXs]) : a.beta * val;
@@ -507,7 +515,7 @@ static hipError_t zy_for(const Inst& in, WS w, const double* Y, int64_t ldY, int
     a.alpha = alpha; a.beta = beta;
     a.E = in.E; a.ldE = in.ldE; a.w = w; a.Y = Y; a.ldY = ldY; a.Xs = Xs; a.ldXs = ldXs;
     a.Out = out; a.ldO = ldOut; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.KM = in.KM; a.R = R;
-    a.ntr = (int)ceil_div(R, YT); a.ntj = (int)ceil_div(in.n_h, YT);
+    a.ntr = (int)ceil_div(R, YR); a.ntj = (int)ceil_div(in.n_h, YJ);
     const int64_t ntiles = (int64_t)a.ntr * a.ntj;
     hipLaunchKernelGGL(zy1_kernel<WS>, dim3((unsigned)(8 * ((ntiles + 7) / 8))), dim3(256), 0, s, a);
     return hipGetLastError();
