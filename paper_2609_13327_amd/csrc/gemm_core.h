@@ -10,10 +10,23 @@
 //   loadA/loadB(ctx, chunk, regs) global -> registers
 //   storeA/storeB(regs, lds)      registers -> LDS (As[k][row], Bs[k][col])
 //   epilogue(ctx, acc)            consume the accumulator tile
+//   OCC (optional)                waves per SIMD the register allocation must allow
+//   XA, XB (optional)             operand stored row-XOR swizzled in LDS (TileF64::mma)
 #pragma once
 #include "pc_common.h"
 
+#include <type_traits>
+
 namespace pc {
+
+template <class P, class = void>
+struct gemm_occupancy { static constexpr int value = 1; };
+template <class P>
+struct gemm_occupancy<P, std::void_t<decltype(P::OCC)>> { static constexpr int value = P::OCC; };
+template <class P, class = void>
+struct gemm_swizzle { static constexpr bool a = false, b = false; };
+template <class P>
+struct gemm_swizzle<P, std::void_t<decltype(P::XA)>> { static constexpr bool a = P::XA, b = P::XB; };
 
 template <class P>
 __device__ __forceinline__ void gemm_tile_f64(const P& prob, const typename P::Ctx& ctx,
@@ -36,7 +49,8 @@ __device__ __forceinline__ void gemm_tile_f64(const P& prob, const typename P::C
       prob.loadA(ctx, c + 1, ar);
       prob.loadB(ctx, c + 1, br);
     }
-    acc.template mma<P::KC, P::LDA, P::LDB>(As0 + (c & 1) * ASZ, Bs0 + (c & 1) * BSZ);
+    acc.template mma<P::KC, P::LDA, P::LDB, gemm_swizzle<P>::a, gemm_swizzle<P>::b>(As0 + (c & 1) * ASZ,
+                                                                                  Bs0 + (c & 1) * BSZ);
     if (more) {
       prob.storeA(ar, As0 + ((c + 1) & 1) * ASZ);
       prob.storeB(br, Bs0 + ((c + 1) & 1) * BSZ);
@@ -45,9 +59,10 @@ __device__ __forceinline__ void gemm_tile_f64(const P& prob, const typename P::C
   }
 }
 
+
 // P::WM * P::WN waves per workgroup (64 * WM * WN threads)
 template <class P>
-__global__ __launch_bounds__(64 * P::WM * P::WN) void gemm_f64_kernel(P prob) {
+__global__ __launch_bounds__(64 * P::WM * P::WN, gemm_occupancy<P>::value) void gemm_f64_kernel(P prob) {
   __shared__ double As[2 * P::KC * P::LDA];
   __shared__ double Bs[2 * P::KC * P::LDB];
   const typename P::Ctx ctx = prob.ctx(blockIdx.x);

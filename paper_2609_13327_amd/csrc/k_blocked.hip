@@ -1,14 +1,16 @@
 // FP64 MFMA products of column-major panels for the blocked outer
-// factorization of large Grams:
+// factorization of large Grams and the blocked triangular solves:
 //   C(i, j) = alpha sum_k A(i, k) B(j, k)            (overwrite), or
 //   C(i, j) = C(i, j) + alpha sum_k A(i, k) B(j, k)  (accumulate),
 // optionally on the lower triangle only (tiles with i >= j; inside a
-// diagonal tile only i >= j is written).  Waves own 64 x 64 sub-tiles; the
-// contraction is staged through LDS 16 columns at a time; both operands are
-// read along their columns (coalesced).  Large products use 256 x 128
-// workgroup tiles (8 waves, two per SIMD): a third less operand traffic per
-// flop than 128 x 128 (four waves), and the second wave on each SIMD hides
-// the latency of the staged loads.
+// diagonal tile only i >= j is written).  Each operand is read either along
+// its columns (A(i, k) at A[i + k lda]) or, with TA / TB, along k
+// (A(i, k) at A[k + i lda]); both reads are coalesced.  Waves own 64 x 64
+// sub-tiles; the contraction is staged through LDS 16 k at a time (k-major
+// operands row-XOR swizzled, so that their transposing stores spread over
+// the banks).  Large products use 256 x 128 workgroup tiles (8 waves, two
+// per SIMD): a third less operand traffic per flop than 128 x 128 (four
+// waves, two workgroups per compute unit).
 #include "pc_common.h"
 #include "pc_internal.h"
 #include "gemm_core.h"
@@ -17,11 +19,14 @@
 
 namespace pc {
 
-template <int BM_, int BN_, int WM_, int WN_>
+template <int BM_, int BN_, int WM_, int WN_, bool TA = false, bool TB = false>
 struct NtGemmProb {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = 16;
   static constexpr int NT = 64 * WM * WN;          // threads
-  static constexpr int LDA = BM + 8, LDB = BN + 8;
+  // two waves per SIMD: two 4-wave workgroups (or one of 8 waves) per compute unit
+  static constexpr int OCC = 2;
+  static constexpr bool XA = TA, XB = TB;
+  static constexpr int LDA = TA ? BM : BM + 8, LDB = TB ? BN : BN + 8;
   static constexpr int NA = BM * KC / NT, NB_ = BN * KC / NT;
   static constexpr int RT = BM / BN;              // column tiles per row tile (lower-triangle mode)
   static_assert(NA >= 1 && NB_ >= 1 && BM * KC % NT == 0 && BN * KC % NT == 0, "tile / thread mismatch");
@@ -33,6 +38,7 @@ struct NtGemmProb {
   double alpha;
   int accumulate, lower;
   int64_t tm, tn, ntiles;
+  const int* skip;                                 // nonzero *skip: the product is not applied
 
   struct Ctx { bool valid; int64_t i0, j0; int nchunks; };
   struct ARegs { double v[NA]; };
@@ -42,7 +48,7 @@ struct NtGemmProb {
     Ctx c;
     const int64_t per = (ntiles + 7) / 8;
     const int64_t u = (b % 8) * per + b / 8;      // consecutive tiles on one XCD
-    c.valid = u < ntiles;
+    c.valid = u < ntiles && !(skip && *skip);
     int64_t ti, tj;
     if (lower) {
       // tile row ti holds the RT (ti + 1) column tiles that reach the lower
@@ -60,36 +66,46 @@ struct NtGemmProb {
     c.nchunks = (int)((K + KC - 1) / KC);
     return c;
   }
+  // Thread t's share of a chunk: elements e = t + NT q of a BR x KC slab,
+  // rows fastest for a column-major operand (row fixed, k steps NT / BR per
+  // q), k fastest for a k-major one (k fixed, row steps NT / KC per q).  The
+  // loads are unconditional (clamped to the operand's first element when out
+  // of range, then zeroed), so that they issue back to back.
+  template <bool T, int BR, int NV>
+  __device__ static void load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, int64_t kmax,
+                                   double* v) {
+    const int t = threadIdx.x;
+    const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
+    constexpr int STEP = T ? NT / KC : NT / BR;      // rows (T) or k (column-major) per q
+    const int64_t r = r0 + row, k = k0 + kk;
+    const double* base = X + (T ? k + r * ldx : r + k * ldx);
+    const int64_t step = (int64_t)STEP * ldx;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const bool ok = T ? (r + STEP * q < rows && k < kmax) : (r < rows && k + STEP * q < kmax);
+      const double x = *(ok ? base + q * step : X);
+      v[q] = ok ? x : 0.0;
+    }
+  }
+  template <bool T, int BR, int NV, int LD>
+  __device__ static void store_slab(const double* v, double* S) {
+    const int t = threadIdx.x;
+    const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
+    constexpr int STEP = T ? NT / KC : NT / BR;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (T) S[kk * LD + ((row + STEP * q) ^ kk)] = v[q];
+      else S[(kk + STEP * q) * LD + row] = v[q];
+    }
+  }
   __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + NT * q, row = e % BM, kk = e / BM;
-      const int64_t i = c.i0 + row, k = (int64_t)chunk * KC + kk;
-      r.v[q] = (i < M && k < K) ? A[i + k * lda] : 0.0;
-    }
+    load_slab<TA, BM, NA>(A, lda, c.i0, M, (int64_t)chunk * KC, K, r.v);
   }
-  __device__ void storeA(const ARegs& r, double* As) const {
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + NT * q;
-      As[(e / BM) * LDA + e % BM] = r.v[q];
-    }
-  }
+  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA, LDA>(r.v, As); }
   __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
-#pragma unroll
-    for (int q = 0; q < NB_; ++q) {
-      const int e = threadIdx.x + NT * q, col = e % BN, kk = e / BN;
-      const int64_t j = c.j0 + col, k = (int64_t)chunk * KC + kk;
-      r.v[q] = (j < N && k < K) ? B[j + k * ldb] : 0.0;
-    }
+    load_slab<TB, BN, NB_>(B, ldb, c.j0, N, (int64_t)chunk * KC, K, r.v);
   }
-  __device__ void storeB(const BRegs& r, double* Bs) const {
-#pragma unroll
-    for (int q = 0; q < NB_; ++q) {
-      const int e = threadIdx.x + NT * q;
-      Bs[(e / BN) * LDB + e % BN] = r.v[q];
-    }
-  }
+  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_, LDB>(r.v, Bs); }
   __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
     acc.for_each([&](int row, int col, double v) {
       const int64_t i = c.i0 + row, j = c.j0 + col;
@@ -106,10 +122,10 @@ using NtGemm256 = NtGemmProb<256, 128, 4, 2>;
 template <class P>
 static hipError_t run_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                               int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower,
-                              hipStream_t s) {
+                              hipStream_t s, const int* skip = nullptr) {
   P g;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
-  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower; g.skip = skip;
   g.tm = ceil_div(M, P::BM);
   g.tn = ceil_div(N, P::BN);
   g.ntiles = lower ? P::RT * g.tm * (g.tm + 1) / 2 : g.tm * g.tn;
@@ -128,6 +144,20 @@ hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t
   if (tile == 2 || (tile == 0 && t256 >= 512))
     return run_nt_gemm<NtGemm256>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
   return run_nt_gemm<NtGemm128>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
+}
+
+// Products of the blocked solves (rectangular, accumulate into C):
+//   tb:      C(i, j) += alpha sum_k A(i, k) B(k, j)      A column-major, B read along k
+//   ta, tb:  C(i, j) += alpha sum_k A(k, i) B(k, j)      both read along k
+using GemmNK = NtGemmProb<128, 128, 2, 2, false, true>;
+using GemmKK = NtGemmProb<128, 128, 2, 2, true, true>;
+
+hipError_t launch_solve_gemm(bool ta, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha, const int* skip,
+                             hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  return ta ? run_nt_gemm<GemmKK>(A, lda, B, ldb, C, ldc, M, N, K, alpha, 1, 0, s, skip)
+            : run_nt_gemm<GemmNK>(A, lda, B, ldb, C, ldc, M, N, K, alpha, 1, 0, s, skip);
 }
 
 // dst (rows x cols, ld ldd) = src (ld lds)

@@ -1461,12 +1461,77 @@ int* chol_solve_fwd_error_flag(const Inst& in) {
   return in.dag + T * T + 2 + T * in.nrt_max + 1;
 }
 
+// Blocked solves for a factor from the blocked factorization, with many
+// right-hand sides: per block column of NO rows, the tile-DAG solve of the
+// diagonal block, then one MFMA product that applies the solved rows to all
+// rows still to come:
+//   forward,  blocks in order:   Z_k = L_kk^{-1} Y_k,  Y_rest -= L_rest,k Z_k   (rows below)
+//   backward, blocks reversed:   Y_k = L_kk^{-T} W_k,  W_rest -= L_k,rest^T Y_k (rows above)
+// so that almost all the flops run as large products instead of 64 x 64
+// tile tasks.  Y (forward) and Wk (backward) are overwritten as they are
+// consumed.  The diagonal-block solves use the 64 x 64 inverses and folded
+// products of the whole factor, restricted to the block.
+constexpr int kBlockedSolveMinTiles = 4;   // right-hand-side tiles of 64 from which the blocked solve is used
+
+static hipError_t launch_chol_solve_blocked(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk,
+                                            int64_t ldW, hipStream_t s, const int* skip) {
+  const int T = (int)(in.KMp / T64);
+  const int64_t ld = in.KMp, NO = in.blk_NO, bs = (int64_t)T * T64 * T64;
+  const int nrt = (int)ceil_div(R, T64);
+  int* err = in.dag + (int64_t)T * T + 1;
+  const int64_t nflags = (int64_t)T * in.nrt_max + 2;      // err, flags, head
+  const unsigned g0 = (unsigned)persistent_grid(solve_dag_kernel_t<false, kSolveWaves>, 0, 64 * kSolveWaves);
+  const int64_t nblk = ceil_div(in.KMp, NO);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t bb = 0; bb < nblk; ++bb) {
+      const int64_t blk = pass ? nblk - 1 - bb : bb;
+      const int64_t k0 = blk * NO, nb = std::min<int64_t>(NO, in.KMp - k0);
+      const int Ts = (int)(nb / T64);
+      const int64_t t0 = k0 / T64;
+      SolveBatch b{};
+      SolveArgs& a = b.one;
+      a.G = in.G + k0 + k0 * ld; a.ld = ld; a.T = Ts;
+      a.Linv = in.Linv + t0 * T64 * T64;
+      if (in.Msol) {
+        a.Mf = in.Msol + t0 * T64 * T64; a.Mb = a.Mf + bs;
+        a.Mf2 = a.Mf + 2 * bs; a.Mb2 = a.Mf + 3 * bs;
+      }
+      if (!pass) { a.In = Y + k0; a.ldIn = ldY; a.Out = Wk + k0; a.ldOut = ldW; }
+      else { a.In = Wk + k0; a.ldIn = ldW; a.Out = Y + k0; a.ldOut = ldY; }
+      a.R = R; a.Rp = nullptr; a.nrt = nrt;
+      a.flags = err + 1; a.info = in.info; a.skip = skip;
+      b.ntasks = (int64_t)Ts * nrt;
+      b.head = a.flags + (int64_t)T * in.nrt_max;
+      b.err = err;
+      b.backward = pass;
+      hipLaunchKernelGGL(dag_reset_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, 256), 1024)),
+                         dim3(256), 0, s, err, nflags);
+      hipLaunchKernelGGL((solve_dag_kernel_t<false, kSolveWaves>), dim3((unsigned)std::min<int64_t>(g0, b.ntasks)),
+                         dim3(64 * kSolveWaves), 0, s, b);
+      hipError_t e;
+      if (!pass) {
+        // Y(k0 + nb.., :) -= L(k0 + nb.., k0..) Z_k
+        const int64_t m = in.KMp - k0 - nb;
+        e = launch_solve_gemm(false, in.G + (k0 + nb) + k0 * ld, ld, Wk + k0, ldW, Y + k0 + nb, ldY, m, R, nb,
+                              -1.0, skip, s);
+      } else {
+        // W(0..k0, :) -= L(k0.., 0..k0)^T Y_k
+        e = launch_solve_gemm(true, in.G + k0, ld, Y + k0, ldY, Wk, ldW, k0, R, nb, -1.0, skip, s);
+      }
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipGetLastError();
+}
+
 // Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) holds the forward result.
 // With first_pass = 1 only the backward pass runs (Wk already holds the
 // forward result).
 hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk, int64_t ldW,
                              hipStream_t s, const int* skip, int first_pass) {
   if (R <= 0) return hipSuccess;
+  if (in.blk_NO > 0 && first_pass == 0 && ceil_div(R, T64) >= kBlockedSolveMinTiles)
+    return launch_chol_solve_blocked(in, Y, ldY, R, Wk, ldW, s, skip);
   const int T = (int)(in.KMp / T64);
   SolveBatch b{};
   b.one = solve_args(in, Y, Wk, R, skip);

@@ -90,19 +90,23 @@ struct TileF64 {
       for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   }
 
-  // Consume KC rows of k from LDS.
-  template <int KC, int LDA, int LDB>
+  // Consume KC rows of k from LDS.  With XA (XB) the operand is stored
+  // row-XOR swizzled: element (k, m) at k * LDA + (m ^ k), k < 16 (a
+  // permutation inside each aligned group of 16 columns).
+  template <int KC, int LDA, int LDB, bool XA = false, bool XB = false>
   __device__ __forceinline__ void mma(const double* As, const double* Bs) {
+    static_assert((!XA && !XB) || KC <= 16, "the swizzle permutes within groups of 16");
     const int lane = lane_id(), w = wave_id();
     const int wm = w / WN, wn = w % WN;
     const int r = lane & 15, kq = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       double a[FM], b[FN];
+      const int k = kk + kq;
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[(kk + kq) * LDA + wm * TM + i * 16 + r];
+      for (int i = 0; i < FM; ++i) a[i] = As[k * LDA + wm * TM + i * 16 + (XA ? (r ^ k) : r)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = Bs[(kk + kq) * LDB + wn * TN + j * 16 + r];
+      for (int j = 0; j < FN; ++j) b[j] = Bs[k * LDB + wn * TN + j * 16 + (XB ? (r ^ k) : r)];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll

@@ -216,6 +216,11 @@ hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                           int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
                           int tile = 0);
+// C (M x N) += alpha opA opB^T for the blocked solves: opA(i, k) = A[i + k lda]
+// (or A[k + i lda] with ta), opB(j, k) = B[k + j ldb]; nothing when *skip != 0.
+hipError_t launch_solve_gemm(bool ta, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha, const int* skip,
+                             hipStream_t s);
 hipError_t launch_copy_panel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
                              hipStream_t s);
 hipError_t launch_identity(double* I, int64_t n, hipStream_t s);

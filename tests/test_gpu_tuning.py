@@ -125,6 +125,31 @@ def test_blocked_factorization_tile_shapes(tile):
     plan.close()
 
 
+@pytest.mark.parametrize("block,prec", [(128, "fp64"), (192, "fp64"), (128, "bf16")])
+def test_blocked_solve_many_right_hand_sides(block, prec):
+    """From four tiles of 64 right-hand sides on, a blocked factor is solved
+    block column by block column (tile-DAG solves of the diagonal blocks,
+    MFMA products for the rest).  R = 300 (ragged last tile, K*M = 420 with a
+    narrower last block) against the oracle, and against the tile-DAG solve
+    of the first 100 columns (one launch per pass) on the same factor; in
+    BF16 the refinement's solves run the blocked path too."""
+    inst = wl.make_instance(20, 40, 6, 70, 300, 0.15, 0.4, 29)
+    kw = {} if prec == "fp64" else {"precision": pc.PC_PREC_BF16_REFINE, "max_refine": 30, "tol": 1e-13,
+                                     "flags": pc.PC_FLAG_FIXED_PRECISION}
+    plan = pc.Plan([inst_dict(inst)], **kw)
+    pc.pc_set_tuning(plan.handle, 0, 0, 0, 0, block)
+    plan.factor()
+    Y = empty(inst.KM, inst.R)
+    plan.apply([dev(inst.X)], [Y])
+    Ys = empty(inst.KM, 100)
+    plan.apply([dev(inst.X[:, :100])], [Ys])
+    plan.close()
+    ref = lsq.left_inverse_apply(inst.E, inst.W, 1, inst.X)
+    got = host(Y)
+    assert _rel(got, ref) <= 1e-10
+    assert _rel(got[:, :100], host(Ys)) <= 1e-12
+
+
 def test_blocked_factorization_reports_rank_deficiency():
     inst = wl.make_instance(10, 20, 4, 40, 3, 0.3, 0.5, 5, centring="sample")
     plan = pc.Plan([inst_dict(inst)])
