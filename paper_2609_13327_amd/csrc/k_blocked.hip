@@ -41,8 +41,6 @@ struct NtGemmProb {
   const int* skip;                                 // nonzero *skip: the product is not applied
 
   struct Ctx { bool valid; int64_t i0, j0; int nchunks; };
-  struct ARegs { double v[NA]; };
-  struct BRegs { double v[NB_]; };
 
   __device__ Ctx ctx(int b) const {
     Ctx c;
@@ -69,43 +67,51 @@ struct NtGemmProb {
   // Thread t's share of a chunk: elements e = t + NT q of a BR x KC slab,
   // rows fastest for a column-major operand (row fixed, k steps NT / BR per
   // q), k fastest for a k-major one (k fixed, row steps NT / KC per q).  The
-  // loads are unconditional (clamped to the operand's first element when out
-  // of range, then zeroed), so that they issue back to back.
+  // loads are unconditional: rows past the edge read the last row (their
+  // products only reach outputs that are not written), k past the edge
+  // reads k = 0 and is zeroed when the slab is stored.  A select right
+  // after the loads would make the compiler wait for them before the
+  // chunk's products.
+  struct Slab { unsigned kok; };               // bit q: element q's k is inside K
+  struct ARegs { double v[NA]; Slab s; };
+  struct BRegs { double v[NB_]; Slab s; };
   template <bool T, int BR, int NV>
-  __device__ static void load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, int64_t kmax,
+  __device__ static Slab load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, int64_t kmax,
                                    double* v) {
     const int t = threadIdx.x;
     const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
     constexpr int STEP = T ? NT / KC : NT / BR;      // rows (T) or k (column-major) per q
-    const int64_t r = r0 + row, k = k0 + kk;
-    const double* base = X + (T ? k + r * ldx : r + k * ldx);
-    const int64_t step = (int64_t)STEP * ldx;
+    Slab sl{0u};
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const bool ok = T ? (r + STEP * q < rows && k < kmax) : (r < rows && k + STEP * q < kmax);
-      const double x = *(ok ? base + q * step : X);
-      v[q] = ok ? x : 0.0;
+      int64_t r = r0 + row + (T ? STEP * q : 0), k = k0 + kk + (T ? 0 : STEP * q);
+      if (k < kmax) sl.kok |= 1u << q;
+      r = r < rows ? r : rows - 1;
+      k = k < kmax ? k : 0;
+      v[q] = X[T ? k + r * ldx : r + k * ldx];
     }
+    return sl;
   }
   template <bool T, int BR, int NV, int LD>
-  __device__ static void store_slab(const double* v, double* S) {
+  __device__ static void store_slab(const double* v, Slab sl, double* S) {
     const int t = threadIdx.x;
     const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
     constexpr int STEP = T ? NT / KC : NT / BR;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      if (T) S[kk * LD + ((row + STEP * q) ^ kk)] = v[q];
-      else S[(kk + STEP * q) * LD + row] = v[q];
+      const double x = (sl.kok >> q) & 1u ? v[q] : 0.0;
+      if (T) S[kk * LD + ((row + STEP * q) ^ kk)] = x;
+      else S[(kk + STEP * q) * LD + row] = x;
     }
   }
   __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
-    load_slab<TA, BM, NA>(A, lda, c.i0, M, (int64_t)chunk * KC, K, r.v);
+    r.s = load_slab<TA, BM, NA>(A, lda, c.i0, M, (int64_t)chunk * KC, K, r.v);
   }
-  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA, LDA>(r.v, As); }
+  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA, LDA>(r.v, r.s, As); }
   __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
-    load_slab<TB, BN, NB_>(B, ldb, c.j0, N, (int64_t)chunk * KC, K, r.v);
+    r.s = load_slab<TB, BN, NB_>(B, ldb, c.j0, N, (int64_t)chunk * KC, K, r.v);
   }
-  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_, LDB>(r.v, Bs); }
+  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_, LDB>(r.v, r.s, Bs); }
   __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
     acc.for_each([&](int row, int col, double v) {
       const int64_t i = c.i0 + row, j = c.j0 + col;

@@ -96,6 +96,7 @@ constexpr int GB = 128, GKC = 16, GWC = 32;
 constexpr int GWS = 36;                           // W row stride in LDS: the four row groups of a read on distinct banks
 constexpr int GSR = GKC / 4;                      // S rows staged per thread and chunk (two pairs each)
 constexpr int GWH = (GKC * GWC + 255) / 256;      // W values staged per thread and chunk
+static_assert(GKC <= kGramZeroRows, "the last chunk reads up to GKC - 1 rows past n_h");
 
 template <class WS>
 struct GramArgs {
@@ -140,23 +141,26 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
     const int wc = wcol[h] < GWC ? wcol[h] : 0;
     wm_idx[h] = (int64_t)qt[2 * (wc / 16) + ((wc % 16) >= 8 ? 1 : 0)] + (wc % 8);
   }
+  // The loads are unconditional, so that the products of a chunk never wait
+  // for the next chunk's loads (loads behind branches, or values selected
+  // right after them, make the compiler wait for them at once): S has GKC
+  // zero rows past n_h, which zero the terms of rows beyond the last; W is
+  // read at clamped, valid indices (finite values: times a zero S row they
+  // give zero, and out-of-range mode columns only reach unwritten outputs).
   double sv[2 * GSR], wv[GWH];
+  const int64_t jlast = a.n_h - 1, mlast = a.M - 1;
   auto load = [&](int chunk) {
     const int64_t j0 = jbeg + (int64_t)chunk * GKC;
 #pragma unroll
     for (int i = 0; i < GSR; ++i) {
-      const int64_t j = j0 + srow + 4 * i;
-      if (j < jend) {
-        const double2 v = *reinterpret_cast<const double2*>(a.S + j * a.ldS + p0 + sp);
-        sv[2 * i] = v.x; sv[2 * i + 1] = v.y;
-      } else {
-        sv[2 * i] = 0.0; sv[2 * i + 1] = 0.0;
-      }
+      const double2 v = *reinterpret_cast<const double2*>(a.S + (j0 + srow + 4 * i) * a.ldS + p0 + sp);
+      sv[2 * i] = v.x;
+      sv[2 * i + 1] = v.y;
     }
 #pragma unroll
     for (int h = 0; h < GWH; ++h) {
       const int64_t j = j0 + wrow[h];
-      wv[h] = (wcol[h] < GWC && j < jend && wm_idx[h] < a.M) ? a.w(j, wm_idx[h]) : 0.0;
+      wv[h] = a.w(j < jlast ? j : jlast, wm_idx[h] < mlast ? wm_idx[h] : mlast);
     }
   };
   auto store = [&](int buf) {

@@ -221,7 +221,7 @@ pc_status alloc_inst(Inst& in, int precision, int flags, bool batched) {
   chk(dalloc(&in.Linv, nblk * pc::NB * pc::NB));
   chk(dalloc(&in.Msol, 4 * nblk * pc::NB * pc::NB));
   in.ldS = pc::round_up(in.P, 128);
-  chk(dalloc(&in.S, in.n_h * in.ldS));
+  chk(dalloc(&in.S, (in.n_h + pc::kGramZeroRows) * in.ldS));
   chk(dalloc(&in.pairs, 2 * in.P));
   std::vector<int> qt = make_qtiles(in.M);
   in.nq = (int)(qt.size() / 4);
@@ -293,8 +293,9 @@ pc_status alloc_inst(Inst& in, int precision, int flags, bool batched) {
     return PC_ERR_DEVICE;
   // padding rows of the right-hand-side buffers stay zero forever
   if (hipMemset(in.B, 0, sizeof(double) * KMp * R) != hipSuccess) return PC_ERR_DEVICE;
-  // S padding columns (pairs P..ldS-1) are read by the Gram tiles and must be zero
-  if (hipMemset(in.S, 0, sizeof(double) * in.n_h * in.ldS) != hipSuccess) return PC_ERR_DEVICE;
+  // S padding columns (pairs P..ldS-1) and the rows past n_h are read by the
+  // Gram tiles and must be zero
+  if (hipMemset(in.S, 0, sizeof(double) * (in.n_h + pc::kGramZeroRows) * in.ldS) != hipSuccess) return PC_ERR_DEVICE;
   if (precision == PC_PREC_FP64 && pc::gram_split_for(in) > 1) {
     if (ensure_gram_parts(in, pc::gram_split_for(in)) != hipSuccess) return PC_ERR_OOM;
   }
@@ -1213,8 +1214,12 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   }
   // The overlap: one unbatched instance in FP64 or with refinement, no graph
   // (the products Z^T x depend on E, W and X only, which the caller's stream
-  // has made ready when the Gram is assembled).
-  const bool overlap = cnt == 1 && R[0] > 0 && !p->batch && !p->lowgram && !p->opt.use_graph;
+  // has made ready when the Gram is assembled), factored by the tile DAG.  A
+  // blocked factorization runs serially after Z^T x instead: its persistent
+  // diagonal-block kernels would wait for compute units that the products
+  // hold, and its panel products leave nothing idle to fill.
+  const bool overlap = cnt == 1 && R[0] > 0 && !p->batch && !p->lowgram && !p->opt.use_graph &&
+                       p->inst[0].blk_NO == 0;
   // (with phase timing on, the sequence runs eagerly: timing events are not captured)
   if (p->opt.use_graph && !p->profiling) return factor_apply_graph(p, X, ldX, R, Y, ldY, s, failed_instance);
   if (!overlap) {
