@@ -123,7 +123,7 @@ static hipError_t run_ztx(const Inst& in, WS w, const double* X, int64_t ldX, in
 // of E scales the W rows when the MFMA fragment is read.  With few tiles the
 // j range is split in two halves accumulated with two atomic adds onto a
 // zeroed output (two addends onto zero: the same result in either order).
-constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1, ZKB = 2;
+constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1, ZKB = 4;
 constexpr int ZNQ = ZKC * ZT / 256;     // X and W values staged per thread and chunk
 
 template <class WS>
