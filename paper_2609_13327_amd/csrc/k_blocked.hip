@@ -29,6 +29,7 @@ struct NtGemmProb {
   static constexpr int LDA = TA ? BM : BM + 8, LDB = TB ? BN : BN + 8;
   static constexpr int NA = BM * KC / NT, NB_ = BN * KC / NT;
   static constexpr int RT = BM / BN;              // column tiles per row tile (lower-triangle mode)
+  static constexpr int LG = 8;                    // tile rows per group (lower-triangle mode, RT = 1)
   static_assert(NA >= 1 && NB_ >= 1 && BM * KC % NT == 0 && BN * KC % NT == 0, "tile / thread mismatch");
   static_assert(BM % BN == 0, "row tiles must cover whole column tiles");
   const double* A; int64_t lda;
@@ -47,8 +48,30 @@ struct NtGemmProb {
     const int64_t per = (ntiles + 7) / 8;
     const int64_t u = (b % 8) * per + b / 8;      // consecutive tiles on one XCD
     c.valid = u < ntiles && !(skip && *skip);
+    c.i0 = c.j0 = 0;
+    c.nchunks = 0;
+    if (!c.valid) return c;                       // (the orders below assume u < ntiles)
     int64_t ti, tj;
-    if (lower) {
+    if (lower && RT == 1) {
+      // groups of LG tile rows; inside a group column by column, so that the
+      // tiles an XCD runs at once share a few row strips of both operands
+      // (the group before row r0 = g LG holds r0 (r0 + 1) / 2 tiles)
+      int64_t g = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5) / LG;
+      while ((g + 1) * LG <= tm && ((g + 1) * LG) * ((g + 1) * LG + 1) / 2 <= u) ++g;
+      while (g > 0 && (g * LG) * (g * LG + 1) / 2 > u) --g;
+      const int64_t r0 = g * LG, rows = (r0 + LG <= tm ? LG : tm - r0);
+      int64_t v = u - r0 * (r0 + 1) / 2;
+      if (v < r0 * rows) {                        // columns left of the group's diagonal block
+        tj = v / rows;
+        ti = r0 + v % rows;
+      } else {                                    // the diagonal block: column r0 + d has rows - d tiles
+        v -= r0 * rows;
+        int64_t d = 0;
+        while (d + 1 < rows && v >= rows - d) { v -= rows - d; ++d; }
+        tj = r0 + d;
+        ti = tj + v;
+      }
+    } else if (lower) {
       // tile row ti holds the RT (ti + 1) column tiles that reach the lower
       // triangle (RT = BM / BN); rows before it hold RT ti (ti + 1) / 2
       ti = (int64_t)((sqrt(8.0 * (double)u / RT + 1.0) - 1.0) * 0.5);
@@ -56,8 +79,9 @@ struct NtGemmProb {
       while (RT * ti * (ti + 1) / 2 > u) --ti;
       tj = u - RT * ti * (ti + 1) / 2;
     } else {
-      ti = u % tm;
-      tj = u / tm;
+      // column tiles fastest: the tiles of a row strip of A run together
+      ti = u / tn;
+      tj = u % tn;
     }
     c.i0 = ti * BM;
     c.j0 = tj * BN;
@@ -66,53 +90,82 @@ struct NtGemmProb {
   }
   // Thread t's share of a chunk: elements e = t + NT q of a BR x KC slab,
   // rows fastest for a column-major operand (row fixed, k steps NT / BR per
-  // q), k fastest for a k-major one (k fixed, row steps NT / KC per q).  The
-  // loads are unconditional: rows past the edge read the last row (their
-  // products only reach outputs that are not written), k past the edge
-  // reads k = 0 and is zeroed when the slab is stored.  A select right
-  // after the loads would make the compiler wait for them before the
-  // chunk's products.
-  struct Slab { unsigned kok; };               // bit q: element q's k is inside K
-  struct ARegs { double v[NA]; Slab s; };
-  struct BRegs { double v[NB_]; Slab s; };
+  // q), k fastest for a k-major one (k fixed, row steps NT / KC per q).  K is
+  // a multiple of KC (checked on the host), so every k is inside; rows past
+  // the edge read the last row (their products only reach outputs that are
+  // not written).  The loads are unconditional and nothing is selected on
+  // their values, so the chunk's products never wait for them.
+  struct ARegs { double v[NA]; };
+  struct BRegs { double v[NB_]; };
   template <bool T, int BR, int NV>
-  __device__ static Slab load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, int64_t kmax,
-                                   double* v) {
+  __device__ static void load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, double* v) {
     const int t = threadIdx.x;
     const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
     constexpr int STEP = T ? NT / KC : NT / BR;      // rows (T) or k (column-major) per q
-    Slab sl{0u};
+    if (!T) {
+      const int64_t r = r0 + row < rows ? r0 + row : rows - 1;
+      const double* p = X + r + (k0 + kk) * ldx;
+      const int64_t qs = (int64_t)STEP * ldx;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      int64_t r = r0 + row + (T ? STEP * q : 0), k = k0 + kk + (T ? 0 : STEP * q);
-      if (k < kmax) sl.kok |= 1u << q;
-      r = r < rows ? r : rows - 1;
-      k = k < kmax ? k : 0;
-      v[q] = X[T ? k + r * ldx : r + k * ldx];
+      for (int q = 0; q < NV; ++q) v[q] = p[q * qs];
+    } else {
+      const double* p = X + k0 + kk;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int64_t r = r0 + row + STEP * q;
+        v[q] = p[(r < rows ? r : rows - 1) * ldx];
+      }
     }
-    return sl;
   }
   template <bool T, int BR, int NV, int LD>
-  __device__ static void store_slab(const double* v, Slab sl, double* S) {
+  __device__ static void store_slab(const double* v, double* S) {
     const int t = threadIdx.x;
     const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
     constexpr int STEP = T ? NT / KC : NT / BR;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const double x = (sl.kok >> q) & 1u ? v[q] : 0.0;
-      if (T) S[kk * LD + ((row + STEP * q) ^ kk)] = x;
-      else S[(kk + STEP * q) * LD + row] = x;
+      if (T) S[kk * LD + ((row + STEP * q) ^ kk)] = v[q];
+      else S[(kk + STEP * q) * LD + row] = v[q];
     }
   }
   __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
-    r.s = load_slab<TA, BM, NA>(A, lda, c.i0, M, (int64_t)chunk * KC, K, r.v);
+    load_slab<TA, BM, NA>(A, lda, c.i0, M, (int64_t)chunk * KC, r.v);
   }
-  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA, LDA>(r.v, r.s, As); }
+  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA, LDA>(r.v, As); }
   __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
-    r.s = load_slab<TB, BN, NB_>(B, ldb, c.j0, N, (int64_t)chunk * KC, K, r.v);
+    load_slab<TB, BN, NB_>(B, ldb, c.j0, N, (int64_t)chunk * KC, r.v);
   }
-  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_, LDB>(r.v, r.s, Bs); }
+  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_, LDB>(r.v, Bs); }
+  // A tile inside C (and strictly below the diagonal in lower mode) reads
+  // the 16 C values of a fragment row with unconditional loads before it
+  // writes any of them: an edge test per element would make every load wait
+  // for the previous one.  Edge tiles test each element.
   __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
+    using Tile = TileF64<BM, BN, WM, WN>;
+    const bool inside = c.i0 + BM <= M && c.j0 + BN <= N && (!lower || c.i0 >= c.j0 + BN);
+    if (inside) {
+      const int lane = lane_id(), w = wave_id();
+      const int wm = w / WN, wn = w % WN;
+      double* Cw = C + (c.i0 + wm * Tile::TM + (lane >> 4)) + (c.j0 + wn * Tile::TN + (lane & 15)) * ldc;
+#pragma unroll
+      for (int i = 0; i < Tile::FM; ++i) {
+        double old[Tile::FN][4];
+        if (accumulate) {
+#pragma unroll
+          for (int j = 0; j < Tile::FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) old[j][v] = Cw[(i * 16 + 4 * v) + (int64_t)(j * 16) * ldc];
+        }
+#pragma unroll
+        for (int j = 0; j < Tile::FN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double x = alpha * acc.acc[i][j][v];
+            Cw[(i * 16 + 4 * v) + (int64_t)(j * 16) * ldc] = accumulate ? old[j][v] + x : x;
+          }
+      }
+      return;
+    }
     acc.for_each([&](int row, int col, double v) {
       const int64_t i = c.i0 + row, j = c.j0 + col;
       if (i >= M || j >= N || (lower && i < j)) return;
@@ -144,6 +197,7 @@ hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t
                           int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
                           int tile) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (K % 16 != 0) return hipErrorInvalidValue;      // whole chunks of k (the loaders read no edge)
   // tile 1: 128 x 128, tile 2: 256 x 128; 0: 256 x 128 once there are enough
   // of them to fill the device twice
   const int64_t t256 = lower ? ceil_div(M, 256) * (ceil_div(M, 256) + 1) : ceil_div(M, 256) * ceil_div(N, 128);
@@ -162,6 +216,7 @@ hipError_t launch_solve_gemm(bool ta, const double* A, int64_t lda, const double
                              int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha, const int* skip,
                              hipStream_t s) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (K % 16 != 0) return hipErrorInvalidValue;      // whole chunks of k (the loaders read no edge)
   return ta ? run_nt_gemm<GemmKK>(A, lda, B, ldb, C, ldc, M, N, K, alpha, 1, 0, s, skip)
             : run_nt_gemm<GemmNK>(A, lda, B, ldb, C, ldc, M, N, K, alpha, 1, 0, s, skip);
 }

@@ -214,12 +214,15 @@ hipError_t launch_export_lower(const double* src, int64_t lds, double* dst, int6
 hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
 // C = alpha A B^T (or C += alpha A B^T when accumulate), column-major, FP64 MFMA;
 // lower != 0 writes only the lower triangle (i >= j) of a square C
-// tile: 0 by size, 1: 128 x 128 tiles, 2: 256 x 128 tiles
+// tile: 0 by size, 1: 128 x 128 tiles, 2: 256 x 128 tiles; K must be a
+// multiple of 16 (hipErrorInvalidValue otherwise; the blocked paths use
+// multiples of 64)
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                           int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
                           int tile = 0);
 // C (M x N) += alpha opA opB^T for the blocked solves: opA(i, k) = A[i + k lda]
-// (or A[k + i lda] with ta), opB(j, k) = B[k + j ldb]; nothing when *skip != 0.
+// (or A[k + i lda] with ta), opB(j, k) = B[k + j ldb]; nothing when *skip != 0;
+// K a multiple of 16.
 hipError_t launch_solve_gemm(bool ta, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
                              int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha, const int* skip,
                              hipStream_t s);
