@@ -80,21 +80,24 @@ hipError_t launch_column_grams(const Inst& in, hipStream_t s) {
 }
 
 // -------------------------------------------------------------- FP64 Gram
-// Tile: 128 pairs p x 128 mode pairs q, the latter two 8 x 8 blocks of
+// Tile: TP pairs p x 128 mode pairs q, the latter two 8 x 8 blocks of
 // (m, m') (origins from the tile table; column c of block h is
 // m = m0_h + c / 8, m' = m0'_h + c % 8).  Per chunk of 16 grid columns j the
-// workgroup stages the S rows of its 128 pairs and the 32 columns of W its
+// workgroup stages the S rows of its TP pairs and the 32 columns of W its
 // mode pairs use; the T operand W[j,m] W[j,m'] is formed when the MFMA
-// fragment is read from LDS.  Four waves own 64 x 64 quadrants (4 x 4
-// fragments of 16 x 16); wave column h covers block h.
+// fragment is read from LDS.  Full tiles (TP = 128): four waves own 64 x 64
+// quadrants (4 x 4 fragments of 16 x 16), wave column h covering block h.
+// The pairs left over after the full tiles (P mod 128, when at most 32)
+// form tail tiles of TP = 32: each wave owns 32 pairs x 32 mode pairs, so
+// that no products of empty pair rows are formed.
 // When the tiles are too few to fill the device the j range is split in two
 // to four parts written to G and G2 and summed afterwards in a fixed order
-// (results are reproducible), as many as keep the rounds of workgroups full.  Workgroups are mapped so that each XCD (the hardware
-// places workgroup b on XCD b mod 8) works on a contiguous range of tiles,
-// which then share S rows in its L2.
-constexpr int GB = 128, GKC = 16, GWC = 32;
+// (results are reproducible), as many as keep the rounds of workgroups full.
+// Workgroups are mapped so that each XCD (the hardware places workgroup b on
+// XCD b mod 8) works on a contiguous range of tiles, which then share S rows
+// in its L2; the tail tiles come first.
+constexpr int GB = 128, GBT = 32, GKC = 16, GWC = 32;
 constexpr int GWS = 36;                           // W row stride in LDS: the four row groups of a read on distinct banks
-constexpr int GSR = GKC / 4;                      // S rows staged per thread and chunk (two pairs each)
 constexpr int GWH = (GKC * GWC + 255) / 256;      // W values staged per thread and chunk
 static_assert(GKC <= kGramZeroRows, "the last chunk reads up to GKC - 1 rows past n_h");
 
@@ -104,32 +107,31 @@ struct GramArgs {
   WS w;
   int64_t n_h, M, P;
   const int* pairs; const int* qtiles;
-  int npt, nq, ntiles, split;
+  int nfull, nq, tail, split;             // full pair tiles, mode-pair tiles, tail pair tile (0 or 1)
   int64_t jlen;
   double* G; double* G2; int64_t ldG;     // part q >= 1 goes to G2 + (q - 1) ldG^2
 };
 
-template <class WS>
-__global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
-  __shared__ double As[2][GKC * GB];
-  __shared__ double Ws[2][GKC * GWS];
-  const int64_t units = (int64_t)a.ntiles * a.split;
-  const int64_t per = (units + 7) / 8;
-  const int64_t b = blockIdx.x;
-  const int64_t u = (b % 8) * per + b / 8;
-  if (u >= units) return;
-  const int part = (int)(u / a.ntiles), tile = (int)(u % a.ntiles);
-  const int pt = tile / a.nq, qi = tile % a.nq;
-  const int64_t p0 = (int64_t)pt * GB;
+// One tile of TP pairs from p0, mode-pair tile qi, contraction part `part`.
+template <int TP, class WS>
+__device__ __forceinline__ void gram_tile(const GramArgs<WS>& a, int part, int64_t p0, int qi, double* As0,
+                                          double* Ws0) {
+  constexpr int FMR = TP == GB ? 4 : 2, FNC = TP == GB ? 4 : 2;   // fragments per wave: rows, columns
+  constexpr int SPR = TP / 2;                                      // threads per staged S row (two pairs each)
+  constexpr int SRP = 256 / SPR, NSR = GKC / SRP;                  // S rows per pass, passes
+  static_assert(NSR * SRP == GKC, "S staging");
   const int* qt = a.qtiles + 4 * qi;                     // (m0, m0') of block 0, then of block 1
   const int64_t jbeg = (int64_t)part * a.jlen;
   const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
   const int nchunks = (int)((jend - jbeg + GKC - 1) / GKC);
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
-  const int wm = w >> 1, wn = w & 1, r = lane & 15, kq = lane >> 4;
+  const int r = lane & 15, kq = lane >> 4;
+  const int rowbase = TP == GB ? (w >> 1) * 64 : 0;      // first pair row of this wave
+  const int blk = TP == GB ? (w & 1) : (w >> 1);         // mode block of this wave
+  const int jbase = TP == GB ? 0 : 2 * (w & 1);          // first column fragment inside the block
 
   // this thread's staging slots
-  const int sp = (t & 63) * 2, srow = t >> 6;           // S: rows srow + 4i, pairs sp, sp+1
+  const int sp = (t % SPR) * 2, srow = t / SPR;          // S: rows srow + SRP i, pairs sp, sp+1
   int wcol[GWH], wrow[GWH];
   int64_t wm_idx[GWH];
 #pragma unroll
@@ -147,13 +149,13 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
   // zero rows past n_h, which zero the terms of rows beyond the last; W is
   // read at clamped, valid indices (finite values: times a zero S row they
   // give zero, and out-of-range mode columns only reach unwritten outputs).
-  double sv[2 * GSR], wv[GWH];
+  double sv[2 * NSR], wv[GWH];
   const int64_t jlast = a.n_h - 1, mlast = a.M - 1;
   auto load = [&](int chunk) {
     const int64_t j0 = jbeg + (int64_t)chunk * GKC;
 #pragma unroll
-    for (int i = 0; i < GSR; ++i) {
-      const double2 v = *reinterpret_cast<const double2*>(a.S + (j0 + srow + 4 * i) * a.ldS + p0 + sp);
+    for (int i = 0; i < NSR; ++i) {
+      const double2 v = *reinterpret_cast<const double2*>(a.S + (j0 + srow + SRP * i) * a.ldS + p0 + sp);
       sv[2 * i] = v.x;
       sv[2 * i + 1] = v.y;
     }
@@ -164,21 +166,23 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
     }
   };
   auto store = [&](int buf) {
+    double* As = As0 + buf * (GKC * TP);
+    double* Ws = Ws0 + buf * (GKC * GWS);
 #pragma unroll
-    for (int i = 0; i < GSR; ++i) {
-      As[buf][(srow + 4 * i) * GB + sp] = sv[2 * i];
-      As[buf][(srow + 4 * i) * GB + sp + 1] = sv[2 * i + 1];
+    for (int i = 0; i < NSR; ++i) {
+      As[(srow + SRP * i) * TP + sp] = sv[2 * i];
+      As[(srow + SRP * i) * TP + sp + 1] = sv[2 * i + 1];
     }
 #pragma unroll
     for (int h = 0; h < GWH; ++h)
-      if (wcol[h] < GWC) Ws[buf][wrow[h] * GWS + wcol[h]] = wv[h];
+      if (wcol[h] < GWC) Ws[wrow[h] * GWS + wcol[h]] = wv[h];
   };
 
-  d4 acc[4][4];
+  d4 acc[FMR][FNC];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FMR; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FNC; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   if (nchunks > 0) {
     load(0);
     store(0);
@@ -186,21 +190,22 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
     for (int c = 0; c < nchunks; ++c) {
       const bool more = c + 1 < nchunks;
       if (more) load(c + 1);
-      const double* Ab = As[c & 1];
-      const double* Wb = Ws[c & 1];
+      const double* Ab = As0 + (c & 1) * (GKC * TP);
+      const double* Wb = Ws0 + (c & 1) * (GKC * GWS);
 #pragma unroll
       for (int kk = 0; kk < GKC; kk += 4) {
         const int krow = kk + kq;
-        double av[4], bv[4];
+        double av[FMR], bv[FNC];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = Ab[krow * GB + wm * 64 + i * 16 + r];
-        const double wmp = Wb[krow * GWS + 16 * wn + 8 + (r & 7)];               // W[j, m']
+        for (int i = 0; i < FMR; ++i) av[i] = Ab[krow * TP + rowbase + i * 16 + r];
+        const double wmp = Wb[krow * GWS + 16 * blk + 8 + (r & 7)];                          // W[j, m']
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = Wb[krow * GWS + 16 * wn + 2 * j + (r >> 3)] * wmp;   // W[j, m] W[j, m']
+        for (int j = 0; j < FNC; ++j)
+          bv[j] = Wb[krow * GWS + 16 * blk + 2 * (jbase + j) + (r >> 3)] * wmp;              // W[j, m] W[j, m']
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FMR; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
+          for (int j = 0; j < FNC; ++j) acc[i][j] = mfma_f64(av[i], bv[j], acc[i][j]);
       }
       if (more) store((c + 1) & 1);
       __syncthreads();
@@ -208,22 +213,43 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
   }
   double* Gout = part == 0 ? a.G : a.G2 + (int64_t)(part - 1) * a.ldG * a.ldG;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FMR; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FNC; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = wm * 64 + i * 16 + kq + 4 * v;   // pair
-        const int c = j * 16 + r;                        // mode pair c of block wn
+        const int row = rowbase + i * 16 + kq + 4 * v;   // pair
+        const int c = (jbase + j) * 16 + r;              // mode pair c of block blk
         const int64_t p = p0 + row;
         if (p >= a.P) continue;
-        const int64_t m = qt[2 * wn] + (c >> 3), mp = qt[2 * wn + 1] + (c & 7);
+        const int64_t m = qt[2 * blk] + (c >> 3), mp = qt[2 * blk + 1] + (c & 7);
         if (mp >= a.M || m > mp) continue;
         const int64_t k = a.pairs[2 * p], kp = a.pairs[2 * p + 1];
         const double val = acc[i][j][v];
         Gout[(kp * a.M + mp) + (k * a.M + m) * a.ldG] = val;
         if (k != kp && m != mp) Gout[(kp * a.M + m) + (k * a.M + mp) * a.ldG] = val;
       }
+}
+
+template <class WS>
+__global__ __launch_bounds__(256) void gram_f64_kernel(GramArgs<WS> a) {
+  __shared__ double As[2 * GKC * GB];
+  __shared__ double Ws[2 * GKC * GWS];
+  // every XCD takes an equal share of the tail units first, then a
+  // contiguous range of the full ones
+  const int64_t tail_units = (int64_t)a.tail * a.nq * a.split, ntiles = (int64_t)a.nfull * a.nq;
+  const int64_t tail_per = (tail_units + 7) / 8, full_per = (ntiles * a.split + 7) / 8;
+  const int64_t xcd = blockIdx.x % 8, l = blockIdx.x / 8;
+  if (l < tail_per) {
+    const int64_t u = xcd * tail_per + l;
+    if (u >= tail_units) return;
+    gram_tile<GBT>(a, (int)(u / a.nq), (int64_t)a.nfull * GB, (int)(u % a.nq), As, Ws);
+    return;
+  }
+  const int64_t v = xcd * full_per + (l - tail_per);
+  if (v >= ntiles * a.split) return;
+  const int part = (int)(v / ntiles), tile = (int)(v % ntiles);
+  gram_tile<GB>(a, part, (int64_t)(tile / a.nq) * GB, tile % a.nq, As, Ws);
 }
 
 // Contraction parts for the untuned FP64 Gram: one when the tiles fill the
@@ -258,12 +284,16 @@ static hipError_t run_gram_f64(const Inst& in, WS w, hipStream_t s) {
   a.S = in.S; a.ldS = in.ldS; a.w = w;
   a.n_h = in.n_h; a.M = in.M; a.P = in.P;
   a.pairs = in.pairs; a.qtiles = in.qtiles;
-  a.npt = (int)ceil_div(in.P, GB); a.nq = in.nq; a.ntiles = a.npt * a.nq;
+  // full tiles of 128 pairs; a leftover of at most 32 pairs goes to the tail tiles
+  const int64_t rest = in.P % GB;
+  a.nfull = (int)(in.P / GB);
+  a.tail = rest > 0 && rest <= GBT ? 1 : 0;
+  if (rest > GBT) ++a.nfull;
+  a.nq = in.nq;
   a.split = gram_parts_used(in);
   a.jlen = round_up(ceil_div(in.n_h, a.split), GKC);
   a.G = in.G; a.G2 = a.split > 1 ? in.G2 : nullptr; a.ldG = in.KMp;
-  const int64_t units = (int64_t)a.ntiles * a.split;
-  const int64_t grid = 8 * ((units + 7) / 8);
+  const int64_t grid = 8 * (ceil_div((int64_t)a.tail * a.nq * a.split, 8) + ceil_div((int64_t)a.nfull * a.nq * a.split, 8));
   hipLaunchKernelGGL(gram_f64_kernel<WS>, dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }

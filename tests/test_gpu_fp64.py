@@ -19,6 +19,7 @@ SHAPES = [
     (12, 24, 2, 9, 31, 70),
     (20, 40, 1, 16, 40, 33),
     (3, 6, 1, 1, 1, 1),
+    (16, 32, 1, 64, 4, 3),     # 2080 member pairs: 16 full pair tiles and a tail of 32
 ]
 
 
