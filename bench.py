@@ -249,6 +249,8 @@ def main():
         tb = time.perf_counter()
         info = [pc.pc_query_info(plan.handle, k) for k in range(len(insts))]
         rungs = [pc.pc_query_instance(plan.handle, k)[0] for k in range(len(insts))]
+        # a blocked factorization: tile-DAG diagonal blocks plus MFMA panel products
+        blocked = all(pc.pc_query_tuning(plan.handle, k, with_block=True)[3] > 0 for k in range(len(insts)))
         Y = [y.cpu().numpy() for y in dY]
         plan.close()
         ms = (t1 - t0) * 1e3 / steps
@@ -269,6 +271,10 @@ def main():
             name, _ = kernel_info(ph, prec_name)
             if ph == "gram" and prec_name != "fp64" and len(insts) > 1:
                 name = f"gram_lowprec_batch_kernel<{code}>"     # all instances' Grams in one launch
+            if blocked and ph in ("cholesky", "solve"):
+                # the phase (time per pass) of several launches: DAG kernels on
+                # the diagonal blocks, gemm_f64_kernel for the panels
+                name = f"blocked: {name} + gemm_f64_kernel<NtGemmProb>"
             kernels[ph] = {"kernel": name, "avg_launch_ms": avg, "launches_per_step": launches_per_step,
                            "flops_per_launch": flops, "achieved_tflops": ach,
                            "peak_tflops": phase_peak(ph, prec_name),
