@@ -53,6 +53,7 @@ KERNELS = {
     ("solve", None): ("solve_dag_kernel_t", [CSRC + "k_dag.hip"]),
 }
 PRECS = {"fp64": (0, 0), "fp32": (1, 30), "bf16": (2, 30), "bf16x3": (3, 30)}
+RUNG_PREC = {code: name for name, (code, _) in PRECS.items()}
 GOLDEN = {4: os.path.join(ROOT, "tests", "golden", "c4_oracle.npz"),
           3: os.path.join(ROOT, "tests", "golden", "c3_oracle.npz")}
 ACCEPT = 1e-8
@@ -265,20 +266,29 @@ def main():
             launches_per_step = per * cnt / steps
             # every instance's work is done once per step, by one launch per
             # instance or by one launch for the whole batch
-            flops = sum(algorithmic_flops(ph, prec_name, i, i.R) for i in insts) * per / launches_per_step
+            # each instance's Gram in the precision of its rung (an FP64 rung:
+            # the structured FP64 Gram); the fraction is the time those flops
+            # need at their own peaks over the measured time
+            inst_prec = [RUNG_PREC.get(r, prec_name) if ph == "gram" else prec_name for r in rungs]
+            scale = per / launches_per_step
+            fl = [algorithmic_flops(ph, q, i, i.R) * scale for q, i in zip(inst_prec, insts)]
+            flops = sum(fl)
+            t_peak = sum(f / (phase_peak(ph, q) * 1e12) for f, q in zip(fl, inst_prec))
             avg = tot_ms / (cnt * per)
             ach = flops / (avg * 1e-3) / 1e12
+            peak = flops / t_peak / 1e12
             name, _ = kernel_info(ph, prec_name)
             if ph == "gram" and prec_name != "fp64" and len(insts) > 1:
                 name = f"gram_lowprec_batch_kernel<{code}>"     # all instances' Grams in one launch
+                if "fp64" in inst_prec and prec_name != "fp64":
+                    name += " + gram_f64_kernel (instances on the FP64 rung)"
             if blocked and ph in ("cholesky", "solve"):
                 # the phase (time per pass) of several launches: DAG kernels on
                 # the diagonal blocks, gemm_f64_kernel for the panels
                 name = f"blocked: {name} + gemm_f64_kernel<NtGemmProb>"
             kernels[ph] = {"kernel": name, "avg_launch_ms": avg, "launches_per_step": launches_per_step,
                            "flops_per_launch": flops, "achieved_tflops": ach,
-                           "peak_tflops": phase_peak(ph, prec_name),
-                           "frac": ach / phase_peak(ph, prec_name)}
+                           "peak_tflops": peak, "frac": ach / peak}
         return {"ms_per_step": ms, "rhs_per_s": total_rhs / (ms * 1e-3),
                 "apply_only_rhs_per_s": total_rhs / ((tb - ta) / napply),
                 "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
@@ -433,6 +443,7 @@ def main():
         "apply_only_rhs_per_s": main_res["apply_only_rhs_per_s"],
         "refine_iters_max": main_res["refine_iters_max"],
         "instances_not_factored": [k for k, ok in enumerate(main_res["factored"]) if not ok],
+        "rungs": {RUNG_PREC[r]: main_res["rungs"].count(r) for r in sorted(set(main_res["rungs"]))},
         "statuses": main_res["statuses"],
         "tuning": {"shapes (gram_split, ztx_split, chol_wgs_per_cu, chol_block, product_tile)": main_res["tuning"]},
         "kernels": kern,
