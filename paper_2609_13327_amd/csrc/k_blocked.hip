@@ -40,6 +40,7 @@ struct NtGemmProb {
   int accumulate, lower;
   int64_t tm, tn, ntiles;
   const int* skip;                                 // nonzero *skip: the product is not applied
+  int tri_b;                                       // B(j, k) = 0 for k > j: column tile j0.. contracts k < j0 + BN only
 
   struct Ctx { bool valid; int64_t i0, j0; int nchunks; };
 
@@ -85,7 +86,8 @@ struct NtGemmProb {
     }
     c.i0 = ti * BM;
     c.j0 = tj * BN;
-    c.nchunks = (int)((K + KC - 1) / KC);
+    const int64_t kend = tri_b && c.j0 + BN < K ? c.j0 + BN : K;
+    c.nchunks = (int)((kend + KC - 1) / KC);
     return c;
   }
   // Thread t's share of a chunk: elements e = t + NT q of a BR x KC slab,
@@ -181,10 +183,11 @@ using NtGemm256 = NtGemmProb<256, 128, 4, 2>;
 template <class P>
 static hipError_t run_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                               int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower,
-                              hipStream_t s, const int* skip = nullptr) {
+                              hipStream_t s, const int* skip = nullptr, int tri_b = 0) {
   P g;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
   g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower; g.skip = skip;
+  g.tri_b = tri_b;
   g.tm = ceil_div(M, P::BM);
   g.tn = ceil_div(N, P::BN);
   g.ntiles = lower ? P::RT * g.tm * (g.tm + 1) / 2 : g.tm * g.tn;
@@ -195,15 +198,15 @@ static hipError_t run_nt_gemm(const double* A, int64_t lda, const double* B, int
 
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                           int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
-                          int tile) {
+                          int tile, int tri_b) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K % 16 != 0) return hipErrorInvalidValue;      // whole chunks of k (the loaders read no edge)
   // tile 1: 128 x 128, tile 2: 256 x 128; 0: 256 x 128 once there are enough
   // of them to fill the device twice
   const int64_t t256 = lower ? ceil_div(M, 256) * (ceil_div(M, 256) + 1) : ceil_div(M, 256) * ceil_div(N, 128);
   if (tile == 2 || (tile == 0 && t256 >= 512))
-    return run_nt_gemm<NtGemm256>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
-  return run_nt_gemm<NtGemm128>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s);
+    return run_nt_gemm<NtGemm256>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s, nullptr, tri_b);
+  return run_nt_gemm<NtGemm128>(A, lda, B, ldb, C, ldc, M, N, K, alpha, accumulate, lower, s, nullptr, tri_b);
 }
 
 // Products of the blocked solves (rectangular, accumulate into C):

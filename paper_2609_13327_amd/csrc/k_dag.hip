@@ -1337,7 +1337,8 @@ static hipError_t launch_cholesky_blocked(const Inst& in, hipStream_t s) {
     double* panel = in.G + (k0 + nb) + k0 * ld;
     hipError_t e = launch_copy_panel(panel, ld, in.blk_P, m, m, nb, s);
     if (e == hipSuccess)
-      e = launch_nt_gemm(in.blk_P, m, in.blk_X, NO, panel, ld, m, nb, nb, 1.0, 0, 0, s, in.tune_gemm_tile);
+      e = launch_nt_gemm(in.blk_P, m, in.blk_X, NO, panel, ld, m, nb, nb, 1.0, 0, 0, s, in.tune_gemm_tile,
+                         1);   // X = L_kk^{-1} is lower triangular
     // 4. trailing lower triangle: G_22 -= L_panel L_panel^T
     if (e == hipSuccess)
       e = launch_nt_gemm(panel, ld, panel, ld, in.G + (k0 + nb) + (k0 + nb) * ld, ld, m, m, nb, -1.0, 1, 1, s,

@@ -217,9 +217,11 @@ hipError_t launch_fill_int(int* p, int v, int64_t count, hipStream_t s);
 // tile: 0 by size, 1: 128 x 128 tiles, 2: 256 x 128 tiles; K must be a
 // multiple of 16 (hipErrorInvalidValue otherwise; the blocked paths use
 // multiples of 64)
+// tri_b != 0: B(j, k) = 0 for k > j (a lower-triangular B), so each column
+// tile contracts only the k up to its last column
 hipError_t launch_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                           int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower, hipStream_t s,
-                          int tile = 0);
+                          int tile = 0, int tri_b = 0);
 // C (M x N) += alpha opA opB^T for the blocked solves: opA(i, k) = A[i + k lda]
 // (or A[k + i lda] with ta), opB(j, k) = B[k + j ldb]; nothing when *skip != 0;
 // K a multiple of 16.
