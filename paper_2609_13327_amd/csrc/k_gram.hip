@@ -96,7 +96,7 @@ hipError_t launch_column_grams(const Inst& in, hipStream_t s) {
 // Workgroups are mapped so that each XCD (the hardware places workgroup b on
 // XCD b mod 8) works on a contiguous range of tiles, which then share S rows
 // in its L2; the tail tiles come first.
-constexpr int GB = 128, GBT = 32, GKC = 16, GWC = 32;
+constexpr int GB = 128, GBT = 32, GKC = 24, GWC = 32;
 constexpr int GWS = 36;                           // W row stride in LDS: the four row groups of a read on distinct banks
 constexpr int GWH = (GKC * GWC + 255) / 256;      // W values staged per thread and chunk
 static_assert(GKC <= kGramZeroRows, "the last chunk reads up to GKC - 1 rows past n_h");
@@ -118,8 +118,8 @@ __device__ __forceinline__ void gram_tile(const GramArgs<WS>& a, int part, int64
                                           double* Ws0) {
   constexpr int FMR = TP == GB ? 4 : 2, FNC = TP == GB ? 4 : 2;   // fragments per wave: rows, columns
   constexpr int SPR = TP / 2;                                      // threads per staged S row (two pairs each)
-  constexpr int SRP = 256 / SPR, NSR = GKC / SRP;                  // S rows per pass, passes
-  static_assert(NSR * SRP == GKC, "S staging");
+  constexpr int SRP = 256 / SPR, NSR = (GKC + SRP - 1) / SRP;      // S rows per pass, passes
+  static_assert(GKC % 4 == 0, "chunks of whole MFMA k-steps");
   const int* qt = a.qtiles + 4 * qi;                     // (m0, m0') of block 0, then of block 1
   const int64_t jbeg = (int64_t)part * a.jlen;
   const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
@@ -155,7 +155,9 @@ __device__ __forceinline__ void gram_tile(const GramArgs<WS>& a, int part, int64
     const int64_t j0 = jbeg + (int64_t)chunk * GKC;
 #pragma unroll
     for (int i = 0; i < NSR; ++i) {
-      const double2 v = *reinterpret_cast<const double2*>(a.S + (j0 + srow + SRP * i) * a.ldS + p0 + sp);
+      // (a last pass that covers rows past the chunk reads its first row again; not stored)
+      const int rr = srow + SRP * i < GKC ? srow + SRP * i : 0;
+      const double2 v = *reinterpret_cast<const double2*>(a.S + (j0 + rr) * a.ldS + p0 + sp);
       sv[2 * i] = v.x;
       sv[2 * i + 1] = v.y;
     }
@@ -170,6 +172,7 @@ __device__ __forceinline__ void gram_tile(const GramArgs<WS>& a, int part, int64
     double* Ws = Ws0 + buf * (GKC * GWS);
 #pragma unroll
     for (int i = 0; i < NSR; ++i) {
+      if (NSR * SRP > GKC && srow + SRP * i >= GKC) continue;
       As[(srow + SRP * i) * TP + sp] = sv[2 * i];
       As[(srow + SRP * i) * TP + sp + 1] = sv[2 * i + 1];
     }

@@ -141,7 +141,7 @@ std::vector<int> make_qtiles(int64_t M);
 hipError_t launch_pairs_init(const Inst& in, hipStream_t s);
 hipError_t launch_column_grams(const Inst& in, hipStream_t s);
 // Zero rows of the per-column Grams S past n_h (read by the FP64 Gram's last chunk).
-constexpr int kGramZeroRows = 16;
+constexpr int kGramZeroRows = 32;
 hipError_t launch_gram_f64(const Inst& in, hipStream_t s);
 hipError_t launch_gram_lowprec(const Inst& in, int precision, hipStream_t s);
 // fp32 copies E32, W32 of E and W (the bf16 forms' operands), before their Gram
