@@ -458,13 +458,18 @@ __global__ __launch_bounds__(256, 2) void zy1_kernel(Zy1Args<WS> a) {
     const int64_t mc = st / a.K, k = st - mc * a.K;
     const int buf = (int)(st & 1);
     if (k == 0) {
-      // a new mode chunk: every wave is past the last fragment reads of Ws
-      __syncthreads();
+      // a new mode chunk: all its W loads in flight together (clamped,
+      // valid indices; out-of-range values zeroed when stored), then every
+      // wave is past the last fragment reads of Ws
+      double wv[YKC];
 #pragma unroll
       for (int mm = 0; mm < YKC; ++mm) {
         const int64_t m = mc * YKC + mm;
-        Ws[mm * WLD + t] = (jin && m < a.M) ? a.w(jt, m) : 0.0;
+        wv[mm] = a.w(jin ? jt : 0, m < a.M ? m : a.M - 1);
       }
+      __syncthreads();
+#pragma unroll
+      for (int mm = 0; mm < YKC; ++mm) Ws[mm * WLD + t] = (jin && mc * YKC + mm < a.M) ? wv[mm] : 0.0;
     }
     store_member(buf);
     __syncthreads();
