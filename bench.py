@@ -266,22 +266,25 @@ def main():
             launches_per_step = per * cnt / steps
             # every instance's work is done once per step, by one launch per
             # instance or by one launch for the whole batch
-            # each instance's Gram in the precision of its rung (an FP64 rung:
-            # the structured FP64 Gram); the fraction is the time those flops
-            # need at their own peaks over the measured time
+            # each instance's Gram in the precision of its rung; in a batch in
+            # reduced precision the phase times the one launch that forms the
+            # reduced-precision Grams (instances on the FP64 rung form theirs
+            # on the internal streams, outside it), so only those count
             inst_prec = [RUNG_PREC.get(r, prec_name) if ph == "gram" else prec_name for r in rungs]
+            batch_low = ph == "gram" and prec_name != "fp64" and len(insts) > 1
             scale = per / launches_per_step
-            fl = [algorithmic_flops(ph, q, i, i.R) * scale for q, i in zip(inst_prec, insts)]
+            fl = [0.0 if batch_low and q == "fp64" else algorithmic_flops(ph, q, i, i.R) * scale
+                  for q, i in zip(inst_prec, insts)]
             flops = sum(fl)
+            if flops <= 0:
+                continue
             t_peak = sum(f / (phase_peak(ph, q) * 1e12) for f, q in zip(fl, inst_prec))
             avg = tot_ms / (cnt * per)
             ach = flops / (avg * 1e-3) / 1e12
             peak = flops / t_peak / 1e12
             name, _ = kernel_info(ph, prec_name)
-            if ph == "gram" and prec_name != "fp64" and len(insts) > 1:
-                name = f"gram_lowprec_batch_kernel<{code}>"     # all instances' Grams in one launch
-                if "fp64" in inst_prec and prec_name != "fp64":
-                    name += " + gram_f64_kernel (instances on the FP64 rung)"
+            if batch_low:
+                name = f"gram_lowprec_batch_kernel<{code}>"     # all reduced-precision Grams in one launch
             if blocked and ph in ("cholesky", "solve"):
                 # the phase (time per pass) of several launches: DAG kernels on
                 # the diagonal blocks, gemm_f64_kernel for the panels
