@@ -204,11 +204,12 @@ pc_status pc_left_inverse_apply(pc_plan *plan, const double *const *X, const int
 /* pc_factor_apply — pc_gram_factor followed by pc_left_inverse_apply, with
  * the same arguments, ownership and statuses (failed_instance as in
  * pc_gram_factor; X need not be ready before the call, only ordered before
- * it on `stream`).  For a plan of one instance without a graph, the
- * products b = Z^T x (Sec. 3.9: they use E, W and X only) run on an
- * internal stream while the factorization runs, which the two separate
- * calls cannot do: pc_gram_factor waits for the pivot status before
- * returning.  Synchronizes `stream` once, at the end.  If the Gram of an
+ * it on `stream`).  For a plan of one instance without a graph whose Gram
+ * is factored by the tile DAG (order up to 8192), the products b = Z^T x
+ * (Sec. 3.9: they use E, W and X only) run on an internal stream while the
+ * factorization runs, which the two separate calls cannot do:
+ * pc_gram_factor waits for the pivot status before returning.  A blocked
+ * factorization (larger orders) runs after the products instead.  Synchronizes `stream` once, at the end.  If the Gram of an
  * instance with right-hand sides is not positive definite (after the
  * precision ladder), its Y is undefined and PC_ERR_NOT_SPD is returned
  * (*failed_instance: the first such instance); the other instances are still

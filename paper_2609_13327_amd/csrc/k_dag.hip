@@ -1525,9 +1525,9 @@ static hipError_t launch_chol_solve_blocked(const Inst& in, double* Y, int64_t l
   return hipGetLastError();
 }
 
-// Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) holds the forward result.
-// With first_pass = 1 only the backward pass runs (Wk already holds the
-// forward result).
+// Y (KMp x R, ld ldY) <- G^{-1} Y; Wk (KMp x R) is work: it holds the
+// forward result between the passes and is overwritten.  With first_pass =
+// 1 only the backward pass runs (Wk already holds the forward result).
 hipError_t launch_chol_solve(const Inst& in, double* Y, int64_t ldY, int64_t R, double* Wk, int64_t ldW,
                              hipStream_t s, const int* skip, int first_pass) {
   if (R <= 0) return hipSuccess;
