@@ -30,7 +30,7 @@ struct NtGemmProb {
   static constexpr int NA = BM * KC / NT, NB_ = BN * KC / NT;
   static constexpr int RT = BM / BN;              // column tiles per row tile (lower-triangle mode)
   static constexpr int LG = 8;                    // tile rows per group (lower-triangle mode, RT = 1)
-  static_assert(NA >= 1 && NB_ >= 1 && BM * KC % NT == 0 && BN * KC % NT == 0, "tile / thread mismatch");
+  static_assert(NA >= 2 && NB_ >= 2 && BM * KC % (2 * NT) == 0 && BN * KC % (2 * NT) == 0, "tile / thread mismatch");
   static_assert(BM % BN == 0, "row tiles must cover whole column tiles");
   const double* A; int64_t lda;
   const double* B; int64_t ldb;
@@ -90,54 +90,72 @@ struct NtGemmProb {
     c.nchunks = (int)((kend + KC - 1) / KC);
     return c;
   }
-  // Thread t's share of a chunk: elements e = t + NT q of a BR x KC slab,
-  // rows fastest for a column-major operand (row fixed, k steps NT / BR per
-  // q), k fastest for a k-major one (k fixed, row steps NT / KC per q).  K is
-  // a multiple of KC (checked on the host), so every k is inside; rows past
-  // the edge read the last row (their products only reach outputs that are
+  // Thread t's share of a chunk, in pairs of elements adjacent in memory
+  // (one 16-byte load each): a column-major operand pairs rows (pair index
+  // fixed per thread, k steps NT / (BR/2) per q), a k-major one pairs k
+  // (k pair fixed, row steps NT / (KC/2) per q).  K is a multiple of KC and
+  // the host checks the alignment (even leading dimensions and column-major
+  // row counts, 16-byte aligned bases), so every k is inside; row pairs past
+  // the edge read the last pair (their products only reach outputs that are
   // not written).  The loads are unconditional and nothing is selected on
   // their values, so the chunk's products never wait for them.
-  struct ARegs { double v[NA]; };
-  struct BRegs { double v[NB_]; };
-  template <bool T, int BR, int NV>
-  __device__ static void load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, double* v) {
+  struct ARegs { double x[NA / 2], y[NA / 2]; };
+  struct BRegs { double x[NB_ / 2], y[NB_ / 2]; };
+  template <bool T, int BR, int NP>
+  __device__ static void load_slab(const double* X, int64_t ldx, int64_t r0, int64_t rows, int64_t k0, double* vx,
+                                   double* vy) {
     const int t = threadIdx.x;
-    const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
-    constexpr int STEP = T ? NT / KC : NT / BR;      // rows (T) or k (column-major) per q
     if (!T) {
-      const int64_t r = r0 + row < rows ? r0 + row : rows - 1;
+      constexpr int STEP = NT / (BR / 2);              // k per q
+      const int pr = t % (BR / 2), kk = t / (BR / 2);
+      const int64_t r = r0 + 2 * pr <= rows - 2 ? r0 + 2 * pr : rows - 2;
       const double* p = X + r + (k0 + kk) * ldx;
       const int64_t qs = (int64_t)STEP * ldx;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) v[q] = p[q * qs];
+      for (int q = 0; q < NP; ++q) {
+        const double2 u = *reinterpret_cast<const double2*>(p + q * qs);
+        vx[q] = u.x;
+        vy[q] = u.y;
+      }
     } else {
-      const double* p = X + k0 + kk;
+      constexpr int STEP = NT / (KC / 2);              // rows per q
+      const int kp = t % (KC / 2), row = t / (KC / 2);
+      const double* p = X + k0 + 2 * kp;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
+      for (int q = 0; q < NP; ++q) {
         const int64_t r = r0 + row + STEP * q;
-        v[q] = p[(r < rows ? r : rows - 1) * ldx];
+        const double2 u = *reinterpret_cast<const double2*>(p + (r < rows ? r : rows - 1) * ldx);
+        vx[q] = u.x;
+        vy[q] = u.y;
       }
     }
   }
-  template <bool T, int BR, int NV, int LD>
-  __device__ static void store_slab(const double* v, double* S) {
+  template <bool T, int BR, int NP, int LD>
+  __device__ static void store_slab(const double* vx, const double* vy, double* S) {
     const int t = threadIdx.x;
-    const int row = T ? t / KC : t % BR, kk = T ? t % KC : t / BR;
-    constexpr int STEP = T ? NT / KC : NT / BR;
+    if (!T) {
+      constexpr int STEP = NT / (BR / 2);
+      const int pr = t % (BR / 2), kk = t / (BR / 2);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      if (T) S[kk * LD + ((row + STEP * q) ^ kk)] = v[q];
-      else S[(kk + STEP * q) * LD + row] = v[q];
+      for (int q = 0; q < NP; ++q) *reinterpret_cast<double2*>(S + (kk + STEP * q) * LD + 2 * pr) = double2{vx[q], vy[q]};
+    } else {
+      constexpr int STEP = NT / (KC / 2);
+      const int kp = t % (KC / 2), row = t / (KC / 2), k = 2 * kp;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        S[k * LD + ((row + STEP * q) ^ k)] = vx[q];
+        S[(k + 1) * LD + ((row + STEP * q) ^ (k + 1))] = vy[q];
+      }
     }
   }
   __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
-    load_slab<TA, BM, NA>(A, lda, c.i0, M, (int64_t)chunk * KC, r.v);
+    load_slab<TA, BM, NA / 2>(A, lda, c.i0, M, (int64_t)chunk * KC, r.x, r.y);
   }
-  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA, LDA>(r.v, As); }
+  __device__ void storeA(const ARegs& r, double* As) const { store_slab<TA, BM, NA / 2, LDA>(r.x, r.y, As); }
   __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
-    load_slab<TB, BN, NB_>(B, ldb, c.j0, N, (int64_t)chunk * KC, r.v);
+    load_slab<TB, BN, NB_ / 2>(B, ldb, c.j0, N, (int64_t)chunk * KC, r.x, r.y);
   }
-  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_, LDB>(r.v, Bs); }
+  __device__ void storeB(const BRegs& r, double* Bs) const { store_slab<TB, BN, NB_ / 2, LDB>(r.x, r.y, Bs); }
   // A tile inside C (and strictly below the diagonal in lower mode) reads
   // the 16 C values of a fragment row with unconditional loads before it
   // writes any of them: an edge test per element would make every load wait
@@ -180,10 +198,18 @@ struct NtGemmProb {
 using NtGemm128 = NtGemmProb<128, 128, 2, 2>;
 using NtGemm256 = NtGemmProb<256, 128, 4, 2>;
 
+// The loaders read pairs of adjacent elements with 16-byte loads: even
+// leading dimensions, 16-byte aligned bases, and an even row count for an
+// operand read along its columns.
+static bool pair_loads_ok(const double* X, int64_t ldx, int64_t rows, bool kmajor) {
+  return ((uintptr_t)X % 16 == 0) && ldx % 2 == 0 && (kmajor || (rows % 2 == 0 && rows >= 2));
+}
+
 template <class P>
 static hipError_t run_nt_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                               int64_t M, int64_t N, int64_t K, double alpha, int accumulate, int lower,
                               hipStream_t s, const int* skip = nullptr, int tri_b = 0) {
+  if (!pair_loads_ok(A, lda, M, P::XA) || !pair_loads_ok(B, ldb, N, P::XB)) return hipErrorInvalidValue;
   P g;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
   g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.accumulate = accumulate; g.lower = lower; g.skip = skip;
