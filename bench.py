@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--tune-cache", default=None, help="tuning cache file (read and updated)")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions")
+    ap.add_argument("--crossover-rhs", type=int, nargs="*", default=[64],
+                    help="256x512 instance: also time FP64 and bf16 with only this many right-hand sides")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the Hybrid product and swift left inverse timings (256x512 instance)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -191,13 +193,18 @@ def main():
     dX = [to_dev(i.X) for i in insts]
     dY = [torch.empty((i.R, i.KM), dtype=torch.float64, device=dev).t() for i in insts]
 
-    def measure(prec_name, steps, warmup, profile=True):
+    def measure(prec_name, steps, warmup, profile=True, flags=0, nrhs=None):
+        """Time factor + apply per step; `flags` are plan flags, `nrhs` the
+        first right-hand sides of each instance only (None: all)."""
         code, refine = PRECS[prec_name]
+        Xall = [x[:, :nrhs] for x in dX] if nrhs else dX
+        Yall = [y[:, :nrhs] for y in dY] if nrhs else dY
+        rhs_total = nrhs * len(insts) if nrhs else total_rhs
         if args.config == 3:
             refine = 20   # FP64 too: corrected semi-normal steps for the ill-conditioned members
         plan = pc.Plan([{"E": e, "W": w, "n_w": 1, "max_rhs": i.R} for e, w, i in zip(dE, dW, insts)],
                        precision=code, max_refine=refine, tol=1e-10 if refine else 0.0,
-                       use_graph=use_graph)
+                       use_graph=use_graph, flags=flags)
         tuning = None
         if not args.no_tune:   # launch shapes, measured on this plan before timing (like an FFT plan)
             pc.pc_autotune(plan.handle, args.tune_cache, True)
@@ -208,10 +215,10 @@ def main():
         # precision ladder) are left out: no right-hand sides, not counted
         st, _ = plan.factor(raise_on_error=False)
         ok = [pc.pc_query_instance(plan.handle, k)[1] for k in range(len(insts))]
-        Xs = [x if good else None for x, good in zip(dX, ok)]
+        Xs = [x if good else None for x, good in zip(Xall, ok)]
         log(f"  {prec_name}: factored, precisions {sorted(set(pc.pc_query_instance(plan.handle, k)[0] for k in range(len(insts))))}")
         for _ in range(warmup):
-            plan.factor_apply(Xs, dY, raise_on_error=False)
+            plan.factor_apply(Xs, Yall, raise_on_error=False)
         torch.cuda.synchronize()
         pc.pc_profile_read(plan.handle)  # drop anything recorded so far
         # a graph carries no timing events: with a graph the timed steps replay
@@ -222,7 +229,7 @@ def main():
         t0 = time.perf_counter()
         statuses = set()
         for k in range(steps):   # one step: factor and apply (the fused call overlaps Z^T x with the factor)
-            statuses.add(plan.factor_apply(Xs, dY, raise_on_error=False)[0])
+            statuses.add(plan.factor_apply(Xs, Yall, raise_on_error=False)[0])
             if args.config == 4:
                 log(f"  {prec_name}: step {k + 1}")   # progress (a step takes seconds here)
         torch.cuda.synchronize()
@@ -230,7 +237,7 @@ def main():
         if profile and use_graph:
             pc.pc_profile_enable(plan.handle, True)
             for _ in range(steps):
-                plan.factor_apply(Xs, dY, raise_on_error=False)
+                plan.factor_apply(Xs, Yall, raise_on_error=False)
             torch.cuda.synchronize()
         phases = pc.pc_profile_read(plan.handle)
         pc.pc_profile_enable(plan.handle, False)
@@ -238,14 +245,14 @@ def main():
         # steps (a reduced-precision Gram that factored but whose refinement
         # diverged, and whose FP64 Gram is not positive definite) have no answer
         ok = [good and pc.pc_query_instance(plan.handle, k)[1] for k, good in enumerate(ok)]
-        Xs = [x if good else None for x, good in zip(dX, ok)]
+        Xs = [x if good else None for x, good in zip(Xall, ok)]
         # apply only (factor reused)
-        plan.apply(Xs, dY, raise_on_error=False)
+        plan.apply(Xs, Yall, raise_on_error=False)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         napply = max(3, steps)
         for _ in range(napply):
-            plan.apply(Xs, dY, raise_on_error=False)
+            plan.apply(Xs, Yall, raise_on_error=False)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         info = [pc.pc_query_info(plan.handle, k) for k in range(len(insts))]
@@ -273,7 +280,7 @@ def main():
             inst_prec = [RUNG_PREC.get(r, prec_name) if ph == "gram" else prec_name for r in rungs]
             batch_low = ph == "gram" and prec_name != "fp64" and len(insts) > 1
             scale = per / launches_per_step
-            fl = [0.0 if batch_low and q == "fp64" else algorithmic_flops(ph, q, i, i.R) * scale
+            fl = [0.0 if batch_low and q == "fp64" else algorithmic_flops(ph, q, i, nrhs or i.R) * scale
                   for q, i in zip(inst_prec, insts)]
             flops = sum(fl)
             if flops <= 0:
@@ -292,8 +299,8 @@ def main():
             kernels[ph] = {"kernel": name, "avg_launch_ms": avg, "launches_per_step": launches_per_step,
                            "flops_per_launch": flops, "achieved_tflops": ach,
                            "peak_tflops": peak, "frac": ach / peak}
-        return {"ms_per_step": ms, "rhs_per_s": total_rhs / (ms * 1e-3),
-                "apply_only_rhs_per_s": total_rhs / ((tb - ta) / napply),
+        return {"ms_per_step": ms, "rhs_per_s": rhs_total / (ms * 1e-3),
+                "apply_only_rhs_per_s": rhs_total / ((tb - ta) / napply), "nrhs": nrhs,
                 "phases_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
                 "kernels": kernels, "tuning": tuning, "factored": ok, "rungs": rungs,
                 "statuses": sorted(pc.pc_status_string(st) for st in statuses),
@@ -371,10 +378,13 @@ def main():
         for k, (cols, ref) in refs.items():
             if not res["factored"][k] or (args.config == 3 and gold["rank_deficient"][k]):
                 continue   # no answer, or none that FP64 can define (numerically rank deficient Z)
-            got = res["Y"][k][:, cols]
+            nr = res.get("nrhs") or insts[k].R
+            keep = [c for c, col in enumerate(cols) if col < nr]    # columns this run solved
+            got = res["Y"][k][:, [cols[c] for c in keep]]
+            ref = ref[:, keep]
             e = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
             errs.append(e)
-            counted += insts[k].R * float(np.mean(e <= ACCEPT))
+            counted += nr * float(np.mean(e <= ACCEPT))
         e = np.concatenate(errs) if errs else np.array([np.inf])
         return float(e.max()), float(np.median(e)), counted
 
@@ -402,6 +412,31 @@ def main():
         for name, v in variants.items():
             if fp64_ms and "ms_per_step" in v:
                 v["speedup_vs_fp64"] = fp64_ms / v["ms_per_step"]
+        if args.config == 4:
+            # reduced-precision Gram and reduced-precision first Z^T x (the refinement stays FP64),
+            # at all right-hand sides and at 64 of them, where a refinement iteration costs 16x less
+            # than at 1024 while the Gram and the factorization cost the same: the crossover with FP64
+            extra = [("bf16+ztx_fp32", "bf16", pc.PC_FLAG_ZTX_FP32, None),
+                     ("bf16+ztx_bf16", "bf16", pc.PC_FLAG_ZTX_BF16, None)]
+            for r in args.crossover_rhs:
+                extra += [(f"fp64@R={r}", "fp64", 0, r), (f"bf16@R={r}", "bf16", 0, r),
+                          (f"bf16+ztx_fp32@R={r}", "bf16", pc.PC_FLAG_ZTX_FP32, r)]
+            for name, prec, fl, nr in extra:
+                try:
+                    v = measure(prec, 2, 1, flags=fl, nrhs=nr)
+                    e_max, _, v_counted = accuracy(v)
+                    variants[name] = {"ms_per_step": v["ms_per_step"], "rhs": nr or total_rhs,
+                                      "rhs_per_s": v_counted / (v["ms_per_step"] * 1e-3),
+                                      "apply_only_rhs_per_s": v["apply_only_rhs_per_s"],
+                                      "refine_iters_max": v["refine_iters_max"], "rel_err_max": e_max,
+                                      "rungs": sorted(set(v["rungs"])), "statuses": v["statuses"],
+                                      "phases_ms_per_step": v["phases_ms_per_step"]}
+                except Exception as ex:
+                    variants[name] = {"error": str(ex)}
+            for name, v in variants.items():
+                base = variants.get(f"fp64@R={v.get('rhs')}", {}).get("ms_per_step") if "@R=" in name else fp64_ms
+                if base and "ms_per_step" in v:
+                    v["speedup_vs_fp64"] = base / v["ms_per_step"]
 
     # roofline of the kernel that takes the most time per step
     kern = main_res["kernels"]

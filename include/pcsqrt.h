@@ -106,7 +106,7 @@ typedef struct {
                           instance, then replays it (both run eagerly while phase timing,
                           pc_profile_enable, is on: a graph carries no timing events) */
   int32_t flags;       /* 0, or PC_FLAG_KEEP_GRAM (optionally with PC_FLAG_CG_MEMBER_BLOCKS),
-                          or PC_FLAG_FIXED_PRECISION */
+                          PC_FLAG_FIXED_PRECISION, PC_FLAG_ZTX_FP32 or PC_FLAG_ZTX_BF16 (or'ed) */
 } pc_options;
 
 /* Keep a symmetric copy of each instance's FP64 Gram, for pc_cg_solve /
@@ -127,6 +127,17 @@ typedef struct {
  * the precision ladder (a failure is reported as PC_ERR_NOT_SPD or
  * PC_ERR_NO_CONVERGENCE instead). */
 #define PC_FLAG_FIXED_PRECISION 4
+
+/* Form the first right-hand side of the normal equations, b = Z^T x, in
+ * reduced precision as well while an instance is on a reduced-precision
+ * rung: the products of pc_sqrt_transpose_apply_lowprec with fp32 operands
+ * (PC_FLAG_ZTX_FP32) or bf16 operands (PC_FLAG_ZTX_BF16), MFMA with fp32
+ * accumulation.  The refinement's Z^T r stays FP64, so the refined result
+ * keeps its accuracy; the rounding of b only changes the starting point.
+ * An instance in FP64 (plan precision or the ladder's last rung) uses the
+ * FP64 product.  At most one of the two flags. */
+#define PC_FLAG_ZTX_FP32 8
+#define PC_FLAG_ZTX_BF16 16
 
 typedef struct pc_plan pc_plan;
 
@@ -266,6 +277,22 @@ const char *pc_status_string(pc_status s);
  * X: device n x R (ldX >= n); B: device K*M x R (ldB >= K*M).  Asynchronous. */
 pc_status pc_sqrt_transpose_apply(pc_plan *plan, int32_t instance, const double *X, int64_t ldX,
                                   int64_t R, double *B, int64_t ldB, void *stream);
+
+/* pc_sqrt_transpose_apply_lowprec — B = Zt^T Xt for instance `instance`, the
+ * reduced-precision form of pc_sqrt_transpose_apply (the first product of a
+ * mixed-precision solve; the precision of the Gram and of Z^T x is not fixed
+ * by the paper, whose method is FP64).  Zt is the rounded Z whose Gram the
+ * reduced-precision modes form and Xt the rounded right-hand sides:
+ *   precision PC_PREC_FP32_REFINE: Zt = fp32(E[i,k] W[j,m]) (the FP64 product
+ *     rounded once), Xt = fp32(X), MFMA f32;
+ *   precision PC_PREC_BF16_REFINE: Zt = bf16(fl32(fp32(E[i,k]) fp32(W[j,m]))),
+ *     Xt = bf16(fp32(X)), MFMA bf16;
+ * rounding to nearest even, j = i mod n_h.  Products accumulate in fp32 over
+ * all n rows of Z; B is stored in FP64.  X: device n x R (ldX >= n); B:
+ * device K*M x R (ldB >= K*M), overwritten.  Other precision values, or bad
+ * sizes, give PC_ERR_INVALID_ARG.  Asynchronous on `stream`. */
+pc_status pc_sqrt_transpose_apply_lowprec(pc_plan *plan, int32_t instance, int32_t precision, const double *X,
+                                          int64_t ldX, int64_t R, double *B, int64_t ldB, void *stream);
 
 /* pc_sqrt_apply — X = Z Y, the back-transform to model variables
  * (x = (P^c)^{1/2} x~, Sec. 2.2).  Y: device K*M x R; X: device n x R. */

@@ -426,6 +426,27 @@ def lowprec_operands(E, W, n_w, fmt: str):
     raise ValueError(fmt)
 
 
+def round_rhs(X: np.ndarray, fmt: str) -> np.ndarray:
+    """The right-hand sides as the reduced-precision Z^T x reads them:
+    "fp32": fp32(x); "bf16": bf16(fp32(x)) -- rounded to float32 first, then
+    to bfloat16, both to nearest even (the two roundings can differ from one
+    direct rounding to bfloat16 at a float32 tie).  Returned as float64."""
+    if fmt == "fp32":
+        return round_fp32(X)
+    if fmt == "bf16":
+        return round_bf16(round_fp32(X))
+    raise ValueError(fmt)
+
+
+def zt_apply_lowprec(E, W, n_w, X, fmt: str):
+    """Exact (float64) product Zt^T Xt of the reduced-precision Z^T x: Zt the
+    rounded square root of `lowprec_operands` ("fp32" or "bf16") and Xt the
+    rounded right-hand sides of `round_rhs`.  The GPU accumulates these
+    products in float32; this is the value that accumulation approximates."""
+    Zt = lowprec_operands(E, W, n_w, fmt)[0]
+    return Zt.T @ round_rhs(X, fmt)
+
+
 def gram_lowprec(E, W, n_w, fmt: str):
     """Exact (float64) Gram of the rounded square root of `lowprec_operands`:
     Zt^T Zt for "bf16" and "fp32"; for "bf16x3" the three-product split-bf16

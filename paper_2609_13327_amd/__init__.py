@@ -38,6 +38,8 @@ PC_PREC_BF16X3_REFINE = 3
 PC_FLAG_KEEP_GRAM = 1
 PC_FLAG_CG_MEMBER_BLOCKS = 2
 PC_FLAG_FIXED_PRECISION = 4
+PC_FLAG_ZTX_FP32 = 8
+PC_FLAG_ZTX_BF16 = 16
 PC_MLP_BF16 = 0
 PC_MLP_FP32 = 1
 
@@ -50,7 +52,7 @@ EXPORTED = [
     "pc_learned_apply", "pc_mlp_training_pairs", "pc_autotune", "pc_query_tuning",
     "pc_set_tuning", "pc_factor_apply", "pc_factor_apply_noalloc", "pc_query_instance", "pc_query_rhs_info", "pc_hybrid_apply",
     "pc_sqrt_build_separable", "pc_set_tile_shape", "pc_query_tile_shape",
-    "pc_swift_build", "pc_swift_apply", "pc_swift_destroy",
+    "pc_swift_build", "pc_swift_apply", "pc_swift_destroy", "pc_sqrt_transpose_apply_lowprec",
 ]
 
 PHASES = ["column_grams", "gram", "pad", "cholesky", "ztx", "solve", "refine", "copyout", "solve_alongside"]
@@ -123,6 +125,8 @@ def load_library(path: str = LIB_PATH):
                                             c_int64, c_void_p]
     lib.pc_sqrt_apply.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                   c_void_p]
+    lib.pc_sqrt_transpose_apply_lowprec.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_int64, c_int64,
+                                                    c_void_p, c_int64, c_void_p]
     lib.pc_gram_assemble.argtypes = [c_void_p, c_void_p]
     lib.pc_gram_export.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p]
     lib.pc_profile_enable.argtypes = [c_void_p, c_int32]
@@ -412,6 +416,13 @@ def pc_sqrt_transpose_apply(plan: int, instance: int, X, B, stream=None):
     _check(load_library().pc_sqrt_transpose_apply(c_void_p(plan), int(instance), _ptr(X), _ld(X),
                                                   int(X.shape[1]), _ptr(B), _ld(B),
                                                   c_void_p(_stream(stream))), "pc_sqrt_transpose_apply")
+
+
+def pc_sqrt_transpose_apply_lowprec(plan: int, instance: int, precision: int, X, B, stream=None):
+    _check(load_library().pc_sqrt_transpose_apply_lowprec(c_void_p(plan), int(instance), int(precision), _ptr(X),
+                                                          _ld(X), int(X.shape[1]), _ptr(B), _ld(B),
+                                                          c_void_p(_stream(stream))),
+           "pc_sqrt_transpose_apply_lowprec")
 
 
 def pc_sqrt_apply(plan: int, instance: int, Y, X, stream=None):

@@ -184,6 +184,11 @@ int* chol_error_flag(const Inst& in);   // device int set when a bounded wait of
 // at once; the refinement loop uses it to stop converged instances on the GPU.
 hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B,
                       int64_t ldB, hipStream_t s, const int* skip = nullptr);
+// B = Zt^T Xt with the rounded operands of a reduced-precision form
+// (precision PC_PREC_FP32_REFINE: fp32; PC_PREC_BF16_REFINE: bf16), MFMA
+// with fp32 accumulation, stored in FP64 (hipErrorInvalidValue otherwise)
+hipError_t launch_ztx_lowprec(const Inst& in, int precision, const double* X, int64_t ldX, int64_t R, double* B,
+                              int64_t ldB, hipStream_t s);
 // out = Xsub - Z Y  (Xsub may be null: out = Z Y)
 hipError_t launch_zy(const Inst& in, const double* Y, int64_t ldY, int64_t R, const double* Xsub,
                      int64_t ldXs, double* out, int64_t ldOut, hipStream_t s, const int* skip = nullptr);

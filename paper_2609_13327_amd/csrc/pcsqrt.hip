@@ -419,6 +419,18 @@ int next_rung(int prec) {
   }
 }
 
+// b = Z^T x, the first right-hand side of the normal equations: with the
+// reduced-precision operands the plan's flags ask for while the instance is
+// on a reduced-precision rung, else FP64.
+hipError_t launch_first_ztx(const pc_plan* p, const Inst& in, const double* X, int64_t ldX, int64_t R, double* B,
+                            int64_t ldB, hipStream_t s) {
+  const int f = p->opt.flags;
+  if (in.prec != PC_PREC_FP64 && (f & (PC_FLAG_ZTX_FP32 | PC_FLAG_ZTX_BF16)))
+    return pc::launch_ztx_lowprec(in, (f & PC_FLAG_ZTX_FP32) ? PC_PREC_FP32_REFINE : PC_PREC_BF16_REFINE, X, ldX,
+                                  R, B, ldB, s);
+  return pc::launch_ztx(in, X, ldX, R, B, ldB, s);
+}
+
 bool ladder_on(const pc_plan* p) { return !(p->opt.flags & PC_FLAG_FIXED_PRECISION); }
 
 // The apply sequence of every instance on the streams (no host wait when
@@ -444,7 +456,7 @@ pc_status enqueue_apply(pc_plan* p, const double* const* X, const int64_t* ldX, 
     hipStream_t si = stream_for(p, i, s);
     if (done_ahead < 1) {
       PhaseTimer t(p, PC_PHASE_ZTX, si);
-      PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si));
+      PC_TRY(launch_first_ztx(p, in, X[i], ldX[i], R[i], in.Y, in.KMp, si));
     }
     {
       PhaseTimer t(p, PC_PHASE_SOLVE, si);
@@ -508,7 +520,7 @@ pc_status enqueue_apply_batched(pc_plan* p, const double* const* X, const int64_
     if (R[i] == 0) continue;
     hipStream_t si = stream_for(p, i, s);
     PhaseTimer t(p, PC_PHASE_ZTX, si);
-    PC_TRY(pc::launch_ztx(in, X[i], ldX[i], R[i], in.Y, in.KMp, si));
+    PC_TRY(launch_first_ztx(p, in, X[i], ldX[i], R[i], in.Y, in.KMp, si));
   }
   PC_TRY(join(p, s));
   PC_TRY(pc::set_batch_rhs(p->batch, R, s));
@@ -716,7 +728,9 @@ static pc_status checked_options(const pc_options* opt, pc_options* o) {
   *o = pc_options{PC_PREC_FP64, 0, 1e-12, 0, 0};
   if (opt) *o = *opt;
   if (o->precision < PC_PREC_FP64 || o->precision > PC_PREC_BF16X3_REFINE || o->max_refine < 0 ||
-      (o->flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS | PC_FLAG_FIXED_PRECISION)) != 0 ||
+      (o->flags & ~(PC_FLAG_KEEP_GRAM | PC_FLAG_CG_MEMBER_BLOCKS | PC_FLAG_FIXED_PRECISION | PC_FLAG_ZTX_FP32 |
+                    PC_FLAG_ZTX_BF16)) != 0 ||
+      ((o->flags & PC_FLAG_ZTX_FP32) && (o->flags & PC_FLAG_ZTX_BF16)) ||
       !std::isfinite(o->tol))
     return PC_ERR_INVALID_ARG;
   if ((o->flags & PC_FLAG_CG_MEMBER_BLOCKS) && !(o->flags & PC_FLAG_KEEP_GRAM)) return PC_ERR_INVALID_ARG;
@@ -1260,7 +1274,7 @@ pc_status pc_factor_apply(pc_plan* p, const double* const* X, const int64_t* ldX
   st = read_factor_status(p, s);
   if (st != PC_OK) return st;
   PC_TRY(hipStreamWaitEvent(p->ovl, p->ev_gram, 0));
-  { PhaseTimer t(p, PC_PHASE_ZTX, p->ovl); PC_TRY(pc::launch_ztx(in, X[0], ldX[0], R[0], in.Y, in.KMp, p->ovl)); }
+  { PhaseTimer t(p, PC_PHASE_ZTX, p->ovl); PC_TRY(launch_first_ztx(p, in, X[0], ldX[0], R[0], in.Y, in.KMp, p->ovl)); }
   if (fwd) {
     PC_TRY(hipStreamWaitEvent(p->ovl, p->ev_reset, 0));
     PhaseTimer t(p, PC_PHASE_SOLVE_ALONGSIDE, p->ovl);
@@ -1328,6 +1342,18 @@ pc_status pc_sqrt_transpose_apply(pc_plan* p, int32_t instance, const double* X,
   if (!X || !B || ldX < in.n || ldB < in.KM) return PC_ERR_INVALID_ARG;
   hipSetDevice(p->device);
   PC_TRY(pc::launch_ztx(in, X, ldX, R, B, ldB, (hipStream_t)stream));
+  return PC_OK;
+}
+
+pc_status pc_sqrt_transpose_apply_lowprec(pc_plan* p, int32_t instance, int32_t precision, const double* X,
+                                          int64_t ldX, int64_t R, double* B, int64_t ldB, void* stream) {
+  if (!p || instance < 0 || (size_t)instance >= p->inst.size() || R < 0) return PC_ERR_INVALID_ARG;
+  if (precision != PC_PREC_FP32_REFINE && precision != PC_PREC_BF16_REFINE) return PC_ERR_INVALID_ARG;
+  const Inst& in = p->inst[instance];
+  if (R == 0) return PC_OK;
+  if (!X || !B || ldX < in.n || ldB < in.KM) return PC_ERR_INVALID_ARG;
+  hipSetDevice(p->device);
+  PC_TRY(pc::launch_ztx_lowprec(in, precision, X, ldX, R, B, ldB, (hipStream_t)stream));
   return PC_OK;
 }
 

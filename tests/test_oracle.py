@@ -491,3 +491,49 @@ def test_separable_modes_match_the_generator():
         # lat-major: row a n_lon + i of W is U[a] * Phi[i]
         a, i, m = n_lat - 2, 3, M - 1
         assert Ws[a * n_lon + i, m] == U[a, m] * Phi[i, m]
+
+
+def test_zt_apply_lowprec_hand_cases():
+    """Reduced-precision Z^T x, hand values.  One row: x = 1 + 2^-8 + 2^-30
+    has the float32 copy 1 + 2^-8, a bfloat16 tie that rounds to even, 1
+    (rounding x straight to bfloat16 would give 1 + 2^-7); with e = w = 1 the
+    bf16 product is 1 and the fp32 one 1 + 2^-8.  Two rows (n_h = 2):
+    z = (1 + 2^-8)^2 = 1 + 2^-7 + 2^-16 rounds to 1 + 2^-7 in bfloat16 and
+    2 * 0.5 = 1 stays; x = (3, 1 + 2^-9) rounds to (3, 1), so the bf16 value
+    is 3 (1 + 2^-7) + 1; in fp32 every operand is exact and the value is the
+    plain 3 (1 + 2^-8)^2 + (1 + 2^-9)."""
+    one = np.array([[1.0]])
+    x = np.array([[1.0 + 2.0 ** -8 + 2.0 ** -30]])
+    assert lsq.zt_apply_lowprec(one, one, 1, x, "bf16")[0, 0] == 1.0
+    assert lsq.round_bf16(x)[0, 0] == 1.0 + 2.0 ** -7
+    assert lsq.zt_apply_lowprec(one, one, 1, x, "fp32")[0, 0] == 1.0 + 2.0 ** -8
+    E = np.array([[1.0 + 2.0 ** -8], [2.0]])
+    W = np.array([[1.0 + 2.0 ** -8], [0.5]])
+    X = np.array([[3.0], [1.0 + 2.0 ** -9]])
+    assert lsq.zt_apply_lowprec(E, W, 1, X, "bf16")[0, 0] == 3.0 * (1.0 + 2.0 ** -7) + 1.0
+    assert lsq.zt_apply_lowprec(E, W, 1, X, "fp32")[0, 0] == 3.0 * (1.0 + 2.0 ** -8) ** 2 + (1.0 + 2.0 ** -9)
+    with pytest.raises(ValueError):
+        lsq.zt_apply_lowprec(E, W, 1, X, "bf16x3")
+
+
+def test_zt_apply_lowprec_bound_and_layout():
+    """On a random multi-level instance: the rounded product lies within the
+    operand rounding bound of the exact Z^T X (bf16: |z~ - z| <= (2^-9 +
+    2^-22)|z|, |x~ - x| <= (2^-9 + 2^-23)|x|; fp32: 2^-23 each, products
+    included), differs from it (the rounding is there), and its column block
+    of member k equals W^T (e_k o X) summed over levels up to that bound --
+    the column order (k, m) and the row order (l, j) of Z."""
+    inst = small_instance(3, 5, 2, 4, 6)
+    rng = np.random.Generator(np.random.PCG64(17))
+    X = rng.standard_normal((inst.n, 7))
+    Z = lsq.form_z(inst.E, inst.W, inst.n_w)
+    exact = Z.T @ X
+    mag = np.abs(Z).T @ np.abs(X)
+    for fmt, u in (("bf16", 2.0 ** -8 + 2.0 ** -20), ("fp32", 2.0 ** -22)):
+        B = lsq.zt_apply_lowprec(inst.E, inst.W, inst.n_w, X, fmt)
+        assert np.all(np.abs(B - exact) <= u * mag), fmt
+        assert not np.array_equal(B, exact)
+        for k in range(inst.K):
+            blk = sum(inst.W.T @ (inst.E[l * inst.n_h:(l + 1) * inst.n_h, k:k + 1]
+                                  * X[l * inst.n_h:(l + 1) * inst.n_h]) for l in range(inst.n_w))
+            assert np.all(np.abs(B[k * inst.M:(k + 1) * inst.M] - blk) <= u * mag[k * inst.M:(k + 1) * inst.M])
