@@ -598,6 +598,42 @@ def next_rows(torch, pc, wl, E, W, X, inst):
                               "status": pc.pc_status_string(st),
                               "mode_bytes_dense": 8 * n_h * M, "mode_bytes_separable": 8 * (n_lat + n_lon) * M,
                               "Y": Ys}
+    del Ys
+    # several levels sharing the horizontal modes: the level sums of Z^T x and
+    # of the per-column Grams come first
+    log("multi-level instance (64x128 grid, 8 levels)")
+    ml = wl.multilevel_config()
+    gml = np.load(os.path.join(ROOT, "tests", "golden", "ml_oracle.npz"))
+    same = all(hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest() == str(gml["digest_" + k])
+               for k, a in (("E", ml.E), ("W", ml.W), ("X", ml.X)))
+    mE, mW, mX = to_dev(ml.E), to_dev(ml.W), to_dev(ml.X)
+    plan = pc.Plan([{"E": mE, "W": mW, "n_w": ml.n_w, "max_rhs": ml.R}])
+    pc.pc_autotune(plan.handle, None, True)
+    mY = torch.empty((ml.R, ml.KM), dtype=torch.float64, device=X.device).t()
+    plan.factor_apply([mX], [mY])
+    torch.cuda.synchronize()
+    pc.pc_profile_read(plan.handle)
+    pc.pc_profile_enable(plan.handle, True)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st, _ = plan.factor_apply([mX], [mY])
+    torch.cuda.synchronize()
+    ml_ms = (time.perf_counter() - t0) * 1e3 / reps
+    ph = pc.pc_profile_read(plan.handle)
+    plan.close()
+    got = mY[:, list(gml["columns"])].cpu().numpy()
+    e = np.linalg.norm(got - gml["Y"], axis=0) / np.linalg.norm(gml["Y"], axis=0)
+    fl_ztx = 2.0 * ml.n_h * ml.M * ml.K * ml.R + 2.0 * ml.n * ml.K * ml.R
+    ztx_ms = ph["ztx"][0] / max(1, ph["ztx"][1])
+    res["multilevel"] = {"workload": f"{wl.MULTILEVEL_NAME}: n_h={ml.n_h}, n_w={ml.n_w}, K={ml.K}, M={ml.M}, "
+                                     f"R={ml.R}, FP64 factor + apply",
+                         "ms_per_step": ml_ms, "rhs_per_s": ml.R / (ml_ms * 1e-3), "status": pc.pc_status_string(st),
+                         "phases_ms_per_step": {k: v[0] / reps for k, v in ph.items()},
+                         "ztx_roofline": {"bound": "mfma", "achieved": fl_ztx / (ztx_ms * 1e-3) / 1e12, "peak": 78.6,
+                                          "unit": "TFLOP/s", "frac": fl_ztx / (ztx_ms * 1e-3) / 1e12 / 78.6},
+                         "rel_err_max": float(e.max()) if same else None, "kappa": float(gml["kappa"]),
+                         "inputs_match_stored_oracle": bool(same)}
     return res
 
 

@@ -1,12 +1,9 @@
 // Products with the modulated square root Z, never forming Z (FP64, MFMA).
 //
 //  Z^T x  (the start of the solve and of every refinement step):
-//      b[k*M + m, r] = sum_j W[j, m] * u[j, (k, r)],
-//      u[j, (k, r)]  = sum_l E[l*n_h + j, k] * X[l*n_h + j, r]
-//    a per-grid-column contraction over the levels (the shape of the
-//    paper's column step V1) followed by a projection on the modes (the
-//    shape of its member step V4).  GEMM rows = (k, r), cols = m, depth = j;
-//    the u operand is formed while it is staged in LDS.
+//      b[k*M + m, r] = sum_i E[i, k] W[j(i), m] X[i, r],   j(i) = i mod n_h,
+//    per member a GEMM X^T (diag(e_k) W) over the n rows of Z; the
+//    scaling by e_k is applied when the MFMA operand is formed.
 //
 //  Z y  (the back-transform, the residual x - Z y of refinement, and the
 //  Hybrid product (1 - beta) v + beta Z (Z^T v)): out = alpha xs + beta (Z y),
@@ -21,109 +18,19 @@
 namespace pc {
 
 // ------------------------------------------------------------------ Z^T X
-template <int BM_, int BN_, int WM_, int WN_, class WS>
-struct ZtxProb {
-  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = 16;
-  static constexpr int LDA = BM + 1, LDB = BN + 1;
-  static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
-  static_assert(NA >= 1 && NB_ >= 1, "tile too small for 256 threads");
-  const double* E; int64_t ldE;
-  WS w;
-  const double* X; int64_t ldX;
-  double* Bout; int64_t ldB;
-  int64_t n_h, n_w, K, M, R, KR;
-  int ntr, ntc;   // tiles along rows (k,r) and cols (m)
-  const int* skip;
-
-  struct Ctx { bool valid; int64_t c0, m0; int nchunks; };
-  struct ARegs { double v[NA]; };
-  struct BRegs { double v[NB_]; };
-
-  __device__ Ctx ctx(int tile) const {
-    Ctx c;
-    const int tr = tile % ntr, tc = tile / ntr;
-    c.valid = tc < ntc && !(skip && *skip);
-    c.c0 = (int64_t)tr * BM;
-    c.m0 = (int64_t)tc * BN;
-    c.nchunks = (int)((n_h + KC - 1) / KC);
-    return c;
-  }
-  // element e of this thread: jj = e_index % KC (fastest, coalesced), row = e_index / KC
-  __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = t + 256 * i;
-      const int jj = e % KC, row = e / KC;
-      const int64_t j = (int64_t)chunk * KC + jj, cc = c.c0 + row;
-      double s = 0.0;
-      if (j < n_h && cc < KR) {
-        const int64_t k = cc / R, rr = cc % R;
-        const double* Ek = E + k * ldE + j;
-        const double* Xr = X + rr * ldX + j;
-        for (int64_t l = 0; l < n_w; ++l) s += Ek[l * n_h] * Xr[l * n_h];
-      }
-      r.v[i] = s;
-    }
-  }
-  __device__ void storeA(const ARegs& r, double* As) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = t + 256 * i;
-      As[(e % KC) * LDA + e / KC] = r.v[i];
-    }
-  }
-  __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < NB_; ++i) {
-      const int e = t + 256 * i;
-      const int jj = e % KC, col = e / KC;
-      const int64_t j = (int64_t)chunk * KC + jj, m = c.m0 + col;
-      r.v[i] = (j < n_h && m < M) ? w(j, m) : 0.0;
-    }
-  }
-  __device__ void storeB(const BRegs& r, double* Bs) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < NB_; ++i) {
-      const int e = t + 256 * i;
-      Bs[(e % KC) * LDB + e / KC] = r.v[i];
-    }
-  }
-  __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
-    acc.for_each([&](int row, int col, double v) {
-      const int64_t cc = c.c0 + row, m = c.m0 + col;
-      if (cc >= KR || m >= M) return;
-      const int64_t k = cc / R, rr = cc % R;
-      Bout[(k * M + m) + rr * ldB] = v;
-    });
-  }
-};
-
-template <class P, class WS>
-static hipError_t run_ztx(const Inst& in, WS w, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
-                          hipStream_t s, const int* skip) {
-  P pr;
-  pr.skip = skip;
-  pr.E = in.E; pr.ldE = in.ldE; pr.w = w;
-  pr.X = X; pr.ldX = ldX; pr.Bout = B; pr.ldB = ldB;
-  pr.n_h = in.n_h; pr.n_w = in.n_w; pr.K = in.K; pr.M = in.M; pr.R = R; pr.KR = in.K * R;
-  pr.ntr = (int)ceil_div(pr.KR, P::BM);
-  pr.ntc = (int)ceil_div(in.M, P::BN);
-  const int64_t tiles = (int64_t)pr.ntr * pr.ntc;
-  hipLaunchKernelGGL(gemm_f64_kernel<P>, dim3((unsigned)tiles), dim3(256), 0, s, pr);
-  return hipGetLastError();
-}
-
-// Single level (n_w = 1): b_k = (X^T Z_k)^T with Z_k[j, m] = E[j, k] W[j, m];
-// tile = 64 right-hand sides x 64 modes of ZKB consecutive members k.  The
+// b_k = (X^T Z_k)^T with Z_k[i, m] = E[i, k] W[j(i), m], the contraction over
+// the n rows i = l n_h + j of Z (j(i) = i mod n_h; one level: j = i);
+// tile = 64 right-hand sides x 64 modes of KB consecutive members k (KB = 4,
+// or 2 or 1 when larger tiles would leave compute units without one).  The
 // staged X and W rows serve all of the tile's members: each member's column
-// of E scales the W rows when the MFMA fragment is read.  With few tiles the
-// j range is split in two halves accumulated with two atomic adds onto a
-// zeroed output (two addends onto zero: the same result in either order).
-constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1, ZKB = 4;
+// of E scales the W rows when the MFMA fragment is read.  Several levels run
+// through the same MFMA contraction over all n rows rather than forming the
+// level sums sum_l E[l n_h + j, k] X[l n_h + j, r] first: that operand would
+// be re-formed for every mode tile from n_w scalar loads of each factor per
+// element.  With few tiles the row range is split in two halves accumulated
+// with two atomic adds onto a zeroed output (two addends onto zero: the same
+// result in either order).
+constexpr int ZT = 64, ZKC = 32, ZLD = ZT + 1;
 constexpr int ZNQ = ZKC * ZT / 256;     // X and W values staged per thread and chunk
 
 template <class WS>
@@ -132,13 +39,13 @@ struct Ztx1Args {
   WS w;
   const double* X; int64_t ldX;
   double* B; int64_t ldB;
-  int64_t n_h, K, M, R;
+  int64_t n, n_h, K, M, R;
   int ntr, ntm, ntk, split;
   int64_t jlen;
   const int* skip;
 };
 
-template <class WS>
+template <int ZKB, bool ONE, class WS>
 __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args<WS> a) {
   if (a.skip && *a.skip) return;
   __shared__ double Xs[2][ZKC * ZLD];
@@ -156,12 +63,15 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args<WS> a) {
   const int64_t k0 = (tile / a.ntm) * ZKB;                         // first member of the tile
   const int64_t r0 = (int64_t)tr * ZT, m0 = (int64_t)tm * ZT;
   const int64_t jbeg = (int64_t)part * a.jlen;
-  const int64_t jend = jbeg + a.jlen < a.n_h ? jbeg + a.jlen : a.n_h;
+  const int64_t jend = jbeg + a.jlen < a.n ? jbeg + a.jlen : a.n;
   const int nchunks = (int)((jend - jbeg + ZKC - 1) / ZKC);
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
 
   double xv[ZNQ], wv[ZNQ], ev = 0.0;
+  // every element this thread stages is in row t % ZKC of the chunk; its W row
+  // for the next chunk to load (several levels)
+  int64_t jw = ONE ? 0 : (jbeg + t % ZKC) % a.n_h;
   // E: thread t < ZKC * ZKB stages member t / ZKC, row t % ZKC (zero past K)
   const int ej = t % ZKC, ek = t / ZKC;
   const bool estage = t < ZKC * ZKB;
@@ -174,9 +84,10 @@ __global__ __launch_bounds__(256) void ztx1_kernel(Ztx1Args<WS> a) {
       const int e = t + 256 * q, jj = e % ZKC, col = e / ZKC;
       const int64_t j = j0 + jj;
       xv[q] = (j < jend && r0 + col < a.R) ? a.X[j + (r0 + col) * a.ldX] : 0.0;
-      wv[q] = (j < jend && m0 + col < a.M) ? a.w(j, m0 + col) : 0.0;
+      wv[q] = (j < jend && m0 + col < a.M) ? a.w(ONE ? j : jw, m0 + col) : 0.0;
     }
     if (estage) ev = (evalid && j0 + ej < jend) ? Ek[j0 + ej] : 0.0;
+    if constexpr (!ONE) jw = (jw + ZKC) % a.n_h;
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -258,31 +169,46 @@ static hipError_t run_ztx1(const Inst& in, WS w, const double* X, int64_t ldX, i
   Ztx1Args<WS> a;
   a.skip = skip;
   a.E = in.E; a.ldE = in.ldE; a.w = w; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
-  a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
-  a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT); a.ntk = (int)ceil_div(in.K, ZKB);
+  a.n = in.n; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
+  a.ntr = (int)ceil_div(R, ZT); a.ntm = (int)ceil_div(in.M, ZT);
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
-  const int64_t ntiles = (int64_t)a.ntr * a.ntm * a.ntk;
-  a.split = (ntiles < 2 * (int64_t)cus && in.n_h >= 4 * ZKC) ? 2 : 1;
-  if (in.tune_ztx_split == 1 || (in.tune_ztx_split == 2 && in.n_h >= 2 * ZKC)) a.split = in.tune_ztx_split;
-  a.jlen = round_up(ceil_div(in.n_h, a.split), ZKC);
+  // members per tile: 4, halved while the launch (with a split row range)
+  // would still give fewer than two workgroups per compute unit
+  const int64_t base = (int64_t)a.ntr * a.ntm;
+  int kb = 4;
+  while (kb > 1 && base * ceil_div(in.K, kb) * (in.n >= 4 * ZKC ? 2 : 1) < 2 * (int64_t)cus) kb /= 2;
+  a.ntk = (int)ceil_div(in.K, kb);
+  const int64_t ntiles = base * a.ntk;
+  a.split = (ntiles < 2 * (int64_t)cus && in.n >= 4 * ZKC) ? 2 : 1;
+  if (in.tune_ztx_split == 1 || (in.tune_ztx_split == 2 && in.n >= 2 * ZKC)) a.split = in.tune_ztx_split;
+  a.jlen = round_up(ceil_div(in.n, a.split), ZKC);
   if (a.split == 2) {
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(in.KM, 256), 64);
     hipLaunchKernelGGL(zero_block_kernel, dim3(gx, (unsigned)R), dim3(256), 0, s, B, ldB, in.KM, R, skip);
   }
   const int64_t units = ntiles * a.split;
-  hipLaunchKernelGGL(ztx1_kernel<WS>, dim3((unsigned)(8 * ((units + 7) / 8))), dim3(256), 0, s, a);
+  const dim3 grid((unsigned)(8 * ((units + 7) / 8)));
+  const bool one = in.n_w == 1;
+  if (kb == 4) {
+    if (one) hipLaunchKernelGGL((ztx1_kernel<4, true, WS>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((ztx1_kernel<4, false, WS>), grid, dim3(256), 0, s, a);
+  } else if (kb == 2) {
+    if (one) hipLaunchKernelGGL((ztx1_kernel<2, true, WS>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((ztx1_kernel<2, false, WS>), grid, dim3(256), 0, s, a);
+  } else {
+    if (one) hipLaunchKernelGGL((ztx1_kernel<1, true, WS>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((ztx1_kernel<1, false, WS>), grid, dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <class WS>
 static hipError_t ztx_for(const Inst& in, WS w, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,
                           hipStream_t s, const int* skip) {
-  if (in.n_w == 1) return run_ztx1(in, w, X, ldX, R, B, ldB, s, skip);
-  if (in.M <= 32) return run_ztx<ZtxProb<128, 32, 4, 1, WS>>(in, w, X, ldX, R, B, ldB, s, skip);
-  return run_ztx<ZtxProb<64, 64, 2, 2, WS>>(in, w, X, ldX, R, B, ldB, s, skip);
+  return run_ztx1(in, w, X, ldX, R, B, ldB, s, skip);
 }
 
 hipError_t launch_ztx(const Inst& in, const double* X, int64_t ldX, int64_t R, double* B, int64_t ldB,

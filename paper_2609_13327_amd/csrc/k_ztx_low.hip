@@ -12,10 +12,11 @@
 // the rounding is per element of Z, so the level sum cannot come first as it
 // does in FP64.
 //
-// Tile: 64 right-hand sides x 64 modes of 4 consecutive members, four waves
+// Tile: 64 right-hand sides x 64 modes of QKB consecutive members (4, or 2
+// or 1 when larger tiles would leave compute units without one), four waves
 // (2 x 2) of 32 x 32 per member; chunks of 32 rows staged in LDS (double
 // buffered, the next chunk's loads issued before the current chunk's
-// MFMAs).  The X and W rows of a chunk serve all four members: each member's
+// MFMAs).  The X and W rows of a chunk serve all the tile's members: each member's
 // E column scales the W rows when the operand fragment is formed and
 // rounded.  Tiles are dealt out in contiguous ranges per XCD.
 #include "pc_common.h"
@@ -27,7 +28,7 @@ namespace pc {
 
 namespace {
 
-constexpr int QT = 64, QKC = 32, QKB = 4;
+constexpr int QT = 64, QKC = 32;
 constexpr int QLD = QT + 1;      // fp32 form: LDS row stride (one row of Z per LDS row)
 constexpr int QBS = QKC + 8;     // bf16 form: bf16 stride of an X column (80 bytes)
 constexpr int QWS = QKC + 4;     // bf16 form: fp32 stride of a W or E column (144 bytes)
@@ -45,7 +46,7 @@ struct ZtxLowArgs {
 
 // Tile of workgroup blockIdx.x: contiguous ranges of tiles per XCD
 // (workgroups are dealt round robin over the 8 XCDs).  False past the end.
-template <class A>
+template <int QKB, class A>
 __device__ __forceinline__ bool ztx_low_tile(const A& a, int64_t& r0, int64_t& m0, int64_t& k0) {
   const int64_t units = (int64_t)a.ntr * a.ntm * a.ntk;
   const int64_t per = (units + 7) / 8;
@@ -69,14 +70,14 @@ __device__ __forceinline__ unsigned pack2(float x, float y) {
 
 // ------------------------------------------------------------------- fp32
 // Thread t stages row t % 32 of the chunk for the tile columns t / 32 + 8 q
-// (q < 8) of X and W; threads t < 128 stage row t % 32 of member t / 32.
-template <bool ONE, class WS>
+// (q < 8) of X and W; threads t < 32 QKB stage row t % 32 of member t / 32.
+template <int QKB, bool ONE, class WS>
 __global__ __launch_bounds__(256) void ztx_f32_kernel(ZtxLowArgs<WS> a) {
   __shared__ float Xs[2][QKC * QLD];
   __shared__ double Ws[2][QKC * QLD];
   __shared__ double Es[2][QKC * QKB];
   int64_t r0, m0, k0;
-  if (!ztx_low_tile(a, r0, m0, k0)) return;
+  if (!ztx_low_tile<QKB>(a, r0, m0, k0)) return;
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
   const int jj = t % QKC, c0 = t / QKC;          // staged row of the chunk, first staged column
@@ -167,15 +168,15 @@ __global__ __launch_bounds__(256) void ztx_f32_kernel(ZtxLowArgs<WS> a) {
 
 // ------------------------------------------------------------------- bf16
 // Thread t stages rows 8 (t % 4) .. + 7 of the chunk for tile column t / 4
-// of X and of W; threads t < 16 stage those rows of member t / 4.  LDS holds
-// X as bf16 (one column of 32 rows per LDS row), W and E as fp32 copies.
-template <bool ONE, class WS>
+// of X and of W; threads t < 4 QKB stage those rows of member t / 4.  LDS
+// holds X as bf16 (one column of 32 rows per LDS row), W and E as fp32 copies.
+template <int QKB, bool ONE, class WS>
 __global__ __launch_bounds__(256) void ztx_bf16_kernel(ZtxLowArgs<WS> a) {
   __shared__ __attribute__((aligned(16))) unsigned short Xs[2][QT * QBS];
   __shared__ __attribute__((aligned(16))) float Ws[2][QT * QWS];
   __shared__ __attribute__((aligned(16))) float Es[2][QKB * QWS];
   int64_t r0, m0, k0;
-  if (!ztx_low_tile(a, r0, m0, k0)) return;
+  if (!ztx_low_tile<QKB>(a, r0, m0, k0)) return;
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w >> 1, wn = w & 1, rr = lane & 15, kq = lane >> 4;
   const int seg = t & 3, col = t >> 2;
@@ -282,19 +283,34 @@ hipError_t run_ztx_low(const Inst& in, WS w, int precision, const double* X, int
   ZtxLowArgs<WS> a;
   a.E = in.E; a.ldE = in.ldE; a.w = w; a.X = X; a.ldX = ldX; a.B = B; a.ldB = ldB;
   a.n = in.n; a.n_h = in.n_h; a.K = in.K; a.M = in.M; a.R = R;
-  a.ntr = (int)ceil_div(R, QT); a.ntm = (int)ceil_div(in.M, QT); a.ntk = (int)ceil_div(in.K, QKB);
-  const int64_t units = (int64_t)a.ntr * a.ntm * a.ntk;
+  a.ntr = (int)ceil_div(R, QT); a.ntm = (int)ceil_div(in.M, QT);
+  if (precision != LP_FP32 && precision != LP_BF16) return hipErrorInvalidValue;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus <= 0) cus = 256;
+  // members per tile: 4, halved while the launch would give fewer than two
+  // workgroups per compute unit
+  const int64_t base = (int64_t)a.ntr * a.ntm;
+  int kb = 4;
+  while (kb > 1 && base * ceil_div(in.K, kb) < 2 * (int64_t)cus) kb /= 2;
+  a.ntk = (int)ceil_div(in.K, kb);
+  const int64_t units = base * a.ntk;
   const dim3 grid((unsigned)(8 * ((units + 7) / 8)));
   const bool one = in.n_w == 1;
-  if (precision == LP_FP32) {
-    if (one) hipLaunchKernelGGL((ztx_f32_kernel<true, WS>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((ztx_f32_kernel<false, WS>), grid, dim3(256), 0, s, a);
-  } else if (precision == LP_BF16) {
-    if (one) hipLaunchKernelGGL((ztx_bf16_kernel<true, WS>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((ztx_bf16_kernel<false, WS>), grid, dim3(256), 0, s, a);
-  } else {
-    return hipErrorInvalidValue;
+  const bool f32 = precision == LP_FP32;
+#define PC_ZTX_LOW_LAUNCH(KB)                                                                   \
+  if (f32) {                                                                                   \
+    if (one) hipLaunchKernelGGL((ztx_f32_kernel<KB, true, WS>), grid, dim3(256), 0, s, a);     \
+    else hipLaunchKernelGGL((ztx_f32_kernel<KB, false, WS>), grid, dim3(256), 0, s, a);        \
+  } else {                                                                                     \
+    if (one) hipLaunchKernelGGL((ztx_bf16_kernel<KB, true, WS>), grid, dim3(256), 0, s, a);    \
+    else hipLaunchKernelGGL((ztx_bf16_kernel<KB, false, WS>), grid, dim3(256), 0, s, a);       \
   }
+  if (kb == 4) { PC_ZTX_LOW_LAUNCH(4) }
+  else if (kb == 2) { PC_ZTX_LOW_LAUNCH(2) }
+  else { PC_ZTX_LOW_LAUNCH(1) }
+#undef PC_ZTX_LOW_LAUNCH
   return hipGetLastError();
 }
 

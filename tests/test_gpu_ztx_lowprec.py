@@ -156,3 +156,30 @@ def test_mixed_solve_from_lowprec_ztx_matches_oracle(flag, prec, fused):
     assert np.linalg.norm(got - d) <= 1e-6 * np.linalg.norm(d) + 1e-10 * np.linalg.norm(host(Y2))
     plan.close()
     plain.close()
+
+
+# Launches large enough for each members-per-tile choice of the two Z^T x
+# kernels (64 x 128 grid): (FP64 tile, reduced-precision tile) = (2, 1), (4, 2), (4, 4)
+BIG = [(64, 128, 1, 24, 256, 512), (64, 128, 1, 24, 320, 640), (64, 128, 1, 32, 256, 1024)]
+
+
+@pytest.mark.parametrize("shape", BIG)
+def test_ztx_tile_choices_match_oracle(shape):
+    inst = _inst(shape, seed=67)
+    plan = pc.Plan([inst_dict(inst)])
+    X = dev(inst.X)
+    B = empty(inst.KM, inst.R)
+    pc.pc_sqrt_transpose_apply(plan.handle, 0, X, B)
+    Z = lsq.form_z(inst.E, inst.W, 1)
+    absZ = np.abs(Z)
+    g = (inst.n + 2) * 2.0 ** -53
+    assert np.all(np.abs(host(B) - Z.T @ inst.X) <= 2 * g / (1 - g) * (absZ.T @ np.abs(inst.X)) + 1e-300)
+    del Z, absZ
+    for fmt in sorted(FMTS):
+        pc.pc_sqrt_transpose_apply_lowprec(plan.handle, 0, FMTS[fmt], X, B)
+        Zt = lsq.lowprec_operands(inst.E, inst.W, 1, fmt)[0]
+        Xt = lsq.round_rhs(inst.X, fmt)
+        ref = Zt.T @ Xt
+        assert np.all(np.abs(host(B) - ref) <= _bound(Zt, Xt, inst.n)), fmt
+        del Zt
+    plan.close()

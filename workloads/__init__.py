@@ -32,6 +32,7 @@ from threadpoolctl import threadpool_limits
 __all__ = [
     "latlon_points", "circulant_spectrum", "grf_draws", "localization_modes",
     "Instance", "make_instance", "config", "batched_config", "CONFIG_NAMES", "mlp_init",
+    "multilevel_config", "MULTILEVEL", "MULTILEVEL_NAME",
 ]
 
 
@@ -261,6 +262,20 @@ CONFIG_NAMES = {
     4: "c4_n131072_K64_M512_R1024",
     5: "c5_learned_n131072_K64_M512",
 }
+
+
+# A multi-level instance (n_w levels of the same horizontal grid share the
+# horizontal localization modes): 64x128 grid, 8 levels, K = 32, M = 128,
+# 256 right-hand sides; Z is 65536 x 4096.
+MULTILEVEL = dict(n_lat=64, n_lon=128, n_w=8, K=32, M=128, R=256, l_ens=0.05, l_loc=0.2, seed=6000)
+MULTILEVEL_NAME = "ml_n65536_nw8_K32_M128_R256"
+
+
+def multilevel_config() -> Instance:
+    """The multi-level instance (each level draws independent members)."""
+    p = MULTILEVEL
+    return make_instance(p["n_lat"], p["n_lon"], p["K"], p["M"], p["R"], p["l_ens"], p["l_loc"], p["seed"],
+                         n_w=p["n_w"])
 
 
 def config_params(c: int) -> dict:
