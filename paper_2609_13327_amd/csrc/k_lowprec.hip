@@ -86,7 +86,12 @@ __device__ __forceinline__ void store_tile(const LowGramInst& g, int64_t a0, int
 }
 
 // ---------------------------------------------------------------- bf16 (and split bf16)
-constexpr int BKC = 32, BST = BKC + 8;   // k per stage, padded LDS row stride (bf16 elements)
+// Contraction rows per stage: two 32-row MFMA steps, so that each
+// workgroup has twice the operand bytes of a 32-row stage in flight while
+// the MFMAs of the previous stage run (the stage loop waits on load latency,
+// not on the MFMAs).  Padded LDS row stride in bf16 elements.
+constexpr int BKC = 64, KH = BKC / 32, BST = BKC + 8;
+static_assert(BKC == kLowRowPad, "the fp32 copies are padded to whole stages");
 
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __bf16 b2v __attribute__((ext_vector_type(2)));
@@ -147,18 +152,16 @@ __device__ __forceinline__ void form8(const Raw8& r, s8& hi, s8& lo) {
 // 64 rows x (256 / BF_WAVES) columns of the 128 x 128 tile; a thread stages
 // BF_NH columns per side.
 constexpr int BF_WAVES = 8;
-constexpr int BF_PREFETCH = 1;   // chunks loaded ahead of the MFMAs (1 or 2 register sets)
 constexpr int BF_THREADS = 64 * BF_WAVES;
 constexpr int BF_NH = 8 / BF_WAVES;
 
 // One 128 x 128 tile (a0.., b0..) of the lower triangle, a0 >= b0, from the
 // staged fp32 copies (E32: ldE32 rows, zero beyond n, and a zero column K
 // used for the columns beyond K M).  X3: the split-bf16 form (hi and lo
-// operands, three products).  Thread t stages rows 8 (t % 4) .. of the
-// chunk for tile column t / 4 on both sides.  The operand loads run two
-// chunks ahead (two register sets): while the MFMAs of chunk c run, the
-// loads of chunks c + 1 and c + 2 are in flight, and chunk c + 1 is
-// converted into the other LDS buffer after them.
+// operands, three products).  Thread t stages rows 32 h + 8 (t % 4) .. (h
+// < KH) of the chunk for tile column t / 4 on both sides.  The loads of
+// chunk c + 1 are issued before the MFMAs of chunk c and formed into the
+// other LDS buffer after them.
 template <bool X3, int WM>
 __device__ __forceinline__ void gram_bf16_tile_w(const LowGramInst& g, int64_t a0, int64_t b0,
                                                  unsigned short (&As)[2][X3 ? 2 : 1][LT * BST],
@@ -167,7 +170,7 @@ __device__ __forceinline__ void gram_bf16_tile_w(const LowGramInst& g, int64_t a
   constexpr int WN = BF_WAVES / 2, CW = 128 / WN;   // waves along the columns, columns per wave
   const int t = threadIdx.x, lane = lane_id(), w = wave_id();
   const int wm = w / WN, wn = w % WN, r = lane & 15, kq = lane >> 4;
-  const int seg = t & 3, col = t >> 2;           // 8-row segment of a 32-row chunk, first tile column
+  const int seg = t & 3, col = t >> 2;           // 8-row segment of each 32-row half, first tile column
   const float* pe[2][BF_NH];
   const float* pw[2][BF_NH];
 #pragma unroll
@@ -180,33 +183,43 @@ __device__ __forceinline__ void gram_bf16_tile_w(const LowGramInst& g, int64_t a
       pe[side][h] = g.E32 + k * g.ldE32;
       pw[side][h] = g.W32 + m * g.ldW32;
     }
-  const int64_t nchunks = g.ldE32 / BKC;         // ldE32 is a multiple of 32 (zero rows beyond n)
-  int64_t jn = (int64_t)seg * 8 % g.n_h;         // row of W for the next chunk to load (n_w > 1)
-  auto load = [&](int64_t c, Raw8 (&raw)[2][BF_NH]) {
-    const int64_t i0 = c * BKC + seg * 8;
-    const int64_t j0 = WM == 0 ? i0 : jn;
+  const int64_t nchunks = g.ldE32 / BKC;         // ldE32 is a multiple of BKC (zero rows beyond n)
+  int64_t jn = (int64_t)seg * 8 % g.n_h;         // W row of the next stage's first half (n_w > 1)
+  auto load = [&](int64_t c, Raw8 (&raw)[2][BF_NH][KH]) {
+    int64_t jh = jn;
 #pragma unroll
-    for (int h = 0; h < BF_NH; ++h) {
-      load8<WM>(pe[0][h] + i0, pw[0][h], j0, g.n_h, raw[0][h]);
-      load8<WM>(pe[1][h] + i0, pw[1][h], j0, g.n_h, raw[1][h]);
+    for (int hh = 0; hh < KH; ++hh) {
+      const int64_t i0 = c * BKC + hh * 32 + seg * 8;
+      const int64_t j0 = WM == 0 ? i0 : jh;
+#pragma unroll
+      for (int h = 0; h < BF_NH; ++h) {
+        load8<WM>(pe[0][h] + i0, pw[0][h], j0, g.n_h, raw[0][h][hh]);
+        load8<WM>(pe[1][h] + i0, pw[1][h], j0, g.n_h, raw[1][h][hh]);
+      }
+      if constexpr (WM != 0) {
+        jh += 32;
+        while (jh >= g.n_h) jh -= g.n_h;
+      }
     }
     if constexpr (WM != 0) {
       jn += BKC;
       while (jn >= g.n_h) jn -= g.n_h;
     }
   };
-  auto convert_store = [&](const Raw8 (&raw)[2][BF_NH], int buf) {
+  auto convert_store = [&](const Raw8 (&raw)[2][BF_NH][KH], int buf) {
 #pragma unroll
-    for (int h = 0; h < BF_NH; ++h) {
-      const int o = (col + (128 / BF_NH) * h) * BST + seg * 8;
-      s8 hi, lo;
-      form8<X3>(raw[0][h], hi, lo);
-      *reinterpret_cast<s8*>(&As[buf][0][o]) = hi;
-      if constexpr (X3) *reinterpret_cast<s8*>(&As[buf][NP - 1][o]) = lo;
-      form8<X3>(raw[1][h], hi, lo);
-      *reinterpret_cast<s8*>(&Bs[buf][0][o]) = hi;
-      if constexpr (X3) *reinterpret_cast<s8*>(&Bs[buf][NP - 1][o]) = lo;
-    }
+    for (int hh = 0; hh < KH; ++hh)
+#pragma unroll
+      for (int h = 0; h < BF_NH; ++h) {
+        const int o = (col + (128 / BF_NH) * h) * BST + hh * 32 + seg * 8;
+        s8 hi, lo;
+        form8<X3>(raw[0][h][hh], hi, lo);
+        *reinterpret_cast<s8*>(&As[buf][0][o]) = hi;
+        if constexpr (X3) *reinterpret_cast<s8*>(&As[buf][NP - 1][o]) = lo;
+        form8<X3>(raw[1][h][hh], hi, lo);
+        *reinterpret_cast<s8*>(&Bs[buf][0][o]) = hi;
+        if constexpr (X3) *reinterpret_cast<s8*>(&Bs[buf][NP - 1][o]) = lo;
+      }
   };
   constexpr int TI = 4, TJ = CW / 16;            // this wave: rows wm*64 + 16 i, columns wn*CW + 16 j
   f4 acc[TI][TJ];
@@ -220,67 +233,48 @@ __device__ __forceinline__ void gram_bf16_tile_w(const LowGramInst& g, int64_t a
       for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
     }
   auto mma = [&](int buf) {
-    s8 af[TI], bf[TJ];
 #pragma unroll
-    for (int i = 0; i < TI; ++i) af[i] = *reinterpret_cast<const s8*>(&As[buf][0][(wm * 64 + i * 16 + r) * BST + kq * 8]);
+    for (int hh = 0; hh < KH; ++hh) {
+      const int ko = hh * 32 + kq * 8;
+      s8 af[TI], bf[TJ];
 #pragma unroll
-    for (int j = 0; j < TJ; ++j) bf[j] = *reinterpret_cast<const s8*>(&Bs[buf][0][(wn * CW + j * 16 + r) * BST + kq * 8]);
-    if constexpr (X3) {
-      s8 al[TI], bl[TJ];
+      for (int i = 0; i < TI; ++i) af[i] = *reinterpret_cast<const s8*>(&As[buf][0][(wm * 64 + i * 16 + r) * BST + ko]);
 #pragma unroll
-      for (int i = 0; i < TI; ++i) al[i] = *reinterpret_cast<const s8*>(&As[buf][NP - 1][(wm * 64 + i * 16 + r) * BST + kq * 8]);
+      for (int j = 0; j < TJ; ++j) bf[j] = *reinterpret_cast<const s8*>(&Bs[buf][0][(wn * CW + j * 16 + r) * BST + ko]);
+      if constexpr (X3) {
+        s8 al[TI], bl[TJ];
 #pragma unroll
-      for (int j = 0; j < TJ; ++j) bl[j] = *reinterpret_cast<const s8*>(&Bs[buf][NP - 1][(wn * CW + j * 16 + r) * BST + kq * 8]);
+        for (int i = 0; i < TI; ++i)
+          al[i] = *reinterpret_cast<const s8*>(&As[buf][NP - 1][(wm * 64 + i * 16 + r) * BST + ko]);
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+        for (int j = 0; j < TJ; ++j)
+          bl[j] = *reinterpret_cast<const s8*>(&Bs[buf][NP - 1][(wn * CW + j * 16 + r) * BST + ko]);
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-          acc[i][j] = mfma_bf16(al[i], bf[j], acc[i][j]);   // small terms first
-          acc[i][j] = mfma_bf16(af[i], bl[j], acc[i][j]);
-          acc[i][j] = mfma_bf16(af[i], bf[j], acc[i][j]);
-        }
-    } else {
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+          for (int j = 0; j < TJ; ++j) {
+            acc[i][j] = mfma_bf16(al[i], bf[j], acc[i][j]);   // small terms first
+            acc[i][j] = mfma_bf16(af[i], bl[j], acc[i][j]);
+            acc[i][j] = mfma_bf16(af[i], bf[j], acc[i][j]);
+          }
+      } else {
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_bf16(af[i], bf[j], acc[i][j]);
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_bf16(af[i], bf[j], acc[i][j]);
+      }
     }
   };
-  if constexpr (BF_PREFETCH == 1) {
-    Raw8 ra[2][BF_NH];
-    load(0, ra);
-    convert_store(ra, 0);
-    __syncthreads();
-    for (int64_t c = 0; c < nchunks; ++c) {
-      const bool more = c + 1 < nchunks;
-      if (more) load(c + 1, ra);
-      mma((int)(c & 1));
-      if ((c + 1) % (FLUSH_ROWS / BKC) == 0) flush_partial(acc, acc64);
-      if (more) convert_store(ra, (int)((c + 1) & 1));
-      __syncthreads();
-    }
-    flush_partial(acc, acc64);
-    store_tile(g, a0, b0, wm * 64, wn * CW, acc64);
-    return;
-  }
-  Raw8 ra[2][BF_NH], rb[2][BF_NH];                // register sets of even and odd chunks
+  Raw8 ra[2][BF_NH][KH];
   load(0, ra);
-  if (nchunks > 1) load(1, rb);
   convert_store(ra, 0);
   __syncthreads();
-  // chunk c: its operands are in LDS buffer c & 1; the raw set of chunk c + 1
-  // is in flight, and the set chunk c used is reloaded with chunk c + 2
-  for (int64_t c = 0; c < nchunks; c += 2) {
-    if (c + 2 < nchunks) load(c + 2, ra);
-    mma(0);
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const bool more = c + 1 < nchunks;
+    if (more) load(c + 1, ra);
+    mma((int)(c & 1));
     if ((c + 1) % (FLUSH_ROWS / BKC) == 0) flush_partial(acc, acc64);
-    if (c + 1 < nchunks) convert_store(rb, 1);
-    __syncthreads();
-    if (c + 1 >= nchunks) break;
-    if (c + 3 < nchunks) load(c + 3, rb);
-    mma(1);
-    if ((c + 2) % (FLUSH_ROWS / BKC) == 0) flush_partial(acc, acc64);
-    if (c + 2 < nchunks) convert_store(ra, 0);
+    if (more) convert_store(ra, (int)((c + 1) & 1));
     __syncthreads();
   }
   flush_partial(acc, acc64);

@@ -31,6 +31,7 @@ struct WSep {
 
 
 constexpr int NB = 64;  // Cholesky / triangular-solve block size
+constexpr int kLowRowPad = 64;   // row padding of the fp32 copies: the contraction rows of one bf16 Gram stage
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -87,8 +88,8 @@ struct Inst {
   int64_t* chol_offs = nullptr;  // first task index of each Cholesky look-ahead iteration
   int64_t chol_ntasks = 0;
   // fp32 copies of E and W for the bf16 Grams: E32 has ldE32 = n rounded up
-  // to 32 rows (zero beyond n) and K + 1 columns (column K zero); W32 has
-  // ldW32 = n_h rounded up to 32 rows (zero beyond n_h)
+  // to kLowRowPad rows (zero beyond n) and K + 1 columns (column K zero); W32
+  // has ldW32 = n_h rounded up to kLowRowPad rows (zero beyond n_h)
   float* E32 = nullptr; int64_t ldE32 = 0;
   float* W32 = nullptr; int64_t ldW32 = 0;
   int* lp_tiles = nullptr; int64_t lp_ntiles = 0;   // reduced-precision Gram tiles (ta, tb), in launch order

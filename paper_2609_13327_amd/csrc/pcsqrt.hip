@@ -240,8 +240,8 @@ pc_status alloc_inst(Inst& in, int precision, int flags, bool batched) {
     if (e == hipSuccess) chk(hipMemcpy(in.lp_tiles, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
   }
   if (precision == PC_PREC_BF16_REFINE || precision == PC_PREC_BF16X3_REFINE) {
-    in.ldE32 = pc::round_up(in.n, 32);
-    in.ldW32 = pc::round_up(in.n_h, 32);
+    in.ldE32 = pc::round_up(in.n, pc::kLowRowPad);
+    in.ldW32 = pc::round_up(in.n_h, pc::kLowRowPad);
     chk(dalloc(&in.E32, in.ldE32 * (in.K + 1)));
     chk(dalloc(&in.W32, in.ldW32 * in.M));
     if (e == hipSuccess) chk(hipMemset(in.E32, 0, sizeof(float) * in.ldE32 * (in.K + 1)));
