@@ -23,7 +23,7 @@
 // accumulated in fp32 (the Lo^T Lo term, 2^-16 relative, is dropped): the
 // operand error falls from 2^-9 to about 2^-17 for three bf16 products.
 //
-// Accumulation: the MFMAs accumulate in fp32 over 256 rows of the
+// Accumulation: the MFMAs accumulate in fp32 over at most 256 rows of the
 // contraction at a time; each such partial Gram is then added into an FP64
 // accumulator.  A single fp32 sum over all n rows would carry a relative
 // error of about u32 sqrt(n) (1e-5 measured at n = 131072, mostly on the
@@ -292,15 +292,19 @@ __device__ __forceinline__ void gram_bf16_tile(const LowGramInst& g, int64_t a0,
 }
 
 // ---------------------------------------------------------------- fp32
-constexpr int FKC = 16, FST = FKC + 1;
+// 24 contraction rows per stage (6 per thread): half as many again operand
+// bytes in flight per workgroup as a 16-row stage, at 224 registers per lane
+// (32 rows would spill).  A partial covers F_FLUSH stages (240 rows).
+constexpr int FKC = 24, FR = FKC / 4, FST = FKC + 1;
+constexpr int F_FLUSH = FLUSH_ROWS / FKC;
 
-// Raw FP64 values of 4 consecutive rows of one Z column.
-struct Raw4 { double e[4], w[4]; };
+// Raw FP64 values of FR consecutive rows of one Z column.
+struct RawF { double e[FR], w[FR]; };
 
 // One 128 x 128 tile of the fp32 Gram: the FP64 products rounded once to
-// fp32 (IEEE round to nearest even), fp32 MFMAs, 256-row partials into FP64.
-// 8 waves (2 x 4, each 64 x 32); thread t stages rows 4 (t % 4) .. of a
-// 16-row chunk for tile column t / 4 on both sides.  The loads of chunk
+// fp32 (IEEE round to nearest even), fp32 MFMAs, 240-row partials into FP64.
+// 8 waves (2 x 4, each 64 x 32); thread t stages rows FR (t % 4) .. of a
+// chunk for tile column t / 4 on both sides.  The loads of chunk
 // c + 1 are issued before the MFMAs of chunk c and converted after them.
 // ONE: n_w = 1 and every chunk but a ragged last one is read as contiguous
 // rows without checks; otherwise each row is checked and j = i mod n_h.
@@ -324,15 +328,15 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, WS ws, int
   }
   const int64_t nchunks = (g.n + FKC - 1) / FKC;
   const int64_t nfull = ONE ? g.n / FKC : 0;     // chunks read without row checks
-  int64_t jn = (int64_t)seg * 4 % g.n_h;         // row of W for the next chunk to load (checked path)
-  Raw4 raw[2];
+  int64_t jn = (int64_t)seg * FR % g.n_h;        // row of W for the next chunk to load (checked path)
+  RawF raw[2];
   auto load = [&](int64_t c) {
-    const int64_t i0 = c * FKC + seg * 4;
+    const int64_t i0 = c * FKC + seg * FR;
     if (ONE && c < nfull) {
 #pragma unroll
       for (int side = 0; side < 2; ++side)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < FR; ++q) {
           raw[side].e[q] = pe[side][i0 + q];
           raw[side].w[q] = ws(i0 + q, mc[side]);
         }
@@ -340,7 +344,7 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, WS ws, int
     }
     int64_t j = ONE ? i0 : jn;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < FR; ++q) {
       const bool in = i0 + q < g.n;
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
@@ -356,9 +360,9 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, WS ws, int
   };
   auto convert_store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[buf][col * FST + seg * 4 + q] = valid[0] ? (float)(raw[0].e[q] * raw[0].w[q]) : 0.f;
-      Bs[buf][col * FST + seg * 4 + q] = valid[1] ? (float)(raw[1].e[q] * raw[1].w[q]) : 0.f;
+    for (int q = 0; q < FR; ++q) {
+      As[buf][col * FST + seg * FR + q] = valid[0] ? (float)(raw[0].e[q] * raw[0].w[q]) : 0.f;
+      Bs[buf][col * FST + seg * FR + q] = valid[1] ? (float)(raw[1].e[q] * raw[1].w[q]) : 0.f;
     }
   };
   constexpr int TI = 4, TJ = 2;
@@ -392,7 +396,7 @@ __device__ __forceinline__ void gram_f32_tile_w(const LowGramInst& g, WS ws, int
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_f32(af[i], bf[j], acc[i][j]);
     }
-    if ((c + 1) % (FLUSH_ROWS / FKC) == 0) flush_partial(acc, acc64);
+    if ((c + 1) % F_FLUSH == 0) flush_partial(acc, acc64);
     if (more) convert_store((int)((c + 1) & 1));
     __syncthreads();
   }
