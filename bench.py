@@ -485,6 +485,10 @@ def main():
         "statuses": main_res["statuses"],
         "tuning": {"shapes (gram_split, ztx_split, chol_wgs_per_cu, chol_block, product_tile)": main_res["tuning"]},
         "kernels": kern,
+        # T_roof / T_measured over the step: each timed phase's algorithmic flops at its
+        # precision's peak, against the measured step (phases without a flop count, e.g.
+        # refinement, add to the measured time only)
+        "pipeline_roofline": pipeline_roofline(kern, main_res["ms_per_step"]),
         "phases_ms_per_step": main_res["phases_ms_per_step"],
         "variants": variants,
     }
@@ -497,6 +501,12 @@ def main():
         sm["rel_err_max"] = float(e.max())
     print(json.dumps(out))
     return 0
+
+
+def pipeline_roofline(kern, ms_per_step):
+    t_roof = sum(k["flops_per_launch"] * k["launches_per_step"] / (k["peak_tflops"] * 1e12) for k in kern.values())
+    return {"t_roof_ms": t_roof * 1e3, "t_measured_ms": ms_per_step, "frac": t_roof * 1e3 / ms_per_step,
+            "phases": sorted(kern)}
 
 
 def _event_ms(torch, fn, reps):
