@@ -12,8 +12,9 @@
 // The paper factors each A_m by SVD; here each A_m is inverted once by
 // Gauss-Jordan elimination with partial pivoting (the same A_m^{-1} up to
 // rounding), at build time, one workgroup per grid column.  V1 then is a
-// small product per column and right-hand-side tile, written as the rows of
-// an n_h x (K R) matrix whose column k R + r is w_k of right-hand side r:
+// small FP64 MFMA product per column and right-hand-side tile (after a
+// transpose that groups the right-hand sides by grid column), written as the
+// rows of an n_h x (K R) matrix whose column k R + r is w_k of right-hand side r:
 // that is the regrouping of V2-V3, and V4 becomes one FP64 MFMA product
 // V_b^T (L x n_h) times that matrix, scaled by delta^{-1/2} and scattered to
 // the member segments of V5.
@@ -109,32 +110,95 @@ __global__ __launch_bounds__(256) void swift_invert_kernel(const double* __restr
   if (t == 0) bad[m] = singular;
 }
 
-// V1: rows m of Wm (n_h x ldw, row-major): Wm[m, k R + r] = sum_l Ainv_m[k, l] x[l n_h + m, r],
-// one workgroup per (grid column, tile of 64 right-hand sides).
-__global__ __launch_bounds__(256) void swift_v1_kernel(const double* __restrict__ Ainv, int K, int64_t n_h,
-                                                       const double* __restrict__ X, int64_t ldX, int64_t R,
-                                                       double* __restrict__ Wm, int64_t ldw) {
-  __shared__ double Ai[SW_KMAX * SW_KMAX];
-  __shared__ double Xs[SW_KMAX][65];
-  const int64_t m = blockIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.y * 64;
-  const int t = threadIdx.x;
-  const int nr = (int)std::min<int64_t>(64, R - r0);
-  const double* A = Ainv + m * (int64_t)K * K;
-  for (int e = t; e < K * K; e += 256) Ai[e] = A[e];
-  for (int e = t; e < K * 64; e += 256) {
-    const int l = e / 64, r = e % 64;
-    Xs[l][r] = r < nr ? X[(int64_t)l * n_h + m + (r0 + r) * ldX] : 0.0;
+// V1 reads the K values of x in grid column m, x[l n_h + m] (l < K), for
+// every right-hand side: a stride of n_h between them.  First X is
+// transposed into Xt[(m K + l) R + r] (one 64 x 64 tile of (grid column,
+// right-hand side) per workgroup and level, through LDS, so that both the
+// reads along m and the writes along r are coalesced); then per grid column
+// one FP64 MFMA product Wm[m, k R + r] = sum_l Ainv_m[k, l] Xt[m, l, r]
+// (swift_v1 of SwiftV1Prob), whose operands are contiguous blocks.
+__global__ __launch_bounds__(256) void swift_xt_kernel(const double* __restrict__ X, int64_t ldX, int64_t n_h, int K,
+                                                       int64_t R, double* __restrict__ Xt) {
+  __shared__ double T[64][65];
+  const int64_t m0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+  const int64_t l = blockIdx.z;
+  const int t = threadIdx.x, a = t & 63, g = t >> 6;
+#pragma unroll 4
+  for (int j = g; j < 64; j += 4) {          // read along m (contiguous in X)
+    const int64_t m = m0 + a, r = r0 + j;
+    T[j][a] = (m < n_h && r < R) ? X[l * n_h + m + r * ldX] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < K * 64; e += 256) {
-    const int k = e / 64, r = e % 64;
-    if (r >= nr) continue;
-    double s = 0.0;
-    for (int l = 0; l < K; ++l) s = fma(Ai[k + l * K], Xs[l][r], s);
-    Wm[m * ldw + (int64_t)k * R + r0 + r] = s;
+#pragma unroll 4
+  for (int i = g; i < 64; i += 4) {          // write along r (contiguous in Xt)
+    const int64_t m = m0 + i, r = r0 + a;
+    if (m < n_h && r < R) Xt[(m * K + l) * R + r] = T[a][i];
   }
 }
+
+// V1 per grid column m and tile of 64 right-hand sides:
+// Wm[m, k R + r] = sum_l Ainv_m[k, l] Xt[m, l, r] (rows k of the product, columns r).
+struct SwiftV1Prob {
+  static constexpr int BM = 64, BN = 64, WM = 2, WN = 2, KC = 16;
+  static constexpr int LDA = BM + 1, LDB = BN;
+  static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
+  const double* Ainv; int K;
+  const double* Xt;
+  double* Wm; int64_t ldw;
+  int64_t R; int nrt;
+
+  struct Ctx { bool valid; int64_t m, r0; int nchunks; };
+  struct ARegs { double v[NA]; };
+  struct BRegs { double v[NB_]; };
+
+  __device__ Ctx ctx(int b) const {
+    Ctx c;
+    c.valid = true;
+    c.m = b / nrt;
+    c.r0 = (int64_t)(b % nrt) * BN;
+    c.nchunks = (K + KC - 1) / KC;
+    return c;
+  }
+  __device__ void loadA(const Ctx& c, int chunk, ARegs& r) const {
+    const double* A = Ainv + c.m * (int64_t)K * K;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q, row = e % BM, kk = e / BM;   // row k contiguous
+      const int l = chunk * KC + kk;
+      r.v[q] = (row < K && l < K) ? A[row + l * K] : 0.0;
+    }
+  }
+  __device__ void storeA(const ARegs& r, double* As) const {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[(e / BM) * LDA + e % BM] = r.v[q];
+    }
+  }
+  __device__ void loadB(const Ctx& c, int chunk, BRegs& r) const {
+    const double* B = Xt + c.m * (int64_t)K * R;
+#pragma unroll
+    for (int q = 0; q < NB_; ++q) {
+      const int e = threadIdx.x + 256 * q, col = e % BN, kk = e / BN;  // right-hand side contiguous
+      const int l = chunk * KC + kk;
+      r.v[q] = (c.r0 + col < R && l < K) ? B[(int64_t)l * R + c.r0 + col] : 0.0;
+    }
+  }
+  __device__ void storeB(const BRegs& r, double* Bs) const {
+#pragma unroll
+    for (int q = 0; q < NB_; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      Bs[(e / BN) * LDB + e % BN] = r.v[q];
+    }
+  }
+  __device__ void epilogue(const Ctx& c, const TileF64<BM, BN, WM, WN>& acc) const {
+    acc.for_each([&](int row, int col, double v) {
+      const int64_t r = c.r0 + col;
+      if (row >= K || r >= R) return;
+      Wm[c.m * ldw + (int64_t)row * R + r] = v;
+    });
+  }
+};
 
 // V4-V5: Y[k L + l, r] = delta_l^{-1/2} sum_m Vb[m, l] Wm[m, k R + r], as a
 // GEMM C (L x K R) = Vb^T Wm over 64 x 64 tiles, contraction over m.
@@ -227,6 +291,7 @@ struct pc_swift {
   double* Ainv = nullptr;   // n_h blocks K x K
   double* rsd = nullptr;    // L: delta^{-1/2}
   double* Wm = nullptr;     // n_h x (K max_rhs), row-major
+  double* Xt = nullptr;     // n_h K max_rhs: the right-hand sides grouped by grid column
   int* bad = nullptr;       // n_h singular flags, then [n_h] delta flag, [n_h + 1] any
 };
 
@@ -236,6 +301,7 @@ static void swift_free(pc_swift* s) {
   (void)hipFree(s->Ainv);
   (void)hipFree(s->rsd);
   (void)hipFree(s->Wm);
+  (void)hipFree(s->Xt);
   (void)hipFree(s->bad);
   delete s;
 }
@@ -257,6 +323,7 @@ extern "C" pc_status pc_swift_build(int64_t n_h, int64_t K, int64_t L, const dou
   bool ok = hipMalloc((void**)&s->Ainv, sizeof(double) * (size_t)(n_h * K * K)) == hipSuccess &&
             hipMalloc((void**)&s->rsd, sizeof(double) * (size_t)L) == hipSuccess &&
             hipMalloc((void**)&s->Wm, sizeof(double) * (size_t)(n_h * K * s->max_rhs)) == hipSuccess &&
+            hipMalloc((void**)&s->Xt, sizeof(double) * (size_t)(n_h * K * s->max_rhs)) == hipSuccess &&
             hipMalloc((void**)&s->bad, sizeof(int) * (size_t)(n_h + 2)) == hipSuccess;
   if (!ok) { swift_free(s); return PC_ERR_OOM; }
   int h[2] = {0, 0};
@@ -288,8 +355,13 @@ extern "C" pc_status pc_swift_apply(pc_swift* s, const double* X, int64_t ldX, i
   (void)hipSetDevice(s->device);
   hipStream_t st = (hipStream_t)stream;
   const int64_t ldw = s->K * R;
-  hipLaunchKernelGGL(pc::swift_v1_kernel, dim3((unsigned)s->n_h, (unsigned)pc::ceil_div(R, 64)), dim3(256), 0, st,
-                     s->Ainv, (int)s->K, s->n_h, X, ldX, R, s->Wm, ldw);
+  hipLaunchKernelGGL(pc::swift_xt_kernel, dim3((unsigned)pc::ceil_div(s->n_h, 64), (unsigned)pc::ceil_div(R, 64),
+                                                (unsigned)s->K),
+                     dim3(256), 0, st, X, ldX, s->n_h, (int)s->K, R, s->Xt);
+  pc::SwiftV1Prob v1;
+  v1.Ainv = s->Ainv; v1.K = (int)s->K; v1.Xt = s->Xt; v1.Wm = s->Wm; v1.ldw = ldw; v1.R = R;
+  v1.nrt = (int)pc::ceil_div(R, pc::SwiftV1Prob::BN);
+  hipLaunchKernelGGL(pc::gemm_f64_kernel<pc::SwiftV1Prob>, dim3((unsigned)(s->n_h * v1.nrt)), dim3(256), 0, st, v1);
   pc::SwiftProjProb g;
   g.Vb = s->Vb; g.ldV = s->ldV; g.Wm = s->Wm; g.ldw = ldw; g.rsd = s->rsd; g.Y = Y; g.ldY = ldY;
   g.L = s->L; g.NC = s->K * R; g.n_h = s->n_h; g.R = R;
