@@ -106,3 +106,42 @@ def test_large_instance_sampled_gram_entries(big):
         assert abs(got - ref) <= 1e-12 * scale, (a, b, got, ref)
     del G
     plan.close()
+
+
+def test_large_instance_lowprec_ztx_sampled_entries(big):
+    """Reduced-precision Z^T x at full size (all 1024 right-hand sides, the
+    launch the mixed solves use): sampled entries against their defining
+    sums over the 131072 rows of the oracle's rounded operands, within the
+    fp32 accumulation bound gamma_{n+1}(u32) sum |z~ x~|."""
+    from oracle import lsq
+    inst, _ = big
+    plan = pc.Plan([inst_dict(inst, max_rhs=1024)])
+    X = dev(inst.X)
+    B = empty(inst.KM, inst.R)
+    rng = np.random.default_rng(9)
+    samples = [(int(rng.integers(inst.K)), int(rng.integers(inst.M)), int(rng.integers(inst.R))) for _ in range(6)]
+    samples += [(inst.K - 1, inst.M - 1, inst.R - 1), (0, 0, 0)]
+    g = (inst.n + 1) * 2.0 ** -24
+    for fmt, code in (("fp32", pc.PC_PREC_FP32_REFINE), ("bf16", pc.PC_PREC_BF16_REFINE)):
+        pc.pc_sqrt_transpose_apply_lowprec(plan.handle, 0, code, X, B)
+        for k, m, r in samples:
+            got = float(B[k * inst.M + m, r].item())
+            zt = lsq.lowprec_operands(inst.E[:, k:k + 1], inst.W[:, m:m + 1], 1, fmt)[0][:, 0]
+            xt = lsq.round_rhs(inst.X[:, r], fmt)
+            ref = float(np.dot(zt, xt))
+            bound = g / (1 - g) * float(np.dot(np.abs(zt), np.abs(xt)))
+            assert abs(got - ref) <= bound, (fmt, k, m, r, got, ref, bound)
+    plan.close()
+
+
+def test_large_instance_mixed_from_lowprec_ztx_against_oracle(big):
+    """bf16 Gram with the first b = Z^T x formed in fp32: the refined
+    answers meet the mixed-precision tolerance against the stored oracle."""
+    inst, g = big
+    X = dev(inst.X)
+    st, Y, it, rung = _solve(inst, X, pc.PC_PREC_BF16_REFINE, max_refine=30, tol=1e-11, flags=pc.PC_FLAG_ZTX_FP32)
+    err = _errors(Y, g)
+    print(f"bf16 + fp32 Z^T x: status {st}, rung {rung}, refinement iterations {it}, max rel err {err.max():.3e}",
+          flush=True)
+    assert st == pc.PC_OK
+    assert np.all(err <= _tolerance(g, 1e-8))
