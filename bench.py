@@ -72,6 +72,8 @@ def parse():
                     help="config 5: precision of the Gram whose factor preconditions CG")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16", "bf16x3"],
                     help="default: fp32 for config 3, fp64 otherwise")
+    ap.add_argument("--ztx-precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="operands of the first Z^T x of a reduced-precision solve (the refinement stays FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--tune-cache", default=None, help="tuning cache file (read and updated)")
@@ -197,6 +199,9 @@ def main():
         """Time factor + apply per step; `flags` are plan flags, `nrhs` the
         first right-hand sides of each instance only (None: all)."""
         code, refine = PRECS[prec_name]
+        # the first Z^T x in reduced precision (only on a reduced-precision plan)
+        zlow = None if prec_name == "fp64" else (
+            "fp32" if flags & pc.PC_FLAG_ZTX_FP32 else "bf16" if flags & pc.PC_FLAG_ZTX_BF16 else None)
         Xall = [x[:, :nrhs] for x in dX] if nrhs else dX
         Yall = [y[:, :nrhs] for y in dY] if nrhs else dY
         rhs_total = nrhs * len(insts) if nrhs else total_rhs
@@ -278,6 +283,9 @@ def main():
             # reduced-precision Grams (instances on the FP64 rung form theirs
             # on the internal streams, outside it), so only those count
             inst_prec = [RUNG_PREC.get(r, prec_name) if ph == "gram" else prec_name for r in rungs]
+            low_ztx = ph == "ztx" and zlow is not None
+            if low_ztx:
+                inst_prec = [zlow] * len(insts)
             batch_low = ph == "gram" and prec_name != "fp64" and len(insts) > 1
             scale = per / launches_per_step
             fl = [0.0 if batch_low and q == "fp64" else algorithmic_flops(ph, q, i, nrhs or i.R) * scale
@@ -285,11 +293,13 @@ def main():
             flops = sum(fl)
             if flops <= 0:
                 continue
-            t_peak = sum(f / (phase_peak(ph, q) * 1e12) for f, q in zip(fl, inst_prec))
+            t_peak = sum(f / ((PEAK_TFLOPS[q] if low_ztx else phase_peak(ph, q)) * 1e12) for f, q in zip(fl, inst_prec))
             avg = tot_ms / (cnt * per)
             ach = flops / (avg * 1e-3) / 1e12
             peak = flops / t_peak / 1e12
             name, _ = kernel_info(ph, prec_name)
+            if low_ztx:
+                name = "ztx_f32_kernel" if zlow == "fp32" else "ztx_bf16_kernel"
             if batch_low:
                 name = f"gram_lowprec_batch_kernel<{code}>"     # all reduced-precision Grams in one launch
             if blocked and ph in ("cholesky", "solve"):
@@ -307,7 +317,8 @@ def main():
                 "refine_iters_max": max(it for it, _ in info), "Y": Y}
 
     log(f"timing {prec_main}: {warmup} warmup + {steps} steps")
-    main_res = measure(prec_main, steps, warmup)
+    ztx_flag = {"fp64": 0, "fp32": pc.PC_FLAG_ZTX_FP32, "bf16": pc.PC_FLAG_ZTX_BF16}[args.ztx_precision]
+    main_res = measure(prec_main, steps, warmup, flags=ztx_flag)
     log(f"  {main_res['ms_per_step']:.3f} ms/step")
 
     # accuracy against the oracle, and the CPU baseline (the oracle on the host)
@@ -467,7 +478,8 @@ def main():
         "config": {"workload": wl.CONFIG_NAMES[args.config], "instances": len(insts),
                    "n": [i.n for i in insts] if len(insts) > 1 else insts[0].n,
                    "KM_max": max(i.KM for i in insts), "rhs": total_rhs, "rhs_counted": counted,
-                   "precision": prec_main, "hipgraph": bool(use_graph), "parallelism": "single GPU"},
+                   "precision": prec_main, "ztx_precision": args.ztx_precision if prec_main != "fp64" else "fp64",
+                   "hipgraph": bool(use_graph), "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "kernel": d["kernel"], "achieved": d["achieved_tflops"],
                      "peak": d["peak_tflops"], "unit": "TFLOP/s", "frac": d["frac"],
                      "traffic": traffic, "flops_per_launch": d["flops_per_launch"],
