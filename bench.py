@@ -146,9 +146,9 @@ def oracle_threads():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build; DESIGN.md says how it would shard)")
+        log("bench.py: only --gpus 1 is supported (the library runs one instance per GPU and has no multi-GPU path)")
         return 2
     if args.copy_probe:
         copy_probe()

@@ -435,7 +435,7 @@ int32_t pc_selftest_task_order(int32_t T, int32_t group);
  * Not part of the paper's method: conjugate gradients on G y = b with
  * G = Z^T Z, started from the prediction of a small network trained on
  * (x, Z^+ x) pairs that the direct method produced; the direct solve stays
- * the fallback and the judge of its error.
+ * the fallback and the reference its error is measured against.
  * ---------------------------------------------------------------------- */
 
 /* pc_cg_solve — preconditioned CG on G y = b (G the FP64 Gram; the
