@@ -201,9 +201,10 @@ struct SwiftV1Prob {
 };
 
 // V4-V5: Y[k L + l, r] = delta_l^{-1/2} sum_m Vb[m, l] Wm[m, k R + r], as a
-// GEMM C (L x K R) = Vb^T Wm over 64 x 64 tiles, contraction over m.
+// GEMM C (L x K R) = Vb^T Wm over 64 x 64 tiles, contraction over m in
+// chunks of 32 (twice the bytes in flight of 16-deep chunks, half the barriers).
 struct SwiftProjProb {
-  static constexpr int BM = 64, BN = 64, WM = 2, WN = 2, KC = 16;
+  static constexpr int BM = 64, BN = 64, WM = 2, WN = 2, KC = 32;
   static constexpr int LDA = BM + 1, LDB = BN;
   static constexpr int NA = BM * KC / 256, NB_ = BN * KC / 256;
   const double* Vb; int64_t ldV;
